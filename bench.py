@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Throughput of the layer-wise multislice hot path on one MI355X.
+
+One step is one fused loss-and-gradient pass (ms_adjoint) over every scan
+position of the workload: shifted probes, the forward multislice chain, the
+far-field modulus residual, the adjoint chain back to the probe, the
+deterministic scatter of the per-position gradients into every slice, the
+probe-gradient reduction and the FP64 loss.  The metric counts
+S * M position-slice forward+adjoint updates per step.
+
+Prints ONE JSON line.  Also reported (outside the timed region): one
+Algorithm 1 sweep (M layer steps and one probe step) and one forward pass.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "position-slice fwd+adjoint updates/s; time-to-loss, learned init vs plain"
+UNIT = "position-slice fwd+adjoint updates/s"
+HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
+ALU_PEAK = 78.6e12           # FP32 FMA flop/s without packed FP32: 256 CU x 64 lanes x 2 x 2.4 GHz
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_adjoint_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2205_03902_amd", "csrc", f)
+                  for f in ("ms_kernels.hpp", "fft_lines.hpp")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def model_per_launch(geo):
+    """Algorithmic bytes and flops of one fused adjoint launch over all positions.
+
+    Bytes per position: measured intensities 4 N^2, incident waves stored and
+    reloaded 2 (M-1) 8 N^2, slice-gradient patches M 8 N^2, probe-gradient
+    patch 8 N^2 (object-patch gathers are cache reuse and not counted).
+    Flops per position: (4M - 2) 2D FFTs of 10 N^2 log2 N, plus 30 N^2 M
+    pointwise (transmission, propagator, gradient products) and 20 N^2 for the
+    modulus residual.
+    """
+    n2 = geo.n * geo.n
+    M = geo.n_slices
+    bytes_pos = 4 * n2 + 8 * n2 * (2 * (M - 1) + M + 1)
+    flops_pos = (4 * M - 2) * 10 * n2 * math.log2(geo.n) + 30 * n2 * M + 20 * n2
+    return bytes_pos * geo.n_pos, flops_pos * geo.n_pos
+
+
+def pass_bytes(geo):
+    """Whole-pass byte model: 32 N^2 M + 4 N^2 per position plus 24 H W M."""
+    n2 = geo.n * geo.n
+    return (32 * n2 * geo.n_slices + 4 * n2) * geo.n_pos + 24 * geo.obj_h * geo.obj_w * geo.n_slices
+
+
+def traffic_record():
+    """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(geo, n_sample: int):
+    """The FP64 oracle on a sample of the same workload (one fwd+adj pass over n_sample positions)."""
+    import numpy as np
+
+    import oracle
+    from paper_2205_03902_amd import synth
+    pos = geo.positions()
+    pick = np.linspace(0, geo.n_pos - 1, n_sample).round().astype(int)
+    md = oracle.Model.from_geometry(geo, positions=pos[pick])
+    probe = oracle.probe(geo.n, geo.pixel_size, geo.wavelength, geo.alpha, geo.defocus)
+    truth = synth.transmissions(synth.specimen(geo))
+    meas = synth.poisson_counts(md.forward(probe, truth), geo.dose, geo.seed + 1)
+    start = np.ones_like(truth)
+    t0 = time.perf_counter()
+    md.loss_grad(probe, start, meas)
+    secs = time.perf_counter() - t0
+    return {"value": n_sample * geo.n_slices / secs, "unit": UNIT, "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{n_sample} of {geo.n_pos} positions (evenly spaced), one fwd+adj pass, "
+                      f"{secs:.2f} s wall, FP64"}
+
+
+def copy_calibration():
+    """A plain device copy of known size, for scaling HBM traffic counters."""
+    import torch
+    n = 1 << 28                      # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: read {a.numel() * 4 / 1024:.0f} KiB, wrote {b.numel() * 4 / 1024:.0f} KiB")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=1, help="workload geometry (0..4)")
+    ap.add_argument("--cpu-sample", type=int, default=256, help="positions in the oracle's timing sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the sweep and forward timings")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}, WORLD_SIZE {world}): this build "
+              "implements the single-GPU hot path only; multi-GPU position sharding is a design note.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    from paper_2205_03902_amd import abi, configs, layerwise, synth
+    geo = configs.CONFIGS[args.config]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"bench: {geo.name} N={geo.n} H=W={geo.obj_h} M={geo.n_slices} S={geo.n_pos}")
+
+    plan = abi.Plan.from_geometry(geo, device=dev)
+    probe_true = plan.make_probe(geo.alpha, geo.defocus)
+    truth = torch.from_numpy(synth.transmissions(synth.specimen(geo))).to(dev)
+    inten = plan.forward(probe_true, truth)
+    if geo.dose > 0:
+        g = torch.Generator(device=dev)
+        g.manual_seed(geo.seed + 1)
+        scale = geo.dose / (geo.n * geo.n)
+        measured = (torch.poisson(inten * scale, generator=g) / scale).contiguous()
+    else:
+        measured = inten
+    # plain start (identity slices) and the 10 %-longer-defocus probe start
+    slices = torch.ones((geo.n_slices, geo.obj_h, geo.obj_w), dtype=torch.complex64, device=dev)
+    probe = plan.make_probe(geo.alpha, 1.1 * geo.defocus)
+    gs = torch.empty_like(slices)
+    gp = torch.empty_like(probe)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        plan.adjoint(probe, slices, measured, grad_slices=gs, grad_probe=gp, loss=loss)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.profile_begin(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.adjoint(probe, slices, measured, grad_slices=gs, grad_probe=gp, loss=loss)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms, launches = plan.profile_end()
+    ms = e0.elapsed_time(e1) / args.steps
+    log(f"bench: {args.steps} steps, {ms:.3f} ms/step (events), {wall * 1e3 / args.steps:.3f} ms/step (wall), "
+        f"fused kernel {kern_ms / max(launches, 1):.3f} ms x {launches}, loss {loss.item():.6e}")
+
+    value = geo.n_pos * geo.n_slices / (ms * 1e-3)
+    byt, flo = model_per_launch(geo)
+    k_s = kern_ms / max(launches, 1) * 1e-3
+    hbm = {"bound": "hbm", "achieved": byt / k_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    hbm["frac"] = hbm["achieved"] / hbm["peak"]
+    alu = {"bound": "alu", "achieved": flo / k_s / 1e12, "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s"}
+    alu["frac"] = alu["achieved"] / alu["peak"]
+    roof = dict(alu if alu["frac"] >= hbm["frac"] else hbm)
+    other = hbm if roof["bound"] == "alu" else alu
+    traffic = traffic_record()
+    roof["traffic"] = traffic
+    roof["kernel"] = f"fused_kernel<{geo.n}, adjoint>"
+    roof["kernel_ms"] = kern_ms / max(launches, 1)
+    roof["other"] = {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    roof["algorithmic_bytes_per_launch"] = byt
+    roof["algorithmic_flops_per_launch"] = flo
+
+    extras = {}
+    if not args.no_extras:
+        # one forward pass
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        for _ in range(3):
+            plan.forward(probe, slices)
+        torch.cuda.synchronize()
+        extras["forward_ms"] = (time.perf_counter() - f0) * 1e3 / 3
+        # one Algorithm 1 sweep: M layer steps and one probe step over all positions
+        sl = slices.clone()
+        pr = probe.clone()
+        h = layerwise.reconstruct(plan, pr, sl, measured, sweeps=1, k_steps=1, probe_steps=1)
+        extras["sweep_ms"] = h.seconds * 1e3
+        extras["sweep_losses"] = [h.loss[0], h.loss[-1]]
+        extras["pass_model_bytes"] = pass_bytes(geo)
+
+    out = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{geo.name}: {geo.n}x{geo.n} window, {geo.obj_h}x{geo.obj_w} object, "
+                                  f"{geo.n_slices} slices, {geo.n_pos} positions",
+                      "n": geo.n, "obj": geo.obj_h, "slices": geo.n_slices, "positions": geo.n_pos,
+                      "parallelism": "single GPU, positions in one batch"},
+           "roofline": roof}
+    out.update(extras)
+    if not args.no_cpu_baseline:
+        log("bench: timing the FP64 oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(geo, min(args.cpu_sample, geo.n_pos))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

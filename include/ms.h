@@ -1,0 +1,154 @@
+/*
+ * libimsp - layer-wise inverse multislice ptychography on one MI355X (gfx950).
+ *
+ * C ABI of the GPU library.  The operations follow Bangun et al.,
+ * "Inverse Multislice Ptychography by Layer-wise Optimisation and Sparse
+ * Matrix Decomposition" (arXiv 2205.03902):
+ *   - the forward multislice model of Sec. 2.1: E_1 = P^s o X_1,
+ *     E_m = V_z(E_{m-1}) o X_m with V_z(E) = F^{-1}(F(E) o H_m) and the Fresnel
+ *     propagator of eq. (fresnel_element), then I^s = |F(E_M^s)|^2;
+ *   - the amplitude least-squares objective of eq. (Opt_Prob_Layerwise),
+ *     L = sum_s sum_k (sqrt(I_k^s) - |F E_M^s|_k)^2 (no factor 1/2), and its
+ *     generalised Wirtinger gradient of Sec. 3.2 (dL/d conj(z), the phase of a
+ *     zero far-field value taken as 0);
+ *   - the layer-wise amplitude-flow step of Algorithm 1 (Sec. 3.3) and the
+ *     probe step of Sec. 3.5, each with step size mu = 1 / (upper bound of
+ *     ||Q||^2), the bound being exact when the slices have unit modulus.
+ *
+ * Data layout.  Complex values are interleaved float32 pairs (ms_c64, the
+ * layout of torch.complex64).  2D arrays are row-major [y][x] with x fastest.
+ *   probe        N x N, the unshifted probe; its window corner is the scan position.
+ *   slices       M x H x W transmission functions t_m (periodic object).
+ *   intensities  S x N x N, detector pixels in FFT order (zero frequency at [0][0]).
+ * A scan position (y, x) is the corner of the N x N window in object pixels;
+ * object indices wrap around modulo H and W (Sec. 1.3).  The integer part of a
+ * position selects the object patch; its fractional part shifts the probe by
+ * the Fourier phase ramp exp(-2 pi i (k_y f_y + k_x f_x) / N), k in FFT order.
+ *
+ * Pointers are device pointers unless marked (host).  The caller owns every
+ * buffer, including the workspace; the library never allocates device
+ * memory.  Every compute call only enqueues work on the given stream and
+ * returns without synchronising; outputs are valid once the stream reaches
+ * that point.  Gradients are overwritten, not accumulated.
+ *
+ * Errors.  Arguments are validated on the host before anything is enqueued;
+ * on error nothing is launched, no output is touched, a negative ms_status is
+ * returned and ms_last_error() describes it.  A HIP error while enqueueing is
+ * reported as MS_ERR_HIP.  No C++ exception crosses this interface.
+ * Calls that share one plan must not overlap in time (the plan's workspace is
+ * reused by every call).
+ */
+#ifndef IMSP_MS_H
+#define IMSP_MS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    float re, im;
+} ms_c64;
+
+typedef enum {
+    MS_OK = 0,
+    MS_ERR_INVALID_ARG = -1,   /* a NULL pointer, a bad size, a non-finite parameter    */
+    MS_ERR_UNSUPPORTED = -2,   /* valid problem outside what this build implements     */
+    MS_ERR_BUDGET = -3,        /* workspace smaller than ms_workspace_size requires    */
+    MS_ERR_HIP = -4            /* the HIP runtime reported an error while enqueueing   */
+} ms_status;
+
+/* The problem statement of Sec. 2.1: probe window, slices, scan positions,
+ * slice distances, wavelength, tilts. */
+typedef struct {
+    int32_t n;                 /* window and detector side N: 16, 32, 64, 128 or 256     */
+    int32_t obj_h, obj_w;      /* object size H, W in pixels, H >= N, W >= N            */
+    int32_t n_slices;          /* M >= 1                                                */
+    int64_t n_pos;             /* S >= 1                                                */
+    const double *positions;   /* (host) S x 2, (y, x) window corners in object pixels  */
+    const double *dz;          /* (host) M - 1 Fresnel distances Delta_m (Angstrom)     */
+    double pixel_size;         /* real-space sampling dx (Angstrom), q = k / (N dx)     */
+    double wavelength;         /* lambda (Angstrom)                                     */
+    double tilt_y, tilt_x;     /* illumination tilts theta_y, theta_x (rad)             */
+} ms_problem;
+
+typedef struct ms_plan ms_plan;
+
+/* Workspace bytes for `pb`.  budget_bytes = 0 processes all positions in one
+ * batch; otherwise positions are processed in the largest batches that fit
+ * the budget (MS_ERR_BUDGET if not even one position fits). */
+ms_status ms_workspace_size(const ms_problem *pb, size_t budget_bytes, size_t *ws_bytes);
+
+/* Builds a plan: copies the host arrays, derives patch origins, probe shift
+ * classes and the scatter lists, and uploads its tables into `workspace`
+ * (device memory of ws_bytes, 256-byte aligned, owned by the caller and kept
+ * alive until ms_plan_destroy).  Blocks until the upload is done. */
+ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes, ms_plan **out);
+void ms_plan_destroy(ms_plan *plan);
+
+/* Positions per batch and number of probe shift classes chosen by the plan. */
+int64_t ms_plan_batch(const ms_plan *plan);
+int32_t ms_plan_shift_classes(const ms_plan *plan);
+
+/* The probe of Sec. 2.1 (caption of Fig. 3): the inverse DFT of the disk
+ * lambda |q| <= alpha (boundary included), multiplied by the propagator of
+ * eq. (fresnel_element) for distance `defocus`, centred at (N/2, N/2) and
+ * scaled to sum |p|^2 = 1.  probe_out: N x N. */
+ms_status ms_make_probe(ms_plan *plan, hipStream_t stream, double alpha, double defocus,
+                        ms_c64 *probe_out);
+
+/* Forward model (Sec. 2.1): intensity_out (S x N x N) = |F E_M^s|^2 and, if
+ * exit_out is not NULL, the exit waves E_M^s (S x N x N). */
+ms_status ms_forward(ms_plan *plan, hipStream_t stream, const ms_c64 *probe, const ms_c64 *slices,
+                     float *intensity_out, ms_c64 *exit_out);
+
+/* Loss and gradients (Sec. 3.2) of every slice and of the probe.
+ *   measured    S x N x N measured intensities (>= 0), FFT order;
+ *   grad_slices M x H x W, dL/d conj(t_m);
+ *   grad_probe  N x N, dL/d conj(P), or NULL to skip it;
+ *   loss_out    one double, the loss L. */
+ms_status ms_adjoint(ms_plan *plan, hipStream_t stream, const ms_c64 *probe, const ms_c64 *slices,
+                     const float *measured, ms_c64 *grad_slices, ms_c64 *grad_probe,
+                     double *loss_out);
+
+/* k_steps amplitude-flow steps on slice `layer` (0-based, i.e. l - 1), the
+ * inner loop of Algorithm 1 with the other slices fixed:
+ *   t_l <- t_l - mu * dL/d conj(t_l),
+ *   mu = 1 / (N^2 * prod_{m > l} max|t_m|^2 * max_pixel sum_s |psi_l^s|^2),
+ * psi_l^s being the wave incident on slice l at position s.  Only slice
+ * `layer` of `slices` is written.  loss_out / mu_out (one double each, may be
+ * NULL) receive the loss and step size of the last step, the loss evaluated
+ * before that step. */
+ms_status ms_layer_step(ms_plan *plan, hipStream_t stream, int32_t layer, int32_t k_steps,
+                        const ms_c64 *probe, ms_c64 *slices, const float *measured,
+                        double *loss_out, double *mu_out);
+
+/* k_steps amplitude-flow steps on the probe (Sec. 3.5) over the positions in
+ * `subset` ((host) n_subset indices in [0, S); NULL = all positions):
+ *   P <- P - mu * dL/d conj(P),  mu = 1 / (N^2 * n_subset * prod_m max|t_m|^2).
+ * The paper's variant uses the single centre position.  loss_out / mu_out as
+ * for ms_layer_step. */
+ms_status ms_probe_step(ms_plan *plan, hipStream_t stream, int32_t k_steps, ms_c64 *probe,
+                        const ms_c64 *slices, const float *measured, const int64_t *subset,
+                        int64_t n_subset, double *loss_out, double *mu_out);
+
+/* Timing of the dominant kernel (the fused per-position multislice kernel).
+ * After ms_profile_begin, the next max_launches launches of that kernel made
+ * through `plan` are each bracketed by a pair of HIP events on their stream.
+ * ms_profile_end waits for the last of them, returns the summed kernel time
+ * (milliseconds) and the number of launches timed, and releases the events.
+ * For measurement tools; not needed for computation. */
+ms_status ms_profile_begin(ms_plan *plan, int32_t max_launches);
+ms_status ms_profile_end(ms_plan *plan, double *total_ms, int64_t *launches);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *ms_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

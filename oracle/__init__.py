@@ -46,6 +46,8 @@ def lib():
             build()
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
+        L.orc_max_threads.restype = C.c_int
+        L.orc_max_threads.argtypes = []
         L.orc_wavelength.restype = C.c_double
         L.orc_wavelength.argtypes = [C.c_double]
         L.orc_dft1d.restype = None
@@ -82,6 +84,10 @@ def _ptr(a):
 def _check(rc, what):
     if rc != 0:
         raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()
 
 
 def wavelength(volts: float) -> float:

@@ -24,6 +24,8 @@ static const double PI = 3.14159265358979323846264338327950288;
 static int is_pow2(int n) { return n >= 1 && (n & (n - 1)) == 0; }
 static long wrap(long i, long n) { long r = i % n; return r < 0 ? r + n : r; }
 
+int orc_max_threads(void) { return omp_get_max_threads(); }
+
 /* ------------------------------------------------------------------ */
 /* Physics constants, Sec. 5.3.2: lambda = h c / sqrt(e^2 U^2 + 2 e U m c^2). */
 double orc_wavelength(double volts)

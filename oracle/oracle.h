@@ -48,6 +48,9 @@ typedef struct {
     int n_threads;           /* worker threads, 0 = OpenMP default                 */
 } orc_problem;
 
+/* Threads the oracle uses when orc_problem.n_threads is 0. */
+int orc_max_threads(void);
+
 /* Electron wavelength (A) for an acceleration voltage U (V), Sec. 5.3.2. */
 double orc_wavelength(double volts);
 

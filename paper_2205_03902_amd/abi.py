@@ -1,0 +1,245 @@
+"""ctypes binding of libimsp (include/ms.h).
+
+Argument marshalling only: every step of the multislice path runs in the HIP
+kernels behind the C ABI.  PyTorch provides device memory (the caller's
+tensors and the plan workspace) and the current stream.  There is no CPU
+fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libimsp.so")
+
+MS_OK, MS_ERR_INVALID_ARG, MS_ERR_UNSUPPORTED, MS_ERR_BUDGET, MS_ERR_HIP = 0, -1, -2, -3, -4
+
+# every entry point declared in include/ms.h
+SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
+           "ms_make_probe", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_probe_step", "ms_profile_begin",
+           "ms_profile_end", "ms_last_error")
+
+
+class MsError(RuntimeError):
+    def __init__(self, status: int, what: str, message: str):
+        super().__init__(f"{what} failed ({status}): {message}")
+        self.status = status
+
+
+class MsProblem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("obj_h", C.c_int32), ("obj_w", C.c_int32), ("n_slices", C.c_int32),
+                ("n_pos", C.c_int64), ("positions", C.c_void_p), ("dz", C.c_void_p),
+                ("pixel_size", C.c_double), ("wavelength", C.c_double),
+                ("tilt_y", C.c_double), ("tilt_x", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libimsp.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2205_03902_amd.build.build() "
+                               "(or __graft_entry__.build()); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.ms_workspace_size.restype = I32
+        L.ms_workspace_size.argtypes = [C.POINTER(MsProblem), C.c_size_t, C.POINTER(C.c_size_t)]
+        L.ms_plan_create.restype = I32
+        L.ms_plan_create.argtypes = [C.POINTER(MsProblem), P, C.c_size_t, C.POINTER(P)]
+        L.ms_plan_destroy.restype = None
+        L.ms_plan_destroy.argtypes = [P]
+        L.ms_plan_batch.restype = I64
+        L.ms_plan_batch.argtypes = [P]
+        L.ms_plan_shift_classes.restype = I32
+        L.ms_plan_shift_classes.argtypes = [P]
+        L.ms_make_probe.restype = I32
+        L.ms_make_probe.argtypes = [P, P, D, D, P]
+        L.ms_forward.restype = I32
+        L.ms_forward.argtypes = [P, P, P, P, P, P]
+        L.ms_adjoint.restype = I32
+        L.ms_adjoint.argtypes = [P, P, P, P, P, P, P, P]
+        L.ms_layer_step.restype = I32
+        L.ms_layer_step.argtypes = [P, P, I32, I32, P, P, P, P, P]
+        L.ms_probe_step.restype = I32
+        L.ms_probe_step.argtypes = [P, P, I32, P, P, P, P, I64, P, P]
+        L.ms_profile_begin.restype = I32
+        L.ms_profile_begin.argtypes = [P, I32]
+        L.ms_profile_end.restype = I32
+        L.ms_profile_end.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.ms_last_error.restype = C.c_char_p
+        L.ms_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != MS_OK:
+        raise MsError(status, what, lib().ms_last_error().decode())
+
+
+def make_problem(n, obj_h, obj_w, n_slices, positions, dz, pixel_size, wavelength, tilt_y=0.0, tilt_x=0.0):
+    """Returns (MsProblem, keepalive) with host arrays owned by the caller's keepalive tuple."""
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
+    dzs = np.ascontiguousarray(np.asarray(dz, dtype=np.float64).reshape(-1))
+    if dzs.size == 0:
+        dzs = np.zeros(1)
+    pb = MsProblem(int(n), int(obj_h), int(obj_w), int(n_slices), pos.shape[0], pos.ctypes.data, dzs.ctypes.data,
+                   float(pixel_size), float(wavelength), float(tilt_y), float(tilt_x))
+    return pb, (pos, dzs)
+
+
+def workspace_size(pb: MsProblem, budget_bytes: int = 0) -> int:
+    out = C.c_size_t(0)
+    _check(lib().ms_workspace_size(C.byref(pb), int(budget_bytes), C.byref(out)), "ms_workspace_size")
+    return out.value
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Plan:
+    """A multislice plan bound to one device: geometry, tables and workspace.
+
+    Every method enqueues on torch's current stream of the plan's device and
+    returns without synchronising.  Calls on one plan must not overlap.
+    """
+
+    def __init__(self, n, obj_h, obj_w, n_slices, positions, dz, pixel_size, wavelength,
+                 tilt_y=0.0, tilt_x=0.0, budget_bytes: int = 0, device=None):
+        torch = _torch()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.n, self.obj_h, self.obj_w, self.n_slices = int(n), int(obj_h), int(obj_w), int(n_slices)
+        self.pb, self._keep = make_problem(n, obj_h, obj_w, n_slices, positions, dz, pixel_size, wavelength,
+                                           tilt_y, tilt_x)
+        self.n_pos = self.pb.n_pos
+        ws = workspace_size(self.pb, budget_bytes)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        handle = C.c_void_p()
+        _check(lib().ms_plan_create(C.byref(self.pb), self.workspace.data_ptr(), ws, C.byref(handle)),
+               "ms_plan_create")
+        self._h = handle
+        self.batch = lib().ms_plan_batch(handle)
+        self.shift_classes = lib().ms_plan_shift_classes(handle)
+
+    @classmethod
+    def from_geometry(cls, geo, positions=None, budget_bytes=0, device=None):
+        pos = geo.positions() if positions is None else positions
+        return cls(geo.n, geo.obj_h, geo.obj_w, geo.n_slices, pos, geo.gaps(), geo.pixel_size, geo.wavelength,
+                   budget_bytes=budget_bytes, device=device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ms_plan_destroy(h)
+            self._h = None
+
+    # -- helpers -------------------------------------------------------------
+    def _stream(self):
+        return _torch().cuda.current_stream(self.device).cuda_stream
+
+    def _expect(self, t, shape: Sequence[int], dtype, name: str):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} is on {t.device}, the plan on {self.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def _probe(self, t, name="probe"):
+        self._expect(t, (self.n, self.n), _torch().complex64, name)
+
+    def _slices(self, t, name="slices"):
+        self._expect(t, (self.n_slices, self.obj_h, self.obj_w), _torch().complex64, name)
+
+    def _patterns(self, t, name="measured"):
+        self._expect(t, (self.n_pos, self.n, self.n), _torch().float32, name)
+
+    # -- kernel timing ---------------------------------------------------------
+    def profile_begin(self, max_launches: int):
+        _check(lib().ms_profile_begin(self._h, int(max_launches)), "ms_profile_begin")
+
+    def profile_end(self):
+        """Returns (summed fused-kernel milliseconds, launches timed)."""
+        ms, n = C.c_double(0.0), C.c_int64(0)
+        _check(lib().ms_profile_end(self._h, C.byref(ms), C.byref(n)), "ms_profile_end")
+        return ms.value, n.value
+
+    # -- entry points --------------------------------------------------------
+    def make_probe(self, alpha: float, defocus: float):
+        torch = _torch()
+        out = torch.empty((self.n, self.n), dtype=torch.complex64, device=self.device)
+        _check(lib().ms_make_probe(self._h, self._stream(), float(alpha), float(defocus), _ptr(out)),
+               "ms_make_probe")
+        return out
+
+    def forward(self, probe, slices, exit_waves: bool = False, out=None):
+        torch = _torch()
+        self._probe(probe)
+        self._slices(slices)
+        inten = out if out is not None else torch.empty((self.n_pos, self.n, self.n), dtype=torch.float32,
+                                                        device=self.device)
+        self._patterns(inten, "intensity_out")
+        ew = torch.empty((self.n_pos, self.n, self.n), dtype=torch.complex64, device=self.device) if exit_waves \
+            else None
+        _check(lib().ms_forward(self._h, self._stream(), _ptr(probe), _ptr(slices), _ptr(inten), _ptr(ew)),
+               "ms_forward")
+        return (inten, ew) if exit_waves else inten
+
+    def adjoint(self, probe, slices, measured, want_probe: bool = True, grad_slices=None, grad_probe=None,
+                loss=None):
+        """Returns (loss (1,) float64, dL/dconj(slices), dL/dconj(probe) or None)."""
+        torch = _torch()
+        self._probe(probe)
+        self._slices(slices)
+        self._patterns(measured)
+        gs = grad_slices if grad_slices is not None else torch.empty_like(slices)
+        self._slices(gs, "grad_slices")
+        gp = None
+        if want_probe:
+            gp = grad_probe if grad_probe is not None else torch.empty_like(probe)
+            self._probe(gp, "grad_probe")
+        lo = loss if loss is not None else torch.empty(1, dtype=torch.float64, device=self.device)
+        _check(lib().ms_adjoint(self._h, self._stream(), _ptr(probe), _ptr(slices), _ptr(measured), _ptr(gs),
+                                _ptr(gp), _ptr(lo)), "ms_adjoint")
+        return lo, gs, gp
+
+    def layer_step(self, layer: int, k_steps: int, probe, slices, measured, loss=None, mu=None):
+        """In place on slices[layer]; loss / mu: optional float64 device scalars (views)."""
+        self._probe(probe)
+        self._slices(slices)
+        self._patterns(measured)
+        _check(lib().ms_layer_step(self._h, self._stream(), int(layer), int(k_steps), _ptr(probe), _ptr(slices),
+                                   _ptr(measured), _ptr(loss), _ptr(mu)), "ms_layer_step")
+
+    def probe_step(self, k_steps: int, probe, slices, measured, subset=None, loss=None, mu=None):
+        """In place on probe; subset: host sequence of position indices or None for all."""
+        self._probe(probe)
+        self._slices(slices)
+        self._patterns(measured)
+        sub = None
+        n_sub = 0
+        if subset is not None:
+            sub = np.ascontiguousarray(np.asarray(subset, dtype=np.int64).reshape(-1))
+            n_sub = sub.size
+        _check(lib().ms_probe_step(self._h, self._stream(), int(k_steps), _ptr(probe), _ptr(slices), _ptr(measured),
+                                   None if sub is None else sub.ctypes.data, n_sub, _ptr(loss), _ptr(mu)),
+               "ms_probe_step")

@@ -1,0 +1,520 @@
+// Device kernels of libimsp.  One workgroup owns one scan position: its N x N
+// wave lives in registers (16 complex values per lane) for the whole multislice
+// chain, LDS only carries line exchanges and transposes.  The Fresnel
+// propagator of eq. (fresnel_element) factorises as h(q_y, q_x) = h_y(q_y) h_x(q_x),
+// so V_z = (F_x^{-1} h_x F_x)(F_y^{-1} h_y F_y): one axis at a time, and the two
+// factors commute, which lets consecutive slices alternate the axis order and
+// pay a single transpose per propagation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_lines.hpp"
+
+namespace imsp {
+
+enum Mode : int {
+    kForward = 0,   // intensities (and exit waves)
+    kAdjoint = 1,   // loss, gradient patches of every slice and of the probe
+    kLayer = 2,     // loss, gradient patch of one slice and its overlap patch
+    kProbe = 3      // loss and probe gradient patch
+};
+
+struct FusedParams {
+    const float2 *class_probe;   // [C][N][N] shifted probes
+    const float2 *slices;        // [M][H][W]
+    const int4 *pos_info;        // [S] (patch origin y in [0,H), x in [0,W), shift class, 0)
+    const int *pos_list;         // [count] global position index of each workgroup
+    const float2 *tw;            // [N] W_N^t
+    const float2 *hy, *hx;       // [M-1][N] propagator factors divided by N, FFT order
+    const float *measured;       // [S][N][N]
+    float *intensity;            // [S][N][N]
+    float2 *exit_waves;          // [S][N][N] or null
+    float2 *waves;               // [count][M][N][N] incident waves, then gradient patches
+    float2 *probe_patch;         // [count][N][N] or null
+    float *overlap_patch;        // [count][N][N]
+    double *loss_pos;            // [count]
+    int H, W, M, layer;
+};
+
+// Incident-wave load/store in natural [y][x] order from either layout.
+template <int N, bool ROW>
+__device__ __forceinline__ void load_window(float2 (&v)[16], const float2 *src, int line, int j)
+{
+    using Wn = Win<N>;
+    line = opaque(line);
+    j = opaque(j);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        int a = Wn::nat(j, k);
+        v[k] = ROW ? src[line * N + a] : src[a * N + line];
+    }
+}
+
+template <int N, bool ROW>
+__device__ __forceinline__ void store_window(const float2 (&v)[16], float2 *dst, int line, int j)
+{
+    using Wn = Win<N>;
+    line = opaque(line);
+    j = opaque(j);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        int a = Wn::nat(j, k);
+        if (ROW) dst[line * N + a] = v[k];
+        else dst[a * N + line] = v[k];
+    }
+}
+
+// v *= T (or conj(T)): the object patch t[(oy + y) mod H][(ox + x) mod W] (Sec. 1.3, 2.1).
+template <int N, bool ROW, bool CONJ>
+__device__ __forceinline__ void apply_patch(float2 (&v)[16], const float2 *slice, int H, int W, int oy,
+                                            int ox, int line, int j)
+{
+    using Wn = Win<N>;
+    line = opaque(line);
+    j = opaque(j);
+    if (ROW) {
+        int yy = oy + line;
+        if (yy >= H) yy -= H;
+        const float2 *row = slice + (size_t)yy * W;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            int xx = ox + Wn::nat(j, k);
+            if (xx >= W) xx -= W;
+            float2 t = row[xx];
+            v[k] = CONJ ? cconjmul(t, v[k]) : cmul(v[k], t);
+        }
+    } else {
+        int xx = ox + line;
+        if (xx >= W) xx -= W;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            int yy = oy + Wn::nat(j, k);
+            if (yy >= H) yy -= H;
+            float2 t = slice[(size_t)yy * W + xx];
+            v[k] = CONJ ? cconjmul(t, v[k]) : cmul(v[k], t);
+        }
+    }
+}
+
+// One Fresnel propagation V_z (or its adjoint G^H when CONJ), starting in layout ROW
+// and ending in the other layout.  hy/hx carry the 1/N factors of both inverse DFTs.
+template <int N, bool ROW, bool CONJ>
+__device__ __forceinline__ void propagate(float2 (&v)[16], const float2 *tw, float2 *lds, const float2 *hy,
+                                          const float2 *hx, int line, int j)
+{
+    using Wn = Win<N>;
+    line = opaque(line);
+    j = opaque(j);
+    float2 *xb = lds + line * Wn::LD;
+    const float2 *h1 = ROW ? hx : hy;
+    const float2 *h2 = ROW ? hy : hx;
+    line_fft_fwd<N>(v, tw, xb, j);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        float2 h = h1[Wn::spec(j, i)];
+        v[i] = CONJ ? cmulc(v[i], h) : cmul(v[i], h);
+    }
+    line_fft_inv<N>(v, tw, xb, j);
+    transpose<N, ROW, false, false>(v, lds, line, j);
+    line_fft_fwd<N>(v, tw, xb, j);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        float2 h = h2[Wn::spec(j, i)];
+        v[i] = CONJ ? cmulc(v[i], h) : cmul(v[i], h);
+    }
+    line_fft_inv<N>(v, tw, xb, j);
+}
+
+template <int N>
+__device__ __forceinline__ double block_sum(double x, double *red)
+{
+    // fixed-order tree: lanes of a wave by xor-shuffle, then waves in index order
+    constexpr int NT = Win<N>::NT;
+    constexpr int NW = (NT + 63) / 64;
+    for (int off = (NT < 64 ? NT / 2 : 32); off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    const int w = threadIdx.x / 64;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = x;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NW; ++i) t += red[i];
+    return t;
+}
+
+// Far field (Sec. 2.1) and amplitude residual (Sec. 3.2) on the 2D spectrum held in
+// layout ROW2 (after the forward 2D FFT): r = Psi - sqrt(I) Psi / |Psi|, 0 where Psi = 0.
+// Returns this lane's FP64 share of sum (sqrt(I) - |Psi|)^2.
+template <int N, bool ROW2>
+__device__ __forceinline__ double residual(float2 (&v)[16], const float *meas, int line, int j)
+{
+    using Wn = Win<N>;
+    line = opaque(line);
+    j = opaque(j);
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        int f = Wn::spec(j, i);
+        int fy = ROW2 ? line : f, fx = ROW2 ? f : line;
+        float m = meas[fy * N + fx];
+        float2 z = v[i];
+        float a2 = cabs2(z);
+        float a = sqrtf(a2);
+        float sq = sqrtf(m);
+        double d = sqrt((double)m) - sqrt((double)z.x * (double)z.x + (double)z.y * (double)z.y);
+        acc += d * d;
+        if (a2 == 0.0f) {
+            v[i] = z;   // zero: the phase is taken as 0, so the residual is Psi itself
+        } else {
+            float k = sq / a;
+            v[i] = make_float2(z.x - k * z.x, z.y - k * z.y);
+        }
+    }
+    return acc;
+}
+
+template <int N, int MODE>
+__global__ __launch_bounds__(Win<N>::NT) void fused_kernel(FusedParams p)
+{
+    using Wn = Win<N>;
+    constexpr int R = Wn::R;
+    constexpr size_t NN = (size_t)N * N;
+    __shared__ float2 lds[N * Wn::LD];
+    __shared__ double red[(Wn::NT + 63) / 64];
+
+    const int tid = threadIdx.x;
+    const int line = tid / R, j = tid % R;
+    const int b = blockIdx.x;
+    const int s = p.pos_list[b];
+    const int4 info = p.pos_info[s];
+    const int oy = info.x, ox = info.y, cls = info.z;
+    const int H = p.H, W = p.W, M = p.M;
+
+    const float2 *tw = p.tw;
+
+    float2 *wave = p.waves ? p.waves + (size_t)b * M * NN : nullptr;
+    const float2 *probe = p.class_probe + (size_t)cls * NN;
+    float2 v[16];
+    load_window<N, true>(v, probe, line, j);
+
+    // ---- forward multislice: E_1 = P^s o X_1, E_m = V(E_{m-1}) o X_m (Sec. 2.1) ----
+    for (int m = 0; m < M; ++m) {
+        const bool row = !(m & 1);
+        const float2 *slice = p.slices + (size_t)m * H * W;
+        const bool store = (MODE == kAdjoint && m > 0) || (MODE == kLayer && m == p.layer && m > 0);
+        if (row) {
+            if (store) store_window<N, true>(v, wave + m * NN, line, j);
+            if (MODE == kLayer && m == p.layer) {
+                float *op = p.overlap_patch + (size_t)b * NN;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) op[line * N + Wn::nat(j, k)] = cabs2(v[k]);
+            }
+            apply_patch<N, true, false>(v, slice, H, W, oy, ox, line, j);
+            if (m + 1 < M) propagate<N, true, false>(v, tw, lds, p.hy + m * N, p.hx + m * N, line, j);
+        } else {
+            if (store) store_window<N, false>(v, wave + m * NN, line, j);
+            if (MODE == kLayer && m == p.layer) {
+                float *op = p.overlap_patch + (size_t)b * NN;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) op[Wn::nat(j, k) * N + line] = cabs2(v[k]);
+            }
+            apply_patch<N, false, false>(v, slice, H, W, oy, ox, line, j);
+            if (m + 1 < M) propagate<N, false, false>(v, tw, lds, p.hy + m * N, p.hx + m * N, line, j);
+        }
+    }
+
+    // ---- far field Psi = F E_M ----
+    const bool rowM = !((M - 1) & 1);
+    float2 *xb = lds + line * Wn::LD;
+    if constexpr (MODE == kForward) {
+        if (p.exit_waves) {
+            float2 *ew = p.exit_waves + (size_t)s * NN;
+            if (rowM) store_window<N, true>(v, ew, line, j);
+            else store_window<N, false>(v, ew, line, j);
+        }
+    }
+    line_fft_fwd<N>(v, tw, xb, j);
+    if (rowM) transpose<N, true, true, false>(v, lds, line, j);
+    else transpose<N, false, true, false>(v, lds, line, j);
+    line_fft_fwd<N>(v, tw, xb, j);
+    // now layout !rowM; line = frequency along the first axis, registers spectral along the second
+
+    if constexpr (MODE == kForward) {
+        float *out = p.intensity + (size_t)s * NN;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            int f = Wn::spec(j, i);
+            int fy = rowM ? f : line, fx = rowM ? line : f;
+            out[fy * N + fx] = cabs2(v[i]);
+        }
+        return;
+    } else {
+        const float *meas = p.measured + (size_t)s * NN;
+        double part = rowM ? residual<N, false>(v, meas, line, j) : residual<N, true>(v, meas, line, j);
+        double tot = block_sum<N>(part, red);
+        if (tid == 0) p.loss_pos[b] = tot;
+
+        // ---- adjoint: g = F^H r, then down the chain (Sec. 3.2 pulled back through eq. exit_wave_mslices) ----
+        line_fft_inv<N>(v, tw, xb, j);
+        if (rowM) transpose<N, false, false, true>(v, lds, line, j);
+        else transpose<N, true, false, true>(v, lds, line, j);
+        line_fft_inv<N>(v, tw, xb, j);
+
+        const int m_stop = (MODE == kLayer) ? p.layer : 0;
+        for (int m = M - 1; m >= m_stop; --m) {
+            const bool row = !(m & 1);
+            const float2 *slice = p.slices + (size_t)m * H * W;
+            const bool patch = (MODE == kAdjoint) || (MODE == kLayer && m == p.layer);
+            if (patch) {
+                const float2 *psi = (m == 0) ? probe : wave + m * NN;
+                float2 *dst = wave + m * NN;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    int a = Wn::nat(j, k);
+                    int idx = row ? line * N + a : a * N + line;
+                    float2 ps = psi[idx];
+                    dst[idx] = cconjmul(ps, v[k]);   // dL/d conj(t_m) on the window: conj(psi_m) o g
+                }
+            }
+            const bool go_on = (m > m_stop) || (MODE != kLayer && m == 0);
+            if (!go_on) break;
+            if (row) apply_patch<N, true, true>(v, slice, H, W, oy, ox, line, j);
+            else apply_patch<N, false, true>(v, slice, H, W, oy, ox, line, j);
+            if (m > 0) {
+                // G_{m-1}^H: start on the axis this layout owns (the last one of the forward step)
+                if (row) propagate<N, true, true>(v, tw, lds, p.hy + (m - 1) * N, p.hx + (m - 1) * N, line, j);
+                else propagate<N, false, true>(v, tw, lds, p.hy + (m - 1) * N, p.hx + (m - 1) * N, line, j);
+            }
+        }
+        if constexpr (MODE == kAdjoint || MODE == kProbe) {
+            if (p.probe_patch) store_window<N, true>(v, p.probe_patch + (size_t)b * NN, line, j);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic segmented scatter-add: every object pixel sums the patches of the
+// positions whose window covers it, in ascending position order (sum over s in
+// eq. Opt_Prob_Layerwise).  Block = one 16 x 16 tile; the host lists, per tile,
+// the batch positions whose window intersects it.
+struct ScatterParams {
+    const float2 *patches;      // patch of position b, slice m: patches + b * pos_stride + m * N * N
+    const float *wpatch;        // [count][N][N] or null
+    long long pos_stride;
+    const int *tile_off;        // [n_tiles + 1]
+    const int *tile_list;       // batch-local position indices
+    const int4 *pos_info;
+    const int *pos_list;
+    float2 *out;                // slice m at out + (m - m0) * H * W
+    float *wout;                // [H][W] or null
+    int H, W, N, tiles_x, m0, accumulate;
+};
+
+__global__ __launch_bounds__(256) void scatter_kernel(ScatterParams p)
+{
+    const int t = blockIdx.x;
+    const int m = p.m0 + blockIdx.y;
+    const int ty = t / p.tiles_x, tx = t % p.tiles_x;
+    const int y = ty * 16 + (threadIdx.x >> 4), x = tx * 16 + (threadIdx.x & 15);
+    if (y >= p.H || x >= p.W) return;
+    const size_t o = (size_t)blockIdx.y * p.H * p.W + (size_t)y * p.W + x;   // output slice m - m0
+    const size_t NN = (size_t)p.N * p.N;
+    float2 acc = p.accumulate ? p.out[o] : make_float2(0.f, 0.f);
+    float wacc = 0.f;
+    if (p.wout) wacc = p.accumulate ? p.wout[(size_t)y * p.W + x] : 0.f;
+    const float2 *base = p.patches + (size_t)m * NN;
+    const int e1 = p.tile_off[t + 1];
+    for (int e = p.tile_off[t]; e < e1; ++e) {
+        const int sb = p.tile_list[e];
+        const int4 info = p.pos_info[p.pos_list[sb]];
+        int ly = y - info.x;
+        if (ly < 0) ly += p.H;
+        int lx = x - info.y;
+        if (lx < 0) lx += p.W;
+        if (ly < p.N && lx < p.N) {
+            const size_t q = (size_t)sb * p.pos_stride + (size_t)ly * p.N + lx;
+            acc = cadd(acc, base[q]);
+            if (p.wout) wacc += p.wpatch[(size_t)sb * NN + (size_t)ly * p.N + lx];
+        }
+    }
+    p.out[o] = acc;
+    if (p.wout) p.wout[(size_t)y * p.W + x] = wacc;
+}
+
+// Per shift class: sum of the probe patches of its positions, ascending order.
+__global__ __launch_bounds__(256) void class_sum_kernel(const float2 *probe_patch, const int *class_off,
+                                                        const int *class_list, float2 *acc, int nn, int accumulate)
+{
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (pix >= nn) return;
+    float2 a = accumulate ? acc[(size_t)c * nn + pix] : make_float2(0.f, 0.f);
+    for (int e = class_off[c]; e < class_off[c + 1]; ++e) a = cadd(a, probe_patch[(size_t)class_list[e] * nn + pix]);
+    acc[(size_t)c * nn + pix] = a;
+}
+
+// out[c] = F^{-1}(F in[c] o (my[c] (x) mx[c])) with multipliers already divided by N:
+// the sub-pixel probe shift of class c (CONJ = false) or its adjoint (CONJ = true).
+// identity[c] != 0 copies instead (integer positions).
+template <int N, bool CONJ>
+__global__ __launch_bounds__(Win<N>::NT) void window_filter_kernel(const float2 *in, long long in_stride, float2 *out,
+                                                                   const float2 *my, const float2 *mx,
+                                                                   const int *identity, const float2 *twg)
+{
+    using Wn = Win<N>;
+    constexpr int R = Wn::R;
+    constexpr size_t NN = (size_t)N * N;
+    __shared__ float2 lds[N * Wn::LD];
+    const int c = blockIdx.x;
+    const int line = threadIdx.x / R, j = threadIdx.x % R;
+    const float2 *src = in + (size_t)c * in_stride;
+    float2 *dst = out + (size_t)c * NN;
+    float2 v[16];
+    load_window<N, true>(v, src, line, j);
+    if (identity[c]) {
+        store_window<N, true>(v, dst, line, j);
+        return;
+    }
+    const float2 *tw = twg;
+    propagate<N, true, CONJ>(v, tw, lds, my + (size_t)c * N, mx + (size_t)c * N, line, j);
+    store_window<N, false>(v, dst, line, j);
+}
+
+// Probe of Sec. 2.1 / Fig. 3: aperture lambda |q| <= alpha times the defocus propagator
+// times (-1)^(ky+kx) (centre at N/2), inverse 2D DFT, unit energy.  One workgroup.
+template <int N>
+__global__ __launch_bounds__(Win<N>::NT) void make_probe_kernel(float2 *out, const float2 *twg, double dx,
+                                                                double lambda, double alpha, double defocus)
+{
+#pragma clang fp contract(off)
+    using Wn = Win<N>;
+    constexpr int R = Wn::R;
+    __shared__ float2 lds[N * Wn::LD];
+    __shared__ double red[(Wn::NT + 63) / 64];
+    __shared__ double total;
+    const int line = threadIdx.x / R, j = threadIdx.x % R;
+    const double PI = 3.14159265358979323846264338327950288;
+    const float2 *tw = twg;
+    const double nd = (double)N * dx;
+    float2 v[16];
+    // ROW layout, spectral along x: register i holds frequency (ky = line, kx = spec(j, i))
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        int iy = line, ix = Wn::spec(j, i);
+        int ky = iy < N / 2 ? iy : iy - N;
+        int kx = ix < N / 2 ? ix : ix - N;
+        double qy = (double)ky / nd, qx = (double)kx / nd;
+        double q2 = qy * qy + qx * qx;
+        float2 a = make_float2(0.f, 0.f);
+        if (lambda * sqrt(q2) <= alpha) {
+            double ph = -PI * defocus * lambda * q2;
+            double sgn = ((iy + ix) & 1) ? -1.0 : 1.0;
+            a = make_float2((float)(sgn * cos(ph)), (float)(sgn * sin(ph)));
+        }
+        v[i] = a;
+    }
+    float2 *xb = lds + line * Wn::LD;
+    line_fft_inv<N>(v, tw, xb, j);
+    transpose<N, true, false, true>(v, lds, line, j);
+    line_fft_inv<N>(v, tw, xb, j);
+    double e = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) e += (double)v[i].x * v[i].x + (double)v[i].y * v[i].y;
+    double t = block_sum<N>(e, red);
+    if (threadIdx.x == 0) total = t;
+    __syncthreads();
+    const float sc = (float)(1.0 / sqrt(total));
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = make_float2(v[i].x * sc, v[i].y * sc);
+    store_window<N, false>(v, out, line, j);
+}
+
+// ---------------------------------------------------------------------------
+// Small reductions and updates (FP64 where the step size is concerned).
+
+// Per-block maximum of |x|^2 (complex) or x (real) over segment blockIdx.y.
+__global__ __launch_bounds__(256) void max_partial_kernel(const float2 *cx, const float *rx, long long seg_len,
+                                                          float *partial)
+{
+    __shared__ float sm[256];
+    const long long base = (long long)blockIdx.y * seg_len;
+    float mx = 0.f;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < seg_len; i += (long long)gridDim.x * 256) {
+        float v = cx ? cabs2(cx[base + i]) : rx[base + i];
+        mx = fmaxf(mx, v);
+    }
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(256) void max_final_kernel(const float *partial, int per_seg, float *out)
+{
+    __shared__ float sm[256];
+    float mx = 0.f;
+    for (int i = threadIdx.x; i < per_seg; i += 256) mx = fmaxf(mx, partial[blockIdx.x * per_seg + i]);
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
+
+// Fixed-order FP64 sum of the per-position losses of one batch, added to *total.
+__global__ __launch_bounds__(256) void loss_sum_kernel(const double *loss_pos, int count, double *total, int accumulate)
+{
+    __shared__ double sm[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < count; i += 256) a += loss_pos[i];
+    sm[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sm[threadIdx.x] += sm[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = (accumulate ? *total : 0.0) + sm[0];
+}
+
+// mu = 1 / (nn * count * prod_{m in [m0, M)} maxt2[m] * wmax); wmax null means 1.
+__global__ void step_size_kernel(const float *maxt2, int m0, int M, const float *wmax, double nn, double count,
+                                 double *mu, double *mu_user, const double *loss, double *loss_user)
+{
+    double den = nn * count;
+    for (int m = m0; m < M; ++m) den *= (double)maxt2[m];
+    if (wmax) den *= (double)*wmax;
+    double r = den > 0.0 ? 1.0 / den : 0.0;
+    *mu = r;
+    if (mu_user) *mu_user = r;
+    if (loss_user) *loss_user = *loss;
+}
+
+// x <- x - mu * g, evaluated in FP64 and rounded once.
+__global__ __launch_bounds__(256) void update_kernel(float2 *x, const float2 *g, long long count, const double *mu)
+{
+    const double m = *mu;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long long)gridDim.x * 256) {
+        float2 a = x[i], d = g[i];
+        x[i] = make_float2((float)((double)a.x - m * (double)d.x), (float)((double)a.y - m * (double)d.y));
+    }
+}
+
+// out = sum_c in[c] (fixed order).
+__global__ __launch_bounds__(256) void sum_classes_kernel(const float2 *in, int n_classes, int nn, float2 *out)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nn) return;
+    float2 a = make_float2(0.f, 0.f);
+    for (int c = 0; c < n_classes; ++c) a = cadd(a, in[(size_t)c * nn + i]);
+    out[i] = a;
+}
+
+__global__ void copy_scalar_kernel(const double *src, double *dst) { *dst = *src; }
+
+}  // namespace imsp

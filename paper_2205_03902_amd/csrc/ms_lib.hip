@@ -1,0 +1,762 @@
+// libimsp host side: validation, plans, workspace layout and kernel launches
+// behind the C ABI declared in include/ms.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "ms.h"
+#include "ms_kernels.hpp"
+
+using namespace imsp;
+
+namespace {
+
+thread_local std::string g_err;
+
+ms_status fail(ms_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+constexpr int kTile = 16;          // scatter tile side
+constexpr int kMaxBlocks = 256;    // partial-maximum blocks per segment
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool supported_n(int n) { return n == 16 || n == 32 || n == 64 || n == 128; }
+
+ms_status validate(const ms_problem *pb)
+{
+    if (!pb) return fail(MS_ERR_INVALID_ARG, "problem is NULL");
+    const int n = pb->n;
+    if (n < 16 || n > 256 || (n & (n - 1)))
+        return fail(MS_ERR_INVALID_ARG, "n must be a power of two in [16, 256]");
+    if (!supported_n(n)) return fail(MS_ERR_UNSUPPORTED, "n = " + std::to_string(n) + " is not implemented");
+    if (pb->obj_h < n || pb->obj_w < n) return fail(MS_ERR_INVALID_ARG, "object must be at least N x N");
+    if (pb->obj_h > (1 << 20) || pb->obj_w > (1 << 20) || (int64_t)pb->obj_h * pb->obj_w > (int64_t)1 << 30)
+        return fail(MS_ERR_INVALID_ARG, "object too large");
+    if (pb->n_slices < 1 || pb->n_slices > 4096) return fail(MS_ERR_INVALID_ARG, "n_slices must be in [1, 4096]");
+    if (pb->n_pos < 1 || pb->n_pos > ((int64_t)1 << 30)) return fail(MS_ERR_INVALID_ARG, "n_pos must be in [1, 2^30]");
+    if (!pb->positions) return fail(MS_ERR_INVALID_ARG, "positions is NULL");
+    if (pb->n_slices > 1 && !pb->dz) return fail(MS_ERR_INVALID_ARG, "dz is NULL");
+    if (!(pb->pixel_size > 0.0) || !std::isfinite(pb->pixel_size))
+        return fail(MS_ERR_INVALID_ARG, "pixel_size must be positive and finite");
+    if (!(pb->wavelength > 0.0) || !std::isfinite(pb->wavelength))
+        return fail(MS_ERR_INVALID_ARG, "wavelength must be positive and finite");
+    if (!std::isfinite(pb->tilt_y) || !std::isfinite(pb->tilt_x)) return fail(MS_ERR_INVALID_ARG, "tilts must be finite");
+    for (int64_t i = 0; i < 2 * pb->n_pos; ++i)
+        if (!std::isfinite(pb->positions[i]) || std::fabs(pb->positions[i]) > 1e9)
+            return fail(MS_ERR_INVALID_ARG, "position " + std::to_string(i / 2) + " is not finite or too large");
+    for (int m = 0; m + 1 < pb->n_slices; ++m)
+        if (!std::isfinite(pb->dz[m])) return fail(MS_ERR_INVALID_ARG, "dz is not finite");
+    return MS_OK;
+}
+
+// Host-side description derived from the problem: patch origins, shift classes,
+// batches and scatter lists.
+struct HostPlan {
+    int n = 0, H = 0, W = 0, M = 0, C = 0;
+    int64_t S = 0, B = 0;
+    int nb = 0, tiles_x = 0, tiles_y = 0, n_tiles = 0;
+    std::vector<int4> pos_info;
+    std::vector<double> cls_fy, cls_fx;
+    std::vector<int> tile_off, tile_list;     // nb x (n_tiles + 1) absolute offsets, batch-local entries
+    std::vector<int> class_off, class_list;   // nb x (C + 1) absolute offsets, batch-local entries
+};
+
+void derive_positions(const ms_problem *pb, HostPlan &hp)
+{
+    hp.n = pb->n; hp.H = pb->obj_h; hp.W = pb->obj_w; hp.M = pb->n_slices; hp.S = pb->n_pos;
+    hp.tiles_y = (hp.H + kTile - 1) / kTile;
+    hp.tiles_x = (hp.W + kTile - 1) / kTile;
+    hp.n_tiles = hp.tiles_y * hp.tiles_x;
+    hp.pos_info.resize(hp.S);
+    std::map<std::pair<double, double>, int> classes;
+    for (int64_t s = 0; s < hp.S; ++s) {
+        double py = pb->positions[2 * s], px = pb->positions[2 * s + 1];
+        double fly = std::floor(py), flx = std::floor(px);
+        int64_t iy = (int64_t)fly % hp.H, ix = (int64_t)flx % hp.W;
+        if (iy < 0) iy += hp.H;
+        if (ix < 0) ix += hp.W;
+        std::pair<double, double> key(py - fly, px - flx);
+        auto it = classes.find(key);
+        int c;
+        if (it == classes.end()) {
+            c = (int)hp.cls_fy.size();
+            classes.emplace(key, c);
+            hp.cls_fy.push_back(key.first);
+            hp.cls_fx.push_back(key.second);
+        } else {
+            c = it->second;
+        }
+        hp.pos_info[s] = make_int4((int)iy, (int)ix, c, 0);
+    }
+    hp.C = (int)hp.cls_fy.size();
+}
+
+// Tiles (row-major) covered by the window of one position.
+void window_tiles(const HostPlan &hp, const int4 &info, std::vector<int> &rows, std::vector<int> &cols,
+                  std::vector<char> &mark_y, std::vector<char> &mark_x)
+{
+    rows.clear(); cols.clear();
+    std::fill(mark_y.begin(), mark_y.end(), 0);
+    std::fill(mark_x.begin(), mark_x.end(), 0);
+    for (int i = 0; i < hp.n; ++i) {
+        int ty = ((info.x + i) % hp.H) / kTile;
+        if (!mark_y[ty]) { mark_y[ty] = 1; rows.push_back(ty); }
+        int tx = ((info.y + i) % hp.W) / kTile;
+        if (!mark_x[tx]) { mark_x[tx] = 1; cols.push_back(tx); }
+    }
+}
+
+void build_lists(HostPlan &hp, int64_t B)
+{
+    hp.B = B;
+    hp.nb = (int)((hp.S + B - 1) / B);
+    std::vector<int> rows, cols;
+    std::vector<char> my(hp.tiles_y), mx(hp.tiles_x);
+    // tile lists: count, prefix sums, fill in ascending batch-local order
+    std::vector<std::vector<int>> per_pos(hp.S);
+    for (int64_t s = 0; s < hp.S; ++s) {
+        window_tiles(hp, hp.pos_info[s], rows, cols, my, mx);
+        per_pos[s].reserve(rows.size() * cols.size());
+        for (int ty : rows)
+            for (int tx : cols) per_pos[s].push_back(ty * hp.tiles_x + tx);
+    }
+    hp.tile_off.assign((size_t)hp.nb * (hp.n_tiles + 1), 0);
+    hp.class_off.assign((size_t)hp.nb * (hp.C + 1), 0);
+    size_t total = 0;
+    for (int64_t s = 0; s < hp.S; ++s) total += per_pos[s].size();
+    hp.tile_list.assign(total, 0);
+    hp.class_list.assign(hp.S, 0);
+    size_t base = 0, cbase = 0;
+    std::vector<int> cnt(hp.n_tiles), ccnt(hp.C);
+    for (int b = 0; b < hp.nb; ++b) {
+        int64_t s0 = (int64_t)b * B, s1 = std::min(hp.S, s0 + B);
+        std::fill(cnt.begin(), cnt.end(), 0);
+        std::fill(ccnt.begin(), ccnt.end(), 0);
+        for (int64_t s = s0; s < s1; ++s) {
+            for (int t : per_pos[s]) cnt[t]++;
+            ccnt[hp.pos_info[s].z]++;
+        }
+        int *off = &hp.tile_off[(size_t)b * (hp.n_tiles + 1)];
+        off[0] = (int)base;
+        for (int t = 0; t < hp.n_tiles; ++t) off[t + 1] = off[t] + cnt[t];
+        int *coff = &hp.class_off[(size_t)b * (hp.C + 1)];
+        coff[0] = (int)cbase;
+        for (int c = 0; c < hp.C; ++c) coff[c + 1] = coff[c] + ccnt[c];
+        std::vector<int> cur(off, off + hp.n_tiles), ccur(coff, coff + hp.C);
+        for (int64_t s = s0; s < s1; ++s) {
+            for (int t : per_pos[s]) hp.tile_list[cur[t]++] = (int)(s - s0);
+            hp.class_list[ccur[hp.pos_info[s].z]++] = (int)(s - s0);
+        }
+        base = off[hp.n_tiles];
+        cbase = coff[hp.C];
+    }
+}
+
+size_t tile_entries(const HostPlan &hp)
+{
+    std::vector<int> rows, cols;
+    std::vector<char> my(hp.tiles_y), mx(hp.tiles_x);
+    size_t total = 0;
+    for (int64_t s = 0; s < hp.S; ++s) {
+        window_tiles(hp, hp.pos_info[s], rows, cols, my, mx);
+        total += rows.size() * cols.size();
+    }
+    return total;
+}
+
+// Workspace layout.  Every region is 256-byte aligned.
+struct Layout {
+    size_t tw, hy, hx, ry, rx, ident, pos_info, pos_list, sub_list;
+    size_t class_probe, class_acc, class_tmp, gp, layer_g, layer_w, maxt2, partial, maxw, scal;
+    size_t tile_off, tile_list, class_off, class_list, sub_class_off, sub_class_list;
+    size_t waves, probe_patch, overlap, loss_pos;
+    size_t total;
+};
+
+Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
+{
+    Layout L{};
+    const size_t n = hp.n, NN = n * n, HW = (size_t)hp.H * hp.W, M = hp.M, C = hp.C, S = hp.S;
+    const size_t gaps = std::max<size_t>(M - 1, 1);
+    const size_t nb = (size_t)((S + B - 1) / B);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += align_up(std::max<size_t>(bytes, 1)); return r; };
+    L.tw = take(n * 8);
+    L.hy = take(gaps * n * 8);
+    L.hx = take(gaps * n * 8);
+    L.ry = take(C * n * 8);
+    L.rx = take(C * n * 8);
+    L.ident = take(C * 4);
+    L.pos_info = take(S * 16);
+    L.pos_list = take(S * 4);
+    L.sub_list = take(S * 4);
+    L.class_probe = take(C * NN * 8);
+    L.class_acc = take(C * NN * 8);
+    L.class_tmp = take(C * NN * 8);
+    L.gp = take(NN * 8);
+    L.layer_g = take(HW * 8);
+    L.layer_w = take(HW * 4);
+    L.maxt2 = take(M * 4);
+    L.partial = take(M * kMaxBlocks * 4 + kMaxBlocks * 4);
+    L.maxw = take(4);
+    L.scal = take(8 * 8);
+    L.tile_off = take(nb * (hp.n_tiles + 1) * 4);
+    L.tile_list = take(n_entries * 4);
+    L.class_off = take(nb * (C + 1) * 4);
+    L.class_list = take(S * 4);
+    L.sub_class_off = take(nb * (C + 1) * 4);
+    L.sub_class_list = take(S * 4);
+    L.waves = take((size_t)B * M * NN * 8);
+    L.probe_patch = take((size_t)B * NN * 8);
+    L.overlap = take((size_t)B * NN * 4);
+    L.loss_pos = take((size_t)B * 8);
+    L.total = o;
+    return L;
+}
+
+int64_t choose_batch(const HostPlan &hp, size_t n_entries, size_t budget)
+{
+    if (budget == 0) return hp.S;
+    if (make_layout(hp, hp.S, n_entries).total <= budget) return hp.S;
+    int64_t lo = 0, hi = hp.S;   // invariant: lo fits (or 0), hi does not
+    while (hi - lo > 1) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (make_layout(hp, mid, n_entries).total <= budget) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace
+
+struct ms_plan {
+    HostPlan hp;
+    Layout L;
+    double dx = 0, lambda = 0, tilt_y = 0, tilt_x = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    // host staging for subset uploads (kept alive until the next call)
+    std::vector<int> sub_list, sub_class_off, sub_class_list;
+    // optional timing of the fused kernel
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    size_t ev_used = 0;
+
+    template <typename T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+namespace {
+
+ms_status check_hip(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return MS_OK;
+}
+
+template <int N>
+void launch_fused_n(int mode, const FusedParams &fp, int count, hipStream_t st)
+{
+    dim3 grid(count), block(Win<N>::NT);
+    switch (mode) {
+        case kForward: fused_kernel<N, kForward><<<grid, block, 0, st>>>(fp); break;
+        case kAdjoint: fused_kernel<N, kAdjoint><<<grid, block, 0, st>>>(fp); break;
+        case kLayer: fused_kernel<N, kLayer><<<grid, block, 0, st>>>(fp); break;
+        default: fused_kernel<N, kProbe><<<grid, block, 0, st>>>(fp); break;
+    }
+}
+
+void launch_fused_raw(int n, int mode, const FusedParams &fp, int count, hipStream_t st)
+{
+    switch (n) {
+        case 16: launch_fused_n<16>(mode, fp, count, st); break;
+        case 32: launch_fused_n<32>(mode, fp, count, st); break;
+        case 64: launch_fused_n<64>(mode, fp, count, st); break;
+        default: launch_fused_n<128>(mode, fp, count, st); break;
+    }
+}
+
+void launch_fused(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream_t st)
+{
+    const bool timed = p->ev_used < p->ev_start.size();
+    if (timed) (void)hipEventRecord(p->ev_start[p->ev_used], st);
+    launch_fused_raw(p->hp.n, mode, fp, count, st);
+    if (timed) (void)hipEventRecord(p->ev_stop[p->ev_used++], st);
+}
+
+template <int N>
+void launch_filter_n(bool conj, const float2 *in, long long in_stride, float2 *out, const float2 *my,
+                     const float2 *mx, const int *ident, const float2 *tw, int count, hipStream_t st)
+{
+    dim3 grid(count), block(Win<N>::NT);
+    if (conj) window_filter_kernel<N, true><<<grid, block, 0, st>>>(in, in_stride, out, my, mx, ident, tw);
+    else window_filter_kernel<N, false><<<grid, block, 0, st>>>(in, in_stride, out, my, mx, ident, tw);
+}
+
+void launch_filter(int n, bool conj, const float2 *in, long long in_stride, float2 *out, const float2 *my,
+                   const float2 *mx, const int *ident, const float2 *tw, int count, hipStream_t st)
+{
+    switch (n) {
+        case 16: launch_filter_n<16>(conj, in, in_stride, out, my, mx, ident, tw, count, st); break;
+        case 32: launch_filter_n<32>(conj, in, in_stride, out, my, mx, ident, tw, count, st); break;
+        case 64: launch_filter_n<64>(conj, in, in_stride, out, my, mx, ident, tw, count, st); break;
+        default: launch_filter_n<128>(conj, in, in_stride, out, my, mx, ident, tw, count, st); break;
+    }
+}
+
+// Shifted probes P_c = F^{-1}(F P o ramp_c) for every shift class.
+void class_probes(ms_plan *p, const ms_c64 *probe, hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
+    launch_filter(hp.n, false, reinterpret_cast<const float2 *>(probe), 0, p->at<float2>(p->L.class_probe),
+                  p->at<float2>(p->L.ry), p->at<float2>(p->L.rx), p->at<int>(p->L.ident), p->at<float2>(p->L.tw),
+                  hp.C, st);
+}
+
+// max |t_m|^2 of every slice into maxt2[M].
+void slice_maxima(ms_plan *p, const ms_c64 *slices, hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
+    const long long hw = (long long)hp.H * hp.W;
+    const int blocks = (int)std::min<long long>(kMaxBlocks, (hw + 255) / 256);
+    max_partial_kernel<<<dim3(blocks, hp.M), 256, 0, st>>>(reinterpret_cast<const float2 *>(slices), nullptr, hw,
+                                                           p->at<float>(p->L.partial));
+    max_final_kernel<<<hp.M, 256, 0, st>>>(p->at<float>(p->L.partial), blocks, p->at<float>(p->L.maxt2));
+}
+
+FusedParams fused_params(ms_plan *p, const ms_c64 *slices, const float *measured)
+{
+    const HostPlan &hp = p->hp;
+    FusedParams fp{};
+    fp.class_probe = p->at<float2>(p->L.class_probe);
+    fp.slices = reinterpret_cast<const float2 *>(slices);
+    fp.pos_info = p->at<int4>(p->L.pos_info);
+    fp.tw = p->at<float2>(p->L.tw);
+    fp.hy = p->at<float2>(p->L.hy);
+    fp.hx = p->at<float2>(p->L.hx);
+    fp.measured = measured;
+    fp.waves = p->at<float2>(p->L.waves);
+    fp.probe_patch = p->at<float2>(p->L.probe_patch);
+    fp.overlap_patch = p->at<float>(p->L.overlap);
+    fp.loss_pos = p->at<double>(p->L.loss_pos);
+    fp.H = hp.H; fp.W = hp.W; fp.M = hp.M; fp.layer = 0;
+    return fp;
+}
+
+void scatter(ms_plan *p, int b, int m0, int n_m, float2 *out, float *wout, int accumulate, hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
+    ScatterParams sp{};
+    sp.patches = p->at<float2>(p->L.waves);
+    sp.wpatch = p->at<float>(p->L.overlap);
+    sp.pos_stride = (long long)hp.M * hp.n * hp.n;
+    sp.tile_off = p->at<int>(p->L.tile_off) + (size_t)b * (hp.n_tiles + 1);
+    sp.tile_list = p->at<int>(p->L.tile_list);
+    sp.pos_info = p->at<int4>(p->L.pos_info);
+    sp.pos_list = p->at<int>(p->L.pos_list) + (size_t)b * hp.B;
+    sp.out = out;
+    sp.wout = wout;
+    sp.H = hp.H; sp.W = hp.W; sp.N = hp.n; sp.tiles_x = hp.tiles_x; sp.m0 = m0; sp.accumulate = accumulate;
+    scatter_kernel<<<dim3(hp.n_tiles, n_m), 256, 0, st>>>(sp);
+}
+
+// Probe gradient from the per-class sums: sum_c S_c^H acc_c.
+void probe_gradient(ms_plan *p, float2 *out, hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
+    const int nn = hp.n * hp.n;
+    launch_filter(hp.n, true, p->at<float2>(p->L.class_acc), nn, p->at<float2>(p->L.class_tmp),
+                  p->at<float2>(p->L.ry), p->at<float2>(p->L.rx), p->at<int>(p->L.ident), p->at<float2>(p->L.tw),
+                  hp.C, st);
+    sum_classes_kernel<<<(nn + 255) / 256, 256, 0, st>>>(p->at<float2>(p->L.class_tmp), hp.C, nn, out);
+}
+
+bool aligned8(const void *ptr) { return ((uintptr_t)ptr & 7) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char *ms_last_error(void) { return g_err.c_str(); }
+
+ms_status ms_workspace_size(const ms_problem *pb, size_t budget_bytes, size_t *ws_bytes)
+{
+    try {
+        g_err.clear();
+        ms_status st = validate(pb);
+        if (st != MS_OK) return st;
+        if (!ws_bytes) return fail(MS_ERR_INVALID_ARG, "ws_bytes is NULL");
+        HostPlan hp;
+        derive_positions(pb, hp);
+        size_t ne = tile_entries(hp);
+        int64_t B = choose_batch(hp, ne, budget_bytes);
+        if (B < 1) return fail(MS_ERR_BUDGET, "budget too small for a single position");
+        *ws_bytes = make_layout(hp, B, ne).total;
+        return MS_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MS_ERR_INVALID_ARG, "host out of memory");
+    } catch (...) {
+        return fail(MS_ERR_INVALID_ARG, "unexpected host error");
+    }
+}
+
+ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes, ms_plan **out)
+{
+    try {
+        g_err.clear();
+        ms_status st = validate(pb);
+        if (st != MS_OK) return st;
+        if (!out) return fail(MS_ERR_INVALID_ARG, "out is NULL");
+        if (!workspace) return fail(MS_ERR_INVALID_ARG, "workspace is NULL");
+        if ((uintptr_t)workspace % kAlign) return fail(MS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+        ms_plan *p = new ms_plan();
+        HostPlan &hp = p->hp;
+        derive_positions(pb, hp);
+        size_t ne = tile_entries(hp);
+        int64_t B = choose_batch(hp, ne, ws_bytes);
+        if (B < 1) { delete p; return fail(MS_ERR_BUDGET, "workspace too small for a single position"); }
+        build_lists(hp, B);
+        p->L = make_layout(hp, B, ne);
+        if (p->L.total > ws_bytes) { delete p; return fail(MS_ERR_BUDGET, "workspace too small"); }
+        p->ws = static_cast<char *>(workspace);
+        p->ws_bytes = ws_bytes;
+        p->dx = pb->pixel_size; p->lambda = pb->wavelength; p->tilt_y = pb->tilt_y; p->tilt_x = pb->tilt_x;
+
+        // Tables, computed in FP64 and rounded once.
+        const int n = hp.n, M = hp.M, C = hp.C;
+        const double PI = 3.14159265358979323846264338327950288;
+        std::vector<float2> tw(n);
+        for (int t = 0; t < n; ++t) {
+            double a = -2.0 * PI * t / n;
+            tw[t] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+        auto freq = [&](int i) { return (double)(i < (n + 1) / 2 ? i : i - n); };
+        const int gaps = std::max(M - 1, 1);
+        std::vector<float2> hy((size_t)gaps * n, make_float2(0.f, 0.f)), hx((size_t)gaps * n, make_float2(0.f, 0.f));
+        for (int g = 0; g + 1 < M; ++g) {
+            double dz = pb->dz[g];
+            for (int i = 0; i < n; ++i) {
+                double q = freq(i) / ((double)n * pb->pixel_size);
+                // eq. (fresnel_element) split per axis: exp(-pi i dz (lambda q^2 + 2 q sin(theta)))
+                double py = -PI * dz * (pb->wavelength * q * q + 2.0 * q * std::sin(pb->tilt_y));
+                double px = -PI * dz * (pb->wavelength * q * q + 2.0 * q * std::sin(pb->tilt_x));
+                hy[(size_t)g * n + i] = make_float2((float)(std::cos(py) / n), (float)(std::sin(py) / n));
+                hx[(size_t)g * n + i] = make_float2((float)(std::cos(px) / n), (float)(std::sin(px) / n));
+            }
+        }
+        std::vector<float2> ry((size_t)C * n), rx((size_t)C * n);
+        std::vector<int> ident(C);
+        for (int c = 0; c < C; ++c) {
+            ident[c] = (hp.cls_fy[c] == 0.0 && hp.cls_fx[c] == 0.0) ? 1 : 0;
+            for (int i = 0; i < n; ++i) {
+                double ay = -2.0 * PI * freq(i) * hp.cls_fy[c] / n;
+                double ax = -2.0 * PI * freq(i) * hp.cls_fx[c] / n;
+                ry[(size_t)c * n + i] = make_float2((float)(std::cos(ay) / n), (float)(std::sin(ay) / n));
+                rx[(size_t)c * n + i] = make_float2((float)(std::cos(ax) / n), (float)(std::sin(ax) / n));
+            }
+        }
+        std::vector<int> pos_list(hp.S);
+        for (int64_t s = 0; s < hp.S; ++s) pos_list[s] = (int)s;
+
+        auto up = [&](size_t off, const void *src, size_t bytes) -> bool {
+            if (bytes == 0) return true;
+            return hipMemcpy(p->ws + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+        };
+        bool ok = up(p->L.tw, tw.data(), tw.size() * 8) && up(p->L.hy, hy.data(), hy.size() * 8) &&
+                  up(p->L.hx, hx.data(), hx.size() * 8) && up(p->L.ry, ry.data(), ry.size() * 8) &&
+                  up(p->L.rx, rx.data(), rx.size() * 8) && up(p->L.ident, ident.data(), ident.size() * 4) &&
+                  up(p->L.pos_info, hp.pos_info.data(), hp.pos_info.size() * 16) &&
+                  up(p->L.pos_list, pos_list.data(), pos_list.size() * 4) &&
+                  up(p->L.tile_off, hp.tile_off.data(), hp.tile_off.size() * 4) &&
+                  up(p->L.tile_list, hp.tile_list.data(), hp.tile_list.size() * 4) &&
+                  up(p->L.class_off, hp.class_off.data(), hp.class_off.size() * 4) &&
+                  up(p->L.class_list, hp.class_list.data(), hp.class_list.size() * 4);
+        if (!ok) {
+            hipError_t e = hipGetLastError();
+            delete p;
+            return fail(MS_ERR_HIP, std::string("table upload failed: ") + hipGetErrorString(e));
+        }
+        // the per-position tile vectors are no longer needed on the host
+        hp.tile_list.clear();
+        hp.tile_list.shrink_to_fit();
+        *out = p;
+        return MS_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MS_ERR_INVALID_ARG, "host out of memory");
+    } catch (...) {
+        return fail(MS_ERR_INVALID_ARG, "unexpected host error");
+    }
+}
+
+void ms_plan_destroy(ms_plan *plan)
+{
+    if (!plan) return;
+    for (hipEvent_t e : plan->ev_start) (void)hipEventDestroy(e);
+    for (hipEvent_t e : plan->ev_stop) (void)hipEventDestroy(e);
+    delete plan;
+}
+
+ms_status ms_profile_begin(ms_plan *p, int32_t max_launches)
+{
+    g_err.clear();
+    if (!p || max_launches < 1 || max_launches > 100000) return fail(MS_ERR_INVALID_ARG, "bad profiling request");
+    for (hipEvent_t e : p->ev_start) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->ev_stop) (void)hipEventDestroy(e);
+    p->ev_start.clear();
+    p->ev_stop.clear();
+    p->ev_used = 0;
+    for (int i = 0; i < max_launches; ++i) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return check_hip("hipEventCreate");
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return check_hip("hipEventCreate");
+        }
+        p->ev_start.push_back(a);
+        p->ev_stop.push_back(b);
+    }
+    return MS_OK;
+}
+
+ms_status ms_profile_end(ms_plan *p, double *total_ms, int64_t *launches)
+{
+    g_err.clear();
+    if (!p || !total_ms || !launches) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    double tot = 0.0;
+    ms_status st = MS_OK;
+    if (p->ev_used > 0 && hipEventSynchronize(p->ev_stop[p->ev_used - 1]) != hipSuccess)
+        st = check_hip("hipEventSynchronize");
+    for (size_t i = 0; i < p->ev_used && st == MS_OK; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->ev_start[i], p->ev_stop[i]) != hipSuccess) st = check_hip("hipEventElapsedTime");
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)p->ev_used;
+    for (hipEvent_t e : p->ev_start) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->ev_stop) (void)hipEventDestroy(e);
+    p->ev_start.clear();
+    p->ev_stop.clear();
+    p->ev_used = 0;
+    return st;
+}
+
+int64_t ms_plan_batch(const ms_plan *plan) { return plan ? plan->hp.B : 0; }
+
+int32_t ms_plan_shift_classes(const ms_plan *plan) { return plan ? plan->hp.C : 0; }
+
+ms_status ms_make_probe(ms_plan *p, hipStream_t st, double alpha, double defocus, ms_c64 *probe_out)
+{
+    g_err.clear();
+    if (!p || !probe_out) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    if (!aligned8(probe_out)) return fail(MS_ERR_INVALID_ARG, "probe_out must be 8-byte aligned");
+    if (!(alpha > 0.0) || !std::isfinite(alpha) || !std::isfinite(defocus))
+        return fail(MS_ERR_INVALID_ARG, "alpha must be positive, both finite");
+    float2 *out = reinterpret_cast<float2 *>(probe_out);
+    const float2 *tw = p->at<float2>(p->L.tw);
+    switch (p->hp.n) {
+        case 16: make_probe_kernel<16><<<1, Win<16>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, defocus); break;
+        case 32: make_probe_kernel<32><<<1, Win<32>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, defocus); break;
+        case 64: make_probe_kernel<64><<<1, Win<64>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, defocus); break;
+        default: make_probe_kernel<128><<<1, Win<128>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, defocus); break;
+    }
+    return check_hip("ms_make_probe");
+}
+
+ms_status ms_forward(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c64 *slices, float *intensity_out,
+                     ms_c64 *exit_out)
+{
+    g_err.clear();
+    if (!p || !probe || !slices || !intensity_out) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    if (!aligned8(probe) || !aligned8(slices) || !aligned8(exit_out) || ((uintptr_t)intensity_out & 3))
+        return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
+    const HostPlan &hp = p->hp;
+    class_probes(p, probe, st);
+    FusedParams fp = fused_params(p, slices, nullptr);
+    fp.intensity = intensity_out;
+    fp.exit_waves = reinterpret_cast<float2 *>(exit_out);
+    fp.waves = nullptr;
+    for (int b = 0; b < hp.nb; ++b) {
+        int64_t s0 = (int64_t)b * hp.B;
+        int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
+        fp.pos_list = p->at<int>(p->L.pos_list) + s0;
+        launch_fused(p, kForward, fp, count, st);
+    }
+    return check_hip("ms_forward");
+}
+
+ms_status ms_adjoint(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c64 *slices, const float *measured,
+                     ms_c64 *grad_slices, ms_c64 *grad_probe, double *loss_out)
+{
+    g_err.clear();
+    if (!p || !probe || !slices || !measured || !grad_slices || !loss_out)
+        return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    if (!aligned8(probe) || !aligned8(slices) || !aligned8(grad_slices) || !aligned8(grad_probe) ||
+        !aligned8(loss_out) || ((uintptr_t)measured & 3))
+        return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
+    const HostPlan &hp = p->hp;
+    const int nn = hp.n * hp.n;
+    class_probes(p, probe, st);
+    FusedParams fp = fused_params(p, slices, measured);
+    if (!grad_probe) fp.probe_patch = nullptr;
+    double *total = p->at<double>(p->L.scal) + 1;
+    for (int b = 0; b < hp.nb; ++b) {
+        int64_t s0 = (int64_t)b * hp.B;
+        int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
+        fp.pos_list = p->at<int>(p->L.pos_list) + s0;
+        launch_fused(p, kAdjoint, fp, count, st);
+        scatter(p, b, 0, hp.M, reinterpret_cast<float2 *>(grad_slices), nullptr, b > 0, st);
+        if (grad_probe)
+            class_sum_kernel<<<dim3((nn + 255) / 256, hp.C), 256, 0, st>>>(
+                p->at<float2>(p->L.probe_patch), p->at<int>(p->L.class_off) + (size_t)b * (hp.C + 1),
+                p->at<int>(p->L.class_list), p->at<float2>(p->L.class_acc), nn, b > 0);
+        loss_sum_kernel<<<1, 256, 0, st>>>(p->at<double>(p->L.loss_pos), count, total, b > 0);
+    }
+    if (grad_probe) probe_gradient(p, reinterpret_cast<float2 *>(grad_probe), st);
+    copy_scalar_kernel<<<1, 1, 0, st>>>(total, loss_out);
+    return check_hip("ms_adjoint");
+}
+
+ms_status ms_layer_step(ms_plan *p, hipStream_t st, int32_t layer, int32_t k_steps, const ms_c64 *probe,
+                        ms_c64 *slices, const float *measured, double *loss_out, double *mu_out)
+{
+    g_err.clear();
+    if (!p || !probe || !slices || !measured) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    const HostPlan &hp = p->hp;
+    if (layer < 0 || layer >= hp.M) return fail(MS_ERR_INVALID_ARG, "layer out of range");
+    if (k_steps < 0) return fail(MS_ERR_INVALID_ARG, "k_steps must be >= 0");
+    if (!aligned8(probe) || !aligned8(slices) || !aligned8(loss_out) || !aligned8(mu_out) || ((uintptr_t)measured & 3))
+        return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
+    if (k_steps == 0) return MS_OK;
+    const long long hw = (long long)hp.H * hp.W;
+    class_probes(p, probe, st);
+    slice_maxima(p, slices, st);
+    FusedParams fp = fused_params(p, slices, measured);
+    fp.layer = layer;
+    fp.probe_patch = nullptr;
+    double *mu = p->at<double>(p->L.scal);
+    double *total = mu + 1;
+    float2 *g = p->at<float2>(p->L.layer_g);
+    float *w = p->at<float>(p->L.layer_w);
+    const int wblocks = (int)std::min<long long>(kMaxBlocks, (hw + 255) / 256);
+    for (int k = 0; k < k_steps; ++k) {
+        for (int b = 0; b < hp.nb; ++b) {
+            int64_t s0 = (int64_t)b * hp.B;
+            int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
+            fp.pos_list = p->at<int>(p->L.pos_list) + s0;
+            launch_fused(p, kLayer, fp, count, st);
+            scatter(p, b, layer, 1, g, w, b > 0, st);
+            loss_sum_kernel<<<1, 256, 0, st>>>(p->at<double>(p->L.loss_pos), count, total, b > 0);
+        }
+        float *part = p->at<float>(p->L.partial) + (size_t)hp.M * kMaxBlocks;
+        max_partial_kernel<<<dim3(wblocks, 1), 256, 0, st>>>(nullptr, w, hw, part);
+        max_final_kernel<<<1, 256, 0, st>>>(part, wblocks, p->at<float>(p->L.maxw));
+        const bool last = (k + 1 == k_steps);
+        step_size_kernel<<<1, 1, 0, st>>>(p->at<float>(p->L.maxt2), layer + 1, hp.M, p->at<float>(p->L.maxw),
+                                          (double)hp.n * hp.n, 1.0, mu, last ? mu_out : nullptr, total,
+                                          last ? loss_out : nullptr);
+        update_kernel<<<(int)std::min<long long>(4096, (hw + 255) / 256), 256, 0, st>>>(
+            reinterpret_cast<float2 *>(slices) + (size_t)layer * hw, g, hw, mu);
+    }
+    return check_hip("ms_layer_step");
+}
+
+ms_status ms_probe_step(ms_plan *p, hipStream_t st, int32_t k_steps, ms_c64 *probe, const ms_c64 *slices,
+                        const float *measured, const int64_t *subset, int64_t n_subset, double *loss_out,
+                        double *mu_out)
+{
+    g_err.clear();
+    if (!p || !probe || !slices || !measured) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    const HostPlan &hp = p->hp;
+    if (k_steps < 0) return fail(MS_ERR_INVALID_ARG, "k_steps must be >= 0");
+    if (!aligned8(probe) || !aligned8(slices) || !aligned8(loss_out) || !aligned8(mu_out) || ((uintptr_t)measured & 3))
+        return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
+    int64_t count_all = hp.S;
+    const int *list = p->at<int>(p->L.pos_list);
+    const int *coff = p->at<int>(p->L.class_off);
+    const int *clist = p->at<int>(p->L.class_list);
+    if (subset) {
+        if (n_subset < 1 || n_subset > hp.S) return fail(MS_ERR_INVALID_ARG, "n_subset must be in [1, S]");
+        for (int64_t i = 0; i < n_subset; ++i)
+            if (subset[i] < 0 || subset[i] >= hp.S) return fail(MS_ERR_INVALID_ARG, "subset index out of range");
+        count_all = n_subset;
+    }
+    if (k_steps == 0) return MS_OK;
+    try {
+        if (subset) {
+            const int64_t nbs = (n_subset + hp.B - 1) / hp.B;
+            p->sub_list.assign(n_subset, 0);
+            p->sub_class_off.assign((size_t)nbs * (hp.C + 1), 0);
+            p->sub_class_list.assign(n_subset, 0);
+            std::vector<int> cnt(hp.C);
+            int base = 0;
+            for (int64_t b = 0; b < nbs; ++b) {
+                int64_t s0 = b * hp.B, s1 = std::min(n_subset, s0 + hp.B);
+                std::fill(cnt.begin(), cnt.end(), 0);
+                for (int64_t i = s0; i < s1; ++i) {
+                    p->sub_list[i] = (int)subset[i];
+                    cnt[hp.pos_info[subset[i]].z]++;
+                }
+                int *o = &p->sub_class_off[(size_t)b * (hp.C + 1)];
+                o[0] = base;
+                for (int c = 0; c < hp.C; ++c) o[c + 1] = o[c] + cnt[c];
+                std::vector<int> cur(o, o + hp.C);
+                for (int64_t i = s0; i < s1; ++i) p->sub_class_list[cur[hp.pos_info[subset[i]].z]++] = (int)(i - s0);
+                base = o[hp.C];
+            }
+            bool ok = hipMemcpyAsync(p->ws + p->L.sub_list, p->sub_list.data(), p->sub_list.size() * 4,
+                                     hipMemcpyHostToDevice, st) == hipSuccess &&
+                      hipMemcpyAsync(p->ws + p->L.sub_class_off, p->sub_class_off.data(),
+                                     p->sub_class_off.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+                      hipMemcpyAsync(p->ws + p->L.sub_class_list, p->sub_class_list.data(),
+                                     p->sub_class_list.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+            if (!ok) return check_hip("ms_probe_step subset upload");
+            list = p->at<int>(p->L.sub_list);
+            coff = p->at<int>(p->L.sub_class_off);
+            clist = p->at<int>(p->L.sub_class_list);
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(MS_ERR_INVALID_ARG, "host out of memory");
+    }
+    const int nn = hp.n * hp.n;
+    const int nbs = (int)((count_all + hp.B - 1) / hp.B);
+    slice_maxima(p, slices, st);
+    FusedParams fp = fused_params(p, slices, measured);
+    double *mu = p->at<double>(p->L.scal);
+    double *total = mu + 1;
+    float2 *gp = p->at<float2>(p->L.gp);
+    for (int k = 0; k < k_steps; ++k) {
+        class_probes(p, probe, st);
+        for (int b = 0; b < nbs; ++b) {
+            int64_t s0 = (int64_t)b * hp.B;
+            int count = (int)std::min<int64_t>(hp.B, count_all - s0);
+            fp.pos_list = list + s0;
+            launch_fused(p, kProbe, fp, count, st);
+            class_sum_kernel<<<dim3((nn + 255) / 256, hp.C), 256, 0, st>>>(
+                p->at<float2>(p->L.probe_patch), coff + (size_t)b * (hp.C + 1), clist, p->at<float2>(p->L.class_acc),
+                nn, b > 0);
+            loss_sum_kernel<<<1, 256, 0, st>>>(p->at<double>(p->L.loss_pos), count, total, b > 0);
+        }
+        probe_gradient(p, gp, st);
+        const bool last = (k + 1 == k_steps);
+        step_size_kernel<<<1, 1, 0, st>>>(p->at<float>(p->L.maxt2), 0, hp.M, nullptr, (double)nn, (double)count_all,
+                                          mu, last ? mu_out : nullptr, total, last ? loss_out : nullptr);
+        update_kernel<<<(nn + 255) / 256, 256, 0, st>>>(reinterpret_cast<float2 *>(probe), gp, nn, mu);
+    }
+    return check_hip("ms_probe_step");
+}
+
+}  // extern "C"

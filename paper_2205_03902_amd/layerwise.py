@@ -1,0 +1,50 @@
+"""Algorithm 1 (layer-wise estimation, Sec. 3.3) with the optional probe step of Sec. 3.5.
+
+Each sweep visits the layers l = 1..M in order (Gauss-Seidel: the layers
+before l already hold their new values, eq. Layerwise_Prefix_Suffix) and runs
+K amplitude-flow steps on layer l through ms_layer_step; a probe step may
+follow every sweep.  Losses and step sizes stay on the device until the run
+ends, so the loop never waits for the GPU.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import List, Optional
+
+import torch
+
+from .abi import Plan
+
+
+@dataclasses.dataclass
+class History:
+    loss: List[float]          # loss before each layer / probe step
+    mu: List[float]            # step size of each step
+    kind: List[str]            # "layer<l>" or "probe"
+    seconds: float             # wall time of the run (GPU work included)
+
+
+def reconstruct(plan: Plan, probe: torch.Tensor, slices: torch.Tensor, measured: torch.Tensor, sweeps: int,
+                k_steps: int = 1, probe_steps: int = 0, subset: Optional[list] = None) -> History:
+    """Runs `sweeps` sweeps in place on `slices` (and `probe` when probe_steps > 0)."""
+    M = plan.n_slices
+    per_sweep = M + (1 if probe_steps > 0 else 0)
+    buf = torch.zeros((max(sweeps * per_sweep, 1), 2), dtype=torch.float64, device=plan.device)
+    kinds = []
+    torch.cuda.synchronize(plan.device)
+    t0 = time.perf_counter()
+    i = 0
+    for _ in range(sweeps):
+        for layer in range(M):
+            plan.layer_step(layer, k_steps, probe, slices, measured, loss=buf[i, 0:1], mu=buf[i, 1:2])
+            kinds.append(f"layer{layer}")
+            i += 1
+        if probe_steps > 0:
+            plan.probe_step(probe_steps, probe, slices, measured, subset=subset, loss=buf[i, 0:1], mu=buf[i, 1:2])
+            kinds.append("probe")
+            i += 1
+    torch.cuda.synchronize(plan.device)
+    secs = time.perf_counter() - t0
+    h = buf[:i].cpu().numpy()
+    return History(loss=h[:, 0].tolist(), mu=h[:, 1].tolist(), kind=kinds, seconds=secs)

@@ -1,0 +1,85 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/ms.h declares, and rejects bad problems before
+anything is enqueued."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2205_03902_amd import abi, configs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "ms.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ms_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_abi():
+    assert set(_declared()) == set(abi.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = abi.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _pb(**kw):
+    geo = configs.small()
+    args = dict(n=geo.n, obj_h=geo.obj_h, obj_w=geo.obj_w, n_slices=geo.n_slices, positions=geo.positions(),
+                dz=geo.gaps(), pixel_size=geo.pixel_size, wavelength=geo.wavelength)
+    args.update(kw)
+    return abi.make_problem(**args)
+
+
+def test_workspace_size_accepts_a_valid_problem():
+    pb, keep = _pb()
+    ws = abi.workspace_size(pb)
+    assert ws > 0
+    # a budget smaller than one batch of everything forces batching but still fits
+    ws_small = abi.workspace_size(pb, budget_bytes=ws // 2)
+    assert 0 < ws_small <= ws // 2
+
+
+@pytest.mark.parametrize("kw, status", [
+    (dict(n=24), abi.MS_ERR_INVALID_ARG),
+    (dict(n=8), abi.MS_ERR_INVALID_ARG),
+    (dict(n=256, obj_h=256, obj_w=256), abi.MS_ERR_UNSUPPORTED),
+    (dict(obj_h=16), abi.MS_ERR_INVALID_ARG),
+    (dict(n_slices=0), abi.MS_ERR_INVALID_ARG),
+    (dict(pixel_size=0.0), abi.MS_ERR_INVALID_ARG),
+    (dict(wavelength=float("nan")), abi.MS_ERR_INVALID_ARG),
+    (dict(positions=np.array([[0.0, float("inf")]])), abi.MS_ERR_INVALID_ARG),
+])
+def test_invalid_problems_are_rejected(kw, status):
+    pb, keep = _pb(**kw)
+    with pytest.raises(abi.MsError) as e:
+        abi.workspace_size(pb)
+    assert e.value.status == status
+    assert abi.lib().ms_last_error().decode() != ""
+
+
+def test_budget_too_small_is_reported():
+    pb, keep = _pb()
+    with pytest.raises(abi.MsError) as e:
+        abi.workspace_size(pb, budget_bytes=1024)
+    assert e.value.status == abi.MS_ERR_BUDGET
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    lib = abi.lib()
+    assert lib.ms_workspace_size(None, 0, None) == abi.MS_ERR_INVALID_ARG
+    pb, keep = _pb()
+    assert lib.ms_workspace_size(C.byref(pb), 0, None) == abi.MS_ERR_INVALID_ARG
+    h = C.c_void_p()
+    assert lib.ms_plan_create(C.byref(pb), None, 0, C.byref(h)) == abi.MS_ERR_INVALID_ARG
+    # the compute calls validate their plan before touching the stream
+    assert lib.ms_forward(None, None, None, None, None, None) == abi.MS_ERR_INVALID_ARG
+    assert lib.ms_adjoint(None, None, None, None, None, None, None, None) == abi.MS_ERR_INVALID_ARG
+    assert lib.ms_layer_step(None, None, 0, 1, None, None, None, None, None) == abi.MS_ERR_INVALID_ARG
+    assert lib.ms_probe_step(None, None, 1, None, None, None, None, 0, None, None) == abi.MS_ERR_INVALID_ARG

@@ -1,0 +1,101 @@
+"""GPU parity at the full sizes of the synthetic workloads, in the launch
+configuration the benchmark times (one plan, all positions in one batch)."""
+import numpy as np
+import pytest
+
+from parity_cases import make_case, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    from paper_2205_03902_amd import configs
+    print("[case] config 0 (64 px, 2 slices, 64 positions)", flush=True)
+    return make_case(configs.CFG0)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    from paper_2205_03902_amd import configs
+    print("[case] config 1 (128 px, 6 slices, 1024 positions)", flush=True)
+    return make_case(configs.CFG1)
+
+
+def test_config0_forward_adjoint_and_three_layer_steps(dev, cfg0):
+    from paper_2205_03902_amd import abi
+    c = cfg0
+    plan = abi.Plan.from_geometry(c.geo, device=dev)
+    p, s, m = _t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev)
+    inten, ew = plan.forward(p, s, exit_waves=True)
+    ref_i, ref_e = c.model.forward(c.probe, c.start, exit_waves=True)
+    assert rel(inten.cpu().numpy(), ref_i) < 1e-5 and rel(ew.cpu().numpy(), ref_e) < 1e-5
+    loss, gs, gp = plan.adjoint(p, s, m)
+    ref_l, ref_gs, ref_gp, _ = c.model.loss_grad(c.probe, c.start, c.measured)
+    assert abs(loss.item() - ref_l) / ref_l < 1e-5
+    assert rel(gs.cpu().numpy(), ref_gs) < 1e-4 and rel(gp.cpu().numpy(), ref_gp) < 1e-4
+    # the first three layer steps of Algorithm 1 (layers 1, 2, then 1 again)
+    ref = c.start.astype(np.complex128)
+    out = torch.zeros(2, dtype=torch.float64, device=dev)
+    for layer in (0, 1, 0):
+        plan.layer_step(layer, 1, p, s, m, loss=out[0:1], mu=out[1:2])
+        ref, ref_l, ref_mu = c.model.layer_step(c.probe, ref, c.measured, layer, 1)
+        assert abs(out[0].item() - ref_l) / ref_l < 1e-5
+        assert abs(out[1].item() - ref_mu) / ref_mu < 1e-5
+        assert rel(s.cpu().numpy(), ref) < 1e-5
+
+
+def test_config1_forward_sampled_positions(dev, cfg1):
+    """All 1024 positions on the GPU; the oracle recomputes a sample of them one by one."""
+    import oracle
+    from paper_2205_03902_amd import abi
+    c = cfg1
+    plan = abi.Plan.from_geometry(c.geo, device=dev)
+    assert plan.batch == c.geo.n_pos and plan.shift_classes == 4
+    inten, ew = plan.forward(_t(c.probe, dev), _t(c.start, dev), exit_waves=True)
+    pick = np.arange(0, c.geo.n_pos, 93)
+    sub = oracle.Model.from_geometry(c.geo, positions=c.model.positions[pick])
+    ref_i, ref_e = sub.forward(c.probe, c.start, exit_waves=True)
+    assert rel(inten.cpu().numpy()[pick], ref_i) < 1e-5
+    assert rel(ew.cpu().numpy()[pick], ref_e) < 1e-5
+    # pure-phase slices and a unit-energy probe: every pattern sums to N^2 (Parseval)
+    sums = inten.double().sum(dim=(1, 2)).cpu().numpy()
+    assert np.abs(sums / c.geo.n ** 2 - 1).max() < 1e-5
+
+
+def test_config1_adjoint_full(dev, cfg1):
+    from paper_2205_03902_amd import abi
+    c = cfg1
+    plan = abi.Plan.from_geometry(c.geo, device=dev)
+    loss, gs, gp = plan.adjoint(_t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev))
+    ref_l, ref_gs, ref_gp, _ = c.model.loss_grad(c.probe, c.start, c.measured)
+    el, egs, egp = abs(loss.item() - ref_l) / ref_l, rel(gs.cpu().numpy(), ref_gs), rel(gp.cpu().numpy(), ref_gp)
+    print(f"config 1 adjoint: loss {el:.2e} grad slices {egs:.2e} grad probe {egp:.2e}")
+    assert el < 1e-5 and egs < 1e-4 and egp < 1e-4
+
+
+def test_config1_first_layer_steps(dev, cfg1):
+    from paper_2205_03902_amd import abi
+    c = cfg1
+    plan = abi.Plan.from_geometry(c.geo, device=dev)
+    p, s, m = _t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev)
+    ref = c.start.astype(np.complex128)
+    out = torch.zeros(2, dtype=torch.float64, device=dev)
+    for layer in (0, 1, 2):
+        plan.layer_step(layer, 1, p, s, m, loss=out[0:1], mu=out[1:2])
+        ref, ref_l, ref_mu = c.model.layer_step(c.probe, ref, c.measured, layer, 1)
+        assert abs(out[0].item() - ref_l) / ref_l < 1e-5
+        assert abs(out[1].item() - ref_mu) / ref_mu < 1e-5
+        assert rel(s.cpu().numpy(), ref) < 1e-5

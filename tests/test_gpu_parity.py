@@ -1,0 +1,214 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (relative L2): exit waves and intensities 1e-5, gradients 1e-4; the loss
+and step sizes 1e-5.  The GPU computes in FP32 complex with FP64 loss and
+step-size reductions, so these bars leave a margin of 10-100x over its
+rounding error after the chained FFTs.
+"""
+import numpy as np
+import pytest
+
+from parity_cases import make_case, rel, small_geometry, small_positions
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_FWD = 1e-5
+TOL_GRAD = 1e-4
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _plan(case, dev, budget=0):
+    from paper_2205_03902_amd import abi
+    return abi.Plan.from_geometry(case.geo, positions=case.model.positions, budget_bytes=budget, device=dev)
+
+
+def _t(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+_CASES = {}
+
+
+def case_for(n):
+    if n not in _CASES:
+        g = small_geometry(n)
+        print(f"[case] n={n} obj={g.obj_h} M={g.n_slices} S={g.n_pos}", flush=True)
+        _CASES[n] = make_case(g, positions=small_positions(g))
+    return _CASES[n]
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+def test_make_probe(dev, n):
+    import oracle
+    c = case_for(n)
+    plan = _plan(c, dev)
+    for defocus in (0.0, c.geo.defocus):
+        p = plan.make_probe(c.geo.alpha, defocus).cpu().numpy()
+        ref = oracle.probe(n, c.geo.pixel_size, c.geo.wavelength, c.geo.alpha, defocus)
+        assert rel(p, ref) < 2e-6, (n, defocus, rel(p, ref))
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+def test_forward(dev, n):
+    c = case_for(n)
+    plan = _plan(c, dev)
+    inten, ew = plan.forward(_t(c.probe, dev), _t(c.start, dev), exit_waves=True)
+    ref_i, ref_e = c.model.forward(c.probe, c.start, exit_waves=True)
+    ei, ee = rel(inten.cpu().numpy(), ref_i), rel(ew.cpu().numpy(), ref_e)
+    print(f"n={n} forward rel L2: intensity {ei:.2e} exit {ee:.2e}")
+    assert ei < TOL_FWD and ee < TOL_FWD
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+def test_adjoint(dev, n):
+    c = case_for(n)
+    plan = _plan(c, dev)
+    loss, gs, gp = plan.adjoint(_t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev))
+    ref_l, ref_gs, ref_gp, _ = c.model.loss_grad(c.probe, c.start, c.measured)
+    el = abs(loss.item() - ref_l) / ref_l
+    egs, egp = rel(gs.cpu().numpy(), ref_gs), rel(gp.cpu().numpy(), ref_gp)
+    print(f"n={n} adjoint: loss {el:.2e} grad slices {egs:.2e} grad probe {egp:.2e}")
+    assert el < TOL_FWD and egs < TOL_GRAD and egp < TOL_GRAD
+
+
+@pytest.mark.parametrize("n,layer", [(32, 0), (32, 1), (32, 2), (128, 1)])
+def test_layer_step(dev, n, layer):
+    c = case_for(n)
+    plan = _plan(c, dev)
+    s_t = _t(c.start, dev)
+    out = torch.zeros(2, dtype=torch.float64, device=dev)
+    plan.layer_step(layer, 2, _t(c.probe, dev), s_t, _t(c.measured, dev), loss=out[0:1], mu=out[1:2])
+    ref_s, ref_l, ref_mu = c.model.layer_step(c.probe, c.start, c.measured, layer, 2)
+    got = s_t.cpu().numpy()
+    el, emu = abs(out[0].item() - ref_l) / ref_l, abs(out[1].item() - ref_mu) / ref_mu
+    es = rel(got, ref_s)
+    ed = rel(got - c.start, ref_s - c.start)
+    print(f"n={n} layer {layer}: loss {el:.2e} mu {emu:.2e} slices {es:.2e} step {ed:.2e}")
+    assert el < TOL_FWD and emu < TOL_FWD and es < TOL_FWD and ed < 10 * TOL_GRAD
+    others = [m for m in range(c.geo.n_slices) if m != layer]
+    assert np.array_equal(got[others], c.start[others])
+
+
+@pytest.mark.parametrize("subset", [None, [0, 4, 8], [4]])
+def test_probe_step(dev, subset):
+    c = case_for(32)
+    plan = _plan(c, dev)
+    p0 = (c.probe * np.exp(0.05j)).astype(np.complex64)
+    p_t = _t(p0, dev)
+    out = torch.zeros(2, dtype=torch.float64, device=dev)
+    plan.probe_step(2, p_t, _t(c.start, dev), _t(c.measured, dev), subset=subset, loss=out[0:1], mu=out[1:2])
+    ref_p, ref_l, ref_mu = c.model.probe_step(p0, c.start, c.measured, subset, 2)
+    got = p_t.cpu().numpy()
+    # a single position is solved almost exactly by one step (Q_p is N x a unitary map
+    # for unit-modulus slices), so the loss is measured against the starting loss
+    scale = c.model.loss(p0, c.start, c.measured, subset=subset)
+    el, emu = abs(out[0].item() - ref_l) / scale, abs(out[1].item() - ref_mu) / ref_mu
+    ep, ed = rel(got, ref_p), rel(got - p0, ref_p - p0)
+    print(f"probe step subset={subset}: loss {el:.2e} mu {emu:.2e} probe {ep:.2e} step {ed:.2e}")
+    assert el < TOL_FWD and emu < TOL_FWD and ep < TOL_FWD and ed < 10 * TOL_GRAD
+
+
+def test_batching_and_repeats_are_bitwise_identical(dev):
+    c = case_for(32)
+    from paper_2205_03902_amd import abi
+    full = _plan(c, dev)
+    ws = full.workspace.numel()
+    small = _plan(c, dev, budget=ws // 3)
+    assert small.batch < full.batch
+    args = (_t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev))
+    l1, g1, p1 = full.adjoint(*args)
+    l1b, g1b, p1b = full.adjoint(*args)
+    l2, g2, p2 = small.adjoint(*args)
+    assert torch.equal(g1, g1b) and torch.equal(p1, p1b) and l1.item() == l1b.item()
+    assert torch.equal(g1, g2) and torch.equal(p1, p2)
+    assert abs(l1.item() - l2.item()) <= 1e-12 * l1.item()
+    i1 = full.forward(args[0], args[1])
+    i2 = small.forward(args[0], args[1])
+    assert torch.equal(i1, i2)
+    del abi
+
+
+def test_autograd_function_matches_oracle(dev):
+    from paper_2205_03902_amd.autograd import amplitude_loss
+    c = case_for(32)
+    plan = _plan(c, dev)
+    p_t = _t(c.probe, dev).requires_grad_(True)
+    s_t = _t(c.start, dev).requires_grad_(True)
+    loss = amplitude_loss(plan, p_t, s_t, _t(c.measured, dev))
+    (3.0 * loss).backward()
+    ref_l, ref_gs, ref_gp, _ = c.model.loss_grad(c.probe, c.start, c.measured)
+    assert abs(loss.item() - ref_l) / ref_l < TOL_FWD
+    # torch's complex gradient of a real loss is 2 dL/d conj(z)
+    assert rel(s_t.grad.cpu().numpy(), 6.0 * ref_gs) < TOL_GRAD
+    assert rel(p_t.grad.cpu().numpy(), 6.0 * ref_gp) < TOL_GRAD
+
+
+def test_gpu_gradient_matches_oracle_finite_differences(dev):
+    from paper_2205_03902_amd import synth
+    c = case_for(32)
+    plan = _plan(c, dev)
+    _, gs, gp = plan.adjoint(_t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev))
+    gs, gp = gs.cpu().numpy().astype(np.complex128), gp.cpu().numpy().astype(np.complex128)
+    start = c.start.astype(np.complex128)
+    probe = c.probe.astype(np.complex128)
+    dirs = synth.complex_directions(start.shape, 6, seed=c.geo.seed + 2)
+    pdirs = synth.complex_directions(probe.shape, 6, seed=c.geo.seed + 5) * 0.01
+    eps = 1e-3
+
+    def fd(f, x, d):
+        # Richardson-extrapolated central difference, O(eps^4)
+        d1 = (f(x + eps * d) - f(x - eps * d)) / (2 * eps)
+        d2 = (f(x + 0.5 * eps * d) - f(x - 0.5 * eps * d)) / eps
+        return (4 * d2 - d1) / 3
+
+    for d in dirs:
+        ref = fd(lambda x: c.model.loss(probe, x, c.measured), start, d)
+        got = 2 * np.vdot(gs, d).real
+        assert abs(got - ref) <= TOL_GRAD * abs(ref), (got, ref)
+    for d in pdirs:
+        ref = fd(lambda x: c.model.loss(x, start, c.measured), probe, d)
+        got = 2 * np.vdot(gp, d).real
+        assert abs(got - ref) <= TOL_GRAD * abs(ref), (got, ref)
+
+
+def test_zero_far_field_follows_the_zero_phase_rule(dev):
+    """Psi = 0 everywhere (zero probe): residual = Psi = 0, so every gradient is exactly 0
+    and the loss is the total measured intensity (Sec. 3.2)."""
+    c = case_for(16)
+    plan = _plan(c, dev)
+    zero = np.zeros_like(c.probe)
+    loss, gs, gp = plan.adjoint(_t(zero, dev), _t(c.start, dev), _t(c.measured, dev))
+    assert torch.count_nonzero(gs).item() == 0 and torch.count_nonzero(gp).item() == 0
+    ref = float(np.sum(c.measured.astype(np.float64)))
+    assert abs(loss.item() - ref) <= 1e-12 * ref
+
+
+@pytest.mark.parametrize("kind", ["single_slice", "one_position", "object_equals_window"])
+def test_edge_geometries(dev, kind):
+    from paper_2205_03902_amd import configs
+    if kind == "single_slice":
+        g = configs.small(n=32, obj=40, n_slices=1, scan=(2, 2), step_px=5.5, seed=3)
+        pos = None
+    elif kind == "one_position":
+        g = configs.small(n=64, obj=64, n_slices=4, scan=(1, 1), step_px=0.0, seed=4)
+        pos = np.array([[17.25, -40.5]])
+    else:
+        # H = W = N: the paper's full-field periodic model, every window wraps
+        g = configs.small(n=32, obj=32, n_slices=3, scan=(3, 3), step_px=7.0, seed=5)
+        pos = None
+    c = make_case(g, positions=pos)
+    plan = _plan(c, dev)
+    inten = plan.forward(_t(c.probe, dev), _t(c.start, dev))
+    loss, gs, gp = plan.adjoint(_t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev))
+    ref_i = c.model.forward(c.probe, c.start)
+    ref_l, ref_gs, ref_gp, _ = c.model.loss_grad(c.probe, c.start, c.measured)
+    assert rel(inten.cpu().numpy(), ref_i) < TOL_FWD
+    assert abs(loss.item() - ref_l) / ref_l < TOL_FWD
+    assert rel(gs.cpu().numpy(), ref_gs) < TOL_GRAD and rel(gp.cpu().numpy(), ref_gp) < TOL_GRAD
