@@ -120,7 +120,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=1, help="workload geometry (0..4)")
-    ap.add_argument("--cpu-sample", type=int, default=256, help="positions in the oracle's timing sample")
+    ap.add_argument("--cpu-sample", type=int, default=1024, help="positions in the oracle's timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the sweep and forward timings")
     ap.add_argument("--copy-calibration", action="store_true")

@@ -120,8 +120,10 @@ def test_batching_and_repeats_are_bitwise_identical(dev):
     from paper_2205_03902_amd import abi
     full = _plan(c, dev)
     ws = full.workspace.numel()
-    small = _plan(c, dev, budget=ws // 3)
-    assert small.batch < full.batch
+    n2 = c.geo.n ** 2
+    per_position = c.geo.n_slices * n2 * 8 + n2 * 8 + n2 * 4 + 8
+    small = _plan(c, dev, budget=ws - 6 * per_position)   # a few positions per batch
+    assert 1 < small.batch < full.batch == c.geo.n_pos
     args = (_t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev))
     l1, g1, p1 = full.adjoint(*args)
     l1b, g1b, p1b = full.adjoint(*args)
@@ -160,7 +162,10 @@ def test_gpu_gradient_matches_oracle_finite_differences(dev):
     probe = c.probe.astype(np.complex128)
     dirs = synth.complex_directions(start.shape, 6, seed=c.geo.seed + 2)
     pdirs = synth.complex_directions(probe.shape, 6, seed=c.geo.seed + 5) * 0.01
-    eps = 1e-3
+    # The amplitude loss bends sharply at dark detector pixels: a step of 1e-3 along a
+    # unit-variance direction leaves a truncation error near 1e-3 even after Richardson
+    # extrapolation, while 1e-5 brings it below 1e-9 with FP64 rounding still ~1e-9.
+    eps = 1e-5
 
     def fd(f, x, d):
         # Richardson-extrapolated central difference, O(eps^4)
