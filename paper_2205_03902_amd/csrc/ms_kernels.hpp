@@ -294,64 +294,118 @@ __global__ __launch_bounds__(Win<N>::NT) void fused_kernel(FusedParams p)
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic segmented scatter-add: every object pixel sums the patches of the
-// positions whose window covers it, in ascending position order (sum over s in
-// eq. Opt_Prob_Layerwise).  Block = one 16 x 16 tile; the host lists, per tile,
-// the batch positions whose window intersects it.
+// Deterministic segmented scatter-add (the sum over positions of eq. Opt_Prob_Layerwise
+// carried into object coordinates).  Positions of a batch are cut into at most kChunks
+// chunks of consecutive positions.  Pass 1: block (tile, chunk, slice) adds, pixel by
+// pixel and in ascending position order, the patches of the chunk's windows that touch
+// the tile; pass 2 adds the chunk partials in chunk order.  The order is fixed by the
+// plan, so results are reproducible bit for bit.
+constexpr int kTileW = 64;   // scatter tile: 64 x 4 pixels, one 256-lane block
+constexpr int kTileH = 4;
+constexpr int kChunks = 16;  // chunks per batch
+constexpr int kUnroll = 8;   // patch loads in flight per lane
+
 struct ScatterParams {
-    const float2 *patches;      // patch of position b, slice m: patches + b * pos_stride + m * N * N
-    const float *wpatch;        // [count][N][N] or null
+    const float2 *patches;      // patch of (position b, slice m): patches + b * pos_stride + m * N * N
+    const float *wpatch;        // [count][N][N] overlap patches, or null
     long long pos_stride;
-    const int *tile_off;        // [n_tiles + 1]
-    const int *tile_list;       // batch-local position indices
-    const int4 *pos_info;
-    const int *pos_list;
-    float2 *out;                // slice m at out + (m - m0) * H * W
-    float *wout;                // [H][W] or null
-    int H, W, N, tiles_x, m0, accumulate;
+    const int *tile_off;        // this batch: [kChunks][n_tiles + 1]
+    const int4 *entries;        // (batch-local position, origin y, origin x, 0)
+    float2 *partial;            // [nch][n_m][H][W]
+    float *wpartial;            // [nch][H][W] or null
+    int H, W, N, tiles_x, n_tiles, m0;
 };
 
-__global__ __launch_bounds__(256) void scatter_kernel(ScatterParams p)
+__global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
 {
-    const int t = blockIdx.x;
-    const int m = p.m0 + blockIdx.y;
-    const int ty = t / p.tiles_x, tx = t % p.tiles_x;
-    const int y = ty * 16 + (threadIdx.x >> 4), x = tx * 16 + (threadIdx.x & 15);
+    const int t = blockIdx.x, c = blockIdx.y, mi = blockIdx.z, n_m = gridDim.z;
+    const int y = (t / p.tiles_x) * kTileH + (int)(threadIdx.x / kTileW);
+    const int x = (t % p.tiles_x) * kTileW + (int)(threadIdx.x % kTileW);
     if (y >= p.H || x >= p.W) return;
-    const size_t o = (size_t)blockIdx.y * p.H * p.W + (size_t)y * p.W + x;   // output slice m - m0
     const size_t NN = (size_t)p.N * p.N;
-    float2 acc = p.accumulate ? p.out[o] : make_float2(0.f, 0.f);
+    const float2 *base = p.patches + (size_t)(p.m0 + mi) * NN;
+    const bool want_w = p.wpartial && mi == 0;
+    const int *off = p.tile_off + (size_t)c * (p.n_tiles + 1);
+    const int e0 = off[t], e1 = off[t + 1];
+    float2 acc = make_float2(0.f, 0.f);
     float wacc = 0.f;
-    if (p.wout) wacc = p.accumulate ? p.wout[(size_t)y * p.W + x] : 0.f;
-    const float2 *base = p.patches + (size_t)m * NN;
-    const int e1 = p.tile_off[t + 1];
-    for (int e = p.tile_off[t]; e < e1; ++e) {
-        const int sb = p.tile_list[e];
-        const int4 info = p.pos_info[p.pos_list[sb]];
-        int ly = y - info.x;
-        if (ly < 0) ly += p.H;
-        int lx = x - info.y;
-        if (lx < 0) lx += p.W;
-        if (ly < p.N && lx < p.N) {
-            const size_t q = (size_t)sb * p.pos_stride + (size_t)ly * p.N + lx;
-            acc = cadd(acc, base[q]);
-            if (p.wout) wacc += p.wpatch[(size_t)sb * NN + (size_t)ly * p.N + lx];
+    for (int e = e0; e < e1; e += kUnroll) {
+        int sl[kUnroll], loc[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            loc[u] = -1;
+            sl[u] = 0;
+            if (e + u < e1) {
+                const int4 en = p.entries[e + u];
+                int ly = y - en.y;
+                if (ly < 0) ly += p.H;
+                int lx = x - en.z;
+                if (lx < 0) lx += p.W;
+                sl[u] = en.x;
+                if (ly < p.N && lx < p.N) loc[u] = ly * p.N + lx;
+            }
+        }
+        float2 v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            v[u] = loc[u] >= 0 ? base[(size_t)sl[u] * p.pos_stride + loc[u]] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) acc = cadd(acc, v[u]);
+        if (want_w) {
+            float w[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) w[u] = loc[u] >= 0 ? p.wpatch[(size_t)sl[u] * NN + loc[u]] : 0.f;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) wacc += w[u];
         }
     }
-    p.out[o] = acc;
-    if (p.wout) p.wout[(size_t)y * p.W + x] = wacc;
+    const size_t HW = (size_t)p.H * p.W, pix = (size_t)y * p.W + x;
+    p.partial[((size_t)c * n_m + mi) * HW + pix] = acc;
+    if (want_w) p.wpartial[(size_t)c * HW + pix] = wacc;
 }
 
-// Per shift class: sum of the probe patches of its positions, ascending order.
-__global__ __launch_bounds__(256) void class_sum_kernel(const float2 *probe_patch, const int *class_off,
-                                                        const int *class_list, float2 *acc, int nn, int accumulate)
+// out[i] = (accumulate ? out[i] : 0) + sum_{c < nch} partial[c * plane + i], chunks in order.
+template <typename T>
+__device__ __forceinline__ T zero_of();
+template <>
+__device__ __forceinline__ float2 zero_of<float2>() { return make_float2(0.f, 0.f); }
+template <>
+__device__ __forceinline__ float zero_of<float>() { return 0.f; }
+__device__ __forceinline__ float2 add_of(float2 a, float2 b) { return cadd(a, b); }
+__device__ __forceinline__ float add_of(float a, float b) { return a + b; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void chunk_reduce_kernel(const T *partial, int nch, long long plane, T *out,
+                                                           int accumulate)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < plane; i += (long long)gridDim.x * 256) {
+        T a = accumulate ? out[i] : zero_of<T>();
+        for (int c = 0; c < nch; ++c) a = add_of(a, partial[(size_t)c * plane + i]);
+        out[i] = a;
+    }
+}
+
+// Probe patches summed per shift class and chunk (ascending positions):
+// cpart[chunk][class][pixel].  Grid (pixel blocks, classes, chunks).
+__global__ __launch_bounds__(256) void class_partial_kernel(const float2 *probe_patch, const int *class_off,
+                                                            const int *class_list, float2 *cpart, int n_classes,
+                                                            int nn)
 {
     const int pix = blockIdx.x * 256 + threadIdx.x;
-    const int c = blockIdx.y;
+    const int k = blockIdx.y, c = blockIdx.z;
     if (pix >= nn) return;
-    float2 a = accumulate ? acc[(size_t)c * nn + pix] : make_float2(0.f, 0.f);
-    for (int e = class_off[c]; e < class_off[c + 1]; ++e) a = cadd(a, probe_patch[(size_t)class_list[e] * nn + pix]);
-    acc[(size_t)c * nn + pix] = a;
+    const int *off = class_off + (size_t)c * (n_classes + 1);
+    const int e0 = off[k], e1 = off[k + 1];
+    float2 a = make_float2(0.f, 0.f);
+    for (int e = e0; e < e1; e += kUnroll) {
+        float2 v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            v[u] = (e + u < e1) ? probe_patch[(size_t)class_list[e + u] * nn + pix] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) a = cadd(a, v[u]);
+    }
+    cpart[((size_t)c * n_classes + k) * nn + pix] = a;
 }
 
 // out[c] = F^{-1}(F in[c] o (my[c] (x) mx[c])) with multipliers already divided by N:

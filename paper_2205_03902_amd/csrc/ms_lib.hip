@@ -27,8 +27,8 @@ ms_status fail(ms_status st, const std::string &msg)
     return st;
 }
 
-constexpr int kTile = 16;          // scatter tile side
 constexpr int kMaxBlocks = 256;    // partial-maximum blocks per segment
+constexpr int kMaxClasses = 256;   // distinct sub-pixel probe shifts per plan
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -70,15 +70,33 @@ struct HostPlan {
     int nb = 0, tiles_x = 0, tiles_y = 0, n_tiles = 0;
     std::vector<int4> pos_info;
     std::vector<double> cls_fy, cls_fx;
-    std::vector<int> tile_off, tile_list;     // nb x (n_tiles + 1) absolute offsets, batch-local entries
-    std::vector<int> class_off, class_list;   // nb x (C + 1) absolute offsets, batch-local entries
+    // Scatter lists.  Each batch is cut into at most kChunks chunks of consecutive
+    // positions; per (batch, chunk, tile) the entries (batch-local s, origin y, origin x)
+    // of the windows that touch the tile, per (batch, chunk, class) its positions.
+    std::vector<int> tile_off;                // nb x kChunks x (n_tiles + 1), absolute offsets
+    std::vector<int4> tile_list;
+    std::vector<int> class_off, class_list;   // nb x kChunks x (C + 1), absolute offsets
 };
+
+// A batch of `count` positions is reduced in nch chunks of cs consecutive positions.
+struct Chunking {
+    int cs, nch;
+};
+
+Chunking chunking(int64_t count)
+{
+    Chunking c;
+    c.cs = (int)((count + kChunks - 1) / kChunks);
+    if (c.cs < 1) c.cs = 1;
+    c.nch = (int)((count + c.cs - 1) / c.cs);
+    return c;
+}
 
 void derive_positions(const ms_problem *pb, HostPlan &hp)
 {
     hp.n = pb->n; hp.H = pb->obj_h; hp.W = pb->obj_w; hp.M = pb->n_slices; hp.S = pb->n_pos;
-    hp.tiles_y = (hp.H + kTile - 1) / kTile;
-    hp.tiles_x = (hp.W + kTile - 1) / kTile;
+    hp.tiles_y = (hp.H + kTileH - 1) / kTileH;
+    hp.tiles_x = (hp.W + kTileW - 1) / kTileW;
     hp.n_tiles = hp.tiles_y * hp.tiles_x;
     hp.pos_info.resize(hp.S);
     std::map<std::pair<double, double>, int> classes;
@@ -104,6 +122,8 @@ void derive_positions(const ms_problem *pb, HostPlan &hp)
     hp.C = (int)hp.cls_fy.size();
 }
 
+bool too_many_classes(const HostPlan &hp) { return hp.C > kMaxClasses; }
+
 // Tiles (row-major) covered by the window of one position.
 void window_tiles(const HostPlan &hp, const int4 &info, std::vector<int> &rows, std::vector<int> &cols,
                   std::vector<char> &mark_y, std::vector<char> &mark_x)
@@ -112,9 +132,9 @@ void window_tiles(const HostPlan &hp, const int4 &info, std::vector<int> &rows, 
     std::fill(mark_y.begin(), mark_y.end(), 0);
     std::fill(mark_x.begin(), mark_x.end(), 0);
     for (int i = 0; i < hp.n; ++i) {
-        int ty = ((info.x + i) % hp.H) / kTile;
+        int ty = ((info.x + i) % hp.H) / kTileH;
         if (!mark_y[ty]) { mark_y[ty] = 1; rows.push_back(ty); }
-        int tx = ((info.y + i) % hp.W) / kTile;
+        int tx = ((info.y + i) % hp.W) / kTileW;
         if (!mark_x[tx]) { mark_x[tx] = 1; cols.push_back(tx); }
     }
 }
@@ -125,43 +145,49 @@ void build_lists(HostPlan &hp, int64_t B)
     hp.nb = (int)((hp.S + B - 1) / B);
     std::vector<int> rows, cols;
     std::vector<char> my(hp.tiles_y), mx(hp.tiles_x);
-    // tile lists: count, prefix sums, fill in ascending batch-local order
     std::vector<std::vector<int>> per_pos(hp.S);
+    size_t total = 0;
     for (int64_t s = 0; s < hp.S; ++s) {
         window_tiles(hp, hp.pos_info[s], rows, cols, my, mx);
         per_pos[s].reserve(rows.size() * cols.size());
         for (int ty : rows)
             for (int tx : cols) per_pos[s].push_back(ty * hp.tiles_x + tx);
+        total += per_pos[s].size();
     }
-    hp.tile_off.assign((size_t)hp.nb * (hp.n_tiles + 1), 0);
-    hp.class_off.assign((size_t)hp.nb * (hp.C + 1), 0);
-    size_t total = 0;
-    for (int64_t s = 0; s < hp.S; ++s) total += per_pos[s].size();
-    hp.tile_list.assign(total, 0);
+    const size_t tstride = (size_t)hp.n_tiles + 1, cstride = (size_t)hp.C + 1;
+    hp.tile_off.assign((size_t)hp.nb * kChunks * tstride, 0);
+    hp.class_off.assign((size_t)hp.nb * kChunks * cstride, 0);
+    hp.tile_list.assign(total, make_int4(0, 0, 0, 0));
     hp.class_list.assign(hp.S, 0);
-    size_t base = 0, cbase = 0;
+    int base = 0, cbase = 0;
     std::vector<int> cnt(hp.n_tiles), ccnt(hp.C);
     for (int b = 0; b < hp.nb; ++b) {
-        int64_t s0 = (int64_t)b * B, s1 = std::min(hp.S, s0 + B);
-        std::fill(cnt.begin(), cnt.end(), 0);
-        std::fill(ccnt.begin(), ccnt.end(), 0);
-        for (int64_t s = s0; s < s1; ++s) {
-            for (int t : per_pos[s]) cnt[t]++;
-            ccnt[hp.pos_info[s].z]++;
+        const int64_t s0 = (int64_t)b * B, count = std::min(hp.S, s0 + B) - s0;
+        const Chunking ch = chunking(count);
+        for (int c = 0; c < kChunks; ++c) {
+            const int64_t a0 = std::min<int64_t>((int64_t)c * ch.cs, count);
+            const int64_t a1 = std::min<int64_t>(a0 + ch.cs, count);
+            std::fill(cnt.begin(), cnt.end(), 0);
+            std::fill(ccnt.begin(), ccnt.end(), 0);
+            for (int64_t a = a0; a < a1; ++a) {
+                for (int t : per_pos[s0 + a]) cnt[t]++;
+                ccnt[hp.pos_info[s0 + a].z]++;
+            }
+            int *off = &hp.tile_off[((size_t)b * kChunks + c) * tstride];
+            off[0] = base;
+            for (int t = 0; t < hp.n_tiles; ++t) off[t + 1] = off[t] + cnt[t];
+            int *coff = &hp.class_off[((size_t)b * kChunks + c) * cstride];
+            coff[0] = cbase;
+            for (int k = 0; k < hp.C; ++k) coff[k + 1] = coff[k] + ccnt[k];
+            std::vector<int> cur(off, off + hp.n_tiles), ccur(coff, coff + hp.C);
+            for (int64_t a = a0; a < a1; ++a) {
+                const int4 info = hp.pos_info[s0 + a];
+                for (int t : per_pos[s0 + a]) hp.tile_list[cur[t]++] = make_int4((int)a, info.x, info.y, 0);
+                hp.class_list[ccur[info.z]++] = (int)a;
+            }
+            base = off[hp.n_tiles];
+            cbase = coff[hp.C];
         }
-        int *off = &hp.tile_off[(size_t)b * (hp.n_tiles + 1)];
-        off[0] = (int)base;
-        for (int t = 0; t < hp.n_tiles; ++t) off[t + 1] = off[t] + cnt[t];
-        int *coff = &hp.class_off[(size_t)b * (hp.C + 1)];
-        coff[0] = (int)cbase;
-        for (int c = 0; c < hp.C; ++c) coff[c + 1] = coff[c] + ccnt[c];
-        std::vector<int> cur(off, off + hp.n_tiles), ccur(coff, coff + hp.C);
-        for (int64_t s = s0; s < s1; ++s) {
-            for (int t : per_pos[s]) hp.tile_list[cur[t]++] = (int)(s - s0);
-            hp.class_list[ccur[hp.pos_info[s].z]++] = (int)(s - s0);
-        }
-        base = off[hp.n_tiles];
-        cbase = coff[hp.C];
     }
 }
 
@@ -182,6 +208,7 @@ struct Layout {
     size_t tw, hy, hx, ry, rx, ident, pos_info, pos_list, sub_list;
     size_t class_probe, class_acc, class_tmp, gp, layer_g, layer_w, maxt2, partial, maxw, scal;
     size_t tile_off, tile_list, class_off, class_list, sub_class_off, sub_class_list;
+    size_t spart, wpart, cpart;
     size_t waves, probe_patch, overlap, loss_pos;
     size_t total;
 };
@@ -213,12 +240,16 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     L.partial = take(M * kMaxBlocks * 4 + kMaxBlocks * 4);
     L.maxw = take(4);
     L.scal = take(8 * 8);
-    L.tile_off = take(nb * (hp.n_tiles + 1) * 4);
-    L.tile_list = take(n_entries * 4);
-    L.class_off = take(nb * (C + 1) * 4);
+    L.tile_off = take(nb * kChunks * (hp.n_tiles + 1) * 4);
+    L.tile_list = take(n_entries * 16);
+    L.class_off = take(nb * kChunks * (C + 1) * 4);
     L.class_list = take(S * 4);
-    L.sub_class_off = take(nb * (C + 1) * 4);
+    L.sub_class_off = take(nb * kChunks * (C + 1) * 4);
     L.sub_class_list = take(S * 4);
+    const size_t nch = (size_t)chunking(B).nch;
+    L.spart = take(nch * M * HW * 8);
+    L.wpart = take(nch * HW * 4);
+    L.cpart = take(nch * C * NN * 8);
     L.waves = take((size_t)B * M * NN * 8);
     L.probe_patch = take((size_t)B * NN * 8);
     L.overlap = take((size_t)B * NN * 4);
@@ -356,21 +387,45 @@ FusedParams fused_params(ms_plan *p, const ms_c64 *slices, const float *measured
     return fp;
 }
 
-void scatter(ms_plan *p, int b, int m0, int n_m, float2 *out, float *wout, int accumulate, hipStream_t st)
+int grid_for(long long count) { return (int)std::max<long long>(1, std::min<long long>(8192, (count + 255) / 256)); }
+
+// Gradient patches of batch b (slices m0 .. m0 + n_m - 1) into out (n_m x H x W), and the
+// overlap patches into wout if given; accumulate adds to what out already holds.
+void scatter(ms_plan *p, int b, int count, int m0, int n_m, float2 *out, float *wout, int accumulate,
+             hipStream_t st)
 {
     const HostPlan &hp = p->hp;
+    const Chunking ch = chunking(count);
     ScatterParams sp{};
     sp.patches = p->at<float2>(p->L.waves);
     sp.wpatch = p->at<float>(p->L.overlap);
     sp.pos_stride = (long long)hp.M * hp.n * hp.n;
-    sp.tile_off = p->at<int>(p->L.tile_off) + (size_t)b * (hp.n_tiles + 1);
-    sp.tile_list = p->at<int>(p->L.tile_list);
-    sp.pos_info = p->at<int4>(p->L.pos_info);
-    sp.pos_list = p->at<int>(p->L.pos_list) + (size_t)b * hp.B;
-    sp.out = out;
-    sp.wout = wout;
-    sp.H = hp.H; sp.W = hp.W; sp.N = hp.n; sp.tiles_x = hp.tiles_x; sp.m0 = m0; sp.accumulate = accumulate;
-    scatter_kernel<<<dim3(hp.n_tiles, n_m), 256, 0, st>>>(sp);
+    sp.tile_off = p->at<int>(p->L.tile_off) + (size_t)b * kChunks * (hp.n_tiles + 1);
+    sp.entries = p->at<int4>(p->L.tile_list);
+    sp.partial = p->at<float2>(p->L.spart);
+    sp.wpartial = wout ? p->at<float>(p->L.wpart) : nullptr;
+    sp.H = hp.H; sp.W = hp.W; sp.N = hp.n; sp.tiles_x = hp.tiles_x; sp.n_tiles = hp.n_tiles; sp.m0 = m0;
+    scatter_partial_kernel<<<dim3(hp.n_tiles, ch.nch, n_m), 256, 0, st>>>(sp);
+    const long long plane = (long long)n_m * hp.H * hp.W;
+    chunk_reduce_kernel<float2><<<grid_for(plane), 256, 0, st>>>(sp.partial, ch.nch, plane, out, accumulate);
+    if (wout) {
+        const long long hw = (long long)hp.H * hp.W;
+        chunk_reduce_kernel<float><<<grid_for(hw), 256, 0, st>>>(sp.wpartial, ch.nch, hw, wout, accumulate);
+    }
+}
+
+// Probe patches of one batch summed per shift class into class_acc (accumulate adds).
+void class_sums(ms_plan *p, const int *class_off, const int *class_list, int count, int accumulate,
+                hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
+    const int nn = hp.n * hp.n;
+    const Chunking ch = chunking(count);
+    class_partial_kernel<<<dim3((nn + 255) / 256, hp.C, ch.nch), 256, 0, st>>>(
+        p->at<float2>(p->L.probe_patch), class_off, class_list, p->at<float2>(p->L.cpart), hp.C, nn);
+    const long long plane = (long long)hp.C * nn;
+    chunk_reduce_kernel<float2><<<grid_for(plane), 256, 0, st>>>(p->at<float2>(p->L.cpart), ch.nch, plane,
+                                                                 p->at<float2>(p->L.class_acc), accumulate);
 }
 
 // Probe gradient from the per-class sums: sum_c S_c^H acc_c.
@@ -401,6 +456,8 @@ ms_status ms_workspace_size(const ms_problem *pb, size_t budget_bytes, size_t *w
         if (!ws_bytes) return fail(MS_ERR_INVALID_ARG, "ws_bytes is NULL");
         HostPlan hp;
         derive_positions(pb, hp);
+        if (too_many_classes(hp))
+            return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(kMaxClasses) + " distinct sub-pixel offsets");
         size_t ne = tile_entries(hp);
         int64_t B = choose_batch(hp, ne, budget_bytes);
         if (B < 1) return fail(MS_ERR_BUDGET, "budget too small for a single position");
@@ -425,6 +482,10 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
         ms_plan *p = new ms_plan();
         HostPlan &hp = p->hp;
         derive_positions(pb, hp);
+        if (too_many_classes(hp)) {
+            delete p;
+            return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(kMaxClasses) + " distinct sub-pixel offsets");
+        }
         size_t ne = tile_entries(hp);
         int64_t B = choose_batch(hp, ne, ws_bytes);
         if (B < 1) { delete p; return fail(MS_ERR_BUDGET, "workspace too small for a single position"); }
@@ -481,7 +542,7 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
                   up(p->L.pos_info, hp.pos_info.data(), hp.pos_info.size() * 16) &&
                   up(p->L.pos_list, pos_list.data(), pos_list.size() * 4) &&
                   up(p->L.tile_off, hp.tile_off.data(), hp.tile_off.size() * 4) &&
-                  up(p->L.tile_list, hp.tile_list.data(), hp.tile_list.size() * 4) &&
+                  up(p->L.tile_list, hp.tile_list.data(), hp.tile_list.size() * 16) &&
                   up(p->L.class_off, hp.class_off.data(), hp.class_off.size() * 4) &&
                   up(p->L.class_list, hp.class_list.data(), hp.class_list.size() * 4);
         if (!ok) {
@@ -608,7 +669,6 @@ ms_status ms_adjoint(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c
         !aligned8(loss_out) || ((uintptr_t)measured & 3))
         return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
     const HostPlan &hp = p->hp;
-    const int nn = hp.n * hp.n;
     class_probes(p, probe, st);
     FusedParams fp = fused_params(p, slices, measured);
     if (!grad_probe) fp.probe_patch = nullptr;
@@ -618,11 +678,10 @@ ms_status ms_adjoint(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c
         int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
         fp.pos_list = p->at<int>(p->L.pos_list) + s0;
         launch_fused(p, kAdjoint, fp, count, st);
-        scatter(p, b, 0, hp.M, reinterpret_cast<float2 *>(grad_slices), nullptr, b > 0, st);
+        scatter(p, b, count, 0, hp.M, reinterpret_cast<float2 *>(grad_slices), nullptr, b > 0, st);
         if (grad_probe)
-            class_sum_kernel<<<dim3((nn + 255) / 256, hp.C), 256, 0, st>>>(
-                p->at<float2>(p->L.probe_patch), p->at<int>(p->L.class_off) + (size_t)b * (hp.C + 1),
-                p->at<int>(p->L.class_list), p->at<float2>(p->L.class_acc), nn, b > 0);
+            class_sums(p, p->at<int>(p->L.class_off) + (size_t)b * kChunks * (hp.C + 1), p->at<int>(p->L.class_list),
+                       count, b > 0, st);
         loss_sum_kernel<<<1, 256, 0, st>>>(p->at<double>(p->L.loss_pos), count, total, b > 0);
     }
     if (grad_probe) probe_gradient(p, reinterpret_cast<float2 *>(grad_probe), st);
@@ -658,7 +717,7 @@ ms_status ms_layer_step(ms_plan *p, hipStream_t st, int32_t layer, int32_t k_ste
             int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
             fp.pos_list = p->at<int>(p->L.pos_list) + s0;
             launch_fused(p, kLayer, fp, count, st);
-            scatter(p, b, layer, 1, g, w, b > 0, st);
+            scatter(p, b, count, layer, 1, g, w, b > 0, st);
             loss_sum_kernel<<<1, 256, 0, st>>>(p->at<double>(p->L.loss_pos), count, total, b > 0);
         }
         float *part = p->at<float>(p->L.partial) + (size_t)hp.M * kMaxBlocks;
@@ -697,25 +756,31 @@ ms_status ms_probe_step(ms_plan *p, hipStream_t st, int32_t k_steps, ms_c64 *pro
     if (k_steps == 0) return MS_OK;
     try {
         if (subset) {
+            // the subset, cut into batches and chunks like the full position list
             const int64_t nbs = (n_subset + hp.B - 1) / hp.B;
             p->sub_list.assign(n_subset, 0);
-            p->sub_class_off.assign((size_t)nbs * (hp.C + 1), 0);
+            p->sub_class_off.assign((size_t)nbs * kChunks * (hp.C + 1), 0);
             p->sub_class_list.assign(n_subset, 0);
             std::vector<int> cnt(hp.C);
             int base = 0;
             for (int64_t b = 0; b < nbs; ++b) {
-                int64_t s0 = b * hp.B, s1 = std::min(n_subset, s0 + hp.B);
-                std::fill(cnt.begin(), cnt.end(), 0);
-                for (int64_t i = s0; i < s1; ++i) {
-                    p->sub_list[i] = (int)subset[i];
-                    cnt[hp.pos_info[subset[i]].z]++;
+                const int64_t s0 = b * hp.B, count = std::min(n_subset, s0 + hp.B) - s0;
+                const Chunking ch = chunking(count);
+                for (int c = 0; c < kChunks; ++c) {
+                    const int64_t a0 = std::min<int64_t>((int64_t)c * ch.cs, count);
+                    const int64_t a1 = std::min<int64_t>(a0 + ch.cs, count);
+                    std::fill(cnt.begin(), cnt.end(), 0);
+                    for (int64_t a = a0; a < a1; ++a) {
+                        p->sub_list[s0 + a] = (int)subset[s0 + a];
+                        cnt[hp.pos_info[subset[s0 + a]].z]++;
+                    }
+                    int *o = &p->sub_class_off[((size_t)b * kChunks + c) * (hp.C + 1)];
+                    o[0] = base;
+                    for (int k = 0; k < hp.C; ++k) o[k + 1] = o[k] + cnt[k];
+                    std::vector<int> cur(o, o + hp.C);
+                    for (int64_t a = a0; a < a1; ++a) p->sub_class_list[cur[hp.pos_info[subset[s0 + a]].z]++] = (int)a;
+                    base = o[hp.C];
                 }
-                int *o = &p->sub_class_off[(size_t)b * (hp.C + 1)];
-                o[0] = base;
-                for (int c = 0; c < hp.C; ++c) o[c + 1] = o[c] + cnt[c];
-                std::vector<int> cur(o, o + hp.C);
-                for (int64_t i = s0; i < s1; ++i) p->sub_class_list[cur[hp.pos_info[subset[i]].z]++] = (int)(i - s0);
-                base = o[hp.C];
             }
             bool ok = hipMemcpyAsync(p->ws + p->L.sub_list, p->sub_list.data(), p->sub_list.size() * 4,
                                      hipMemcpyHostToDevice, st) == hipSuccess &&
@@ -745,9 +810,7 @@ ms_status ms_probe_step(ms_plan *p, hipStream_t st, int32_t k_steps, ms_c64 *pro
             int count = (int)std::min<int64_t>(hp.B, count_all - s0);
             fp.pos_list = list + s0;
             launch_fused(p, kProbe, fp, count, st);
-            class_sum_kernel<<<dim3((nn + 255) / 256, hp.C), 256, 0, st>>>(
-                p->at<float2>(p->L.probe_patch), coff + (size_t)b * (hp.C + 1), clist, p->at<float2>(p->L.class_acc),
-                nn, b > 0);
+            class_sums(p, coff + (size_t)b * kChunks * (hp.C + 1), clist, count, b > 0, st);
             loss_sum_kernel<<<1, 256, 0, st>>>(p->at<double>(p->L.loss_pos), count, total, b > 0);
         }
         probe_gradient(p, gp, st);

