@@ -158,7 +158,13 @@ struct Win {
     static constexpr int R = N / 16;        // lanes per line
     static constexpr int G = 16 / R;        // k1 values per lane after the exchange
     static constexpr int NT = N * R;        // lanes per window
-    static constexpr int LD = N + 1;        // padded LDS row stride (complex)
+    // LDS: line exchange slots of LD = N + R complex values (stride = R mod 16), and the
+    // N x N transpose tile stored with an XOR swizzle; both are free of bank conflicts for
+    // the 64-bit accesses of a wavefront (32 banks, 16 lanes per cycle).
+    static constexpr int LD = N + R;
+    static constexpr int LDS_WORDS = N * LD;            // complex values of LDS per window
+    static constexpr int SWZ = (N == 64) ? 5 : 9;       // transpose swizzle multiplier
+    __device__ static __forceinline__ int tpos(int y, int x) { return y * N + (x ^ ((SWZ * y) & 15)); }
     // natural position of register k along the owned axis
     __device__ static __forceinline__ int nat(int j, int k) { return j + R * k; }
     // frequency held by register i in spectral order
@@ -182,12 +188,12 @@ __device__ __forceinline__ void line_fft_fwd(float2 (&v)[16], const float2 *twg,
 #pragma unroll
         for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[k1]);
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) xb[k1 * R + j] = v[k1];
+        for (int k1 = 0; k1 < 16; ++k1) xb[k1 * R + (j ^ (k1 / G))] = v[k1];   // skewed slot
         wave_sync();
 #pragma unroll
         for (int u = 0; u < G; ++u)
 #pragma unroll
-            for (int jj = 0; jj < R; ++jj) v[u * R + jj] = xb[(j * G + u) * R + jj];
+            for (int jj = 0; jj < R; ++jj) v[u * R + jj] = xb[(j * G + u) * R + (jj ^ j)];
         wave_sync();
 #pragma unroll
         for (int u = 0; u < G; ++u) dft_small<R, false>(&v[u * R]);
@@ -209,10 +215,10 @@ __device__ __forceinline__ void line_fft_inv(float2 (&v)[16], const float2 *twg,
 #pragma unroll
         for (int u = 0; u < G; ++u)
 #pragma unroll
-            for (int jj = 0; jj < R; ++jj) xb[(j * G + u) * R + jj] = v[u * R + jj];
+            for (int jj = 0; jj < R; ++jj) xb[(j * G + u) * R + (jj ^ j)] = v[u * R + jj];
         wave_sync();
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) v[k1] = xb[k1 * R + j];
+        for (int k1 = 0; k1 < 16; ++k1) v[k1] = xb[k1 * R + (j ^ (k1 / G))];
         wave_sync();
 #pragma unroll
         for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmulc(v[k1], tw[k1]);
@@ -233,15 +239,15 @@ __device__ __forceinline__ void transpose(float2 (&v)[16], float2 *lds, int line
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         int a = SPEC_IN ? W::spec(j, i) : W::nat(j, i);
-        if (FROM_ROW) lds[line * W::LD + a] = v[i];
-        else lds[a * W::LD + line] = v[i];
+        if (FROM_ROW) lds[W::tpos(line, a)] = v[i];
+        else lds[W::tpos(a, line)] = v[i];
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         int b = SPEC_OUT ? W::spec(j, i) : W::nat(j, i);
-        if (FROM_ROW) v[i] = lds[b * W::LD + line];
-        else v[i] = lds[line * W::LD + b];
+        if (FROM_ROW) v[i] = lds[W::tpos(b, line)];
+        else v[i] = lds[W::tpos(line, b)];
     }
     __syncthreads();
 }

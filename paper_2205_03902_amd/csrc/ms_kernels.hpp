@@ -180,7 +180,7 @@ __global__ __launch_bounds__(Win<N>::NT) void fused_kernel(FusedParams p)
     using Wn = Win<N>;
     constexpr int R = Wn::R;
     constexpr size_t NN = (size_t)N * N;
-    __shared__ float2 lds[N * Wn::LD];
+    __shared__ float2 lds[Wn::LDS_WORDS];
     __shared__ double red[(Wn::NT + 63) / 64];
 
     const int tid = threadIdx.x;
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(Win<N>::NT) void window_filter_kernel(const float2 
     using Wn = Win<N>;
     constexpr int R = Wn::R;
     constexpr size_t NN = (size_t)N * N;
-    __shared__ float2 lds[N * Wn::LD];
+    __shared__ float2 lds[Wn::LDS_WORDS];
     const int c = blockIdx.x;
     const int line = threadIdx.x / R, j = threadIdx.x % R;
     const float2 *src = in + (size_t)c * in_stride;
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(Win<N>::NT) void make_probe_kernel(float2 *out, con
 #pragma clang fp contract(off)
     using Wn = Win<N>;
     constexpr int R = Wn::R;
-    __shared__ float2 lds[N * Wn::LD];
+    __shared__ float2 lds[Wn::LDS_WORDS];
     __shared__ double red[(Wn::NT + 63) / 64];
     __shared__ double total;
     const int line = threadIdx.x / R, j = threadIdx.x % R;
