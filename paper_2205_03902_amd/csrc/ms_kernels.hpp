@@ -13,6 +13,12 @@
 
 namespace imsp {
 
+// Distinct slice distances whose propagator factors fit in LDS next to the window.
+template <int N>
+struct HCap {
+    static constexpr int U = (N == 128) ? 8 : 4;
+};
+
 enum Mode : int {
     kForward = 0,   // intensities (and exit waves)
     kAdjoint = 1,   // loss, gradient patches of every slice and of the probe
@@ -26,7 +32,9 @@ struct FusedParams {
     const int4 *pos_info;        // [S] (patch origin y in [0,H), x in [0,W), shift class, 0)
     const int *pos_list;         // [count] global position index of each workgroup
     const float2 *tw;            // [N] W_N^t
-    const float2 *hy, *hx;       // [M-1][N] propagator factors divided by N, FFT order
+    const float2 *hy, *hx;       // [U][N] propagator factors of the distinct distances, divided by N
+    const int *gap_table;        // [M-1] which of the U distinct distances each gap uses
+    int n_tables;                // U <= HCap<N>::U
     const float *measured;       // [S][N][N]
     float *intensity;            // [S][N][N]
     float2 *exit_waves;          // [S][N][N] or null
@@ -174,13 +182,22 @@ __device__ __forceinline__ double residual(float2 (&v)[16], const float *meas, i
     return acc;
 }
 
+// Copies n complex values into LDS with the whole workgroup.
+template <int N>
+__device__ __forceinline__ void stage(float2 *dst, const float2 *src, int n)
+{
+    for (int i = threadIdx.x; i < n; i += Win<N>::NT) dst[i] = src[i];
+}
+
 template <int N, int MODE>
-__global__ __launch_bounds__(Win<N>::NT) void fused_kernel(FusedParams p)
+__global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4))) void fused_kernel(FusedParams p)
 {
     using Wn = Win<N>;
     constexpr int R = Wn::R;
     constexpr size_t NN = (size_t)N * N;
     __shared__ float2 lds[Wn::LDS_WORDS];
+    __shared__ float2 s_tw[N];
+    __shared__ float2 s_hy[HCap<N>::U * N], s_hx[HCap<N>::U * N];
     __shared__ double red[(Wn::NT + 63) / 64];
 
     const int tid = threadIdx.x;
@@ -191,7 +208,12 @@ __global__ __launch_bounds__(Win<N>::NT) void fused_kernel(FusedParams p)
     const int oy = info.x, ox = info.y, cls = info.z;
     const int H = p.H, W = p.W, M = p.M;
 
-    const float2 *tw = p.tw;
+    // twiddles and propagator factors live in LDS for the whole chain
+    stage<N>(s_tw, p.tw, N);
+    stage<N>(s_hy, p.hy, p.n_tables * N);
+    stage<N>(s_hx, p.hx, p.n_tables * N);
+    __syncthreads();
+    const float2 *tw = s_tw;
 
     float2 *wave = p.waves ? p.waves + (size_t)b * M * NN : nullptr;
     const float2 *probe = p.class_probe + (size_t)cls * NN;
@@ -211,7 +233,10 @@ __global__ __launch_bounds__(Win<N>::NT) void fused_kernel(FusedParams p)
                 for (int k = 0; k < 16; ++k) op[line * N + Wn::nat(j, k)] = cabs2(v[k]);
             }
             apply_patch<N, true, false>(v, slice, H, W, oy, ox, line, j);
-            if (m + 1 < M) propagate<N, true, false>(v, tw, lds, p.hy + m * N, p.hx + m * N, line, j);
+            if (m + 1 < M) {
+                const int u = p.gap_table[m] * N;
+                propagate<N, true, false>(v, tw, lds, s_hy + u, s_hx + u, line, j);
+            }
         } else {
             if (store) store_window<N, false>(v, wave + m * NN, line, j);
             if (MODE == kLayer && m == p.layer) {
@@ -220,7 +245,10 @@ __global__ __launch_bounds__(Win<N>::NT) void fused_kernel(FusedParams p)
                 for (int k = 0; k < 16; ++k) op[Wn::nat(j, k) * N + line] = cabs2(v[k]);
             }
             apply_patch<N, false, false>(v, slice, H, W, oy, ox, line, j);
-            if (m + 1 < M) propagate<N, false, false>(v, tw, lds, p.hy + m * N, p.hx + m * N, line, j);
+            if (m + 1 < M) {
+                const int u = p.gap_table[m] * N;
+                propagate<N, false, false>(v, tw, lds, s_hy + u, s_hx + u, line, j);
+            }
         }
     }
 
@@ -283,8 +311,9 @@ __global__ __launch_bounds__(Win<N>::NT) void fused_kernel(FusedParams p)
             else apply_patch<N, false, true>(v, slice, H, W, oy, ox, line, j);
             if (m > 0) {
                 // G_{m-1}^H: start on the axis this layout owns (the last one of the forward step)
-                if (row) propagate<N, true, true>(v, tw, lds, p.hy + (m - 1) * N, p.hx + (m - 1) * N, line, j);
-                else propagate<N, false, true>(v, tw, lds, p.hy + (m - 1) * N, p.hx + (m - 1) * N, line, j);
+                const int u = p.gap_table[m - 1] * N;
+                if (row) propagate<N, true, true>(v, tw, lds, s_hy + u, s_hx + u, line, j);
+                else propagate<N, false, true>(v, tw, lds, s_hy + u, s_hx + u, line, j);
             }
         }
         if constexpr (MODE == kAdjoint || MODE == kProbe) {
@@ -430,8 +459,10 @@ __global__ __launch_bounds__(Win<N>::NT) void window_filter_kernel(const float2 
         store_window<N, true>(v, dst, line, j);
         return;
     }
-    const float2 *tw = twg;
-    propagate<N, true, CONJ>(v, tw, lds, my + (size_t)c * N, mx + (size_t)c * N, line, j);
+    __shared__ float2 s_tw[N];
+    stage<N>(s_tw, twg, N);
+    __syncthreads();
+    propagate<N, true, CONJ>(v, s_tw, lds, my + (size_t)c * N, mx + (size_t)c * N, line, j);
     store_window<N, false>(v, dst, line, j);
 }
 
@@ -449,7 +480,10 @@ __global__ __launch_bounds__(Win<N>::NT) void make_probe_kernel(float2 *out, con
     __shared__ double total;
     const int line = threadIdx.x / R, j = threadIdx.x % R;
     const double PI = 3.14159265358979323846264338327950288;
-    const float2 *tw = twg;
+    __shared__ float2 s_tw[N];
+    stage<N>(s_tw, twg, N);
+    __syncthreads();
+    const float2 *tw = s_tw;
     const double nd = (double)N * dx;
     float2 v[16];
     // ROW layout, spectral along x: register i holds frequency (ky = line, kx = spec(j, i))

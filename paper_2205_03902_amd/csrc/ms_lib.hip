@@ -70,6 +70,8 @@ struct HostPlan {
     int nb = 0, tiles_x = 0, tiles_y = 0, n_tiles = 0;
     std::vector<int4> pos_info;
     std::vector<double> cls_fy, cls_fx;
+    std::vector<double> dz_unique;            // distinct slice distances
+    std::vector<int> gap_table;               // M - 1 entries: index into dz_unique
     // Scatter lists.  Each batch is cut into at most kChunks chunks of consecutive
     // positions; per (batch, chunk, tile) the entries (batch-local s, origin y, origin x)
     // of the windows that touch the tile, per (batch, chunk, class) its positions.
@@ -120,6 +122,28 @@ void derive_positions(const ms_problem *pb, HostPlan &hp)
         hp.pos_info[s] = make_int4((int)iy, (int)ix, c, 0);
     }
     hp.C = (int)hp.cls_fy.size();
+    hp.gap_table.assign(std::max(hp.M - 1, 1), 0);
+    for (int g = 0; g + 1 < hp.M; ++g) {
+        auto it = std::find(hp.dz_unique.begin(), hp.dz_unique.end(), pb->dz[g]);
+        if (it == hp.dz_unique.end()) {
+            hp.gap_table[g] = (int)hp.dz_unique.size();
+            hp.dz_unique.push_back(pb->dz[g]);
+        } else {
+            hp.gap_table[g] = (int)(it - hp.dz_unique.begin());
+        }
+    }
+    if (hp.dz_unique.empty()) hp.dz_unique.push_back(0.0);
+}
+
+// Distinct slice distances the fused kernel keeps in LDS (HCap in ms_kernels.hpp).
+int table_capacity(int n)
+{
+    switch (n) {
+        case 16: return HCap<16>::U;
+        case 32: return HCap<32>::U;
+        case 64: return HCap<64>::U;
+        default: return HCap<128>::U;
+    }
 }
 
 bool too_many_classes(const HostPlan &hp) { return hp.C > kMaxClasses; }
@@ -205,7 +229,7 @@ size_t tile_entries(const HostPlan &hp)
 
 // Workspace layout.  Every region is 256-byte aligned.
 struct Layout {
-    size_t tw, hy, hx, ry, rx, ident, pos_info, pos_list, sub_list;
+    size_t tw, hy, hx, gap_table, ry, rx, ident, pos_info, pos_list, sub_list;
     size_t class_probe, class_acc, class_tmp, gp, layer_g, layer_w, maxt2, partial, maxw, scal;
     size_t tile_off, tile_list, class_off, class_list, sub_class_off, sub_class_list;
     size_t spart, wpart, cpart;
@@ -222,8 +246,9 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += align_up(std::max<size_t>(bytes, 1)); return r; };
     L.tw = take(n * 8);
-    L.hy = take(gaps * n * 8);
-    L.hx = take(gaps * n * 8);
+    L.hy = take(hp.dz_unique.size() * n * 8);
+    L.hx = take(hp.dz_unique.size() * n * 8);
+    L.gap_table = take(gaps * 4);
     L.ry = take(C * n * 8);
     L.rx = take(C * n * 8);
     L.ident = take(C * 4);
@@ -378,6 +403,8 @@ FusedParams fused_params(ms_plan *p, const ms_c64 *slices, const float *measured
     fp.tw = p->at<float2>(p->L.tw);
     fp.hy = p->at<float2>(p->L.hy);
     fp.hx = p->at<float2>(p->L.hx);
+    fp.gap_table = p->at<int>(p->L.gap_table);
+    fp.n_tables = (int)hp.dz_unique.size();
     fp.measured = measured;
     fp.waves = p->at<float2>(p->L.waves);
     fp.probe_patch = p->at<float2>(p->L.probe_patch);
@@ -458,6 +485,8 @@ ms_status ms_workspace_size(const ms_problem *pb, size_t budget_bytes, size_t *w
         derive_positions(pb, hp);
         if (too_many_classes(hp))
             return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(kMaxClasses) + " distinct sub-pixel offsets");
+        if ((int)hp.dz_unique.size() > table_capacity(hp.n))
+            return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(table_capacity(hp.n)) + " distinct slice distances");
         size_t ne = tile_entries(hp);
         int64_t B = choose_batch(hp, ne, budget_bytes);
         if (B < 1) return fail(MS_ERR_BUDGET, "budget too small for a single position");
@@ -486,6 +515,10 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
             delete p;
             return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(kMaxClasses) + " distinct sub-pixel offsets");
         }
+        if ((int)hp.dz_unique.size() > table_capacity(hp.n)) {
+            delete p;
+            return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(table_capacity(hp.n)) + " distinct slice distances");
+        }
         size_t ne = tile_entries(hp);
         int64_t B = choose_batch(hp, ne, ws_bytes);
         if (B < 1) { delete p; return fail(MS_ERR_BUDGET, "workspace too small for a single position"); }
@@ -497,7 +530,7 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
         p->dx = pb->pixel_size; p->lambda = pb->wavelength; p->tilt_y = pb->tilt_y; p->tilt_x = pb->tilt_x;
 
         // Tables, computed in FP64 and rounded once.
-        const int n = hp.n, M = hp.M, C = hp.C;
+        const int n = hp.n, C = hp.C;
         const double PI = 3.14159265358979323846264338327950288;
         std::vector<float2> tw(n);
         for (int t = 0; t < n; ++t) {
@@ -505,10 +538,10 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
             tw[t] = make_float2((float)std::cos(a), (float)std::sin(a));
         }
         auto freq = [&](int i) { return (double)(i < (n + 1) / 2 ? i : i - n); };
-        const int gaps = std::max(M - 1, 1);
-        std::vector<float2> hy((size_t)gaps * n, make_float2(0.f, 0.f)), hx((size_t)gaps * n, make_float2(0.f, 0.f));
-        for (int g = 0; g + 1 < M; ++g) {
-            double dz = pb->dz[g];
+        const int U = (int)hp.dz_unique.size();
+        std::vector<float2> hy((size_t)U * n), hx((size_t)U * n);
+        for (int g = 0; g < U; ++g) {
+            double dz = hp.dz_unique[g];
             for (int i = 0; i < n; ++i) {
                 double q = freq(i) / ((double)n * pb->pixel_size);
                 // eq. (fresnel_element) split per axis: exp(-pi i dz (lambda q^2 + 2 q sin(theta)))
@@ -538,6 +571,7 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
         };
         bool ok = up(p->L.tw, tw.data(), tw.size() * 8) && up(p->L.hy, hy.data(), hy.size() * 8) &&
                   up(p->L.hx, hx.data(), hx.size() * 8) && up(p->L.ry, ry.data(), ry.size() * 8) &&
+                  up(p->L.gap_table, hp.gap_table.data(), hp.gap_table.size() * 4) &&
                   up(p->L.rx, rx.data(), rx.size() * 8) && up(p->L.ident, ident.data(), ident.size() * 4) &&
                   up(p->L.pos_info, hp.pos_info.data(), hp.pos_info.size() * 16) &&
                   up(p->L.pos_list, pos_list.data(), pos_list.size() * 4) &&
