@@ -165,6 +165,8 @@ struct Win {
     static constexpr int LDS_WORDS = N * LD;            // complex values of LDS per window
     static constexpr int SWZ = (N == 64) ? 5 : 9;       // transpose swizzle multiplier
     __device__ static __forceinline__ int tpos(int y, int x) { return y * N + (x ^ ((SWZ * y) & 15)); }
+    // twiddle table: W_N^{j k1} at j * 17 + k1 (rows padded to 17 so the lanes of a line hit distinct banks)
+    static constexpr int TW_WORDS = R * 17;
     // natural position of register k along the owned axis
     __device__ static __forceinline__ int nat(int j, int k) { return j + R * k; }
     // frequency held by register i in spectral order
@@ -172,7 +174,7 @@ struct Win {
 };
 
 // Forward DFT (unnormalised) of the line owned by lanes j = 0..R-1; natural -> spectral.
-// twg[t] = W_N^t (the lane uses W_N^{j k1}); xb is the line's LDS slot (N complex values).
+// twg[j * 17 + k1] = W_N^{j k1}; xb is the line's LDS slot (N complex values).
 template <int N>
 __device__ __forceinline__ void line_fft_fwd(float2 (&v)[16], const float2 *twg, float2 *xb, int j)
 {
@@ -181,7 +183,7 @@ __device__ __forceinline__ void line_fft_fwd(float2 (&v)[16], const float2 *twg,
     if constexpr (R > 1) {
         j = opaque(j);
 #pragma unroll
-        for (int k1 = 1; k1 < 16; ++k1) tw[k1] = twg[j * k1];
+        for (int k1 = 1; k1 < 16; ++k1) tw[k1] = twg[j * 17 + k1];
     }
     dft16<false>(v);
     if constexpr (R > 1) {
@@ -209,7 +211,7 @@ __device__ __forceinline__ void line_fft_inv(float2 (&v)[16], const float2 *twg,
         j = opaque(j);
         float2 tw[16];
 #pragma unroll
-        for (int k1 = 1; k1 < 16; ++k1) tw[k1] = twg[j * k1];
+        for (int k1 = 1; k1 < 16; ++k1) tw[k1] = twg[j * 17 + k1];
 #pragma unroll
         for (int u = 0; u < G; ++u) dft_small<R, true>(&v[u * R]);
 #pragma unroll

@@ -31,7 +31,7 @@ struct FusedParams {
     const float2 *slices;        // [M][H][W]
     const int4 *pos_info;        // [S] (patch origin y in [0,H), x in [0,W), shift class, 0)
     const int *pos_list;         // [count] global position index of each workgroup
-    const float2 *tw;            // [N] W_N^t
+    const float2 *tw;            // [R][17] W_N^{j k1}
     const float2 *hy, *hx;       // [U][N] propagator factors of the distinct distances, divided by N
     const int *gap_table;        // [M-1] which of the U distinct distances each gap uses
     int n_tables;                // U <= HCap<N>::U
@@ -79,27 +79,32 @@ __device__ __forceinline__ void apply_patch(float2 (&v)[16], const float2 *slice
                                             int ox, int line, int j)
 {
     using Wn = Win<N>;
+    constexpr int R = Wn::R;
     line = opaque(line);
     j = opaque(j);
+    // 32-bit element offsets (H W <= 2^30): a step of R along the owned axis adds a constant,
+    // and crossing the object edge subtracts one period.
     if (ROW) {
         int yy = oy + line;
         if (yy >= H) yy -= H;
-        const float2 *row = slice + (size_t)yy * W;
+        const unsigned row = (unsigned)(yy * W);
+        const int x0 = ox + j;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            int xx = ox + Wn::nat(j, k);
-            if (xx >= W) xx -= W;
-            float2 t = row[xx];
+            const int xx = x0 + R * k;
+            const unsigned off = row + (unsigned)(xx >= W ? xx - W : xx);
+            float2 t = slice[off];
             v[k] = CONJ ? cconjmul(t, v[k]) : cmul(v[k], t);
         }
     } else {
         int xx = ox + line;
         if (xx >= W) xx -= W;
+        const int y0 = oy + j;
+        const unsigned base = (unsigned)(y0 * W + xx), wrap = (unsigned)(H * W), step = (unsigned)(R * W);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            int yy = oy + Wn::nat(j, k);
-            if (yy >= H) yy -= H;
-            float2 t = slice[(size_t)yy * W + xx];
+            const unsigned off = base + step * k - ((y0 + R * k >= H) ? wrap : 0u);
+            float2 t = slice[off];
             v[k] = CONJ ? cconjmul(t, v[k]) : cmul(v[k], t);
         }
     }
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
     constexpr int R = Wn::R;
     constexpr size_t NN = (size_t)N * N;
     __shared__ float2 lds[Wn::LDS_WORDS];
-    __shared__ float2 s_tw[N];
+    __shared__ float2 s_tw[Wn::TW_WORDS];
     __shared__ float2 s_hy[HCap<N>::U * N], s_hx[HCap<N>::U * N];
     __shared__ double red[(Wn::NT + 63) / 64];
 
@@ -209,7 +214,7 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
     const int H = p.H, W = p.W, M = p.M;
 
     // twiddles and propagator factors live in LDS for the whole chain
-    stage<N>(s_tw, p.tw, N);
+    stage<N>(s_tw, p.tw, Wn::TW_WORDS);
     stage<N>(s_hy, p.hy, p.n_tables * N);
     stage<N>(s_hx, p.hx, p.n_tables * N);
     __syncthreads();
@@ -459,8 +464,8 @@ __global__ __launch_bounds__(Win<N>::NT) void window_filter_kernel(const float2 
         store_window<N, true>(v, dst, line, j);
         return;
     }
-    __shared__ float2 s_tw[N];
-    stage<N>(s_tw, twg, N);
+    __shared__ float2 s_tw[Wn::TW_WORDS];
+    stage<N>(s_tw, twg, Wn::TW_WORDS);
     __syncthreads();
     propagate<N, true, CONJ>(v, s_tw, lds, my + (size_t)c * N, mx + (size_t)c * N, line, j);
     store_window<N, false>(v, dst, line, j);
@@ -480,8 +485,8 @@ __global__ __launch_bounds__(Win<N>::NT) void make_probe_kernel(float2 *out, con
     __shared__ double total;
     const int line = threadIdx.x / R, j = threadIdx.x % R;
     const double PI = 3.14159265358979323846264338327950288;
-    __shared__ float2 s_tw[N];
-    stage<N>(s_tw, twg, N);
+    __shared__ float2 s_tw[Wn::TW_WORDS];
+    stage<N>(s_tw, twg, Wn::TW_WORDS);
     __syncthreads();
     const float2 *tw = s_tw;
     const double nd = (double)N * dx;

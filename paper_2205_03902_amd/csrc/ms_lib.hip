@@ -245,7 +245,7 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     const size_t nb = (size_t)((S + B - 1) / B);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += align_up(std::max<size_t>(bytes, 1)); return r; };
-    L.tw = take(n * 8);
+    L.tw = take((n / 16) * 17 * 8);
     L.hy = take(hp.dz_unique.size() * n * 8);
     L.hx = take(hp.dz_unique.size() * n * 8);
     L.gap_table = take(gaps * 4);
@@ -532,11 +532,14 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
         // Tables, computed in FP64 and rounded once.
         const int n = hp.n, C = hp.C;
         const double PI = 3.14159265358979323846264338327950288;
-        std::vector<float2> tw(n);
-        for (int t = 0; t < n; ++t) {
-            double a = -2.0 * PI * t / n;
-            tw[t] = make_float2((float)std::cos(a), (float)std::sin(a));
-        }
+        // twiddles W_N^{j k1} of lane j, rows of 17 (see Win::TW_WORDS)
+        const int R = n / 16;
+        std::vector<float2> tw((size_t)R * 17, make_float2(1.f, 0.f));
+        for (int j = 0; j < R; ++j)
+            for (int k1 = 0; k1 < 16; ++k1) {
+                double a = -2.0 * PI * (double)(j * k1) / n;
+                tw[(size_t)j * 17 + k1] = make_float2((float)std::cos(a), (float)std::sin(a));
+            }
         auto freq = [&](int i) { return (double)(i < (n + 1) / 2 ? i : i - n); };
         const int U = (int)hp.dz_unique.size();
         std::vector<float2> hy((size_t)U * n), hx((size_t)U * n);
