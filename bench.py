@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the sweep and forward timings")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="positions per batch (0 = all at once); sets the plan's workspace budget")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -144,7 +146,17 @@ def main():
     torch.cuda.set_device(dev)
     log(f"bench: {geo.name} N={geo.n} H=W={geo.obj_h} M={geo.n_slices} S={geo.n_pos}")
 
-    plan = abi.Plan.from_geometry(geo, device=dev)
+    budget = 0
+    if args.batch and args.batch < geo.n_pos:
+        # workspace of a plan whose batches hold args.batch positions
+        pb, keep = abi.make_problem(geo.n, geo.obj_h, geo.obj_w, geo.n_slices, geo.positions(), geo.gaps(),
+                                    geo.pixel_size, geo.wavelength)
+        full = abi.workspace_size(pb)
+        n2 = geo.n * geo.n
+        per_pos = geo.n_slices * n2 * 8 + n2 * 8 + n2 * 4 + 8
+        budget = full - (geo.n_pos - args.batch) * per_pos
+    plan = abi.Plan.from_geometry(geo, budget_bytes=budget, device=dev)
+    log(f"bench: {plan.batch} positions per batch")
     probe_true = plan.make_probe(geo.alpha, geo.defocus)
     truth = torch.from_numpy(synth.transmissions(synth.specimen(geo))).to(dev)
     inten = plan.forward(probe_true, truth)

@@ -173,18 +173,23 @@ struct Win {
     __device__ static __forceinline__ int spec(int j, int i) { return (j * G + i / R) + 16 * (i % R); }
 };
 
-// Forward DFT (unnormalised) of the line owned by lanes j = 0..R-1; natural -> spectral.
-// twg[j * 17 + k1] = W_N^{j k1}; xb is the line's LDS slot (N complex values).
+// Twiddles W_N^{j k1}, k1 = 1..15, of lane j from the table twg[j * 17 + k1].
 template <int N>
-__device__ __forceinline__ void line_fft_fwd(float2 (&v)[16], const float2 *twg, float2 *xb, int j)
+__device__ __forceinline__ void load_twiddles(float2 (&tw)[16], const float2 *twg, int j)
 {
-    constexpr int R = Win<N>::R, G = Win<N>::G;
-    float2 tw[16];
-    if constexpr (R > 1) {
+    if constexpr (Win<N>::R > 1) {
         j = opaque(j);
 #pragma unroll
         for (int k1 = 1; k1 < 16; ++k1) tw[k1] = twg[j * 17 + k1];
     }
+}
+
+// Forward DFT (unnormalised) of the line owned by lanes j = 0..R-1; natural -> spectral.
+// tw from load_twiddles; xb is the line's LDS slot (N complex values).
+template <int N>
+__device__ __forceinline__ void line_fft_fwd(float2 (&v)[16], const float2 (&tw)[16], float2 *xb, int j)
+{
+    constexpr int R = Win<N>::R, G = Win<N>::G;
     dft16<false>(v);
     if constexpr (R > 1) {
 #pragma unroll
@@ -204,14 +209,10 @@ __device__ __forceinline__ void line_fft_fwd(float2 (&v)[16], const float2 *twg,
 
 // Inverse DFT without the 1/N factor; spectral -> natural.
 template <int N>
-__device__ __forceinline__ void line_fft_inv(float2 (&v)[16], const float2 *twg, float2 *xb, int j)
+__device__ __forceinline__ void line_fft_inv(float2 (&v)[16], const float2 (&tw)[16], float2 *xb, int j)
 {
     constexpr int R = Win<N>::R, G = Win<N>::G;
     if constexpr (R > 1) {
-        j = opaque(j);
-        float2 tw[16];
-#pragma unroll
-        for (int k1 = 1; k1 < 16; ++k1) tw[k1] = twg[j * 17 + k1];
 #pragma unroll
         for (int u = 0; u < G; ++u) dft_small<R, true>(&v[u * R]);
 #pragma unroll
@@ -226,6 +227,23 @@ __device__ __forceinline__ void line_fft_inv(float2 (&v)[16], const float2 *twg,
         for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmulc(v[k1], tw[k1]);
     }
     dft16<true>(v);
+}
+
+// Same with the twiddles read from the table on the way (short register lifetime).
+template <int N>
+__device__ __forceinline__ void line_fft_fwd(float2 (&v)[16], const float2 *twg, float2 *xb, int j)
+{
+    float2 tw[16];
+    load_twiddles<N>(tw, twg, j);
+    line_fft_fwd<N>(v, tw, xb, j);
+}
+
+template <int N>
+__device__ __forceinline__ void line_fft_inv(float2 (&v)[16], const float2 *twg, float2 *xb, int j)
+{
+    float2 tw[16];
+    load_twiddles<N>(tw, twg, j);
+    line_fft_inv<N>(v, tw, xb, j);
 }
 
 // Moves the window between the two layouts through LDS.  ROW: lane (line = y, j)

@@ -113,7 +113,7 @@ __device__ __forceinline__ void apply_patch(float2 (&v)[16], const float2 *slice
 // One Fresnel propagation V_z (or its adjoint G^H when CONJ), starting in layout ROW
 // and ending in the other layout.  hy/hx carry the 1/N factors of both inverse DFTs.
 template <int N, bool ROW, bool CONJ>
-__device__ __forceinline__ void propagate(float2 (&v)[16], const float2 *tw, float2 *lds, const float2 *hy,
+__device__ __forceinline__ void propagate(float2 (&v)[16], const float2 *twg, float2 *lds, const float2 *hy,
                                           const float2 *hx, int line, int j)
 {
     using Wn = Win<N>;
@@ -122,21 +122,21 @@ __device__ __forceinline__ void propagate(float2 (&v)[16], const float2 *tw, flo
     float2 *xb = lds + line * Wn::LD;
     const float2 *h1 = ROW ? hx : hy;
     const float2 *h2 = ROW ? hy : hx;
-    line_fft_fwd<N>(v, tw, xb, j);
+    line_fft_fwd<N>(v, twg, xb, j);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         float2 h = h1[Wn::spec(j, i)];
         v[i] = CONJ ? cmulc(v[i], h) : cmul(v[i], h);
     }
-    line_fft_inv<N>(v, tw, xb, j);
+    line_fft_inv<N>(v, twg, xb, j);
     transpose<N, ROW, false, false>(v, lds, line, j);
-    line_fft_fwd<N>(v, tw, xb, j);
+    line_fft_fwd<N>(v, twg, xb, j);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         float2 h = h2[Wn::spec(j, i)];
         v[i] = CONJ ? cmulc(v[i], h) : cmul(v[i], h);
     }
-    line_fft_inv<N>(v, tw, xb, j);
+    line_fft_inv<N>(v, twg, xb, j);
 }
 
 template <int N>
