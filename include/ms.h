@@ -94,6 +94,15 @@ void ms_plan_destroy(ms_plan *plan);
 int64_t ms_plan_batch(const ms_plan *plan);
 int32_t ms_plan_shift_classes(const ms_plan *plan);
 
+/* How the per-position multislice chain is executed.  MS_PATH_FUSED keeps each
+ * N x N window of one position in one workgroup for the whole chain (N <= 128);
+ * MS_PATH_LINES runs one launch per slice, each workgroup holding 16 rows or 16
+ * columns of a window, with the half-propagated window in the workspace between
+ * launches (N >= 32; the only path for N = 256).  MS_PATH_AUTO (the default)
+ * takes the fused path whenever it fits.  Both compute the same quantities. */
+typedef enum { MS_PATH_AUTO = 0, MS_PATH_FUSED = 1, MS_PATH_LINES = 2 } ms_path;
+ms_status ms_plan_set_path(ms_plan *plan, int32_t path);
+
 /* The probe of Sec. 2.1 (caption of Fig. 3): the inverse DFT of the disk
  * lambda |q| <= alpha (boundary included), multiplied by the propagator of
  * eq. (fresnel_element) for distance `defocus`, centred at (N/2, N/2) and

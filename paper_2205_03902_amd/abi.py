@@ -17,9 +17,11 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libimsp.so")
 
 MS_OK, MS_ERR_INVALID_ARG, MS_ERR_UNSUPPORTED, MS_ERR_BUDGET, MS_ERR_HIP = 0, -1, -2, -3, -4
+MS_PATH_AUTO, MS_PATH_FUSED, MS_PATH_LINES = 0, 1, 2
 
 # every entry point declared in include/ms.h
 SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
+           "ms_plan_set_path",
            "ms_make_probe", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_probe_step", "ms_profile_begin",
            "ms_profile_end", "ms_last_error")
 
@@ -59,6 +61,8 @@ def lib():
         L.ms_plan_batch.argtypes = [P]
         L.ms_plan_shift_classes.restype = I32
         L.ms_plan_shift_classes.argtypes = [P]
+        L.ms_plan_set_path.restype = I32
+        L.ms_plan_set_path.argtypes = [P, I32]
         L.ms_make_probe.restype = I32
         L.ms_make_probe.argtypes = [P, P, D, D, P]
         L.ms_forward.restype = I32
@@ -172,6 +176,10 @@ class Plan:
 
     def _patterns(self, t, name="measured"):
         self._expect(t, (self.n_pos, self.n, self.n), _torch().float32, name)
+
+    def set_path(self, path: int):
+        """MS_PATH_AUTO, MS_PATH_FUSED or MS_PATH_LINES (see include/ms.h)."""
+        _check(lib().ms_plan_set_path(self._h, int(path)), "ms_plan_set_path")
 
     # -- kernel timing ---------------------------------------------------------
     def profile_begin(self, max_launches: int):

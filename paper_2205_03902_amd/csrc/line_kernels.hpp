@@ -1,0 +1,341 @@
+// Line-resident multislice kernels for windows too large for one workgroup
+// (N = 256: a 256 x 256 complex window is 512 KB, beyond the LDS and the
+// register file of a CU).  A workgroup owns 16 lines (rows or columns) of one
+// position; each line is held by R = N/16 lanes of one wavefront exactly as in
+// the fused kernel.  Between launches the half-propagated window lives in a
+// per-position buffer A in global memory (L2/MALL-resident for a batch).
+//
+// The Fresnel propagator factorises over the two axes, so a propagation is a
+// row pass and a column pass that commute.  Launch m works in layout L_m (rows
+// for even m, columns for odd m): it finishes the propagation of gap m-1 along
+// its own axis, which yields the incident wave psi_m, applies slice m, and
+// starts the propagation of gap m along the same axis.  The next launch, in the
+// other layout, finishes it.  One global round trip per slice.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_lines.hpp"
+#include "ms_kernels.hpp"
+
+namespace imsp {
+
+constexpr int kLinesPerGroup = 16;
+
+enum LineStage : int {
+    kStageForward = 0,   // forward launch for slice m
+    kStageFar = 1,       // second axis of the far-field FFT, residual (or intensities), first inverse axis
+    kStageAdjoint = 2    // adjoint launch for slice m
+};
+
+struct LineParams {
+    const float2 *class_probe;   // [C][N][N]
+    const float2 *slices;        // [M][H][W]
+    const int4 *pos_info;        // [S]
+    const int *pos_list;         // [count]
+    const float2 *tw;            // [R][17]
+    const float2 *hy, *hx;       // [U][N] (divided by N)
+    const int *gap_table;        // [M-1]
+    const float *measured;       // [S][N][N]
+    float *intensity;            // [S][N][N] (forward mode)
+    float2 *exit_waves;          // [S][N][N] or null
+    float2 *A;                   // [count][N][N] half-propagated window
+    float2 *waves;               // [count][M][N][N] incident waves, then gradient patches (or null)
+    float2 *probe_patch;         // [count][N][N] or null
+    float *overlap_patch;        // [count][N][N] (layer mode)
+    double *loss_part;           // [count][N / 16]
+    int H, W, M, m;
+    int mode;                    // kForward / kAdjoint / kLayer / kProbe
+    int layer;                   // layer mode: the slice whose gradient is wanted
+};
+
+// Global-memory window access for a line group in either layout: lane (line, j) owns
+// along its axis the positions nat(j, k) (SPEC = false) or spec(j, i) (SPEC = true).
+template <int N, bool ROW, bool SPEC>
+__device__ __forceinline__ void gload(float2 (&v)[16], const float2 *src, int line, int j)
+{
+    using Wn = Win<N>;
+    line = opaque(line);
+    j = opaque(j);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int a = SPEC ? Wn::spec(j, i) : Wn::nat(j, i);
+        v[i] = ROW ? src[line * N + a] : src[a * N + line];
+    }
+}
+
+template <int N, bool ROW, bool SPEC>
+__device__ __forceinline__ void gstore(const float2 (&v)[16], float2 *dst, int line, int j)
+{
+    using Wn = Win<N>;
+    line = opaque(line);
+    j = opaque(j);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int a = SPEC ? Wn::spec(j, i) : Wn::nat(j, i);
+        if (ROW) dst[line * N + a] = v[i];
+        else dst[a * N + line] = v[i];
+    }
+}
+
+// 1D propagation along the owned axis with the factor table h (LDS), or its adjoint.
+template <int N, bool CONJ>
+__device__ __forceinline__ void prop_axis(float2 (&v)[16], const float2 *tw, float2 *xb, const float2 *h, int j)
+{
+    using Wn = Win<N>;
+    line_fft_fwd<N>(v, tw, xb, j);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        float2 f = h[Wn::spec(j, i)];
+        v[i] = CONJ ? cmulc(v[i], f) : cmul(v[i], f);
+    }
+    line_fft_inv<N>(v, tw, xb, j);
+}
+
+template <int N>
+__device__ __forceinline__ double group_sum(double x, double *red)
+{
+    constexpr int NT = kLinesPerGroup * Win<N>::R;
+    constexpr int NW = (NT + 63) / 64;
+    for (int off = (NT < 64 ? NT / 2 : 32); off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = x;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NW; ++i) t += red[i];
+    return t;
+}
+
+template <int N, bool ROW>
+__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LineParams p, int stage)
+{
+    using Wn = Win<N>;
+    constexpr int R = Wn::R;
+    constexpr int NT = kLinesPerGroup * R;
+    constexpr size_t NN = (size_t)N * N;
+    __shared__ float2 xbuf[kLinesPerGroup * Wn::LD];
+    __shared__ float2 s_tw[Wn::TW_WORDS];
+    __shared__ float2 s_h[2 * N];
+    __shared__ double red[(NT + 63) / 64];
+
+    const int tid = threadIdx.x;
+    const int lloc = tid / R, j = tid % R;
+    const int line = blockIdx.x * kLinesPerGroup + lloc;
+    const int b = blockIdx.y;
+    const int s = p.pos_list[b];
+    const int4 info = p.pos_info[s];
+    const int oy = info.x, ox = info.y, cls = info.z;
+    const int M = p.M, m = p.m;
+    const int mode = p.mode;
+    float2 *xb = xbuf + lloc * Wn::LD;
+    float2 *A = p.A + (size_t)b * NN;
+    float2 *wave = p.waves ? p.waves + (size_t)b * M * NN : nullptr;
+    const float2 *probe = p.class_probe + (size_t)cls * NN;
+    const float2 *hown = ROW ? p.hx : p.hy;
+
+    // tables for this launch: twiddles, the own-axis factor of the gap that is finished
+    // (s_h) and of the gap that is started (s_h + N)
+    for (int i = tid; i < Wn::TW_WORDS; i += NT) s_tw[i] = p.tw[i];
+    int g_fin = -1, g_start = -1;
+    if (stage == kStageForward) {
+        g_fin = m - 1;
+        g_start = (m + 1 < M) ? m : -1;
+    } else if (stage == kStageAdjoint) {
+        g_fin = (m + 1 < M) ? m : -1;
+        g_start = m - 1;
+    }
+    if (g_fin >= 0)
+        for (int i = tid; i < N; i += NT) s_h[i] = hown[p.gap_table[g_fin] * N + i];
+    if (g_start >= 0)
+        for (int i = tid; i < N; i += NT) s_h[N + i] = hown[p.gap_table[g_start] * N + i];
+    __syncthreads();
+
+    float2 v[16];
+    if (stage == kStageForward) {
+        // ---- psi_m: the probe, or the propagation of gap m-1 finished along this axis ----
+        if (m == 0) {
+            gload<N, ROW, false>(v, probe, line, j);
+        } else {
+            gload<N, ROW, false>(v, A, line, j);
+            prop_axis<N, false>(v, s_tw, xb, s_h, j);
+        }
+        const bool store = (mode == kAdjoint && m > 0) || (mode == kLayer && m == p.layer && m > 0);
+        if (store) gstore<N, ROW, false>(v, wave + m * NN, line, j);
+        if (mode == kLayer && m == p.layer) {
+            float *op = p.overlap_patch + (size_t)b * NN;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int a = Wn::nat(j, k);
+                op[ROW ? line * N + a : a * N + line] = cabs2(v[k]);
+            }
+        }
+        apply_patch<N, ROW, false>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, line, j);
+        if (m + 1 < M) {
+            prop_axis<N, false>(v, s_tw, xb, s_h + N, j);
+            gstore<N, ROW, false>(v, A, line, j);
+        } else {
+            if (mode == kForward && p.exit_waves) gstore<N, ROW, false>(v, p.exit_waves + (size_t)s * NN, line, j);
+            line_fft_fwd<N>(v, s_tw, xb, j);
+            gstore<N, ROW, true>(v, A, line, j);    // spectral along this axis, at natural frequency
+        }
+        return;
+    }
+
+    if (stage == kStageFar) {
+        // line index = frequency along the first axis (natural); FFT along this axis
+        gload<N, ROW, false>(v, A, line, j);
+        line_fft_fwd<N>(v, s_tw, xb, j);
+        if (mode == kForward) {
+            float *out = p.intensity + (size_t)s * NN;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int f = Wn::spec(j, i);
+                out[ROW ? line * N + f : f * N + line] = cabs2(v[i]);
+            }
+            return;
+        }
+        const float *meas = p.measured + (size_t)s * NN;
+        double part = residual<N, ROW>(v, meas, line, j);
+        double tot = group_sum<N>(part, red);
+        if (tid == 0) p.loss_part[(size_t)b * gridDim.x + blockIdx.x] = tot;
+        line_fft_inv<N>(v, s_tw, xb, j);
+        gstore<N, ROW, false>(v, A, line, j);
+        return;
+    }
+
+    // ---- adjoint launch for slice m ----
+    if (m + 1 == M) {
+        // finish F^H r along this axis: A holds it at natural frequency positions
+        gload<N, ROW, true>(v, A, line, j);
+        line_fft_inv<N>(v, s_tw, xb, j);
+    } else {
+        gload<N, ROW, false>(v, A, line, j);
+        prop_axis<N, true>(v, s_tw, xb, s_h, j);
+    }
+    const int m_stop = (mode == kLayer) ? p.layer : 0;
+    const bool patch = (mode == kAdjoint) || (mode == kLayer && m == p.layer);
+    if (patch) {
+        const float2 *psi = (m == 0) ? probe : wave + m * NN;
+        float2 *dst = wave + m * NN;
+        const int l2 = opaque(line), j2 = opaque(j);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int a = Wn::nat(j2, k);
+            const int idx = ROW ? l2 * N + a : a * N + l2;
+            dst[idx] = cconjmul(psi[idx], v[k]);
+        }
+    }
+    const bool go_on = (m > m_stop) || (mode != kLayer && m == 0);
+    if (!go_on) return;
+    apply_patch<N, ROW, true>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, line, j);
+    if (m > 0) {
+        prop_axis<N, true>(v, s_tw, xb, s_h + N, j);
+        gstore<N, ROW, false>(v, A, line, j);
+    } else if (p.probe_patch) {
+        gstore<N, ROW, false>(v, p.probe_patch + (size_t)b * NN, line, j);
+    }
+}
+
+}  // namespace imsp
+
+namespace imsp {
+
+// out[c] = in[c] filtered along one axis: F_a^{-1}(F_a in o t[c]) with t divided by N (CONJ: conj(t)),
+// for the sub-pixel probe shift done as a row pass and a column pass.  identity[c] copies.
+template <int N, bool ROW, bool CONJ>
+__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_filter_kernel(
+    const float2 *in, long long in_stride, float2 *out, const float2 *table, const int *identity, const float2 *twg)
+{
+    using Wn = Win<N>;
+    constexpr int R = Wn::R;
+    constexpr int NT = kLinesPerGroup * R;
+    constexpr size_t NN = (size_t)N * N;
+    __shared__ float2 xbuf[kLinesPerGroup * Wn::LD];
+    __shared__ float2 s_tw[Wn::TW_WORDS];
+    __shared__ float2 s_h[N];
+    const int tid = threadIdx.x;
+    const int lloc = tid / R, j = tid % R;
+    const int line = blockIdx.x * kLinesPerGroup + lloc;
+    const int c = blockIdx.y;
+    const float2 *src = in + (size_t)c * in_stride;
+    float2 *dst = out + (size_t)c * NN;
+    float2 v[16];
+    gload<N, ROW, false>(v, src, line, j);
+    if (identity[c]) {
+        gstore<N, ROW, false>(v, dst, line, j);
+        return;
+    }
+    for (int i = tid; i < Wn::TW_WORDS; i += NT) s_tw[i] = twg[i];
+    for (int i = tid; i < N; i += NT) s_h[i] = table[(size_t)c * N + i];
+    __syncthreads();
+    prop_axis<N, CONJ>(v, s_tw, xbuf + lloc * Wn::LD, s_h, j);
+    gstore<N, ROW, false>(v, dst, line, j);
+}
+
+// Probe (Sec. 2.1, Fig. 3) for line-resident windows.  Pass 1 (rows): the aperture
+// lambda |q| <= alpha times the defocus propagator times (-1)^(ky+kx), inverse DFT along x.
+// Pass 2 (columns): inverse DFT along y and FP64 energy partial per line group.
+// Pass 3: scale to unit energy.
+template <int N, bool ROW>
+__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_probe_kernel(
+    float2 *out, double *energy_part, const float2 *twg, double dx, double lambda, double alpha, double defocus)
+{
+#pragma clang fp contract(off)
+    using Wn = Win<N>;
+    constexpr int R = Wn::R;
+    constexpr int NT = kLinesPerGroup * R;
+    __shared__ float2 xbuf[kLinesPerGroup * Wn::LD];
+    __shared__ float2 s_tw[Wn::TW_WORDS];
+    __shared__ double red[(NT + 63) / 64];
+    const int tid = threadIdx.x;
+    const int lloc = tid / R, j = tid % R;
+    const int line = blockIdx.x * kLinesPerGroup + lloc;
+    for (int i = tid; i < Wn::TW_WORDS; i += NT) s_tw[i] = twg[i];
+    __syncthreads();
+    float2 *xb = xbuf + lloc * Wn::LD;
+    float2 v[16];
+    if (ROW) {
+        const double PI = 3.14159265358979323846264338327950288;
+        const double nd = (double)N * dx;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int iy = line, ix = Wn::spec(j, i);
+            const int ky = iy < N / 2 ? iy : iy - N;
+            const int kx = ix < N / 2 ? ix : ix - N;
+            const double qy = (double)ky / nd, qx = (double)kx / nd;
+            const double q2 = qy * qy + qx * qx;
+            float2 a = make_float2(0.f, 0.f);
+            if (lambda * sqrt(q2) <= alpha) {
+                const double ph = -PI * defocus * lambda * q2;
+                const double sgn = ((iy + ix) & 1) ? -1.0 : 1.0;
+                a = make_float2((float)(sgn * cos(ph)), (float)(sgn * sin(ph)));
+            }
+            v[i] = a;
+        }
+        line_fft_inv<N>(v, s_tw, xb, j);
+        gstore<N, true, false>(v, out, line, j);
+    } else {
+        gload<N, false, true>(v, out, line, j);
+        line_fft_inv<N>(v, s_tw, xb, j);
+        double e = 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) e += (double)v[i].x * v[i].x + (double)v[i].y * v[i].y;
+        double t = group_sum<N>(e, red);
+        if (tid == 0) energy_part[blockIdx.x] = t;
+        gstore<N, false, false>(v, out, line, j);
+    }
+}
+
+// x *= 1 / sqrt(sum of the energy partials), the partials summed in order.
+__global__ __launch_bounds__(256) void scale_unit_energy_kernel(float2 *x, long long count, const double *part,
+                                                                int n_part)
+{
+    double e = 0.0;
+    for (int i = 0; i < n_part; ++i) e += part[i];
+    const float sc = (float)(1.0 / sqrt(e));
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long long)gridDim.x * 256)
+        x[i] = make_float2(x[i].x * sc, x[i].y * sc);
+}
+
+}  // namespace imsp

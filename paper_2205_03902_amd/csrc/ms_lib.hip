@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "ms.h"
+#include "line_kernels.hpp"
 #include "ms_kernels.hpp"
 
 using namespace imsp;
@@ -33,7 +34,10 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-bool supported_n(int n) { return n == 16 || n == 32 || n == 64 || n == 128; }
+bool supported_n(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
+
+// Windows up to 128 fit one workgroup (fused kernel); larger ones use the line kernels.
+bool fused_fits(int n) { return n <= 128; }
 
 ms_status validate(const ms_problem *pb)
 {
@@ -142,7 +146,8 @@ int table_capacity(int n)
         case 16: return HCap<16>::U;
         case 32: return HCap<32>::U;
         case 64: return HCap<64>::U;
-        default: return HCap<128>::U;
+        case 128: return HCap<128>::U;
+        default: return 1 << 30;   // the line kernels stage the two tables each launch needs
     }
 }
 
@@ -233,7 +238,7 @@ struct Layout {
     size_t class_probe, class_acc, class_tmp, gp, layer_g, layer_w, maxt2, partial, maxw, scal;
     size_t tile_off, tile_list, class_off, class_list, sub_class_off, sub_class_list;
     size_t spart, wpart, cpart;
-    size_t waves, probe_patch, overlap, loss_pos;
+    size_t waves, probe_patch, overlap, loss_pos, half, loss_part, energy;
     size_t total;
 };
 
@@ -279,6 +284,11 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     L.probe_patch = take((size_t)B * NN * 8);
     L.overlap = take((size_t)B * NN * 4);
     L.loss_pos = take((size_t)B * 8);
+    // line kernels: the half-propagated window per position and per-line-group partials
+    const bool lines_possible = hp.n >= 32;
+    L.half = take(lines_possible ? (size_t)B * NN * 8 : 0);
+    L.loss_part = take(lines_possible ? (size_t)B * (n / 16) * 8 : 0);
+    L.energy = take((n / 16) * 8);
     L.total = o;
     return L;
 }
@@ -309,6 +319,7 @@ struct ms_plan {
     // optional timing of the fused kernel
     std::vector<hipEvent_t> ev_start, ev_stop;
     size_t ev_used = 0;
+    bool lines = false;   // line kernels instead of the fused per-position kernel
 
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -341,16 +352,76 @@ void launch_fused_raw(int n, int mode, const FusedParams &fp, int count, hipStre
         case 16: launch_fused_n<16>(mode, fp, count, st); break;
         case 32: launch_fused_n<32>(mode, fp, count, st); break;
         case 64: launch_fused_n<64>(mode, fp, count, st); break;
-        default: launch_fused_n<128>(mode, fp, count, st); break;
+        case 128: launch_fused_n<128>(mode, fp, count, st); break;
+        default: break;   // larger windows always take the line kernels
     }
 }
 
+template <int N>
+void launch_line(bool row, const LineParams &lp, int stage, int count, hipStream_t st)
+{
+    dim3 grid(N / kLinesPerGroup, count), block(kLinesPerGroup * Win<N>::R);
+    if (row) line_kernel<N, true><<<grid, block, 0, st>>>(lp, stage);
+    else line_kernel<N, false><<<grid, block, 0, st>>>(lp, stage);
+}
+
+void launch_line_n(int n, bool row, const LineParams &lp, int stage, int count, hipStream_t st)
+{
+    switch (n) {
+        case 32: launch_line<32>(row, lp, stage, count, st); break;
+        case 64: launch_line<64>(row, lp, stage, count, st); break;
+        case 128: launch_line<128>(row, lp, stage, count, st); break;
+        default: launch_line<256>(row, lp, stage, count, st); break;
+    }
+}
+
+// Forward launches m = 0..M-1 (layout of slice m: rows for even m), the far-field launch
+// in the other layout, then (unless forward-only) the adjoint launches m = M-1 .. m_stop.
+void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
+    LineParams lp{};
+    lp.class_probe = fp.class_probe; lp.slices = fp.slices; lp.pos_info = fp.pos_info; lp.pos_list = fp.pos_list;
+    lp.tw = fp.tw; lp.hy = fp.hy; lp.hx = fp.hx; lp.gap_table = fp.gap_table;
+    lp.measured = fp.measured; lp.intensity = fp.intensity; lp.exit_waves = fp.exit_waves;
+    lp.A = p->at<float2>(p->L.half);
+    lp.waves = fp.waves; lp.probe_patch = fp.probe_patch; lp.overlap_patch = fp.overlap_patch;
+    lp.loss_part = p->at<double>(p->L.loss_part);
+    lp.H = hp.H; lp.W = hp.W; lp.M = hp.M; lp.mode = mode; lp.layer = fp.layer;
+    const int M = hp.M;
+    for (int m = 0; m < M; ++m) {
+        lp.m = m;
+        launch_line_n(hp.n, (m & 1) == 0, lp, kStageForward, count, st);
+    }
+    lp.m = M - 1;
+    launch_line_n(hp.n, ((M - 1) & 1) != 0, lp, kStageFar, count, st);
+    if (mode == kForward) return;
+    const int m_stop = (mode == kLayer) ? fp.layer : 0;
+    for (int m = M - 1; m >= m_stop; --m) {
+        lp.m = m;
+        launch_line_n(hp.n, (m & 1) == 0, lp, kStageAdjoint, count, st);
+    }
+}
+
+// All per-position work of one batch, with optional timing.
 void launch_fused(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream_t st)
 {
     const bool timed = p->ev_used < p->ev_start.size();
     if (timed) (void)hipEventRecord(p->ev_start[p->ev_used], st);
-    launch_fused_raw(p->hp.n, mode, fp, count, st);
+    if (p->lines) run_lines(p, mode, fp, count, st);
+    else launch_fused_raw(p->hp.n, mode, fp, count, st);
     if (timed) (void)hipEventRecord(p->ev_stop[p->ev_used++], st);
+}
+
+// Per-position losses of the last batch: where they are and how many.
+const double *loss_entries(ms_plan *p, int count, int *n_entries)
+{
+    if (p->lines) {
+        *n_entries = count * (p->hp.n / kLinesPerGroup);
+        return p->at<double>(p->L.loss_part);
+    }
+    *n_entries = count;
+    return p->at<double>(p->L.loss_pos);
 }
 
 template <int N>
@@ -369,7 +440,30 @@ void launch_filter(int n, bool conj, const float2 *in, long long in_stride, floa
         case 16: launch_filter_n<16>(conj, in, in_stride, out, my, mx, ident, tw, count, st); break;
         case 32: launch_filter_n<32>(conj, in, in_stride, out, my, mx, ident, tw, count, st); break;
         case 64: launch_filter_n<64>(conj, in, in_stride, out, my, mx, ident, tw, count, st); break;
-        default: launch_filter_n<128>(conj, in, in_stride, out, my, mx, ident, tw, count, st); break;
+        case 128: launch_filter_n<128>(conj, in, in_stride, out, my, mx, ident, tw, count, st); break;
+        default: break;
+    }
+}
+
+template <int N>
+void launch_line_filter(bool row, bool conj, const float2 *in, long long in_stride, float2 *out,
+                        const float2 *table, const int *ident, const float2 *tw, int count, hipStream_t st)
+{
+    dim3 grid(N / kLinesPerGroup, count), block(kLinesPerGroup * Win<N>::R);
+    if (row && conj) line_filter_kernel<N, true, true><<<grid, block, 0, st>>>(in, in_stride, out, table, ident, tw);
+    else if (row) line_filter_kernel<N, true, false><<<grid, block, 0, st>>>(in, in_stride, out, table, ident, tw);
+    else if (conj) line_filter_kernel<N, false, true><<<grid, block, 0, st>>>(in, in_stride, out, table, ident, tw);
+    else line_filter_kernel<N, false, false><<<grid, block, 0, st>>>(in, in_stride, out, table, ident, tw);
+}
+
+void line_filter(int n, bool row, bool conj, const float2 *in, long long in_stride, float2 *out, const float2 *table,
+                 const int *ident, const float2 *tw, int count, hipStream_t st)
+{
+    switch (n) {
+        case 32: launch_line_filter<32>(row, conj, in, in_stride, out, table, ident, tw, count, st); break;
+        case 64: launch_line_filter<64>(row, conj, in, in_stride, out, table, ident, tw, count, st); break;
+        case 128: launch_line_filter<128>(row, conj, in, in_stride, out, table, ident, tw, count, st); break;
+        default: launch_line_filter<256>(row, conj, in, in_stride, out, table, ident, tw, count, st); break;
     }
 }
 
@@ -377,6 +471,15 @@ void launch_filter(int n, bool conj, const float2 *in, long long in_stride, floa
 void class_probes(ms_plan *p, const ms_c64 *probe, hipStream_t st)
 {
     const HostPlan &hp = p->hp;
+    if (p->lines) {
+        // x ramps on rows into class_tmp, then y ramps on columns into class_probe
+        line_filter(hp.n, true, false, reinterpret_cast<const float2 *>(probe), 0, p->at<float2>(p->L.class_tmp),
+                    p->at<float2>(p->L.rx), p->at<int>(p->L.ident), p->at<float2>(p->L.tw), hp.C, st);
+        line_filter(hp.n, false, false, p->at<float2>(p->L.class_tmp), (long long)hp.n * hp.n,
+                    p->at<float2>(p->L.class_probe), p->at<float2>(p->L.ry), p->at<int>(p->L.ident),
+                    p->at<float2>(p->L.tw), hp.C, st);
+        return;
+    }
     launch_filter(hp.n, false, reinterpret_cast<const float2 *>(probe), 0, p->at<float2>(p->L.class_probe),
                   p->at<float2>(p->L.ry), p->at<float2>(p->L.rx), p->at<int>(p->L.ident), p->at<float2>(p->L.tw),
                   hp.C, st);
@@ -460,6 +563,14 @@ void probe_gradient(ms_plan *p, float2 *out, hipStream_t st)
 {
     const HostPlan &hp = p->hp;
     const int nn = hp.n * hp.n;
+    if (p->lines) {
+        line_filter(hp.n, true, true, p->at<float2>(p->L.class_acc), nn, p->at<float2>(p->L.class_tmp),
+                    p->at<float2>(p->L.rx), p->at<int>(p->L.ident), p->at<float2>(p->L.tw), hp.C, st);
+        line_filter(hp.n, false, true, p->at<float2>(p->L.class_tmp), nn, p->at<float2>(p->L.class_acc),
+                    p->at<float2>(p->L.ry), p->at<int>(p->L.ident), p->at<float2>(p->L.tw), hp.C, st);
+        sum_classes_kernel<<<(nn + 255) / 256, 256, 0, st>>>(p->at<float2>(p->L.class_acc), hp.C, nn, out);
+        return;
+    }
     launch_filter(hp.n, true, p->at<float2>(p->L.class_acc), nn, p->at<float2>(p->L.class_tmp),
                   p->at<float2>(p->L.ry), p->at<float2>(p->L.rx), p->at<int>(p->L.ident), p->at<float2>(p->L.tw),
                   hp.C, st);
@@ -526,6 +637,7 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
         p->L = make_layout(hp, B, ne);
         if (p->L.total > ws_bytes) { delete p; return fail(MS_ERR_BUDGET, "workspace too small"); }
         p->ws = static_cast<char *>(workspace);
+        p->lines = !fused_fits(hp.n);
         p->ws_bytes = ws_bytes;
         p->dx = pb->pixel_size; p->lambda = pb->wavelength; p->tilt_y = pb->tilt_y; p->tilt_x = pb->tilt_x;
 
@@ -656,6 +768,28 @@ int64_t ms_plan_batch(const ms_plan *plan) { return plan ? plan->hp.B : 0; }
 
 int32_t ms_plan_shift_classes(const ms_plan *plan) { return plan ? plan->hp.C : 0; }
 
+ms_status ms_plan_set_path(ms_plan *p, int32_t path)
+{
+    g_err.clear();
+    if (!p) return fail(MS_ERR_INVALID_ARG, "plan is NULL");
+    const int n = p->hp.n;
+    switch (path) {
+        case MS_PATH_AUTO:
+            p->lines = !fused_fits(n);
+            return MS_OK;
+        case MS_PATH_FUSED:
+            if (!fused_fits(n)) return fail(MS_ERR_UNSUPPORTED, "the fused kernel holds windows up to 128 x 128");
+            p->lines = false;
+            return MS_OK;
+        case MS_PATH_LINES:
+            if (n < 32) return fail(MS_ERR_UNSUPPORTED, "the line kernels need n >= 32");
+            p->lines = true;
+            return MS_OK;
+        default:
+            return fail(MS_ERR_INVALID_ARG, "unknown path");
+    }
+}
+
 ms_status ms_make_probe(ms_plan *p, hipStream_t st, double alpha, double defocus, ms_c64 *probe_out)
 {
     g_err.clear();
@@ -665,6 +799,16 @@ ms_status ms_make_probe(ms_plan *p, hipStream_t st, double alpha, double defocus
         return fail(MS_ERR_INVALID_ARG, "alpha must be positive, both finite");
     float2 *out = reinterpret_cast<float2 *>(probe_out);
     const float2 *tw = p->at<float2>(p->L.tw);
+    if (p->hp.n == 256) {
+        // rows: aperture and inverse DFT along x; columns: inverse DFT along y; unit energy
+        constexpr int N = 256, G = N / kLinesPerGroup;
+        double *part = p->at<double>(p->L.energy);
+        dim3 grid(G, 1), block(kLinesPerGroup * Win<N>::R);
+        line_probe_kernel<N, true><<<grid, block, 0, st>>>(out, part, tw, p->dx, p->lambda, alpha, defocus);
+        line_probe_kernel<N, false><<<grid, block, 0, st>>>(out, part, tw, p->dx, p->lambda, alpha, defocus);
+        scale_unit_energy_kernel<<<64, 256, 0, st>>>(out, (long long)N * N, part, G);
+        return check_hip("ms_make_probe");
+    }
     switch (p->hp.n) {
         case 16: make_probe_kernel<16><<<1, Win<16>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, defocus); break;
         case 32: make_probe_kernel<32><<<1, Win<32>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, defocus); break;
@@ -719,7 +863,11 @@ ms_status ms_adjoint(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c
         if (grad_probe)
             class_sums(p, p->at<int>(p->L.class_off) + (size_t)b * kChunks * (hp.C + 1), p->at<int>(p->L.class_list),
                        count, b > 0, st);
-        loss_sum_kernel<<<1, 256, 0, st>>>(p->at<double>(p->L.loss_pos), count, total, b > 0);
+        {
+            int n_loss;
+            const double *lsrc = loss_entries(p, count, &n_loss);
+            loss_sum_kernel<<<1, 256, 0, st>>>(lsrc, n_loss, total, b > 0);
+        }
     }
     if (grad_probe) probe_gradient(p, reinterpret_cast<float2 *>(grad_probe), st);
     copy_scalar_kernel<<<1, 1, 0, st>>>(total, loss_out);
@@ -755,7 +903,11 @@ ms_status ms_layer_step(ms_plan *p, hipStream_t st, int32_t layer, int32_t k_ste
             fp.pos_list = p->at<int>(p->L.pos_list) + s0;
             launch_fused(p, kLayer, fp, count, st);
             scatter(p, b, count, layer, 1, g, w, b > 0, st);
-            loss_sum_kernel<<<1, 256, 0, st>>>(p->at<double>(p->L.loss_pos), count, total, b > 0);
+            {
+                int n_loss;
+                const double *lsrc = loss_entries(p, count, &n_loss);
+                loss_sum_kernel<<<1, 256, 0, st>>>(lsrc, n_loss, total, b > 0);
+            }
         }
         float *part = p->at<float>(p->L.partial) + (size_t)hp.M * kMaxBlocks;
         max_partial_kernel<<<dim3(wblocks, 1), 256, 0, st>>>(nullptr, w, hw, part);
@@ -848,7 +1000,11 @@ ms_status ms_probe_step(ms_plan *p, hipStream_t st, int32_t k_steps, ms_c64 *pro
             fp.pos_list = list + s0;
             launch_fused(p, kProbe, fp, count, st);
             class_sums(p, coff + (size_t)b * kChunks * (hp.C + 1), clist, count, b > 0, st);
-            loss_sum_kernel<<<1, 256, 0, st>>>(p->at<double>(p->L.loss_pos), count, total, b > 0);
+            {
+                int n_loss;
+                const double *lsrc = loss_entries(p, count, &n_loss);
+                loss_sum_kernel<<<1, 256, 0, st>>>(lsrc, n_loss, total, b > 0);
+            }
         }
         probe_gradient(p, gp, st);
         const bool last = (k + 1 == k_steps);

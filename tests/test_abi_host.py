@@ -49,7 +49,11 @@ def test_workspace_size_accepts_a_valid_problem():
 @pytest.mark.parametrize("kw, status", [
     (dict(n=24), abi.MS_ERR_INVALID_ARG),
     (dict(n=8), abi.MS_ERR_INVALID_ARG),
-    (dict(n=256, obj_h=256, obj_w=256), abi.MS_ERR_UNSUPPORTED),
+    (dict(n=512, obj_h=512, obj_w=512), abi.MS_ERR_INVALID_ARG),
+    # more distinct sub-pixel offsets than the plan keeps shifted probes for
+    (dict(positions=np.stack([np.arange(300) * 0.001, np.zeros(300)], axis=1)), abi.MS_ERR_UNSUPPORTED),
+    # more distinct slice distances than the fused kernel keeps in LDS at this window size
+    (dict(n_slices=6, dz=np.array([1.0, 2.0, 3.0, 4.0, 5.0])), abi.MS_ERR_UNSUPPORTED),
     (dict(obj_h=16), abi.MS_ERR_INVALID_ARG),
     (dict(n_slices=0), abi.MS_ERR_INVALID_ARG),
     (dict(pixel_size=0.0), abi.MS_ERR_INVALID_ARG),
