@@ -8,9 +8,10 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libimsp.so")
-SOURCES = [os.path.join(PKG, "csrc", "ms_lib.hip")]
-HEADERS = [os.path.join(ROOT, "include", "ms.h"), os.path.join(PKG, "csrc", "ms_kernels.hpp"),
-           os.path.join(PKG, "csrc", "fft_lines.hpp")]
+SOURCES = [os.path.join(PKG, "csrc", "ms_lib.hip"), os.path.join(PKG, "csrc", "unet_lib.hip")]
+HEADERS = [os.path.join(ROOT, "include", "ms.h"), os.path.join(ROOT, "include", "unet.h"),
+           os.path.join(PKG, "csrc", "ms_kernels.hpp"), os.path.join(PKG, "csrc", "fft_lines.hpp"),
+           os.path.join(PKG, "csrc", "line_kernels.hpp"), os.path.join(PKG, "csrc", "unet_kernels.hpp")]
 ARCH = "gfx950"
 
 

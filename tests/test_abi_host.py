@@ -87,3 +87,39 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.ms_adjoint(None, None, None, None, None, None, None, None) == abi.MS_ERR_INVALID_ARG
     assert lib.ms_layer_step(None, None, 0, 1, None, None, None, None, None) == abi.MS_ERR_INVALID_ARG
     assert lib.ms_probe_step(None, None, 1, None, None, None, None, 0, None, None) == abi.MS_ERR_INVALID_ARG
+
+
+def _unet_declared():
+    text = open(os.path.join(ROOT, "include", "unet.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(un_[a-z_]+)\s*\(", text)))
+
+
+def test_unet_header_declares_the_binding_and_the_library_exports_it():
+    from paper_2205_03902_amd import unet
+    assert set(_unet_declared()) == set(unet.SYMBOLS)
+    L = unet.lib()
+    for name in _unet_declared():
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("kw", [dict(in_ch=0), dict(out_ch=9), dict(levels=0), dict(levels=6), dict(base=12),
+                                dict(base=64, levels=4), dict(height=48), dict(width=4), dict(max_batch=0),
+                                dict(height=8, levels=5, base=8)])
+def test_unet_invalid_configs_are_rejected(kw):
+    from paper_2205_03902_amd import unet
+    args = dict(in_ch=6, out_ch=6, base=32, levels=4, height=256, width=256, max_batch=2)
+    args.update(kw)
+    cfg = unet.UnConfig(*[args[k] for k in ("in_ch", "out_ch", "base", "levels", "height", "width", "max_batch")])
+    with pytest.raises(abi.MsError) as e:
+        unet.workspace_size(cfg)
+    assert e.value.status == abi.MS_ERR_INVALID_ARG
+    assert unet.lib().un_last_error().decode() != ""
+
+
+def test_unet_workspace_and_layer_table():
+    from paper_2205_03902_amd import unet
+    cfg = unet.UnConfig(6, 6, 32, 4, 256, 256, 4)
+    ws = unet.workspace_size(cfg)
+    assert 100e6 < ws < 4e9
+    assert unet.workspace_size(unet.UnConfig(6, 6, 32, 4, 256, 256, 8)) > ws
