@@ -8,10 +8,12 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libimsp.so")
-SOURCES = [os.path.join(PKG, "csrc", "ms_lib.hip"), os.path.join(PKG, "csrc", "unet_lib.hip")]
+SOURCES = [os.path.join(PKG, "csrc", "ms_lib.hip"), os.path.join(PKG, "csrc", "unet_lib.hip"),
+           os.path.join(PKG, "csrc", "datagen_lib.hip")]
 HEADERS = [os.path.join(ROOT, "include", "ms.h"), os.path.join(ROOT, "include", "unet.h"),
            os.path.join(PKG, "csrc", "ms_kernels.hpp"), os.path.join(PKG, "csrc", "fft_lines.hpp"),
-           os.path.join(PKG, "csrc", "line_kernels.hpp"), os.path.join(PKG, "csrc", "unet_kernels.hpp")]
+           os.path.join(PKG, "csrc", "line_kernels.hpp"), os.path.join(PKG, "csrc", "unet_kernels.hpp"),
+           os.path.join(ROOT, "include", "datagen.h"), os.path.join(PKG, "csrc", "datagen_kernels.hpp")]
 ARCH = "gfx950"
 
 

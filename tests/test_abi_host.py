@@ -123,3 +123,24 @@ def test_unet_workspace_and_layer_table():
     ws = unet.workspace_size(cfg)
     assert 100e6 < ws < 4e9
     assert unet.workspace_size(unet.UnConfig(6, 6, 32, 4, 256, 256, 8)) > ws
+
+
+def test_datagen_header_declares_the_binding_and_the_library_exports_it():
+    from paper_2205_03902_amd import datagen
+    text = open(os.path.join(ROOT, "include", "datagen.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    declared = set(re.findall(r"\b(dg_[a-z_]+)\s*\(", text))
+    assert declared == set(datagen.SYMBOLS)
+    L = datagen.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_datagen_rejects_bad_arguments_without_a_device():
+    from paper_2205_03902_amd import datagen
+    L = datagen.lib()
+    s = datagen.SpecimenFamily(2, 16, 16).struct(0)          # 3.2 A: smaller than two atom reaches
+    assert L.dg_make_specimen(None, C.byref(s), 0.5, 1, None) == abi.MS_ERR_INVALID_ARG
+    assert L.dg_poisson(None, None, 10, 64, 1e5, 1, 1, None) == abi.MS_ERR_INVALID_ARG
+    assert L.dg_crop_phase(None, 1, 6, 32, 32, 0, 0, 64, 16, 8, 1) == abi.MS_ERR_INVALID_ARG
+    assert L.dg_last_error().decode() != ""
