@@ -110,6 +110,14 @@ def _torch():
     return torch
 
 
+def _indexed(dev):
+    """A CUDA device with its index made explicit ('cuda' -> 'cuda:<current>')."""
+    torch = _torch()
+    if dev.type == "cuda" and dev.index is None:
+        return torch.device("cuda", torch.cuda.current_device())
+    return dev
+
+
 def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
@@ -124,7 +132,7 @@ class Plan:
     def __init__(self, n, obj_h, obj_w, n_slices, positions, dz, pixel_size, wavelength,
                  tilt_y=0.0, tilt_x=0.0, budget_bytes: int = 0, device=None):
         torch = _torch()
-        self.device = torch.device(device if device is not None else "cuda")
+        self.device = _indexed(torch.device(device if device is not None else "cuda"))
         self.n, self.obj_h, self.obj_w, self.n_slices = int(n), int(obj_h), int(obj_w), int(n_slices)
         self.pb, self._keep = make_problem(n, obj_h, obj_w, n_slices, positions, dz, pixel_size, wavelength,
                                            tilt_y, tilt_x)

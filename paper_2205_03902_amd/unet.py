@@ -13,6 +13,7 @@ from typing import Dict, List, Tuple
 import numpy as np
 
 from . import abi
+from .abi import _indexed
 
 UN_CONV3X3, UN_UPCONV2X2, UN_CONV1X1 = 0, 1, 2
 
@@ -103,7 +104,7 @@ class UNet:
     def __init__(self, in_ch: int, out_ch: int, base: int = 32, levels: int = 4, height: int = 256,
                  width: int = 256, max_batch: int = 8, device=None):
         import torch
-        self.device = torch.device(device if device is not None else "cuda")
+        self.device = _indexed(torch.device(device if device is not None else "cuda"))
         self.cfg = UnConfig(in_ch, out_ch, base, levels, height, width, max_batch)
         self.in_pad = (in_ch + 7) // 8 * 8
         ws = workspace_size(self.cfg)
@@ -166,6 +167,42 @@ class UNet:
             flat[li.b_offset: li.b_offset + li.cout] = np.asarray(b, dtype=np.float32)
         self.params.copy_(torch.from_numpy(flat))
         _check(lib().un_sync_weights(self._h, self._stream()), "un_sync_weights")
+
+    def shapes(self) -> Dict[str, tuple]:
+        """Weight shapes {name: (Cout, Cin, k, k) or (Cin, Cout, 2, 2)} with the real input channels."""
+        out = {}
+        for name, li in self.layers.items():
+            cin = self.cfg.in_ch if name == "enc0.conv0" else li.cin
+            if li.kind == UN_UPCONV2X2:
+                out[name] = (cin, li.cout, 2, 2)
+            else:
+                k = 3 if li.kind == UN_CONV3X3 else 1
+                out[name] = (li.cout, cin, k, k)
+        return out
+
+    def init_he(self, seed: int):
+        """He-normal weights (standard deviation sqrt(2 / fan_in)) and zero biases."""
+        rng = np.random.Generator(np.random.PCG64(seed))
+        params = {}
+        for name, shp in self.shapes().items():
+            fan_in = shp[0] * shp[2] * shp[3] if self.layers[name].kind == UN_UPCONV2X2 else shp[1] * shp[2] * shp[3]
+            params[name] = (rng.standard_normal(shp) * np.sqrt(2.0 / fan_in), np.zeros(shp[1] if
+                            self.layers[name].kind == UN_UPCONV2X2 else shp[0]))
+        self.set_params(params)
+
+    def flops_per_sample(self) -> float:
+        """Forward multiply-adds x 2 of one image (real channels, no padding); the training step
+        (forward, data and weight gradients) is about three times this."""
+        total = 0.0
+        h, w = self.cfg.height, self.cfg.width
+        for name, shp in self.shapes().items():
+            level = int(name[3]) if name.startswith(("enc", "dec")) else 0
+            px = (h >> level) * (w >> level)
+            if self.layers[name].kind == UN_UPCONV2X2:
+                total += 2.0 * px * shp[0] * shp[1]          # every output pixel: Cin x Cout
+            else:
+                total += 2.0 * px * shp[0] * shp[1] * shp[2] * shp[3]
+        return total
 
     def _unflatten(self, flat: np.ndarray, shapes) -> Dict[str, Tuple[np.ndarray, np.ndarray]]:
         out = {}
