@@ -126,6 +126,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
                     help="positions per batch (0 = all at once); sets the plan's workspace budget")
+    ap.add_argument("--no-time-to-loss", action="store_true",
+                    help="skip the learned-initialisation run (generation, training, time to loss)")
+    ap.add_argument("--ttl-train", type=int, default=1000, help="training specimens of the time-to-loss run")
+    ap.add_argument("--ttl-test", type=int, default=20, help="held-out specimens of the time-to-loss run")
+    ap.add_argument("--ttl-epochs", type=int, default=12, help="training epochs of the time-to-loss run")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -140,7 +145,7 @@ def main():
         copy_calibration()
         return
 
-    from paper_2205_03902_amd import abi, configs, layerwise, synth
+    from paper_2205_03902_amd import abi, configs, datagen, layerwise, synth
     geo = configs.CONFIGS[args.config]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -161,10 +166,7 @@ def main():
     truth = torch.from_numpy(synth.transmissions(synth.specimen(geo))).to(dev)
     inten = plan.forward(probe_true, truth)
     if geo.dose > 0:
-        g = torch.Generator(device=dev)
-        g.manual_seed(geo.seed + 1)
-        scale = geo.dose / (geo.n * geo.n)
-        measured = (torch.poisson(inten * scale, generator=g) / scale).contiguous()
+        measured = datagen.poisson(inten, geo.dose, seed=geo.seed + 1, stream_id=0)
     else:
         measured = inten
     # plain start (identity slices) and the 10 %-longer-defocus probe start
@@ -206,7 +208,8 @@ def main():
     other = hbm if roof["bound"] == "alu" else alu
     traffic = traffic_record()
     roof["traffic"] = traffic
-    roof["kernel"] = f"fused_kernel<{geo.n}, adjoint>"
+    roof["kernel"] = f"fused_kernel<{geo.n}, adjoint>" if geo.n <= 128 else \
+        f"line_kernel<{geo.n}> (all launches of one adjoint pass)"
     roof["kernel_ms"] = kern_ms / max(launches, 1)
     roof["other"] = {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
     roof["algorithmic_bytes_per_launch"] = byt
@@ -238,6 +241,15 @@ def main():
                       "parallelism": "single GPU, positions in one batch"},
            "roofline": roof}
     out.update(extras)
+    if not args.no_time_to_loss:
+        from paper_2205_03902_amd import learned_init
+        log("bench: learned initialisation (generate, train, time to loss)")
+        res = learned_init.main(["--train", str(args.ttl_train), "--test", str(args.ttl_test),
+                                 "--epochs", str(args.ttl_epochs)], log=log)
+        out["time_to_loss"] = dict(res["time_to_loss"], workload=res["workload"], train=res["train"],
+                                   epochs=res["epochs"], sweeps=res["sweeps"], generation_s=res["generation_s"],
+                                   training_s=res["training_s"], heldout_loss=res["heldout_loss"][-1:],
+                                   unet=res["unet"])
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(geo, min(args.cpu_sample, geo.n_pos))

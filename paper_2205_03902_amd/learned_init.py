@@ -265,9 +265,10 @@ def unet_throughput(net: UNet, X, Y, batch: int, reps: int = 10) -> Dict:
                 gflop_per_sample=net.flops_per_sample() * 1e-9, peak_bf16_tflops=2500.0)
 
 
-def main(argv=None):
+def main(argv=None, log=None):
     import argparse
     import json
+    import sys
     ap = argparse.ArgumentParser(description="learned initialisation: generate, train, time to loss")
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--test", type=int, default=100)
@@ -279,7 +280,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         raise SystemExit("a GPU is required")
-    log = lambda m: print(f"[learned-init] {m}", flush=True)
+    if log is None:
+        log = lambda m: print(f"[learned-init] {m}", file=sys.stderr, flush=True)
     setup = Setup(sweeps=args.sweeps)
     sim = Simulator(setup, "cuda")
     M = setup.geo.n_slices
