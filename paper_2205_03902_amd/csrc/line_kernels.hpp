@@ -78,6 +78,157 @@ __device__ __forceinline__ void gstore(const float2 (&v)[16], float2 *dst, int l
     }
 }
 
+// Column-resident launches move their 16 columns of an image through LDS, so that global
+// accesses are rows of 16 consecutive columns (128 contiguous bytes) instead of 32-byte pieces
+// of 16 rows per wavefront.  Column c of the tile lives at c * LD (the line's own exchange
+// region) with its rows XOR-swizzled by 4 ((c / 2) mod 4): the row-wise fill and the
+// column-wise reads then each spread over all banks.  tile_fill / tile_drain are collective
+// (every lane of the workgroup calls them; they synchronise the workgroup).
+__device__ __forceinline__ int tile_swz(int c) { return 4 * ((c >> 1) & 3); }
+
+template <int N, class F>
+__device__ __forceinline__ void tile_fill(float2 *tile, F load)
+{
+    constexpr int RP = kLinesPerGroup * Win<N>::R / 16;
+    const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4, sw = tile_swz(c);
+    __syncthreads();
+#pragma unroll 4
+    for (int r = r0; r < N; r += RP) tile[c * Win<N>::LD + (r ^ sw)] = load(r, c);
+    __syncthreads();
+}
+
+template <int N, class F>
+__device__ __forceinline__ void tile_drain(const float2 *tile, F store)
+{
+    constexpr int RP = kLinesPerGroup * Win<N>::R / 16;
+    const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4, sw = tile_swz(c);
+    __syncthreads();
+#pragma unroll 4
+    for (int r = r0; r < N; r += RP) store(r, c, tile[c * Win<N>::LD + (r ^ sw)]);
+    __syncthreads();
+}
+
+template <int N, bool SPEC>
+__device__ __forceinline__ void tile_get(float2 (&v)[16], const float2 *tile, int lloc, int j)
+{
+    using Wn = Win<N>;
+    const float2 *col = tile + lloc * Wn::LD;
+    const int sw = tile_swz(lloc);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = col[(SPEC ? Wn::spec(j, i) : Wn::nat(j, i)) ^ sw];
+}
+
+template <int N, bool SPEC>
+__device__ __forceinline__ void tile_put(const float2 (&v)[16], float2 *tile, int lloc, int j)
+{
+    using Wn = Win<N>;
+    float2 *col = tile + lloc * Wn::LD;
+    const int sw = tile_swz(lloc);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) col[(SPEC ? Wn::spec(j, i) : Wn::nat(j, i)) ^ sw] = v[i];
+}
+
+// Where this lane's line is: (line) for row launches; for column launches also the
+// workgroup's first column c0 and the lane's column within the tile, lloc.
+struct LinePos {
+    int line, lloc, j, c0;
+};
+
+template <int N, bool ROW, bool SPEC>
+__device__ __forceinline__ void line_load(float2 (&v)[16], const float2 *src, const LinePos &q, float2 *tile)
+{
+    if (ROW) {
+        gload<N, true, SPEC>(v, src, q.line, q.j);
+    } else {
+        tile_fill<N>(tile, [&](int r, int c) { return src[r * N + q.c0 + c]; });
+        tile_get<N, SPEC>(v, tile, q.lloc, q.j);
+    }
+}
+
+template <int N, bool ROW, bool SPEC>
+__device__ __forceinline__ void line_store(const float2 (&v)[16], float2 *dst, const LinePos &q, float2 *tile)
+{
+    if (ROW) {
+        gstore<N, true, SPEC>(v, dst, q.line, q.j);
+    } else {
+        tile_put<N, SPEC>(v, tile, q.lloc, q.j);
+        tile_drain<N>(tile, [&](int r, int c, float2 x) { dst[r * N + q.c0 + c] = x; });
+    }
+}
+
+// |v|^2 into a float image (SPEC: at spectral positions).
+template <int N, bool ROW, bool SPEC>
+__device__ __forceinline__ void line_store_abs2(const float2 (&v)[16], float *dst, const LinePos &q, float2 *tile)
+{
+    using Wn = Win<N>;
+    if (ROW) {
+        const int l2 = opaque(q.line), j2 = opaque(q.j);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) dst[l2 * N + (SPEC ? Wn::spec(j2, i) : Wn::nat(j2, i))] = cabs2(v[i]);
+    } else {
+        float2 a[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = make_float2(cabs2(v[i]), 0.0f);
+        tile_put<N, SPEC>(a, tile, q.lloc, q.j);
+        tile_drain<N>(tile, [&](int r, int c, float2 x) { dst[r * N + q.c0 + c] = x.x; });
+    }
+}
+
+// Transmission by the object patch (or its conjugate) with wrap-around.
+template <int N, bool ROW, bool CONJ>
+__device__ __forceinline__ void line_patch(float2 (&v)[16], const float2 *slice, int H, int W, int oy, int ox,
+                                           const LinePos &q, float2 *tile)
+{
+    if (ROW) {
+        apply_patch<N, true, CONJ>(v, slice, H, W, oy, ox, q.line, q.j);
+    } else {
+        tile_fill<N>(tile, [&](int r, int c) {
+            int yy = oy + r, xx = ox + q.c0 + c;
+            if (yy >= H) yy -= H;
+            if (xx >= W) xx -= W;
+            return slice[(unsigned)(yy * W + xx)];
+        });
+        float2 t[16];
+        tile_get<N, false>(t, tile, q.lloc, q.j);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = CONJ ? cconjmul(t[k], v[k]) : cmul(v[k], t[k]);
+    }
+}
+
+// Amplitude residual at spectral positions against measured intensities (as residual<>, with
+// the measured values already in registers); returns this lane's FP64 loss share.
+template <int N>
+__device__ __forceinline__ double residual_vals(float2 (&v)[16], const float (&mv)[16])
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const float m = mv[i];
+        const float2 z = v[i];
+        const float a2 = cabs2(z);
+        const double d = sqrt((double)m) - sqrt((double)z.x * (double)z.x + (double)z.y * (double)z.y);
+        acc += d * d;
+        if (a2 != 0.0f) {
+            const float k = sqrtf(m) / sqrtf(a2);
+            v[i] = make_float2(z.x - k * z.x, z.y - k * z.y);
+        }
+    }
+    return acc;
+}
+
+template <int N, bool ROW>
+__device__ __forceinline__ double line_residual(float2 (&v)[16], const float *meas, const LinePos &q, float2 *tile)
+{
+    if (ROW) return residual<N, true>(v, meas, q.line, q.j);
+    tile_fill<N>(tile, [&](int r, int c) { return make_float2(meas[r * N + q.c0 + c], 0.0f); });
+    float2 t[16];
+    tile_get<N, true>(t, tile, q.lloc, q.j);
+    float mv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) mv[i] = t[i].x;
+    return residual_vals<N>(v, mv);
+}
+
 // 1D propagation along the owned axis with the factor table h (LDS), or its adjoint.
 template <int N, bool CONJ>
 __device__ __forceinline__ void prop_axis(float2 (&v)[16], const float2 *tw, float2 *xb, const float2 *h, int j)
@@ -151,66 +302,54 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LinePa
         for (int i = tid; i < N; i += NT) s_h[N + i] = hown[p.gap_table[g_start] * N + i];
     __syncthreads();
 
+    const LinePos q{line, lloc, j, (int)blockIdx.x * kLinesPerGroup};
     float2 v[16];
     if (stage == kStageForward) {
         // ---- psi_m: the probe, or the propagation of gap m-1 finished along this axis ----
         if (m == 0) {
-            gload<N, ROW, false>(v, probe, line, j);
+            line_load<N, ROW, false>(v, probe, q, xbuf);
         } else {
-            gload<N, ROW, false>(v, A, line, j);
+            line_load<N, ROW, false>(v, A, q, xbuf);
             prop_axis<N, false>(v, s_tw, xb, s_h, j);
         }
         const bool store = (mode == kAdjoint && m > 0) || (mode == kLayer && m == p.layer && m > 0);
-        if (store) gstore<N, ROW, false>(v, wave + m * NN, line, j);
-        if (mode == kLayer && m == p.layer) {
-            float *op = p.overlap_patch + (size_t)b * NN;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int a = Wn::nat(j, k);
-                op[ROW ? line * N + a : a * N + line] = cabs2(v[k]);
-            }
-        }
-        apply_patch<N, ROW, false>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, line, j);
+        if (store) line_store<N, ROW, false>(v, wave + m * NN, q, xbuf);
+        if (mode == kLayer && m == p.layer) line_store_abs2<N, ROW, false>(v, p.overlap_patch + (size_t)b * NN, q, xbuf);
+        line_patch<N, ROW, false>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, q, xbuf);
         if (m + 1 < M) {
             prop_axis<N, false>(v, s_tw, xb, s_h + N, j);
-            gstore<N, ROW, false>(v, A, line, j);
+            line_store<N, ROW, false>(v, A, q, xbuf);
         } else {
-            if (mode == kForward && p.exit_waves) gstore<N, ROW, false>(v, p.exit_waves + (size_t)s * NN, line, j);
+            if (mode == kForward && p.exit_waves) line_store<N, ROW, false>(v, p.exit_waves + (size_t)s * NN, q, xbuf);
             line_fft_fwd<N>(v, s_tw, xb, j);
-            gstore<N, ROW, true>(v, A, line, j);    // spectral along this axis, at natural frequency
+            line_store<N, ROW, true>(v, A, q, xbuf);    // spectral along this axis, at natural frequency
         }
         return;
     }
 
     if (stage == kStageFar) {
         // line index = frequency along the first axis (natural); FFT along this axis
-        gload<N, ROW, false>(v, A, line, j);
+        line_load<N, ROW, false>(v, A, q, xbuf);
         line_fft_fwd<N>(v, s_tw, xb, j);
         if (mode == kForward) {
-            float *out = p.intensity + (size_t)s * NN;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int f = Wn::spec(j, i);
-                out[ROW ? line * N + f : f * N + line] = cabs2(v[i]);
-            }
+            line_store_abs2<N, ROW, true>(v, p.intensity + (size_t)s * NN, q, xbuf);
             return;
         }
-        const float *meas = p.measured + (size_t)s * NN;
-        double part = residual<N, ROW>(v, meas, line, j);
+        double part = line_residual<N, ROW>(v, p.measured + (size_t)s * NN, q, xbuf);
         double tot = group_sum<N>(part, red);
         if (tid == 0) p.loss_part[(size_t)b * gridDim.x + blockIdx.x] = tot;
         line_fft_inv<N>(v, s_tw, xb, j);
-        gstore<N, ROW, false>(v, A, line, j);
+        line_store<N, ROW, false>(v, A, q, xbuf);
         return;
     }
 
     // ---- adjoint launch for slice m ----
     if (m + 1 == M) {
         // finish F^H r along this axis: A holds it at natural frequency positions
-        gload<N, ROW, true>(v, A, line, j);
+        line_load<N, ROW, true>(v, A, q, xbuf);
         line_fft_inv<N>(v, s_tw, xb, j);
     } else {
-        gload<N, ROW, false>(v, A, line, j);
+        line_load<N, ROW, false>(v, A, q, xbuf);
         prop_axis<N, true>(v, s_tw, xb, s_h, j);
     }
     const int m_stop = (mode == kLayer) ? p.layer : 0;
@@ -218,22 +357,29 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LinePa
     if (patch) {
         const float2 *psi = (m == 0) ? probe : wave + m * NN;
         float2 *dst = wave + m * NN;
-        const int l2 = opaque(line), j2 = opaque(j);
+        if (ROW) {
+            const int l2 = opaque(line), j2 = opaque(j);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int a = Wn::nat(j2, k);
-            const int idx = ROW ? l2 * N + a : a * N + l2;
-            dst[idx] = cconjmul(psi[idx], v[k]);
+            for (int k = 0; k < 16; ++k) {
+                const int idx = l2 * N + Wn::nat(j2, k);
+                dst[idx] = cconjmul(psi[idx], v[k]);
+            }
+        } else {
+            float2 g[16];
+            line_load<N, false, false>(g, psi, q, xbuf);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) g[k] = cconjmul(g[k], v[k]);
+            line_store<N, false, false>(g, dst, q, xbuf);
         }
     }
     const bool go_on = (m > m_stop) || (mode != kLayer && m == 0);
     if (!go_on) return;
-    apply_patch<N, ROW, true>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, line, j);
+    line_patch<N, ROW, true>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, q, xbuf);
     if (m > 0) {
         prop_axis<N, true>(v, s_tw, xb, s_h + N, j);
-        gstore<N, ROW, false>(v, A, line, j);
+        line_store<N, ROW, false>(v, A, q, xbuf);
     } else if (p.probe_patch) {
-        gstore<N, ROW, false>(v, p.probe_patch + (size_t)b * NN, line, j);
+        line_store<N, ROW, false>(v, p.probe_patch + (size_t)b * NN, q, xbuf);
     }
 }
 
