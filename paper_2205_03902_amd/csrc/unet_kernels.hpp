@@ -403,36 +403,59 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const WgradArgs a)
     }
 }
 
-// grad[i] = sum_z part[z][i], z ascending.
+// grad[i] = sum_z part[z][i], z ascending.  Four consecutive elements per lane when count is a
+// multiple of 4; the loads of 8 splits are issued before their (in-order) additions.
 __global__ void sum_splits_kernel(const float *__restrict__ part, int splits, long long count, float *__restrict__ grad)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    float s = 0.0f;
-    for (int z = 0; z < splits; ++z) s += part[(long long)z * count + i];
-    grad[i] = s;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((count & 3) == 0) {
+        const long long i = 4 * t;
+        if (i >= count) return;
+        float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 8
+        for (int z = 0; z < splits; ++z) {
+            const float4 v = *reinterpret_cast<const float4 *>(part + (long long)z * count + i);
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+            s.w += v.w;
+        }
+        *reinterpret_cast<float4 *>(grad + i) = s;
+    } else {
+        if (t >= count) return;
+        float s = 0.0f;
+#pragma unroll 8
+        for (int z = 0; z < splits; ++z) s += part[(long long)z * count + t];
+        grad[t] = s;
+    }
 }
 
-// Per-channel sums of an output gradient [pixels][gyc] over a pixel chunk.  The 256 lanes
-// are cp channels x (256 / cp) phases (cp: a power of two >= nout), reduced over phases in a
-// fixed order.
+// Per-channel sums of an output gradient [pixels][gyc] over a pixel chunk.  A lane owns 8
+// channels (one 16-byte load per pixel); the 256 lanes are gyc / 8 channel groups x phases over
+// the chunk's pixels, reduced over phases in a fixed order.
 __global__ __launch_bounds__(kThreads) void colsum_partial_kernel(const uint16_t *__restrict__ gy, int gyc, int nout,
-                                                                  int cp, long long pixels, int chunk,
-                                                                  float *__restrict__ part)
+                                                                  long long pixels, int chunk, float *__restrict__ part)
 {
-    __shared__ float red[kThreads];
+    __shared__ float red[kThreads * 8];
     const int tid = threadIdx.x;
-    const int c = tid % cp, ph = tid / cp, nph = kThreads / cp;
+    const int groups = gyc >> 3;                 // <= 32
+    const int g = tid % groups, ph = tid / groups, nph = kThreads / groups;
     const long long p0 = (long long)blockIdx.x * chunk;
     const long long p1 = min(pixels, p0 + chunk);
-    float s = 0.0f;
-    if (c < nout)
-        for (long long p = p0 + ph; p < p1; p += nph) s += bf2f(gy[p * gyc + c]);
-    red[tid] = s;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (ph < nph)
+        for (long long p = p0 + ph; p < p1; p += nph) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(gy + p * gyc + g * 8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[e] += bf2f(bf_at(v, e));
+        }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[tid * 8 + e] = acc[e];
     __syncthreads();
-    if (ph == 0 && c < nout) {
+    for (int c = tid; c < nout; c += kThreads) {
+        const int cg = c >> 3, e = c & 7;
         float t = 0.0f;
-        for (int k = 0; k < nph; ++k) t += red[k * cp + c];
+        for (int k = 0; k < nph; ++k) t += red[(k * groups + cg) * 8 + e];
         part[(long long)blockIdx.x * nout + c] = t;
     }
 }
@@ -565,18 +588,23 @@ __global__ void maxpool_backward_kernel(const uint16_t *__restrict__ a, const ui
         *reinterpret_cast<uint4 *>(ga + src[q] * c + cg) = make_uint4(o[q][0], o[q][1], o[q][2], o[q][3]);
 }
 
-// Centred mean-squared error, first pass: per (sample, channel) sums of e = y - target and
-// e^2 in FP64 (one workgroup per sample, fixed-order reduction).
-__global__ __launch_bounds__(kThreads) void mse_stats_kernel(const float *__restrict__ y, const float *__restrict__ tg,
-                                                             int oc, long long hw, double *__restrict__ stats)
+// Centred mean-squared error, first pass: per (sample, pixel chunk, channel) sums of
+// e = y - target and e^2 in FP64, fixed-order reduction inside the workgroup.
+constexpr int kMseChunks = 64;   // pixel chunks per sample
+
+__global__ __launch_bounds__(kThreads) void mse_partial_kernel(const float *__restrict__ y, const float *__restrict__ tg,
+                                                               int oc, long long hw, double *__restrict__ part)
 {
     __shared__ double red[kThreads];
     const int tid = threadIdx.x;
-    const long long base = (long long)blockIdx.x * hw * oc;
+    const long long b = blockIdx.y;
+    const long long chunk = (hw + kMseChunks - 1) / kMseChunks;
+    const long long q0 = blockIdx.x * chunk, q1 = min(hw, q0 + chunk);
+    const long long base = b * hw * oc;
     for (int c = 0; c < oc; ++c) {
         double s1 = 0.0, s2 = 0.0;
-        for (long long p = tid; p < hw; p += kThreads) {
-            const double e = (double)y[base + p * oc + c] - (double)tg[base + p * oc + c];
+        for (long long q = q0 + tid; q < q1; q += kThreads) {
+            const double e = (double)y[base + q * oc + c] - (double)tg[base + q * oc + c];
             s1 += e;
             s2 += e * e;
         }
@@ -587,10 +615,24 @@ __global__ __launch_bounds__(kThreads) void mse_stats_kernel(const float *__rest
                 if (tid < w) red[tid] += red[tid + w];
                 __syncthreads();
             }
-            if (tid == 0) stats[((long long)blockIdx.x * oc + c) * 2 + pass] = red[0];
+            if (tid == 0) part[((b * oc + c) * kMseChunks + blockIdx.x) * 2 + pass] = red[0];
             __syncthreads();
         }
     }
+}
+
+// The chunk partials of each (sample, channel) added in order.
+__global__ void mse_stats_kernel(const double *__restrict__ part, int groups, double *__restrict__ stats)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= groups) return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < kMseChunks; ++k) {
+        s1 += part[((long long)g * kMseChunks + k) * 2];
+        s2 += part[((long long)g * kMseChunks + k) * 2 + 1];
+    }
+    stats[2 * g] = s1;
+    stats[2 * g + 1] = s2;
 }
 
 // Second pass: d loss / d y = 2 (e - mean e) / count, written as bf16 with 8 channels

@@ -25,8 +25,9 @@ un_status ufail(un_status st, const std::string &msg)
 }
 
 constexpr size_t kAlign = 256;
-constexpr int kWgradTarget = 1024;   // workgroups a weight-gradient launch aims for
-constexpr int kMaxSplits = 64;       // pixel splits of one weight gradient
+constexpr int kWgradTarget = 2048;   // workgroups a weight-gradient launch aims for
+constexpr int kMaxSplits = 256;      // pixel splits of one weight gradient
+constexpr size_t kMaxPartialFloats = (size_t)8 << 20;   // FP32 partials of one weight gradient (32 MiB)
 constexpr int kMaxColSplits = 512;   // pixel splits of one bias gradient
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -50,7 +51,7 @@ struct Layer {
 };
 
 struct Layout {
-    size_t params, grads, adam_m, adam_v, wbf, wdf, gout, gx, gy, stats, wpart, bpart, total;
+    size_t params, grads, adam_m, adam_v, wbf, wdf, gout, gx, gy, stats, mse_part, wpart, bpart, total;
     std::vector<size_t> enc_a0, enc_a1, pool, dec_up, dec_a0, dec_a1, dskip;
 };
 
@@ -99,8 +100,8 @@ un_status check_config(const un_config *c)
 
 int wgrad_tiles(const un_layer &li)
 {
-    const int bm = li.n_rows <= 32 && li.kpad >= 128 ? 32 : li.n_rows <= 64 && li.kpad >= 128 ? 64 : 128;
-    const int bn = li.kpad >= 128 ? 128 : 32;
+    const int bm = li.n_rows <= 32 ? 32 : li.n_rows <= 64 && li.kpad >= 128 ? 64 : 128;
+    const int bn = (li.n_rows <= 32 || li.kpad >= 128) ? 128 : 32;
     return (int)(cdiv(li.n_rows, bm) * cdiv(li.kpad, bn));
 }
 
@@ -155,7 +156,10 @@ void plan(un_net &n)
         ly.wd = wd;
         wd += (size_t)ly.d_rows * ly.d_k;
         wd = (wd + 127) / 128 * 128;
-        ly.splits = (int)std::min<long long>(kMaxSplits, std::max<long long>(1, cdiv(kWgradTarget, wgrad_tiles(ly.info))));
+        const long long per_split = (long long)ly.info.n_rows * ly.info.kpad;
+        ly.splits = (int)std::min<long long>({(long long)kMaxSplits, cdiv(kWgradTarget, wgrad_tiles(ly.info)),
+                                              std::max<long long>(1, (long long)kMaxPartialFloats / per_split)});
+        ly.splits = std::max(ly.splits, 1);
         wp = std::max(wp, (size_t)ly.splits * ly.info.n_rows * ly.info.kpad);
     }
     n.wbf_count = wb;
@@ -201,6 +205,7 @@ void plan(un_net &n)
     y.gx = take(gmax);
     y.gy = take(gmax);
     y.stats = take((size_t)B * c.out_ch * 2 * sizeof(double));
+    y.mse_part = take((size_t)B * c.out_ch * kMseChunks * 2 * sizeof(double));
     y.wpart = take(wp * sizeof(float));
     y.bpart = take((size_t)kMaxColSplits * 256 * sizeof(float));
     y.total = o;
@@ -230,7 +235,7 @@ void gemm(const GemmArgs &a, hipStream_t st)
 void wgrad(const WgradArgs &a, int splits, hipStream_t st)
 {
     const int R = a.n_rows, K = a.kpad;
-    if (R <= 32 && K >= 128) {
+    if (R <= 32) {
         wgrad_kernel<32, 128, 1, 4><<<dim3((unsigned)cdiv(K, 128), (unsigned)cdiv(R, 32), splits), kThreads, 0, st>>>(a);
     } else if (R <= 64 && K >= 128) {
         wgrad_kernel<64, 128, 2, 2><<<dim3((unsigned)cdiv(K, 128), (unsigned)cdiv(R, 64), splits), kThreads, 0, st>>>(a);
@@ -347,15 +352,14 @@ void layer_weight_grad(un_net &n, int li, int batch, int level, const uint16_t *
     wgrad(a, splits, st);
     float *grads = n.at<float>(n.lay.grads);
     const long long wcount = (long long)a.n_rows * a.kpad;
-    sum_splits_kernel<<<(unsigned)cdiv(wcount, 256), 256, 0, st>>>(a.part, splits, wcount, grads + ly.info.w_offset);
+    sum_splits_kernel<<<(unsigned)cdiv(cdiv(wcount, 4), 256), 256, 0, st>>>(a.part, splits, wcount,
+                                                                           grads + ly.info.w_offset);
 
     const int cout = ly.info.cout;
-    int cp = 1;
-    while (cp < cout) cp <<= 1;
-    const long long cchunk = std::max<long long>(1024, cdiv(out_pixels, kMaxColSplits));
+    const long long cchunk = std::max<long long>(256, cdiv(out_pixels, kMaxColSplits));
     const int csplits = (int)cdiv(out_pixels, cchunk);
     float *bpart = n.at<float>(n.lay.bpart);
-    colsum_partial_kernel<<<csplits, kThreads, 0, st>>>(gy, gyc, cout, cp, out_pixels, (int)cchunk, bpart);
+    colsum_partial_kernel<<<csplits, kThreads, 0, st>>>(gy, gyc, cout, out_pixels, (int)cchunk, bpart);
     sum_splits_kernel<<<(unsigned)cdiv(cout, 256), 256, 0, st>>>(bpart, csplits, cout, grads + ly.info.b_offset);
 }
 
@@ -423,7 +427,9 @@ void run_backward(un_net &n, int batch, const uint16_t *x, const float *target, 
     const long long hw = n.pixels(1, 0);
     double *stats = n.at<double>(L.stats);
     uint16_t *gout = n.at<uint16_t>(L.gout);
-    mse_stats_kernel<<<batch, kThreads, 0, st>>>(y, target, oc, hw, stats);
+    double *mpart = n.at<double>(L.mse_part);
+    mse_partial_kernel<<<dim3(kMseChunks, batch), kThreads, 0, st>>>(y, target, oc, hw, mpart);
+    mse_stats_kernel<<<(unsigned)cdiv(batch * oc, 64), 64, 0, st>>>(mpart, batch * oc, stats);
     mse_grad_kernel<<<(unsigned)cdiv(P, 256), 256, 0, st>>>(y, target, stats, oc, hw, P, gout, loss);
 
     uint16_t *X = n.at<uint16_t>(L.gx), *Y = n.at<uint16_t>(L.gy);
