@@ -36,7 +36,9 @@ class Problem(C.Structure):
     _fields_ = [("n", C.c_int), ("obj_h", C.c_int), ("obj_w", C.c_int), ("n_slices", C.c_int),
                 ("n_pos", C.c_long), ("positions", C.c_void_p), ("dz", C.c_void_p),
                 ("pixel_size", C.c_double), ("wavelength", C.c_double),
-                ("tilt_y", C.c_double), ("tilt_x", C.c_double), ("n_threads", C.c_int)]
+                ("tilt_y", C.c_double), ("tilt_x", C.c_double), ("n_threads", C.c_int), ("objective", C.c_int)]
+
+AMPLITUDE, POISSON = 0, 1
 
 
 def lib():
@@ -149,19 +151,19 @@ class Model:
     """A multislice geometry: window N, periodic H x W object, M slices, S positions."""
 
     def __init__(self, n, obj_h, obj_w, n_slices, positions, dz, pixel_size, wavelength,
-                 tilt_y=0.0, tilt_x=0.0, n_threads=0):
+                 tilt_y=0.0, tilt_x=0.0, n_threads=0, objective=0):
         self.n, self.obj_h, self.obj_w, self.n_slices = int(n), int(obj_h), int(obj_w), int(n_slices)
         self.positions = _f64(np.asarray(positions).reshape(-1, 2))
         self.dz = _f64(np.asarray(dz).reshape(-1)) if n_slices > 1 else np.zeros(1)
         self.pb = Problem(self.n, self.obj_h, self.obj_w, self.n_slices, self.positions.shape[0],
                           self.positions.ctypes.data, self.dz.ctypes.data, float(pixel_size),
-                          float(wavelength), float(tilt_y), float(tilt_x), int(n_threads))
+                          float(wavelength), float(tilt_y), float(tilt_x), int(n_threads), int(objective))
 
     @classmethod
-    def from_geometry(cls, geo, positions=None, n_threads=0):
+    def from_geometry(cls, geo, positions=None, n_threads=0, objective=0):
         pos = geo.positions() if positions is None else positions
         return cls(geo.n, geo.obj_h, geo.obj_w, geo.n_slices, pos, geo.gaps(), geo.pixel_size,
-                   geo.wavelength, n_threads=n_threads)
+                   geo.wavelength, n_threads=n_threads, objective=objective)
 
     @property
     def n_pos(self):

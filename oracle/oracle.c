@@ -209,6 +209,7 @@ static int check_problem(const orc_problem *pb)
     if (pb->n_pos > 0 && !pb->positions) return -1;
     if (pb->n_slices > 1 && !pb->dz) return -1;
     if (!(pb->pixel_size > 0.0) || !(pb->wavelength > 0.0)) return -1;
+    if (pb->objective != ORC_AMPLITUDE && pb->objective != ORC_POISSON) return -1;
     return 0;
 }
 
@@ -348,12 +349,26 @@ static void loss_grad_one(const model *md, long s, const double complex *probe, 
 
     const double *meas = measured + (size_t)s * n2;
     double loss = 0.0;
-    for (size_t k = 0; k < n2; ++k) {
-        double a = cabs(far[k]);
-        double sq = sqrt(meas[k]);
-        double d = sq - a;
-        loss += d * d;
-        g[k] = (a == 0.0) ? far[k] : far[k] - sq * (far[k] / a);
+    if (pb->objective == ORC_POISSON) {
+        /* deviance |Psi|^2 - I + I log(I / |Psi|^2), residual Psi (1 - I / |Psi|^2) */
+        for (size_t k = 0; k < n2; ++k) {
+            double a2 = creal(far[k]) * creal(far[k]) + cimag(far[k]) * cimag(far[k]);
+            double y = meas[k];
+            if (a2 == 0.0) {
+                g[k] = far[k];
+                continue;
+            }
+            loss += a2 - y + (y > 0.0 ? y * log(y / a2) : 0.0);
+            g[k] = far[k] * (1.0 - y / a2);
+        }
+    } else {
+        for (size_t k = 0; k < n2; ++k) {
+            double a = cabs(far[k]);
+            double sq = sqrt(meas[k]);
+            double d = sq - a;
+            loss += d * d;
+            g[k] = (a == 0.0) ? far[k] : far[k] - sq * (far[k] / a);
+        }
     }
     ac->loss += loss;
 
@@ -505,6 +520,7 @@ int orc_layer_step(const orc_problem *pb, const double complex *probe, double co
         double wmax = 0.0;
         for (size_t i = 0; i < hw; ++i) if (w[i] > wmax) wmax = w[i];
         double mu = (wmax > 0.0 && prod > 0.0) ? 1.0 / (n2 * prod * wmax) : 0.0;
+        if (pb->objective == ORC_POISSON) mu *= 0.5;
         double complex *o = slices + (size_t)layer * hw;
         for (size_t i = 0; i < hw; ++i) o[i] -= mu * g[i];
         if (loss_out) *loss_out = L;
@@ -533,6 +549,7 @@ int orc_probe_step(const orc_problem *pb, double complex *probe, const double co
         rc = orc_loss_grad(pb, probe, slices, measured, subset, n_subset, -1, NULL, g, NULL, &L);
         if (rc) break;
         double mu = prod > 0.0 ? 1.0 / ((double)n2 * (double)count * prod) : 0.0;
+        if (pb->objective == ORC_POISSON) mu *= 0.5;
         for (size_t i = 0; i < n2; ++i) probe[i] -= mu * g[i];
         if (loss_out) *loss_out = L;
         if (mu_out) *mu_out = mu;

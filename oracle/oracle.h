@@ -22,7 +22,14 @@
  *     Fourier phase ramp;
  *   - the loss is L = sum_s sum_k (sqrt(I_k) - |Psi_k|)^2 without a factor 1/2
  *     (Sec. 3.2) and every gradient is the generalised Wirtinger gradient of
- *     Sec. 3.2, i.e. dL/d(conj z), with the phase set to 0 where Psi_k = 0.
+ *     Sec. 3.2, i.e. dL/d(conj z), with the phase set to 0 where Psi_k = 0;
+ *   - with objective = ORC_POISSON the loss is the Poisson deviance that the
+ *     outlook of Sec. 6 proposes for low-dose data,
+ *       L = sum_s sum_k |Psi_k|^2 - I_k + I_k log(I_k / |Psi_k|^2)
+ *     (the negative log-likelihood of counts with mean proportional to |Psi|^2,
+ *     up to a constant and the dose factor; 0 log 0 = 0), whose Wirtinger
+ *     gradient in Psi is Psi (1 - I / |Psi|^2); where Psi_k = 0 exactly the
+ *     pixel adds nothing and its residual is Psi_k, as for the amplitude loss.
  *
  * Every function returns 0 on success and a negative value on invalid input.
  */
@@ -46,7 +53,10 @@ typedef struct {
     double wavelength;       /* lambda (A)                                         */
     double tilt_y, tilt_x;   /* illumination tilts theta_y, theta_x (rad)          */
     int n_threads;           /* worker threads, 0 = OpenMP default                 */
+    int objective;           /* ORC_AMPLITUDE (Sec. 3.2) or ORC_POISSON (Sec. 6)   */
 } orc_problem;
+
+enum { ORC_AMPLITUDE = 0, ORC_POISSON = 1 };
 
 /* Threads the oracle uses when orc_problem.n_threads is 0. */
 int orc_max_threads(void);
@@ -96,7 +106,9 @@ int orc_loss_grad(const orc_problem *pb, const double complex *probe, const doub
                   double *loss);
 
 /* K amplitude-flow steps on slice `layer` (Algorithm 1, inner loop), in place.
- * loss_out: loss at the iterate before the last step; mu_out: its step size. */
+ * loss_out: loss at the iterate before the last step; mu_out: its step size.
+ * With the Poisson objective the step is half the amplitude-flow step: near the
+ * data the deviance bends twice as fast along |Psi| as the amplitude loss. */
 int orc_layer_step(const orc_problem *pb, const double complex *probe, double complex *slices,
                    const double *measured, int layer, int k_steps, double *loss_out, double *mu_out);
 
