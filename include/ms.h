@@ -103,6 +103,21 @@ int32_t ms_plan_shift_classes(const ms_plan *plan);
 typedef enum { MS_PATH_AUTO = 0, MS_PATH_FUSED = 1, MS_PATH_LINES = 2 } ms_path;
 ms_status ms_plan_set_path(ms_plan *plan, int32_t path);
 
+/* The data term of every loss, gradient and step of the plan.
+ * MS_OBJECTIVE_AMPLITUDE (the default): L = sum (sqrt(I) - |Psi|)^2, the amplitude
+ * flow of Sec. 3.2, residual Psi - sqrt(I) Psi / |Psi|.
+ * MS_OBJECTIVE_POISSON: the Poisson deviance L = sum |Psi|^2 - I + I log(I / |Psi|^2)
+ * (0 log 0 = 0), the maximum-likelihood objective the outlook of Sec. 6 proposes for
+ * low-dose data (the negative log-likelihood of counts of mean proportional to |Psi|^2,
+ * up to a constant and the dose factor); residual Psi (1 - I / |Psi|^2).  Where Psi is
+ * exactly 0 a pixel adds nothing and its residual is Psi, for both objectives.  The
+ * paper gives no step rule for it: ms_layer_step and ms_probe_step take half the
+ * amplitude-flow step (near the data the deviance bends twice as fast along |Psi|),
+ * without the amplitude flow's descent guarantee.  Invalid values return
+ * MS_ERR_INVALID_ARG. */
+typedef enum { MS_OBJECTIVE_AMPLITUDE = 0, MS_OBJECTIVE_POISSON = 1 } ms_objective;
+ms_status ms_plan_set_objective(ms_plan *plan, int32_t objective);
+
 /* The probe of Sec. 2.1 (caption of Fig. 3): the inverse DFT of the disk
  * lambda |q| <= alpha (boundary included), multiplied by the propagator of
  * eq. (fresnel_element) for distance `defocus`, centred at (N/2, N/2) and

@@ -18,10 +18,11 @@ LIB_PATH = os.path.join(PKG, "libimsp.so")
 
 MS_OK, MS_ERR_INVALID_ARG, MS_ERR_UNSUPPORTED, MS_ERR_BUDGET, MS_ERR_HIP = 0, -1, -2, -3, -4
 MS_PATH_AUTO, MS_PATH_FUSED, MS_PATH_LINES = 0, 1, 2
+MS_OBJECTIVE_AMPLITUDE, MS_OBJECTIVE_POISSON = 0, 1
 
 # every entry point declared in include/ms.h
 SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
-           "ms_plan_set_path",
+           "ms_plan_set_path", "ms_plan_set_objective",
            "ms_make_probe", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_probe_step", "ms_profile_begin",
            "ms_profile_end", "ms_last_error")
 
@@ -63,6 +64,8 @@ def lib():
         L.ms_plan_shift_classes.argtypes = [P]
         L.ms_plan_set_path.restype = I32
         L.ms_plan_set_path.argtypes = [P, I32]
+        L.ms_plan_set_objective.restype = I32
+        L.ms_plan_set_objective.argtypes = [P, I32]
         L.ms_make_probe.restype = I32
         L.ms_make_probe.argtypes = [P, P, D, D, P]
         L.ms_forward.restype = I32
@@ -188,6 +191,10 @@ class Plan:
     def set_path(self, path: int):
         """MS_PATH_AUTO, MS_PATH_FUSED or MS_PATH_LINES (see include/ms.h)."""
         _check(lib().ms_plan_set_path(self._h, int(path)), "ms_plan_set_path")
+
+    def set_objective(self, objective: int):
+        """MS_OBJECTIVE_AMPLITUDE or MS_OBJECTIVE_POISSON (see include/ms.h)."""
+        _check(lib().ms_plan_set_objective(self._h, int(objective)), "ms_plan_set_objective")
 
     # -- kernel timing ---------------------------------------------------------
     def profile_begin(self, max_launches: int):

@@ -47,6 +47,7 @@ struct LineParams {
     int H, W, M, m;
     int mode;                    // kForward / kAdjoint / kLayer / kProbe
     int layer;                   // layer mode: the slice whose gradient is wanted
+    int objective;               // 0 amplitude, 1 Poisson deviance
 };
 
 // Global-memory window access for a line group in either layout: lane (line, j) owns
@@ -195,10 +196,10 @@ __device__ __forceinline__ void line_patch(float2 (&v)[16], const float2 *slice,
     }
 }
 
-// Amplitude residual at spectral positions against measured intensities (as residual<>, with
-// the measured values already in registers); returns this lane's FP64 loss share.
+// Residual at spectral positions against measured intensities (as residual<>, with the
+// measured values already in registers); returns this lane's FP64 loss share.
 template <int N>
-__device__ __forceinline__ double residual_vals(float2 (&v)[16], const float (&mv)[16])
+__device__ __forceinline__ double residual_vals(float2 (&v)[16], const float (&mv)[16], int poisson)
 {
     double acc = 0.0;
 #pragma unroll
@@ -206,27 +207,37 @@ __device__ __forceinline__ double residual_vals(float2 (&v)[16], const float (&m
         const float m = mv[i];
         const float2 z = v[i];
         const float a2 = cabs2(z);
-        const double d = sqrt((double)m) - sqrt((double)z.x * (double)z.x + (double)z.y * (double)z.y);
-        acc += d * d;
-        if (a2 != 0.0f) {
-            const float k = sqrtf(m) / sqrtf(a2);
-            v[i] = make_float2(z.x - k * z.x, z.y - k * z.y);
+        const double a2d = (double)z.x * (double)z.x + (double)z.y * (double)z.y;
+        if (poisson) {
+            if (a2d != 0.0) acc += a2d - (double)m + (m > 0.0f ? (double)m * log((double)m / a2d) : 0.0);
+            if (a2 != 0.0f) {
+                const float k = m / a2;
+                v[i] = make_float2(z.x - k * z.x, z.y - k * z.y);
+            }
+        } else {
+            const double d = sqrt((double)m) - sqrt(a2d);
+            acc += d * d;
+            if (a2 != 0.0f) {
+                const float k = sqrtf(m) / sqrtf(a2);
+                v[i] = make_float2(z.x - k * z.x, z.y - k * z.y);
+            }
         }
     }
     return acc;
 }
 
 template <int N, bool ROW>
-__device__ __forceinline__ double line_residual(float2 (&v)[16], const float *meas, const LinePos &q, float2 *tile)
+__device__ __forceinline__ double line_residual(float2 (&v)[16], const float *meas, const LinePos &q, float2 *tile,
+                                                int poisson)
 {
-    if (ROW) return residual<N, true>(v, meas, q.line, q.j);
+    if (ROW) return residual<N, true>(v, meas, q.line, q.j, poisson);
     tile_fill<N>(tile, [&](int r, int c) { return make_float2(meas[r * N + q.c0 + c], 0.0f); });
     float2 t[16];
     tile_get<N, true>(t, tile, q.lloc, q.j);
     float mv[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) mv[i] = t[i].x;
-    return residual_vals<N>(v, mv);
+    return residual_vals<N>(v, mv, poisson);
 }
 
 // 1D propagation along the owned axis with the factor table h (LDS), or its adjoint.
@@ -335,7 +346,7 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LinePa
             line_store_abs2<N, ROW, true>(v, p.intensity + (size_t)s * NN, q, xbuf);
             return;
         }
-        double part = line_residual<N, ROW>(v, p.measured + (size_t)s * NN, q, xbuf);
+        double part = line_residual<N, ROW>(v, p.measured + (size_t)s * NN, q, xbuf, p.objective);
         double tot = group_sum<N>(part, red);
         if (tid == 0) p.loss_part[(size_t)b * gridDim.x + blockIdx.x] = tot;
         line_fft_inv<N>(v, s_tw, xb, j);

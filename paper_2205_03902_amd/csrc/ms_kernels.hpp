@@ -43,6 +43,7 @@ struct FusedParams {
     float *overlap_patch;        // [count][N][N]
     double *loss_pos;            // [count]
     int H, W, M, layer;
+    int objective;               // 0 amplitude, 1 Poisson deviance
 };
 
 // Incident-wave load/store in natural [y][x] order from either layout.
@@ -158,14 +159,33 @@ __device__ __forceinline__ double block_sum(double x, double *red)
 
 // Far field (Sec. 2.1) and amplitude residual (Sec. 3.2) on the 2D spectrum held in
 // layout ROW2 (after the forward 2D FFT): r = Psi - sqrt(I) Psi / |Psi|, 0 where Psi = 0.
-// Returns this lane's FP64 share of sum (sqrt(I) - |Psi|)^2.
+// Returns this lane's FP64 share of the loss: sum (sqrt(I) - |Psi|)^2 (amplitude) or, when
+// poisson is set, sum |Psi|^2 - I + I log(I / |Psi|^2); v becomes the residual
+// Psi - sqrt(I) Psi / |Psi| or Psi (1 - I / |Psi|^2) (Psi itself where Psi == 0).
 template <int N, bool ROW2>
-__device__ __forceinline__ double residual(float2 (&v)[16], const float *meas, int line, int j)
+__device__ __forceinline__ double residual(float2 (&v)[16], const float *meas, int line, int j, int poisson)
 {
     using Wn = Win<N>;
     line = opaque(line);
     j = opaque(j);
     double acc = 0.0;
+    if (poisson) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            int f = Wn::spec(j, i);
+            int fy = ROW2 ? line : f, fx = ROW2 ? f : line;
+            float m = meas[fy * N + fx];
+            float2 z = v[i];
+            float a2 = cabs2(z);
+            double a2d = (double)z.x * (double)z.x + (double)z.y * (double)z.y;
+            if (a2d != 0.0) acc += a2d - (double)m + (m > 0.0f ? (double)m * log((double)m / a2d) : 0.0);
+            if (a2 != 0.0f) {
+                float k = m / a2;
+                v[i] = make_float2(z.x - k * z.x, z.y - k * z.y);
+            }
+        }
+        return acc;
+    }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         int f = Wn::spec(j, i);
@@ -284,7 +304,8 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
         return;
     } else {
         const float *meas = p.measured + (size_t)s * NN;
-        double part = rowM ? residual<N, false>(v, meas, line, j) : residual<N, true>(v, meas, line, j);
+        double part = rowM ? residual<N, false>(v, meas, line, j, p.objective)
+                           : residual<N, true>(v, meas, line, j, p.objective);
         double tot = block_sum<N>(part, red);
         if (tid == 0) p.loss_pos[b] = tot;
 

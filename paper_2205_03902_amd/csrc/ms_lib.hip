@@ -320,6 +320,7 @@ struct ms_plan {
     std::vector<hipEvent_t> ev_start, ev_stop;
     size_t ev_used = 0;
     bool lines = false;   // line kernels instead of the fused per-position kernel
+    int objective = MS_OBJECTIVE_AMPLITUDE;
 
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -388,6 +389,7 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
     lp.waves = fp.waves; lp.probe_patch = fp.probe_patch; lp.overlap_patch = fp.overlap_patch;
     lp.loss_part = p->at<double>(p->L.loss_part);
     lp.H = hp.H; lp.W = hp.W; lp.M = hp.M; lp.mode = mode; lp.layer = fp.layer;
+    lp.objective = fp.objective;
     const int M = hp.M;
     for (int m = 0; m < M; ++m) {
         lp.m = m;
@@ -514,7 +516,15 @@ FusedParams fused_params(ms_plan *p, const ms_c64 *slices, const float *measured
     fp.overlap_patch = p->at<float>(p->L.overlap);
     fp.loss_pos = p->at<double>(p->L.loss_pos);
     fp.H = hp.H; fp.W = hp.W; fp.M = hp.M; fp.layer = 0;
+    fp.objective = p->objective;
     return fp;
+}
+
+// N^2 of the step-size denominator; doubled (half step) for the Poisson objective.
+double step_norm(const ms_plan *p)
+{
+    const double nn = (double)p->hp.n * p->hp.n;
+    return p->objective == MS_OBJECTIVE_POISSON ? 2.0 * nn : nn;
 }
 
 int grid_for(long long count) { return (int)std::max<long long>(1, std::min<long long>(8192, (count + 255) / 256)); }
@@ -768,6 +778,16 @@ int64_t ms_plan_batch(const ms_plan *plan) { return plan ? plan->hp.B : 0; }
 
 int32_t ms_plan_shift_classes(const ms_plan *plan) { return plan ? plan->hp.C : 0; }
 
+ms_status ms_plan_set_objective(ms_plan *p, int32_t objective)
+{
+    g_err.clear();
+    if (!p) return fail(MS_ERR_INVALID_ARG, "plan is NULL");
+    if (objective != MS_OBJECTIVE_AMPLITUDE && objective != MS_OBJECTIVE_POISSON)
+        return fail(MS_ERR_INVALID_ARG, "unknown objective");
+    p->objective = objective;
+    return MS_OK;
+}
+
 ms_status ms_plan_set_path(ms_plan *p, int32_t path)
 {
     g_err.clear();
@@ -914,7 +934,7 @@ ms_status ms_layer_step(ms_plan *p, hipStream_t st, int32_t layer, int32_t k_ste
         max_final_kernel<<<1, 256, 0, st>>>(part, wblocks, p->at<float>(p->L.maxw));
         const bool last = (k + 1 == k_steps);
         step_size_kernel<<<1, 1, 0, st>>>(p->at<float>(p->L.maxt2), layer + 1, hp.M, p->at<float>(p->L.maxw),
-                                          (double)hp.n * hp.n, 1.0, mu, last ? mu_out : nullptr, total,
+                                          step_norm(p), 1.0, mu, last ? mu_out : nullptr, total,
                                           last ? loss_out : nullptr);
         update_kernel<<<(int)std::min<long long>(4096, (hw + 255) / 256), 256, 0, st>>>(
             reinterpret_cast<float2 *>(slices) + (size_t)layer * hw, g, hw, mu);
@@ -1008,7 +1028,7 @@ ms_status ms_probe_step(ms_plan *p, hipStream_t st, int32_t k_steps, ms_c64 *pro
         }
         probe_gradient(p, gp, st);
         const bool last = (k + 1 == k_steps);
-        step_size_kernel<<<1, 1, 0, st>>>(p->at<float>(p->L.maxt2), 0, hp.M, nullptr, (double)nn, (double)count_all,
+        step_size_kernel<<<1, 1, 0, st>>>(p->at<float>(p->L.maxt2), 0, hp.M, nullptr, step_norm(p), (double)count_all,
                                           mu, last ? mu_out : nullptr, total, last ? loss_out : nullptr);
         update_kernel<<<(nn + 255) / 256, 256, 0, st>>>(reinterpret_cast<float2 *>(probe), gp, nn, mu);
     }
