@@ -46,32 +46,43 @@ struct FusedParams {
     int objective;               // 0 amplitude, 1 Poisson deviance
 };
 
-// Incident-wave load/store in natural [y][x] order from either layout.
+// Incident-wave load/store in natural [y][x] order from either layout, with 32-bit element
+// offsets from the window base (N^2 < 2^31), so that each access needs one address register.
+template <int N, bool ROW>
+__device__ __forceinline__ unsigned window_base(int line, int j)
+{
+    return ROW ? (unsigned)(line * N + j) : (unsigned)(j * N + line);
+}
+
+template <int N, bool ROW>
+constexpr unsigned window_step()
+{
+    return ROW ? (unsigned)Win<N>::R : (unsigned)(Win<N>::R * N);
+}
+
 template <int N, bool ROW>
 __device__ __forceinline__ void load_window(float2 (&v)[16], const float2 *src, int line, int j)
 {
-    using Wn = Win<N>;
-    line = opaque(line);
-    j = opaque(j);
+    const unsigned base = window_base<N, ROW>(opaque(line), opaque(j));
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        int a = Wn::nat(j, k);
-        v[k] = ROW ? src[line * N + a] : src[a * N + line];
-    }
+    for (int k = 0; k < 16; ++k) v[k] = src[base + window_step<N, ROW>() * k];
 }
 
 template <int N, bool ROW>
 __device__ __forceinline__ void store_window(const float2 (&v)[16], float2 *dst, int line, int j)
 {
-    using Wn = Win<N>;
-    line = opaque(line);
-    j = opaque(j);
+    const unsigned base = window_base<N, ROW>(opaque(line), opaque(j));
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        int a = Wn::nat(j, k);
-        if (ROW) dst[line * N + a] = v[k];
-        else dst[a * N + line] = v[k];
-    }
+    for (int k = 0; k < 16; ++k) dst[base + window_step<N, ROW>() * k] = v[k];
+}
+
+// |v|^2 of the window into a float image, natural order.
+template <int N, bool ROW>
+__device__ __forceinline__ void store_window_abs2(const float2 (&v)[16], float *dst, int line, int j)
+{
+    const unsigned base = window_base<N, ROW>(opaque(line), opaque(j));
+#pragma unroll
+    for (int k = 0; k < 16; ++k) dst[base + window_step<N, ROW>() * k] = cabs2(v[k]);
 }
 
 // v *= T (or conj(T)): the object patch t[(oy + y) mod H][(ox + x) mod W] (Sec. 1.3, 2.1).
@@ -252,11 +263,7 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
         const bool store = (MODE == kAdjoint && m > 0) || (MODE == kLayer && m == p.layer && m > 0);
         if (row) {
             if (store) store_window<N, true>(v, wave + m * NN, line, j);
-            if (MODE == kLayer && m == p.layer) {
-                float *op = p.overlap_patch + (size_t)b * NN;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) op[line * N + Wn::nat(j, k)] = cabs2(v[k]);
-            }
+            if (MODE == kLayer && m == p.layer) store_window_abs2<N, true>(v, p.overlap_patch + (size_t)b * NN, line, j);
             apply_patch<N, true, false>(v, slice, H, W, oy, ox, line, j);
             if (m + 1 < M) {
                 const int u = p.gap_table[m] * N;
@@ -264,11 +271,7 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
             }
         } else {
             if (store) store_window<N, false>(v, wave + m * NN, line, j);
-            if (MODE == kLayer && m == p.layer) {
-                float *op = p.overlap_patch + (size_t)b * NN;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) op[Wn::nat(j, k) * N + line] = cabs2(v[k]);
-            }
+            if (MODE == kLayer && m == p.layer) store_window_abs2<N, false>(v, p.overlap_patch + (size_t)b * NN, line, j);
             apply_patch<N, false, false>(v, slice, H, W, oy, ox, line, j);
             if (m + 1 < M) {
                 const int u = p.gap_table[m] * N;
@@ -323,12 +326,16 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
             if (patch) {
                 const float2 *psi = (m == 0) ? probe : wave + m * NN;
                 float2 *dst = wave + m * NN;
+                // 32-bit element offsets from the window base (N^2 < 2^31): one address
+                // register per access instead of a 64-bit pointer each
+                const int l2 = opaque(line), j2 = opaque(j);
+                const unsigned base = row ? (unsigned)(l2 * N + j2) : (unsigned)(j2 * N + l2);
+                const unsigned step = row ? (unsigned)R : (unsigned)(R * N);
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
-                    int a = Wn::nat(j, k);
-                    int idx = row ? line * N + a : a * N + line;
-                    float2 ps = psi[idx];
-                    dst[idx] = cconjmul(ps, v[k]);   // dL/d conj(t_m) on the window: conj(psi_m) o g
+                    const unsigned off = base + step * k;
+                    float2 ps = psi[off];
+                    dst[off] = cconjmul(ps, v[k]);   // dL/d conj(t_m) on the window: conj(psi_m) o g
                 }
             }
             const bool go_on = (m > m_stop) || (MODE != kLayer && m == 0);
