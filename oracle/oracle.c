@@ -530,6 +530,45 @@ int orc_layer_step(const orc_problem *pb, const double complex *probe, double co
     return rc;
 }
 
+int orc_full_step(const orc_problem *pb, const double complex *probe, double complex *slices,
+                  const double *measured, int k_steps, double *loss_out, double *mu_out)
+{
+    if (check_problem(pb) || k_steps < 0) return -1;
+    const int M = pb->n_slices;
+    size_t hw = (size_t)pb->obj_h * pb->obj_w;
+    double n2 = (double)pb->n * (double)pb->n;
+    double complex *g = (double complex *)malloc(sizeof(double complex) * hw * (size_t)M);
+    double complex *gl = (double complex *)malloc(sizeof(double complex) * hw);
+    double *w = (double *)malloc(sizeof(double) * hw);
+    double *mu = (double *)malloc(sizeof(double) * (size_t)M);
+    if (!g || !gl || !w || !mu) { free(g); free(gl); free(w); free(mu); return -2; }
+    int rc = 0;
+    for (int k = 0; k < k_steps && rc == 0; ++k) {
+        double L = 0.0;
+        rc = orc_loss_grad(pb, probe, slices, measured, NULL, 0, -1, g, NULL, NULL, &L);
+        /* every step size at the current iterate, before any slice changes */
+        for (int l = 0; l < M && rc == 0; ++l) {
+            double dummy = 0.0;
+            rc = orc_loss_grad(pb, probe, slices, measured, NULL, 0, l, gl, NULL, w, &dummy);
+            double wmax = 0.0, prod = 1.0;
+            for (size_t i = 0; i < hw; ++i) if (w[i] > wmax) wmax = w[i];
+            for (int m = l + 1; m < M; ++m) prod *= max_abs2(slices + (size_t)m * hw, hw);
+            mu[l] = (wmax > 0.0 && prod > 0.0) ? 1.0 / (n2 * prod * wmax) : 0.0;
+            if (pb->objective == ORC_POISSON) mu[l] *= 0.5;
+        }
+        if (rc) break;
+        for (int l = 0; l < M; ++l) {
+            double complex *o = slices + (size_t)l * hw;
+            const double complex *gg = g + (size_t)l * hw;
+            for (size_t i = 0; i < hw; ++i) o[i] -= mu[l] * gg[i];
+        }
+        if (loss_out) *loss_out = L;
+        if (mu_out) for (int l = 0; l < M; ++l) mu_out[l] = mu[l];
+    }
+    free(g); free(gl); free(w); free(mu);
+    return rc;
+}
+
 int orc_probe_step(const orc_problem *pb, double complex *probe, const double complex *slices,
                    const double *measured, const long *subset, long n_subset, int k_steps,
                    double *loss_out, double *mu_out)

@@ -82,3 +82,30 @@ def test_config0_fifty_sweeps_reduce_the_loss(orc):
     lf = md.loss(p, sl, meas)
     assert np.all(np.diff(hist) <= 1e-12 * hist[0])
     assert lf < 0.5 * l0
+
+
+def test_full_step_is_every_layer_step_taken_from_the_same_iterate(orc):
+    """The full-gradient (Jacobi) step moves each slice exactly as a layer step of Algorithm 1
+    started from the same slices would; with one slice it is the layer step."""
+    import numpy as np
+    from paper_2205_03902_amd import synth
+    rng = np.random.default_rng(3)
+    n, obj, m = 16, 24, 3
+    pos = np.array([[0.0, 0.0], [3.5, 2.25], [-3.0, 17.5], [9.0, 9.5]])
+    for objective in (0, 1):
+        md = orc.Model(n, obj, obj, m, pos, np.array([2.0, 1.5]), 0.2, 0.0487, objective=objective)
+        p = orc.probe(n, 0.2, 0.0487, 0.03, 15.0)
+        truth = np.exp(1j * rng.uniform(0, 0.8, (m, obj, obj)))
+        meas = synth.poisson_counts(md.forward(p, truth), 1e4, 4).astype(np.float64)
+        start = np.exp(1j * rng.uniform(0, 0.3, (m, obj, obj))) * rng.uniform(0.9, 1.1, (m, obj, obj))
+        new, loss, mu = md.full_step(p, start, meas)
+        assert loss == md.loss(p, start, meas)
+        for layer in range(m):
+            ls, ll, lmu = md.layer_step(p, start, meas, layer, 1)
+            assert lmu == mu[layer]
+            assert np.array_equal(new[layer], ls[layer])
+    one = orc.Model(n, obj, obj, 1, pos, np.zeros(1), 0.2, 0.0487)
+    meas1 = one.forward(p, truth[:1])
+    a, la, ma = one.full_step(p, start[:1], meas1)
+    b, lb, mb = one.layer_step(p, start[:1], meas1, 0, 1)
+    assert np.array_equal(a, b) and la == lb and ma[0] == mb
