@@ -151,6 +151,17 @@ ms_status ms_layer_step(ms_plan *plan, hipStream_t stream, int32_t layer, int32_
                         const ms_c64 *probe, ms_c64 *slices, const float *measured,
                         double *loss_out, double *mu_out);
 
+/* K full-gradient steps: the gradient-based alternative the introduction (Sec. 1)
+ * contrasts with the layer-wise method.  One fwd+adj pass gives the gradient of every
+ * slice; each slice then takes the step of a layer step of Algorithm 1 (its own
+ * mu_m = 1 / (N^2 prod_{m' > m} max|t_m'|^2 max_pixel sum_s |psi_m^s|^2), halved for the
+ * Poisson objective), all from the same iterate (a Jacobi update instead of the
+ * Gauss-Seidel sweep; unlike a layer step it has no descent guarantee).  slices
+ * (in/out): all M slices change.  loss_out (device FP64 or NULL): the loss at the
+ * iterate before the last step; mu_out (device FP64 [M] or NULL): that step's sizes. */
+ms_status ms_full_step(ms_plan *plan, hipStream_t stream, int32_t k_steps, const ms_c64 *probe, ms_c64 *slices,
+                       const float *measured, double *loss_out, double *mu_out);
+
 /* k_steps amplitude-flow steps on the probe (Sec. 3.5) over the positions in
  * `subset` ((host) n_subset indices in [0, S); NULL = all positions):
  *   P <- P - mu * dL/d conj(P),  mu = 1 / (N^2 * n_subset * prod_m max|t_m|^2).

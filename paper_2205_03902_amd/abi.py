@@ -23,7 +23,7 @@ MS_OBJECTIVE_AMPLITUDE, MS_OBJECTIVE_POISSON = 0, 1
 # every entry point declared in include/ms.h
 SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
            "ms_plan_set_path", "ms_plan_set_objective",
-           "ms_make_probe", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_probe_step", "ms_profile_begin",
+           "ms_make_probe", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_profile_begin",
            "ms_profile_end", "ms_last_error")
 
 
@@ -74,6 +74,8 @@ def lib():
         L.ms_adjoint.argtypes = [P, P, P, P, P, P, P, P]
         L.ms_layer_step.restype = I32
         L.ms_layer_step.argtypes = [P, P, I32, I32, P, P, P, P, P]
+        L.ms_full_step.restype = I32
+        L.ms_full_step.argtypes = [P, P, I32, P, P, P, P, P]
         L.ms_probe_step.restype = I32
         L.ms_probe_step.argtypes = [P, P, I32, P, P, P, P, I64, P, P]
         L.ms_profile_begin.restype = I32
@@ -252,6 +254,14 @@ class Plan:
         self._patterns(measured)
         _check(lib().ms_layer_step(self._h, self._stream(), int(layer), int(k_steps), _ptr(probe), _ptr(slices),
                                    _ptr(measured), _ptr(loss), _ptr(mu)), "ms_layer_step")
+
+    def full_step(self, k_steps: int, probe, slices, measured, loss=None, mu=None):
+        """In place on every slice; loss: optional float64 device scalar, mu: optional float64 device [M]."""
+        self._probe(probe)
+        self._slices(slices)
+        self._patterns(measured)
+        _check(lib().ms_full_step(self._h, self._stream(), int(k_steps), _ptr(probe), _ptr(slices), _ptr(measured),
+                                  _ptr(loss), _ptr(mu)), "ms_full_step")
 
     def probe_step(self, k_steps: int, probe, slices, measured, subset=None, loss=None, mu=None):
         """In place on probe; subset: host sequence of position indices or None for all."""

@@ -42,12 +42,13 @@ struct LineParams {
     float2 *A;                   // [count][N][N] half-propagated window
     float2 *waves;               // [count][M][N][N] incident waves, then gradient patches (or null)
     float2 *probe_patch;         // [count][N][N] or null
-    float *overlap_patch;        // [count][N][N] (layer mode)
+    float *overlap_patch;        // [count][M][N][N]: |psi_m|^2 (layer mode: the layer; full: every slice)
     double *loss_part;           // [count][N / 16]
     int H, W, M, m;
     int mode;                    // kForward / kAdjoint / kLayer / kProbe
     int layer;                   // layer mode: the slice whose gradient is wanted
     int objective;               // 0 amplitude, 1 Poisson deviance
+    int full;                    // adjoint mode: also write |psi_m|^2 of every slice
 };
 
 // Global-memory window access for a line group in either layout: lane (line, j) owns
@@ -325,7 +326,8 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LinePa
         }
         const bool store = (mode == kAdjoint && m > 0) || (mode == kLayer && m == p.layer && m > 0);
         if (store) line_store<N, ROW, false>(v, wave + m * NN, q, xbuf);
-        if (mode == kLayer && m == p.layer) line_store_abs2<N, ROW, false>(v, p.overlap_patch + (size_t)b * NN, q, xbuf);
+        if (mode == kLayer && m == p.layer)
+            line_store_abs2<N, ROW, false>(v, p.overlap_patch + ((size_t)b * M + m) * NN, q, xbuf);
         line_patch<N, ROW, false>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, q, xbuf);
         if (m + 1 < M) {
             prop_axis<N, false>(v, s_tw, xb, s_h + N, j);
@@ -368,16 +370,20 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LinePa
     if (patch) {
         const float2 *psi = (m == 0) ? probe : wave + m * NN;
         float2 *dst = wave + m * NN;
+        float *ovl = (mode == kAdjoint && p.full) ? p.overlap_patch + ((size_t)b * M + m) * NN : nullptr;
         if (ROW) {
             const int l2 = opaque(line), j2 = opaque(j);
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int idx = l2 * N + Wn::nat(j2, k);
-                dst[idx] = cconjmul(psi[idx], v[k]);
+                const float2 ps = psi[idx];
+                if (ovl) ovl[idx] = cabs2(ps);
+                dst[idx] = cconjmul(ps, v[k]);
             }
         } else {
             float2 g[16];
             line_load<N, false, false>(g, psi, q, xbuf);
+            if (ovl) line_store_abs2<N, false, false>(g, ovl, q, xbuf);
 #pragma unroll
             for (int k = 0; k < 16; ++k) g[k] = cconjmul(g[k], v[k]);
             line_store<N, false, false>(g, dst, q, xbuf);

@@ -40,10 +40,11 @@ struct FusedParams {
     float2 *exit_waves;          // [S][N][N] or null
     float2 *waves;               // [count][M][N][N] incident waves, then gradient patches
     float2 *probe_patch;         // [count][N][N] or null
-    float *overlap_patch;        // [count][N][N]
+    float *overlap_patch;        // [count][M][N][N]: |psi_m|^2 of slice m (layer mode: the layer; full: all)
     double *loss_pos;            // [count]
     int H, W, M, layer;
     int objective;               // 0 amplitude, 1 Poisson deviance
+    int full;                    // adjoint mode: also write |psi_m|^2 of every slice
 };
 
 // Incident-wave load/store in natural [y][x] order from either layout, with 32-bit element
@@ -263,7 +264,8 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
         const bool store = (MODE == kAdjoint && m > 0) || (MODE == kLayer && m == p.layer && m > 0);
         if (row) {
             if (store) store_window<N, true>(v, wave + m * NN, line, j);
-            if (MODE == kLayer && m == p.layer) store_window_abs2<N, true>(v, p.overlap_patch + (size_t)b * NN, line, j);
+            if (MODE == kLayer && m == p.layer)
+                store_window_abs2<N, true>(v, p.overlap_patch + ((size_t)b * M + m) * NN, line, j);
             apply_patch<N, true, false>(v, slice, H, W, oy, ox, line, j);
             if (m + 1 < M) {
                 const int u = p.gap_table[m] * N;
@@ -271,7 +273,8 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
             }
         } else {
             if (store) store_window<N, false>(v, wave + m * NN, line, j);
-            if (MODE == kLayer && m == p.layer) store_window_abs2<N, false>(v, p.overlap_patch + (size_t)b * NN, line, j);
+            if (MODE == kLayer && m == p.layer)
+                store_window_abs2<N, false>(v, p.overlap_patch + ((size_t)b * M + m) * NN, line, j);
             apply_patch<N, false, false>(v, slice, H, W, oy, ox, line, j);
             if (m + 1 < M) {
                 const int u = p.gap_table[m] * N;
@@ -331,10 +334,12 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
                 const int l2 = opaque(line), j2 = opaque(j);
                 const unsigned base = row ? (unsigned)(l2 * N + j2) : (unsigned)(j2 * N + l2);
                 const unsigned step = row ? (unsigned)R : (unsigned)(R * N);
+                float *ovl = (MODE == kAdjoint && p.full) ? p.overlap_patch + ((size_t)b * M + m) * NN : nullptr;
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     const unsigned off = base + step * k;
                     float2 ps = psi[off];
+                    if (ovl) ovl[off] = cabs2(ps);
                     dst[off] = cconjmul(ps, v[k]);   // dL/d conj(t_m) on the window: conj(psi_m) o g
                 }
             }
@@ -369,12 +374,13 @@ constexpr int kUnroll = 8;   // patch loads in flight per lane
 
 struct ScatterParams {
     const float2 *patches;      // patch of (position b, slice m): patches + b * pos_stride + m * N * N
-    const float *wpatch;        // [count][N][N] overlap patches, or null
+    const float *wpatch;        // overlap patch of (position b, slice m): wpatch + b * w_stride + m * N * N
     long long pos_stride;
     const int *tile_off;        // this batch: [kChunks][n_tiles + 1]
     const int4 *entries;        // (batch-local position, origin y, origin x, 0)
     float2 *partial;            // [nch][n_m][H][W]
-    float *wpartial;            // [nch][H][W] or null
+    float *wpartial;            // [nch][n_m][H][W] or null
+    long long w_stride;
     int H, W, N, tiles_x, n_tiles, m0;
 };
 
@@ -386,7 +392,8 @@ __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
     if (y >= p.H || x >= p.W) return;
     const size_t NN = (size_t)p.N * p.N;
     const float2 *base = p.patches + (size_t)(p.m0 + mi) * NN;
-    const bool want_w = p.wpartial && mi == 0;
+    const bool want_w = p.wpartial != nullptr;
+    const float *wbase = want_w ? p.wpatch + (size_t)(p.m0 + mi) * NN : nullptr;
     const int *off = p.tile_off + (size_t)c * (p.n_tiles + 1);
     const int e0 = off[t], e1 = off[t + 1];
     float2 acc = make_float2(0.f, 0.f);
@@ -416,14 +423,14 @@ __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
         if (want_w) {
             float w[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) w[u] = loc[u] >= 0 ? p.wpatch[(size_t)sl[u] * NN + loc[u]] : 0.f;
+            for (int u = 0; u < kUnroll; ++u) w[u] = loc[u] >= 0 ? wbase[(size_t)sl[u] * p.w_stride + loc[u]] : 0.f;
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) wacc += w[u];
         }
     }
     const size_t HW = (size_t)p.H * p.W, pix = (size_t)y * p.W + x;
     p.partial[((size_t)c * n_m + mi) * HW + pix] = acc;
-    if (want_w) p.wpartial[(size_t)c * HW + pix] = wacc;
+    if (want_w) p.wpartial[((size_t)c * n_m + mi) * HW + pix] = wacc;
 }
 
 // out[i] = (accumulate ? out[i] : 0) + sum_{c < nch} partial[c * plane + i], chunks in order.

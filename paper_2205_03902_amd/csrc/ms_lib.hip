@@ -236,6 +236,7 @@ size_t tile_entries(const HostPlan &hp)
 struct Layout {
     size_t tw, hy, hx, gap_table, ry, rx, ident, pos_info, pos_list, sub_list;
     size_t class_probe, class_acc, class_tmp, gp, layer_g, layer_w, maxt2, partial, maxw, scal;
+    size_t full_g, full_w, maxw_all, mu_all;
     size_t tile_off, tile_list, class_off, class_list, sub_class_off, sub_class_list;
     size_t spart, wpart, cpart;
     size_t waves, probe_patch, overlap, loss_pos, half, loss_part, energy;
@@ -270,6 +271,10 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     L.partial = take(M * kMaxBlocks * 4 + kMaxBlocks * 4);
     L.maxw = take(4);
     L.scal = take(8 * 8);
+    L.full_g = take(M * HW * 8);
+    L.full_w = take(M * HW * 4);
+    L.maxw_all = take(M * 4);
+    L.mu_all = take(M * 8);
     L.tile_off = take(nb * kChunks * (hp.n_tiles + 1) * 4);
     L.tile_list = take(n_entries * 16);
     L.class_off = take(nb * kChunks * (C + 1) * 4);
@@ -278,11 +283,11 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     L.sub_class_list = take(S * 4);
     const size_t nch = (size_t)chunking(B).nch;
     L.spart = take(nch * M * HW * 8);
-    L.wpart = take(nch * HW * 4);
+    L.wpart = take(nch * M * HW * 4);
     L.cpart = take(nch * C * NN * 8);
     L.waves = take((size_t)B * M * NN * 8);
     L.probe_patch = take((size_t)B * NN * 8);
-    L.overlap = take((size_t)B * NN * 4);
+    L.overlap = take((size_t)B * M * NN * 4);
     L.loss_pos = take((size_t)B * 8);
     // line kernels: the half-propagated window per position and per-line-group partials
     const bool lines_possible = hp.n >= 32;
@@ -390,6 +395,7 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
     lp.loss_part = p->at<double>(p->L.loss_part);
     lp.H = hp.H; lp.W = hp.W; lp.M = hp.M; lp.mode = mode; lp.layer = fp.layer;
     lp.objective = fp.objective;
+    lp.full = fp.full;
     const int M = hp.M;
     for (int m = 0; m < M; ++m) {
         lp.m = m;
@@ -517,6 +523,7 @@ FusedParams fused_params(ms_plan *p, const ms_c64 *slices, const float *measured
     fp.loss_pos = p->at<double>(p->L.loss_pos);
     fp.H = hp.H; fp.W = hp.W; fp.M = hp.M; fp.layer = 0;
     fp.objective = p->objective;
+    fp.full = 0;
     return fp;
 }
 
@@ -544,13 +551,15 @@ void scatter(ms_plan *p, int b, int count, int m0, int n_m, float2 *out, float *
     sp.entries = p->at<int4>(p->L.tile_list);
     sp.partial = p->at<float2>(p->L.spart);
     sp.wpartial = wout ? p->at<float>(p->L.wpart) : nullptr;
+    sp.w_stride = (long long)hp.M * hp.n * hp.n;
     sp.H = hp.H; sp.W = hp.W; sp.N = hp.n; sp.tiles_x = hp.tiles_x; sp.n_tiles = hp.n_tiles; sp.m0 = m0;
     scatter_partial_kernel<<<dim3(hp.n_tiles, ch.nch, n_m), 256, 0, st>>>(sp);
     const long long plane = (long long)n_m * hp.H * hp.W;
     chunk_reduce_kernel<float2><<<grid_for(plane), 256, 0, st>>>(sp.partial, ch.nch, plane, out, accumulate);
     if (wout) {
         const long long hw = (long long)hp.H * hp.W;
-        chunk_reduce_kernel<float><<<grid_for(hw), 256, 0, st>>>(sp.wpartial, ch.nch, hw, wout, accumulate);
+        chunk_reduce_kernel<float><<<grid_for(n_m * hw), 256, 0, st>>>(sp.wpartial, ch.nch, n_m * hw, wout,
+                                                                        accumulate);
     }
 }
 
@@ -940,6 +949,57 @@ ms_status ms_layer_step(ms_plan *p, hipStream_t st, int32_t layer, int32_t k_ste
             reinterpret_cast<float2 *>(slices) + (size_t)layer * hw, g, hw, mu);
     }
     return check_hip("ms_layer_step");
+}
+
+ms_status ms_full_step(ms_plan *p, hipStream_t st, int32_t k_steps, const ms_c64 *probe, ms_c64 *slices,
+                       const float *measured, double *loss_out, double *mu_out)
+{
+    g_err.clear();
+    if (!p || !probe || !slices || !measured) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    const HostPlan &hp = p->hp;
+    if (k_steps < 0) return fail(MS_ERR_INVALID_ARG, "k_steps must be >= 0");
+    if (!aligned8(probe) || !aligned8(slices) || !aligned8(loss_out) || !aligned8(mu_out) || ((uintptr_t)measured & 3))
+        return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
+    if (k_steps == 0) return MS_OK;
+    const long long hw = (long long)hp.H * hp.W;
+    const int M = hp.M;
+    class_probes(p, probe, st);
+    FusedParams fp = fused_params(p, slices, measured);
+    fp.probe_patch = nullptr;
+    fp.full = 1;
+    double *total = p->at<double>(p->L.scal) + 1;
+    double *mu = p->at<double>(p->L.mu_all);
+    float *maxw = p->at<float>(p->L.maxw_all);
+    float2 *g = p->at<float2>(p->L.full_g);
+    float *w = p->at<float>(p->L.full_w);
+    float *part = p->at<float>(p->L.partial) + (size_t)M * kMaxBlocks;
+    const int wblocks = (int)std::min<long long>(kMaxBlocks, (hw + 255) / 256);
+    for (int k = 0; k < k_steps; ++k) {
+        // every step size is taken at the current iterate, before any slice changes
+        slice_maxima(p, slices, st);
+        for (int b = 0; b < hp.nb; ++b) {
+            int64_t s0 = (int64_t)b * hp.B;
+            int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
+            fp.pos_list = p->at<int>(p->L.pos_list) + s0;
+            launch_fused(p, kAdjoint, fp, count, st);
+            scatter(p, b, count, 0, M, g, w, b > 0, st);
+            int n_loss;
+            const double *lsrc = loss_entries(p, count, &n_loss);
+            loss_sum_kernel<<<1, 256, 0, st>>>(lsrc, n_loss, total, b > 0);
+        }
+        const bool last = (k + 1 == k_steps);
+        for (int m = 0; m < M; ++m) {
+            max_partial_kernel<<<dim3(wblocks, 1), 256, 0, st>>>(nullptr, w + (size_t)m * hw, hw, part);
+            max_final_kernel<<<1, 256, 0, st>>>(part, wblocks, maxw + m);
+            step_size_kernel<<<1, 1, 0, st>>>(p->at<float>(p->L.maxt2), m + 1, M, maxw + m, step_norm(p), 1.0,
+                                              mu + m, (last && mu_out) ? mu_out + m : nullptr, total,
+                                              last ? loss_out : nullptr);
+        }
+        for (int m = 0; m < M; ++m)
+            update_kernel<<<(int)std::min<long long>(4096, (hw + 255) / 256), 256, 0, st>>>(
+                reinterpret_cast<float2 *>(slices) + (size_t)m * hw, g + (size_t)m * hw, hw, mu + m);
+    }
+    return check_hip("ms_full_step");
 }
 
 ms_status ms_probe_step(ms_plan *p, hipStream_t st, int32_t k_steps, ms_c64 *probe, const ms_c64 *slices,

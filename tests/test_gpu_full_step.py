@@ -1,0 +1,99 @@
+"""GPU parity of the full-gradient (Jacobi) step and of several inner steps (K > 1) against
+the oracle, on both execution paths, for both objectives, batched and unbatched."""
+import numpy as np
+import pytest
+
+from parity_cases import make_case, rel, small_geometry, small_positions
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+_CASES = {}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def case_for(n):
+    if n not in _CASES:
+        g = small_geometry(n, n_slices=3, seed=31)
+        print(f"[case] full step n={n}", flush=True)
+        _CASES[n] = make_case(g, positions=small_positions(g))
+    return _CASES[n]
+
+
+def _t(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def _plan(c, dev, path, objective=0, budget=0):
+    from paper_2205_03902_amd import abi
+    plan = abi.Plan.from_geometry(c.geo, positions=c.model.positions, budget_bytes=budget, device=dev)
+    plan.set_path(path)
+    plan.set_objective(objective)
+    return plan
+
+
+def _oracle(c, objective):
+    import oracle
+    g = c.geo
+    return oracle.Model(g.n, g.obj_h, g.obj_w, g.n_slices, c.model.positions, g.gaps(), g.pixel_size, g.wavelength,
+                        objective=objective)
+
+
+@pytest.mark.parametrize("n,path,objective", [(64, 1, 0), (128, 1, 0), (64, 2, 0), (256, 2, 0), (64, 1, 1),
+                                              (256, 2, 1)])
+def test_full_step_matches_the_oracle(dev, n, path, objective):
+    c = case_for(n)
+    plan = _plan(c, dev, path, objective)
+    md = _oracle(c, objective)
+    M = c.geo.n_slices
+    s = _t(c.start, dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    mu = torch.zeros(M, dtype=torch.float64, device=dev)
+    plan.full_step(1, _t(c.probe, dev), s, _t(c.measured, dev), loss=loss, mu=mu)
+    ref_s, ref_l, ref_mu = md.full_step(c.probe, c.start, c.measured, 1)
+    assert abs(loss.item() - ref_l) <= 1e-5 * max(ref_l, 1e-3 * c.measured.sum())
+    assert np.abs(mu.cpu().numpy() / ref_mu - 1).max() < 1e-5
+    got = s.cpu().numpy()
+    assert rel(got, ref_s) < 1e-5
+    assert rel(got - c.start, ref_s - c.start) < 1e-3
+
+
+@pytest.mark.parametrize("n,path", [(64, 1), (256, 2)])
+def test_several_inner_steps(dev, n, path):
+    c = case_for(n)
+    plan = _plan(c, dev, path)
+    md = _oracle(c, 0)
+    p, m = _t(c.probe, dev), _t(c.measured, dev)
+    out = torch.zeros(2, dtype=torch.float64, device=dev)
+    s = _t(c.start, dev)
+    plan.layer_step(1, 3, p, s, m, loss=out[0:1], mu=out[1:2])
+    ref_s, ref_l, ref_mu = md.layer_step(c.probe, c.start, c.measured, 1, 3)
+    assert abs(out[0].item() - ref_l) / ref_l < 1e-5 and abs(out[1].item() - ref_mu) / ref_mu < 1e-5
+    assert rel(s.cpu().numpy() - c.start, ref_s - c.start) < 1e-3
+    s = _t(c.start, dev)
+    mu = torch.zeros(c.geo.n_slices, dtype=torch.float64, device=dev)
+    plan.full_step(2, p, s, m, loss=out[0:1], mu=mu)
+    ref_s, ref_l, ref_mu = md.full_step(c.probe, c.start, c.measured, 2)
+    assert abs(out[0].item() - ref_l) / ref_l < 1e-5
+    assert rel(s.cpu().numpy() - c.start, ref_s - c.start) < 1e-3
+
+
+def test_batched_full_step_equals_one_batch(dev):
+    from paper_2205_03902_amd import abi
+    c = case_for(64)
+    one = _plan(c, dev, 1)
+    ws = abi.workspace_size(one.pb)
+    n2 = 64 * 64
+    per_pos = c.geo.n_slices * n2 * 12 + n2 * 16
+    small = _plan(c, dev, 1, budget=ws - 6 * per_pos)
+    assert 1 < small.batch < c.geo.n_pos
+    p, m = _t(c.probe, dev), _t(c.measured, dev)
+    s1, s2 = _t(c.start, dev), _t(c.start, dev)
+    one.full_step(1, p, s1, m)
+    small.full_step(1, p, s2, m)
+    assert rel(s2.cpu().numpy() - c.start, s1.cpu().numpy() - c.start) < 1e-6
