@@ -61,6 +61,7 @@ def lib():
         L.orc_propagator.restype = None
         L.orc_propagator.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, P]
         L.orc_probe.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, P]
+        L.orc_probe_aberrated.argtypes = [C.c_int] + [C.c_double] * 7 + [P]
         L.orc_shift.argtypes = [P, C.c_int, C.c_double, C.c_double, P]
         L.orc_unshift.argtypes = [P, C.c_int, C.c_double, C.c_double, P]
         L.orc_forward.argtypes = [C.POINTER(Problem), P, P, P, P]
@@ -132,6 +133,14 @@ def probe(n, dx, lam, alpha, defocus):
     p = np.empty((n, n), dtype=np.complex128)
     _check(lib().orc_probe(n, float(dx), float(lam), float(alpha), float(defocus), _ptr(p)), "probe")
     return p
+
+
+def probe_aberrated(n, dx, lam, alpha, c1, a1=0.0, phi_a1=0.0, c3=0.0):
+    """Probe with defocus C1, twofold astigmatism A1 at phi_A1 and spherical aberration C3."""
+    out = np.empty((n, n), dtype=np.complex128)
+    _check(lib().orc_probe_aberrated(int(n), float(dx), float(lam), float(alpha), float(c1), float(a1),
+                                     float(phi_a1), float(c3), _ptr(out)), "probe_aberrated")
+    return out
 
 
 def shift(p, fy, fx):

@@ -138,6 +138,39 @@ void orc_propagator(int n, double dx, double lambda, double dz, double tilt_y, d
  * propagator of the same equation with distance `defocus`; the factor
  * (-1)^(ky + kx) moves the probe centre from (0, 0) to (n/2, n/2); the result
  * is scaled to unit energy. */
+int orc_probe_aberrated(int n, double dx, double lambda, double alpha, double c1, double a1, double phi_a1,
+                        double c3, double complex *p)
+{
+    if (!is_pow2(n) || n < 2) return -1;
+    double *q = (double *)malloc(sizeof(double) * (size_t)n);
+    orc_fftfreq(n, dx, q);
+    for (int y = 0; y < n; ++y) {
+        for (int x = 0; x < n; ++x) {
+            double q2 = q[y] * q[y] + q[x] * q[x];
+            double complex a = 0.0;
+            if (lambda * sqrt(q2) <= alpha) {
+                /* chi = pi lambda C1 q^2 + pi lambda A1 q^2 cos 2(phi - phi_A1) + pi/2 lambda^3 C3 q^4,
+                 * the aperture multiplied by exp(-i chi) (C1 alone: the propagator of eq.
+                 * fresnel_element over the defocus distance) */
+                double phi = atan2(q[y], q[x]);
+                double chi = PI * lambda * c1 * q2 + PI * lambda * a1 * q2 * cos(2.0 * (phi - phi_a1))
+                             + 0.5 * PI * lambda * lambda * lambda * c3 * q2 * q2;
+                a = cos(chi) - I * sin(chi);
+                if ((x + y) & 1) a = -a;
+            }
+            p[(size_t)y * n + x] = a;
+        }
+    }
+    free(q);
+    orc_fft2d(p, n, +1);
+    double e = 0.0;
+    for (size_t i = 0; i < (size_t)n * n; ++i) e += creal(p[i]) * creal(p[i]) + cimag(p[i]) * cimag(p[i]);
+    if (e <= 0.0) return -1;
+    double s = 1.0 / sqrt(e);
+    for (size_t i = 0; i < (size_t)n * n; ++i) p[i] *= s;
+    return 0;
+}
+
 int orc_probe(int n, double dx, double lambda, double alpha, double defocus, double complex *p)
 {
     if (!is_pow2(n) || n < 2) return -1;

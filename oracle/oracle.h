@@ -84,6 +84,13 @@ void orc_propagator(int n, double dx, double lambda, double dz, double tilt_y, d
  * `defocus`, centred at (n/2, n/2) and scaled to sum |p|^2 = 1. */
 int orc_probe(int n, double dx, double lambda, double alpha, double defocus, double complex *p);
 
+/* The same probe with a probe-forming lens that has, besides defocus C1, twofold
+ * astigmatism A1 at angle phi_A1 and spherical aberration C3 (A, rad): the aperture times
+ * exp(-i chi(q)), chi = pi lambda C1 q^2 + pi lambda A1 q^2 cos 2(phi - phi_A1)
+ * + pi/2 lambda^3 C3 q^4 with phi the azimuth of q; C1 alone gives orc_probe. */
+int orc_probe_aberrated(int n, double dx, double lambda, double alpha, double c1, double a1, double phi_a1,
+                        double c3, double complex *p);
+
 /* Sub-pixel shift out = F^{-1}( F p * exp(-2 pi i (ky fy + kx fx) / n) ), identity when fy = fx = 0. */
 int orc_shift(const double complex *p, int n, double fy, double fx, double complex *out);
 

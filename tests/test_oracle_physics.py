@@ -121,3 +121,41 @@ def test_shift_integer_is_roll_and_adjoint(orc):
     # two half-pixel shifts compose to a one-pixel roll (the Nyquist bin uses k = -N/2)
     h2 = orc.shift(orc.shift(p, 0.5, 0.0), 0.5, 0.0)
     assert np.abs(h2 - np.roll(p, 1, axis=0)).max() < 1e-12
+
+
+def test_aberrated_probe_with_defocus_only_is_the_probe(orc):
+    a = orc.probe_aberrated(32, 0.2, 0.0487, 0.03, 40.0)
+    b = orc.probe(32, 0.2, 0.0487, 0.03, 40.0)
+    assert np.abs(a - b).max() < 1e-13
+
+
+def test_aberrated_probe_is_the_disk_sum_of_its_definition(orc):
+    """Brute-force inverse DFT over the aperture (no FFT) with the aberration phase
+    chi = pi lam C1 q^2 + pi lam A1 q^2 cos 2(phi - phi_A1) + pi/2 lam^3 C3 q^4."""
+    n, dx, lam, alpha = 16, 0.2, 0.0487, 0.05
+    c1, a1, pa, c3 = 30.0, 12.0, 0.4, 2.0e5
+    got = orc.probe_aberrated(n, dx, lam, alpha, c1, a1, pa, c3)
+    k = np.fft.fftfreq(n) * n
+    want = np.zeros((n, n), complex)
+    yy, xx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    for iy in range(n):
+        for ix in range(n):
+            qy, qx = k[iy] / (n * dx), k[ix] / (n * dx)
+            q = np.hypot(qy, qx)
+            if lam * q > alpha:
+                continue
+            chi = (np.pi * lam * c1 * q * q + np.pi * lam * a1 * q * q * np.cos(2 * (np.arctan2(qy, qx) - pa))
+                   + 0.5 * np.pi * lam ** 3 * c3 * q ** 4)
+            want += np.exp(-1j * chi) * (-1.0) ** (iy + ix) * np.exp(2j * np.pi * (k[iy] * yy + k[ix] * xx) / n)
+    want /= np.linalg.norm(want)
+    assert np.abs(got - want).max() < 1e-12
+
+
+def test_astigmatism_rotation_and_spherical_symmetry(orc):
+    n, dx, lam, alpha = 32, 0.2, 0.0487, 0.03
+    a = orc.probe_aberrated(n, dx, lam, alpha, 20.0, 15.0, 0.3)
+    b = orc.probe_aberrated(n, dx, lam, alpha, 20.0, -15.0, 0.3 + np.pi / 2)
+    assert np.abs(a - b).max() < 1e-12
+    s = orc.probe_aberrated(n, dx, lam, alpha, 20.0, 0.0, 0.0, 5.0e5)
+    assert np.abs(s - s.T).max() < 1e-12          # rotationally symmetric aberrations
+    assert np.abs(a - a.T).max() > 1e-3           # astigmatism is not
