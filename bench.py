@@ -230,6 +230,26 @@ def main():
         h = layerwise.reconstruct(plan, pr, sl, measured, sweeps=1, k_steps=1, probe_steps=1)
         extras["sweep_ms"] = h.seconds * 1e3
         extras["sweep_losses"] = [h.loss[0], h.loss[-1]]
+        # the full-gradient (Jacobi) variant from the same start: 4 steps against one sweep,
+        # with the layer steps as they are and averaged (step scale 1/M)
+        end = torch.zeros(1, dtype=torch.float64, device=dev)
+        for tag, scale in (("full_step", 1.0), ("full_step_avg", 1.0 / geo.n_slices)):
+            sl = slices.clone()
+            fl = torch.zeros(1, dtype=torch.float64, device=dev)
+            losses = []
+            torch.cuda.synchronize()
+            t0f = time.perf_counter()
+            for _ in range(4):
+                plan.full_step(1, probe, sl, measured, loss=fl, step_scale=scale)
+                losses.append(fl.clone())
+            torch.cuda.synchronize()
+            extras[f"{tag}_ms"] = (time.perf_counter() - t0f) * 1e3 / 4
+            plan.adjoint(probe, sl, measured, grad_slices=gs, grad_probe=gp, loss=end)
+            extras[f"{tag}_losses"] = [x.item() for x in losses] + [end.item()]
+        sl2 = slices.clone()
+        h2 = layerwise.reconstruct(plan, probe.clone(), sl2, measured, sweeps=1)
+        plan.adjoint(probe, sl2, measured, grad_slices=gs, grad_probe=gp, loss=end)
+        extras["sweep_loss_after"] = end.item()
         extras["pass_model_bytes"] = pass_bytes(geo)
 
     out = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,

@@ -125,6 +125,14 @@ ms_status ms_plan_set_objective(ms_plan *plan, int32_t objective);
 ms_status ms_make_probe(ms_plan *plan, hipStream_t stream, double alpha, double defocus,
                         ms_c64 *probe_out);
 
+/* The probe of a lens with aberrations beyond defocus (experimental probes, Sec. 5.3 and
+ * the outlook of Sec. 6): the disk times exp(-i chi(q)),
+ *   chi = pi lambda C1 q^2 + pi lambda A1 q^2 cos 2(phi - phi_A1) + pi/2 lambda^3 C3 q^4,
+ * phi the azimuth of q.  aberrations (host, 4 doubles): C1 (defocus, A), A1 (twofold
+ * astigmatism, A), phi_A1 (rad), C3 (spherical aberration, A).  C1 alone is ms_make_probe. */
+ms_status ms_make_probe_aberrated(ms_plan *plan, hipStream_t stream, double alpha, const double *aberrations,
+                                  ms_c64 *probe_out);
+
 /* Forward model (Sec. 2.1): intensity_out (S x N x N) = |F E_M^s|^2 and, if
  * exit_out is not NULL, the exit waves E_M^s (S x N x N). */
 ms_status ms_forward(ms_plan *plan, hipStream_t stream, const ms_c64 *probe, const ms_c64 *slices,
@@ -155,12 +163,14 @@ ms_status ms_layer_step(ms_plan *plan, hipStream_t stream, int32_t layer, int32_
  * contrasts with the layer-wise method.  One fwd+adj pass gives the gradient of every
  * slice; each slice then takes the step of a layer step of Algorithm 1 (its own
  * mu_m = 1 / (N^2 prod_{m' > m} max|t_m'|^2 max_pixel sum_s |psi_m^s|^2), halved for the
- * Poisson objective), all from the same iterate (a Jacobi update instead of the
- * Gauss-Seidel sweep; unlike a layer step it has no descent guarantee).  slices
+ * Poisson objective) times step_scale, all from the same iterate (a Jacobi update
+ * instead of the Gauss-Seidel sweep).  With step_scale = 1 the M simultaneous layer
+ * steps overshoot (each is sized for moving its slice alone; there is no descent
+ * guarantee); 1/M averages them.  step_scale must be positive and finite.  slices
  * (in/out): all M slices change.  loss_out (device FP64 or NULL): the loss at the
  * iterate before the last step; mu_out (device FP64 [M] or NULL): that step's sizes. */
-ms_status ms_full_step(ms_plan *plan, hipStream_t stream, int32_t k_steps, const ms_c64 *probe, ms_c64 *slices,
-                       const float *measured, double *loss_out, double *mu_out);
+ms_status ms_full_step(ms_plan *plan, hipStream_t stream, int32_t k_steps, double step_scale, const ms_c64 *probe,
+                       ms_c64 *slices, const float *measured, double *loss_out, double *mu_out);
 
 /* k_steps amplitude-flow steps on the probe (Sec. 3.5) over the positions in
  * `subset` ((host) n_subset indices in [0, S); NULL = all positions):

@@ -68,7 +68,7 @@ def lib():
         L.orc_loss_grad.argtypes = [C.POINTER(Problem), P, P, P, P, C.c_long, C.c_int, P, P, P, P]
         L.orc_layer_step.argtypes = [C.POINTER(Problem), P, P, P, C.c_int, C.c_int, P, P]
         L.orc_probe_step.argtypes = [C.POINTER(Problem), P, P, P, P, C.c_long, C.c_int, P, P]
-        L.orc_full_step.argtypes = [C.POINTER(Problem), P, P, P, C.c_int, P, P]
+        L.orc_full_step.argtypes = [C.POINTER(Problem), P, P, P, C.c_int, C.c_double, P, P]
         _lib = L
     return _lib
 
@@ -217,13 +217,13 @@ class Model:
                                     int(k_steps), _ptr(loss), _ptr(mu)), "layer_step")
         return sl, float(loss[0]), float(mu[0])
 
-    def full_step(self, probe, slices, measured, k_steps=1):
+    def full_step(self, probe, slices, measured, k_steps=1, step_scale=1.0):
         """Returns (new slices, loss before the last step, the M step sizes of the last step)."""
         pr, sl, ms = _c128(probe), _c128(slices).copy(), _f64(measured)
         loss = np.zeros(1)
         mu = np.zeros(self.n_slices)
-        _check(lib().orc_full_step(C.byref(self.pb), _ptr(pr), _ptr(sl), _ptr(ms), int(k_steps), _ptr(loss),
-                                   _ptr(mu)), "full_step")
+        _check(lib().orc_full_step(C.byref(self.pb), _ptr(pr), _ptr(sl), _ptr(ms), int(k_steps), float(step_scale),
+                                   _ptr(loss), _ptr(mu)), "full_step")
         return sl, float(loss[0]), mu
 
     def probe_step(self, probe, slices, measured, subset=None, k_steps=1):

@@ -564,9 +564,9 @@ int orc_layer_step(const orc_problem *pb, const double complex *probe, double co
 }
 
 int orc_full_step(const orc_problem *pb, const double complex *probe, double complex *slices,
-                  const double *measured, int k_steps, double *loss_out, double *mu_out)
+                  const double *measured, int k_steps, double step_scale, double *loss_out, double *mu_out)
 {
-    if (check_problem(pb) || k_steps < 0) return -1;
+    if (check_problem(pb) || k_steps < 0 || !(step_scale > 0.0)) return -1;
     const int M = pb->n_slices;
     size_t hw = (size_t)pb->obj_h * pb->obj_w;
     double n2 = (double)pb->n * (double)pb->n;
@@ -588,6 +588,7 @@ int orc_full_step(const orc_problem *pb, const double complex *probe, double com
             for (int m = l + 1; m < M; ++m) prod *= max_abs2(slices + (size_t)m * hw, hw);
             mu[l] = (wmax > 0.0 && prod > 0.0) ? 1.0 / (n2 * prod * wmax) : 0.0;
             if (pb->objective == ORC_POISSON) mu[l] *= 0.5;
+            mu[l] *= step_scale;
         }
         if (rc) break;
         for (int l = 0; l < M; ++l) {

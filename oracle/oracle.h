@@ -122,10 +122,11 @@ int orc_layer_step(const orc_problem *pb, const double complex *probe, double co
 /* K full-gradient steps (the gradient-based alternative the introduction contrasts with
  * the layer-wise method): every slice takes the step it would take in a layer step of
  * Algorithm 1, all from the same iterate (Jacobi), i.e. t_m -= mu_m dL/dconj(t_m) with
- * mu_m the layer-step size of slice m.  loss_out: loss at the iterate before the last
- * step; mu_out (M values, may be NULL): the step sizes of the last step. */
+ * mu_m the layer-step size of slice m times step_scale (> 0; 1 / M averages the M layer
+ * steps).  loss_out: loss at the iterate before the last step; mu_out (M values, may be
+ * NULL): the step sizes of the last step. */
 int orc_full_step(const orc_problem *pb, const double complex *probe, double complex *slices,
-                  const double *measured, int k_steps, double *loss_out, double *mu_out);
+                  const double *measured, int k_steps, double step_scale, double *loss_out, double *mu_out);
 
 /* K amplitude-flow steps on the probe over `subset` (NULL = all), in place. */
 int orc_probe_step(const orc_problem *pb, double complex *probe, const double complex *slices,

@@ -23,7 +23,7 @@ MS_OBJECTIVE_AMPLITUDE, MS_OBJECTIVE_POISSON = 0, 1
 # every entry point declared in include/ms.h
 SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
            "ms_plan_set_path", "ms_plan_set_objective",
-           "ms_make_probe", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_profile_begin",
+           "ms_make_probe", "ms_make_probe_aberrated", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_profile_begin",
            "ms_profile_end", "ms_last_error")
 
 
@@ -68,6 +68,8 @@ def lib():
         L.ms_plan_set_objective.argtypes = [P, I32]
         L.ms_make_probe.restype = I32
         L.ms_make_probe.argtypes = [P, P, D, D, P]
+        L.ms_make_probe_aberrated.restype = I32
+        L.ms_make_probe_aberrated.argtypes = [P, P, D, P, P]
         L.ms_forward.restype = I32
         L.ms_forward.argtypes = [P, P, P, P, P, P]
         L.ms_adjoint.restype = I32
@@ -75,7 +77,7 @@ def lib():
         L.ms_layer_step.restype = I32
         L.ms_layer_step.argtypes = [P, P, I32, I32, P, P, P, P, P]
         L.ms_full_step.restype = I32
-        L.ms_full_step.argtypes = [P, P, I32, P, P, P, P, P]
+        L.ms_full_step.argtypes = [P, P, I32, D, P, P, P, P, P]
         L.ms_probe_step.restype = I32
         L.ms_probe_step.argtypes = [P, P, I32, P, P, P, P, I64, P, P]
         L.ms_profile_begin.restype = I32
@@ -216,6 +218,15 @@ class Plan:
                "ms_make_probe")
         return out
 
+    def make_probe_aberrated(self, alpha: float, c1: float, a1: float = 0.0, phi_a1: float = 0.0, c3: float = 0.0):
+        """Probe with defocus C1, twofold astigmatism A1 at phi_A1 and spherical aberration C3 (A, rad)."""
+        torch = _torch()
+        out = torch.empty((self.n, self.n), dtype=torch.complex64, device=self.device)
+        ab = np.array([c1, a1, phi_a1, c3], dtype=np.float64)
+        _check(lib().ms_make_probe_aberrated(self._h, self._stream(), float(alpha), ab.ctypes.data, _ptr(out)),
+               "ms_make_probe_aberrated")
+        return out
+
     def forward(self, probe, slices, exit_waves: bool = False, out=None):
         torch = _torch()
         self._probe(probe)
@@ -255,13 +266,13 @@ class Plan:
         _check(lib().ms_layer_step(self._h, self._stream(), int(layer), int(k_steps), _ptr(probe), _ptr(slices),
                                    _ptr(measured), _ptr(loss), _ptr(mu)), "ms_layer_step")
 
-    def full_step(self, k_steps: int, probe, slices, measured, loss=None, mu=None):
+    def full_step(self, k_steps: int, probe, slices, measured, loss=None, mu=None, step_scale: float = 1.0):
         """In place on every slice; loss: optional float64 device scalar, mu: optional float64 device [M]."""
         self._probe(probe)
         self._slices(slices)
         self._patterns(measured)
-        _check(lib().ms_full_step(self._h, self._stream(), int(k_steps), _ptr(probe), _ptr(slices), _ptr(measured),
-                                  _ptr(loss), _ptr(mu)), "ms_full_step")
+        _check(lib().ms_full_step(self._h, self._stream(), int(k_steps), float(step_scale), _ptr(probe), _ptr(slices),
+                                  _ptr(measured), _ptr(loss), _ptr(mu)), "ms_full_step")
 
     def probe_step(self, k_steps: int, probe, slices, measured, subset=None, loss=None, mu=None):
         """In place on probe; subset: host sequence of position indices or None for all."""

@@ -442,7 +442,7 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_filter_kernel
 // Pass 3: scale to unit energy.
 template <int N, bool ROW>
 __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_probe_kernel(
-    float2 *out, double *energy_part, const float2 *twg, double dx, double lambda, double alpha, double defocus)
+    float2 *out, double *energy_part, const float2 *twg, double dx, double lambda, double alpha, Aberrations ab)
 {
 #pragma clang fp contract(off)
     using Wn = Win<N>;
@@ -459,7 +459,6 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_probe_kernel(
     float2 *xb = xbuf + lloc * Wn::LD;
     float2 v[16];
     if (ROW) {
-        const double PI = 3.14159265358979323846264338327950288;
         const double nd = (double)N * dx;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -470,7 +469,7 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_probe_kernel(
             const double q2 = qy * qy + qx * qx;
             float2 a = make_float2(0.f, 0.f);
             if (lambda * sqrt(q2) <= alpha) {
-                const double ph = -PI * defocus * lambda * q2;
+                const double ph = -aberration_phase(ab, lambda, qy, qx);
                 const double sgn = ((iy + ix) & 1) ? -1.0 : 1.0;
                 a = make_float2((float)(sgn * cos(ph)), (float)(sgn * sin(ph)));
             }

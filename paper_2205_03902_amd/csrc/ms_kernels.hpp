@@ -508,9 +508,26 @@ __global__ __launch_bounds__(Win<N>::NT) void window_filter_kernel(const float2 
 
 // Probe of Sec. 2.1 / Fig. 3: aperture lambda |q| <= alpha times the defocus propagator
 // times (-1)^(ky+kx) (centre at N/2), inverse 2D DFT, unit energy.  One workgroup.
+// Aperture phase of the probe-forming lens: defocus C1, twofold astigmatism A1 at phi_A1,
+// spherical aberration C3 (A, rad).  chi = pi lambda (C1 q^2 + A1 ((qx^2 - qy^2) cos 2 phi_A1
+// + 2 qx qy sin 2 phi_A1)) + pi/2 lambda^3 C3 q^4, i.e. A1 q^2 cos 2(phi - phi_A1) written
+// without the azimuth.  The probe takes exp(-i chi).
+struct Aberrations {
+    double c1, a1, cos2a, sin2a, c3;
+};
+
+__device__ __forceinline__ double aberration_phase(const Aberrations &ab, double lambda, double qy, double qx)
+{
+#pragma clang fp contract(off)
+    const double PI = 3.14159265358979323846264338327950288;
+    const double q2 = qy * qy + qx * qx;
+    const double astig = (qx * qx - qy * qy) * ab.cos2a + 2.0 * qx * qy * ab.sin2a;
+    return PI * lambda * (ab.c1 * q2 + ab.a1 * astig) + 0.5 * PI * lambda * lambda * lambda * ab.c3 * q2 * q2;
+}
+
 template <int N>
 __global__ __launch_bounds__(Win<N>::NT) void make_probe_kernel(float2 *out, const float2 *twg, double dx,
-                                                                double lambda, double alpha, double defocus)
+                                                                double lambda, double alpha, Aberrations ab)
 {
 #pragma clang fp contract(off)
     using Wn = Win<N>;
@@ -519,7 +536,6 @@ __global__ __launch_bounds__(Win<N>::NT) void make_probe_kernel(float2 *out, con
     __shared__ double red[(Wn::NT + 63) / 64];
     __shared__ double total;
     const int line = threadIdx.x / R, j = threadIdx.x % R;
-    const double PI = 3.14159265358979323846264338327950288;
     __shared__ float2 s_tw[Wn::TW_WORDS];
     stage<N>(s_tw, twg, Wn::TW_WORDS);
     __syncthreads();
@@ -536,7 +552,7 @@ __global__ __launch_bounds__(Win<N>::NT) void make_probe_kernel(float2 *out, con
         double q2 = qy * qy + qx * qx;
         float2 a = make_float2(0.f, 0.f);
         if (lambda * sqrt(q2) <= alpha) {
-            double ph = -PI * defocus * lambda * q2;
+            double ph = -aberration_phase(ab, lambda, qy, qx);
             double sgn = ((iy + ix) & 1) ? -1.0 : 1.0;
             a = make_float2((float)(sgn * cos(ph)), (float)(sgn * sin(ph)));
         }

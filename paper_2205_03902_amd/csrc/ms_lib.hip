@@ -819,13 +819,10 @@ ms_status ms_plan_set_path(ms_plan *p, int32_t path)
     }
 }
 
-ms_status ms_make_probe(ms_plan *p, hipStream_t st, double alpha, double defocus, ms_c64 *probe_out)
+namespace {
+
+ms_status make_probe(ms_plan *p, hipStream_t st, double alpha, const Aberrations &ab, ms_c64 *probe_out)
 {
-    g_err.clear();
-    if (!p || !probe_out) return fail(MS_ERR_INVALID_ARG, "NULL argument");
-    if (!aligned8(probe_out)) return fail(MS_ERR_INVALID_ARG, "probe_out must be 8-byte aligned");
-    if (!(alpha > 0.0) || !std::isfinite(alpha) || !std::isfinite(defocus))
-        return fail(MS_ERR_INVALID_ARG, "alpha must be positive, both finite");
     float2 *out = reinterpret_cast<float2 *>(probe_out);
     const float2 *tw = p->at<float2>(p->L.tw);
     if (p->hp.n == 256) {
@@ -833,18 +830,44 @@ ms_status ms_make_probe(ms_plan *p, hipStream_t st, double alpha, double defocus
         constexpr int N = 256, G = N / kLinesPerGroup;
         double *part = p->at<double>(p->L.energy);
         dim3 grid(G, 1), block(kLinesPerGroup * Win<N>::R);
-        line_probe_kernel<N, true><<<grid, block, 0, st>>>(out, part, tw, p->dx, p->lambda, alpha, defocus);
-        line_probe_kernel<N, false><<<grid, block, 0, st>>>(out, part, tw, p->dx, p->lambda, alpha, defocus);
+        line_probe_kernel<N, true><<<grid, block, 0, st>>>(out, part, tw, p->dx, p->lambda, alpha, ab);
+        line_probe_kernel<N, false><<<grid, block, 0, st>>>(out, part, tw, p->dx, p->lambda, alpha, ab);
         scale_unit_energy_kernel<<<64, 256, 0, st>>>(out, (long long)N * N, part, G);
         return check_hip("ms_make_probe");
     }
     switch (p->hp.n) {
-        case 16: make_probe_kernel<16><<<1, Win<16>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, defocus); break;
-        case 32: make_probe_kernel<32><<<1, Win<32>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, defocus); break;
-        case 64: make_probe_kernel<64><<<1, Win<64>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, defocus); break;
-        default: make_probe_kernel<128><<<1, Win<128>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, defocus); break;
+        case 16: make_probe_kernel<16><<<1, Win<16>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, ab); break;
+        case 32: make_probe_kernel<32><<<1, Win<32>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, ab); break;
+        case 64: make_probe_kernel<64><<<1, Win<64>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, ab); break;
+        default: make_probe_kernel<128><<<1, Win<128>::NT, 0, st>>>(out, tw, p->dx, p->lambda, alpha, ab); break;
     }
     return check_hip("ms_make_probe");
+}
+
+}  // namespace
+
+ms_status ms_make_probe(ms_plan *p, hipStream_t st, double alpha, double defocus, ms_c64 *probe_out)
+{
+    g_err.clear();
+    if (!p || !probe_out) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    if (!aligned8(probe_out)) return fail(MS_ERR_INVALID_ARG, "probe_out must be 8-byte aligned");
+    if (!(alpha > 0.0) || !std::isfinite(alpha) || !std::isfinite(defocus))
+        return fail(MS_ERR_INVALID_ARG, "alpha must be positive, both finite");
+    return make_probe(p, st, alpha, Aberrations{defocus, 0.0, 1.0, 0.0, 0.0}, probe_out);
+}
+
+ms_status ms_make_probe_aberrated(ms_plan *p, hipStream_t st, double alpha, const double *aberrations,
+                                  ms_c64 *probe_out)
+{
+    g_err.clear();
+    if (!p || !probe_out || !aberrations) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    if (!aligned8(probe_out)) return fail(MS_ERR_INVALID_ARG, "probe_out must be 8-byte aligned");
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(aberrations[i])) return fail(MS_ERR_INVALID_ARG, "aberrations must be finite");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(MS_ERR_INVALID_ARG, "alpha must be positive and finite");
+    const Aberrations ab{aberrations[0], aberrations[1], std::cos(2.0 * aberrations[2]), std::sin(2.0 * aberrations[2]),
+                         aberrations[3]};
+    return make_probe(p, st, alpha, ab, probe_out);
 }
 
 ms_status ms_forward(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c64 *slices, float *intensity_out,
@@ -951,13 +974,14 @@ ms_status ms_layer_step(ms_plan *p, hipStream_t st, int32_t layer, int32_t k_ste
     return check_hip("ms_layer_step");
 }
 
-ms_status ms_full_step(ms_plan *p, hipStream_t st, int32_t k_steps, const ms_c64 *probe, ms_c64 *slices,
-                       const float *measured, double *loss_out, double *mu_out)
+ms_status ms_full_step(ms_plan *p, hipStream_t st, int32_t k_steps, double step_scale, const ms_c64 *probe,
+                       ms_c64 *slices, const float *measured, double *loss_out, double *mu_out)
 {
     g_err.clear();
     if (!p || !probe || !slices || !measured) return fail(MS_ERR_INVALID_ARG, "NULL argument");
     const HostPlan &hp = p->hp;
     if (k_steps < 0) return fail(MS_ERR_INVALID_ARG, "k_steps must be >= 0");
+    if (!(step_scale > 0.0) || !std::isfinite(step_scale)) return fail(MS_ERR_INVALID_ARG, "step_scale must be > 0");
     if (!aligned8(probe) || !aligned8(slices) || !aligned8(loss_out) || !aligned8(mu_out) || ((uintptr_t)measured & 3))
         return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
     if (k_steps == 0) return MS_OK;
@@ -991,7 +1015,7 @@ ms_status ms_full_step(ms_plan *p, hipStream_t st, int32_t k_steps, const ms_c64
         for (int m = 0; m < M; ++m) {
             max_partial_kernel<<<dim3(wblocks, 1), 256, 0, st>>>(nullptr, w + (size_t)m * hw, hw, part);
             max_final_kernel<<<1, 256, 0, st>>>(part, wblocks, maxw + m);
-            step_size_kernel<<<1, 1, 0, st>>>(p->at<float>(p->L.maxt2), m + 1, M, maxw + m, step_norm(p), 1.0,
+            step_size_kernel<<<1, 1, 0, st>>>(p->at<float>(p->L.maxt2), m + 1, M, maxw + m, step_norm(p) / step_scale, 1.0,
                                               mu + m, (last && mu_out) ? mu_out + m : nullptr, total,
                                               last ? loss_out : nullptr);
         }

@@ -64,6 +64,17 @@ def test_full_step_matches_the_oracle(dev, n, path, objective):
 
 
 @pytest.mark.parametrize("n,path", [(64, 1), (256, 2)])
+def test_full_step_with_a_step_scale(dev, n, path):
+    c = case_for(n)
+    plan = _plan(c, dev, path)
+    md = _oracle(c, 0)
+    s = _t(c.start, dev)
+    plan.full_step(1, _t(c.probe, dev), s, _t(c.measured, dev), step_scale=1.0 / 3)
+    ref_s, _, _ = md.full_step(c.probe, c.start, c.measured, 1, step_scale=1.0 / 3)
+    assert rel(s.cpu().numpy() - c.start, ref_s - c.start) < 1e-3
+
+
+@pytest.mark.parametrize("n,path", [(64, 1), (256, 2)])
 def test_several_inner_steps(dev, n, path):
     c = case_for(n)
     plan = _plan(c, dev, path)

@@ -219,3 +219,17 @@ def test_edge_geometries(dev, kind):
     assert rel(inten.cpu().numpy(), ref_i) < TOL_FWD
     assert abs(loss.item() - ref_l) / ref_l < TOL_FWD
     assert rel(gs.cpu().numpy(), ref_gs) < TOL_GRAD and rel(gp.cpu().numpy(), ref_gp) < TOL_GRAD
+
+
+@pytest.mark.parametrize("n", [32, 128, 256])
+def test_make_probe_with_aberrations(dev, n):
+    """Astigmatism and spherical aberration on top of defocus (ms_make_probe_aberrated)."""
+    import oracle
+    from paper_2205_03902_amd import abi, configs
+    g = configs.small(n=n, obj=n + n // 2, n_slices=2)
+    plan = abi.Plan.from_geometry(g, device=dev)
+    got = plan.make_probe_aberrated(0.02, 120.0, 25.0, 0.7, 4.0e5).cpu().numpy()
+    ref = oracle.probe_aberrated(n, g.pixel_size, g.wavelength, 0.02, 120.0, 25.0, 0.7, 4.0e5)
+    assert rel(got, ref) < 2e-6
+    plain = plan.make_probe(0.02, 120.0).cpu().numpy()
+    assert rel(plain, oracle.probe(n, g.pixel_size, g.wavelength, 0.02, 120.0)) < 2e-6

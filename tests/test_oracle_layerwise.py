@@ -109,3 +109,10 @@ def test_full_step_is_every_layer_step_taken_from_the_same_iterate(orc):
     a, la, ma = one.full_step(p, start[:1], meas1)
     b, lb, mb = one.layer_step(p, start[:1], meas1, 0, 1)
     assert np.array_equal(a, b) and la == lb and ma[0] == mb
+    # a step scale multiplies every step size
+    md = orc.Model(n, obj, obj, m, pos, np.array([2.0, 1.5]), 0.2, 0.0487)
+    meas = md.forward(p, truth)
+    full, _, mu1 = md.full_step(p, start, meas)
+    half, _, mu2 = md.full_step(p, start, meas, step_scale=0.5)
+    assert np.allclose(mu2, 0.5 * mu1, rtol=1e-15)
+    assert np.allclose(half - start, 0.5 * (full - start), rtol=0, atol=1e-13)
