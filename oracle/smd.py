@@ -12,16 +12,19 @@ product path never imports it.  Plain dense numpy in the paper's order and notat
       A <- A - mu F^H ((|F A P| - sqrt(I)) o F A P / |F A P|) P^H,  mu = 1 / (N^2 ||P||^2),
     with the phase taken as 0 where F A P = 0;
   * step 2, eq. (Prox_Min): for l = 1..M, with the prefix R_l = O_M G_{M-1} ... G_l and
-    the suffix S_l = G_{l-1} O_{l-1} ... G_1 O_1 (R_M = S_1 = identity),
-      O_l <- Proj(O_l - mu lambda R_l^H (lambda R_l O_l S_l - A_hat) S_l^H),
-      mu = 1 / (lambda ||R_l|| ||S_l||)^2,
+    the suffix S_l = G_{l-1} O_{l-1} ... G_1 O_1 (R_M = S_1 = identity) of the slices of
+    iteration t (the paper's R_l^t, S_l^t: every layer of a pass sees the same slices),
+      O_l <- Proj(O_l - mu conj(lambda) diag(R_l^H (lambda R_l O_l S_l - A_hat) S_l^H)),
+      mu = 1 / c,  c = (|lambda| prod_{m != l} max|o_m|)^2 >= (|lambda| ||R_l|| ||S_l||)^2
+    (G_m is unitary, so each factor's norm is at most the largest entry of its diagonal),
     Proj keeping the diagonal scaled to unit Frobenius norm;
   * lambda = Tr(A_hat^H A~) / Tr(A~^H A~) (eq. Update Lambda), A~ = O_M prod G_m O_m;
   * the next A is lambda A~; the result is lambda^(1/M) O_m.
 
-Readings: the paper's lambda is a complex scalar here (the trace ratio is complex for
-complex A); mu uses spectral norms; F_2D is the unnormalised 2D DFT of the rest of the
-oracle, so ||F_2D||^2 = N^2.
+Readings: the paper's lambda is a complex scalar here, the least-squares value
+Tr(A~^H A_hat) / Tr(A~^H A~) (its trace ratio with the conjugation on A~, which is real
+lambda's formula when lambda is real); the matrix step uses the spectral norm of P;
+F_2D is the unnormalised 2D DFT of the rest of the oracle, so ||F_2D||^2 = N^2.
 """
 from __future__ import annotations
 
@@ -99,21 +102,23 @@ def project(d: np.ndarray) -> np.ndarray:
 
 
 def decompose_pass(a_hat: np.ndarray, slices: np.ndarray, lam: complex, gs):
-    """One pass over the layers l = 1..M (eq. Prox_Min), then the lambda update.
-    Returns (slices, lambda, A~)."""
-    slices = slices.copy()
+    """One pass over the layers l = 1..M (eq. Prox_Min) with the prefixes and suffixes of the
+    incoming slices, then the lambda update.  Returns (slices, lambda, A~)."""
+    old = slices.copy()
+    new = slices.copy()
     M = slices.shape[0]
+    peak = [np.abs(old[m]).max() for m in range(M)]
     for l in range(M):
-        r, s = prefix_suffix(slices, gs, l)
-        o = slices[l].reshape(-1)
+        r, s = prefix_suffix(old, gs, l)
+        o = old[l].reshape(-1)
         x = lam * (r @ (o[:, None] * s)) - a_hat
         grad = np.einsum("ik,ij,kj->k", np.conj(r), x, np.conj(s))      # diag(R^H X S^H)
-        mu = 1.0 / (abs(lam) * np.linalg.norm(r, 2) * np.linalg.norm(s, 2)) ** 2
-        o = project(o - mu * np.conj(lam) * grad)
-        slices[l] = o.reshape(slices[l].shape)
-    at = compose(slices, gs)
+        c = (abs(lam) * np.prod([peak[m] for m in range(M) if m != l])) ** 2
+        o = project(o - (1.0 / c) * np.conj(lam) * grad)
+        new[l] = o.reshape(old[l].shape)
+    at = compose(new, gs)
     lam = np.vdot(at, a_hat) / np.vdot(at, at)        # Tr(A~^H A_hat) / Tr(A~^H A~)
-    return slices, lam, at
+    return new, lam, at
 
 
 def algorithm2(probe, positions, meas, slices0, gs, iterations: int, a_steps: int):

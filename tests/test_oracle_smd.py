@@ -65,6 +65,15 @@ def test_lambda_is_the_least_squares_scale(orc):
         assert np.linalg.norm(a_hat - (lam + dl) * at) > res
 
 
+def test_prox_step_bound_dominates_the_spectral_norms(orc):
+    rng, pos, dz, gs, truth, probe, md = _setup(orc)
+    peak = [np.abs(truth[m]).max() for m in range(M)]
+    for l in range(M):
+        r, s = smd.prefix_suffix(truth, gs, l)
+        bound = np.prod([peak[m] for m in range(M) if m != l])
+        assert np.linalg.norm(r, 2) * np.linalg.norm(s, 2) <= bound * (1 + 1e-12)
+
+
 def test_normalised_truth_is_a_fixed_point_and_perturbed_starts_descend(orc):
     rng, pos, dz, gs, truth, probe, md = _setup(orc)
     unit = np.stack([smd.project(s.reshape(-1)).reshape(N, N) for s in truth])
