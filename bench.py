@@ -102,6 +102,60 @@ def cpu_baseline(geo, n_sample: int):
                       f"{secs:.2f} s wall, FP64"}
 
 
+FP32_MFMA_PEAK = 157.3e12   # flop/s, MI355X dense FP32 matrix peak (the complex GEMMs of Algorithm 2)
+
+
+def algorithm2_benchmark(n: int, m: int, iterations: int = 3, a_steps: int = 5, oracle_check: bool = False):
+    """Algorithm 2 (sparse matrix decomposition) on the full-field model: an N x N object, a
+    probe moved by integer shifts on an 8 x 8 grid (S = 64), M slices.  Measurements come from
+    the multislice forward of the layer-wise path (the two models agree for integer shifts of a
+    periodic object).  Reports ms per iteration (A estimate with `a_steps` steps, one
+    decomposition pass, the next A; the probe matrix and its norm are set up before the timed
+    region) and the GEMM rate against the FP32 matrix peak."""
+    import numpy as np
+    import torch
+
+    from paper_2205_03902_amd import abi, smd, synth
+    dev = torch.device("cuda:0")
+    step = n // 8
+    pos = np.array([[y * step, x * step] for y in range(8) for x in range(8)], dtype=np.float64)
+    S = pos.shape[0]
+    dx, lam = 0.2, 0.0251
+    dz = [2.0] * (m - 1)
+    ms = abi.Plan(n, n, n, m, pos, dz, dx, lam, device=dev)
+    probe = ms.make_probe(0.02, 30.0)
+    truth = torch.from_numpy(synth.unit_phase_field((m, n, n), 7, 0.5)).to(dev)
+    meas = ms.forward(probe, truth)
+    plan = smd.SmdPlan(n, m, pos, dz, dx, lam, device=dev)
+    start = torch.ones((m, n, n), dtype=torch.complex64, device=dev)
+    plan.set_probe(probe)
+    plan.iterate(meas, start.clone(), 1.0, 1, 1)                 # warm-up (rocBLAS kernel selection)
+    hist = torch.zeros(iterations, dtype=torch.float64, device=dev)
+    sl = start.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.iterate(meas, sl, 1.0, iterations, a_steps, hist)
+    torch.cuda.synchronize()
+    secs = (time.perf_counter() - t0) / iterations
+    n2 = n * n
+    macs = a_steps * 4 * n2 * n2 * S + (4 * (m - 1) + 2 * m) * n2 ** 3
+    res = {"n": n, "slices": m, "positions": S, "iterations": iterations, "a_steps": a_steps,
+           "ms_per_iteration": secs * 1e3, "gemm_tflops": 8 * macs / secs / 1e12,
+           "frac_of_fp32_matrix_peak": 8 * macs / secs / FP32_MFMA_PEAK,
+           "flops_per_iteration": 8 * macs, "matrix_loss": [float(h) for h in hist.cpu().numpy()]}
+    if oracle_check:
+        from oracle import smd as osmd
+        import oracle
+        pr = probe.cpu().numpy().astype(np.complex128)
+        gs = [osmd.propagator_matrix(oracle.propagator(n, dx, lam, d)) for d in dz]
+        mm = meas.cpu().numpy().reshape(S, n2).T.astype(np.float64)
+        t1 = time.perf_counter()
+        ro, rl, rh = osmd.algorithm2(pr, pos, mm, np.ones((m, n, n), complex), gs, iterations=1, a_steps=a_steps)
+        res["oracle_s_per_iteration"] = time.perf_counter() - t1
+        res["oracle_threads"] = oracle.max_threads()
+    return res
+
+
 def copy_calibration():
     """A plain device copy of known size, for scaling HBM traffic counters."""
     import torch
@@ -131,6 +185,8 @@ def main():
     ap.add_argument("--ttl-train", type=int, default=1000, help="training specimens of the time-to-loss run")
     ap.add_argument("--ttl-test", type=int, default=20, help="held-out specimens of the time-to-loss run")
     ap.add_argument("--ttl-epochs", type=int, default=12, help="training epochs of the time-to-loss run")
+    ap.add_argument("--algorithm2-only", type=int, default=0, metavar="N",
+                    help="time only Algorithm 2 at window N (M = 3) and print its JSON")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -143,6 +199,11 @@ def main():
     import torch
     if args.copy_calibration:
         copy_calibration()
+        return
+
+    if args.algorithm2_only:
+        torch.cuda.set_device(0)
+        print(json.dumps(algorithm2_benchmark(args.algorithm2_only, 3)), flush=True)
         return
 
     from paper_2205_03902_amd import abi, configs, datagen, layerwise, synth
@@ -251,6 +312,9 @@ def main():
         plan.adjoint(probe, sl2, measured, grad_slices=gs, grad_probe=gp, loss=end)
         extras["sweep_loss_after"] = end.item()
         extras["pass_model_bytes"] = pass_bytes(geo)
+        log("bench: Algorithm 2 (sparse matrix decomposition) at N = 32 and 64")
+        extras["algorithm2"] = [algorithm2_benchmark(32, 3, oracle_check=not args.no_cpu_baseline),
+                                algorithm2_benchmark(64, 3)]
 
     out = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",

@@ -9,12 +9,14 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libimsp.so")
 SOURCES = [os.path.join(PKG, "csrc", "ms_lib.hip"), os.path.join(PKG, "csrc", "unet_lib.hip"),
-           os.path.join(PKG, "csrc", "datagen_lib.hip")]
+           os.path.join(PKG, "csrc", "datagen_lib.hip"), os.path.join(PKG, "csrc", "smd_lib.hip")]
 HEADERS = [os.path.join(ROOT, "include", "ms.h"), os.path.join(ROOT, "include", "unet.h"),
            os.path.join(PKG, "csrc", "ms_kernels.hpp"), os.path.join(PKG, "csrc", "fft_lines.hpp"),
            os.path.join(PKG, "csrc", "line_kernels.hpp"), os.path.join(PKG, "csrc", "unet_kernels.hpp"),
-           os.path.join(ROOT, "include", "datagen.h"), os.path.join(PKG, "csrc", "datagen_kernels.hpp")]
+           os.path.join(ROOT, "include", "datagen.h"), os.path.join(PKG, "csrc", "datagen_kernels.hpp"),
+           os.path.join(ROOT, "include", "smd.h")]
 ARCH = "gfx950"
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 
 def hipcc() -> str:
@@ -29,7 +31,9 @@ def command(out: str = LIB) -> list:
             # packed FP32 instructions stay disabled in every kernel
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-            "-Wall", "-Wno-unused-result", "-o", out] + SOURCES
+            "-Wall", "-Wno-unused-result", "-o", out] + SOURCES + [
+            # the dense products of the sparse matrix decomposition are rocBLAS GEMMs
+            "-L", os.path.join(ROCM, "lib"), "-lrocblas", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
 
 
 def build(verbose: bool = False) -> str:

@@ -144,3 +144,39 @@ def test_datagen_rejects_bad_arguments_without_a_device():
     assert L.dg_poisson(None, None, 10, 64, 1e5, 1, 1, None) == abi.MS_ERR_INVALID_ARG
     assert L.dg_crop_phase(None, 1, 6, 32, 32, 0, 0, 64, 16, 8, 1) == abi.MS_ERR_INVALID_ARG
     assert L.dg_last_error().decode() != ""
+
+
+def test_smd_header_declares_the_binding_and_the_library_exports_it():
+    from paper_2205_03902_amd import smd
+    text = open(os.path.join(ROOT, "include", "smd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    declared = set(re.findall(r"\b(smd_[a-z_0-9]+)\s*\(", text))
+    assert declared == set(smd.SYMBOLS)
+    L = smd.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("kw", [dict(n=12), dict(n=128), dict(n_slices=0), dict(positions=[[0.5, 1.0]]),
+                                dict(wavelength=0.0), dict(dz=[float("nan")])])
+def test_smd_rejects_invalid_problems_without_a_device(kw):
+    from paper_2205_03902_amd import smd
+    args = dict(n=8, n_slices=2, positions=[[0, 0], [3, 5]], dz=[2.0], pixel_size=0.2, wavelength=0.0487)
+    args.update(kw)
+    pb, keep = smd.make_problem(**args)
+    out = C.c_size_t(0)
+    assert smd.lib().smd_workspace_size(C.byref(pb), C.byref(out)) == abi.MS_ERR_INVALID_ARG
+    assert smd.lib().smd_last_error().decode() != ""
+
+
+def test_smd_workspace_holds_the_dense_matrices():
+    from paper_2205_03902_amd import smd
+    pb, keep = smd.make_problem(32, 3, [[0, 0]] * 40, [2.0, 2.0], 0.2, 0.0487)
+    ws = smd.workspace_size(pb)
+    n2 = 32 * 32
+    # F, G_1..G_2, four scratch matrices, three prefixes and three suffixes
+    assert ws >= (1 + 2 + 4 + 3 + 3) * n2 * n2 * 8
+    assert ws < (1 + 2 + 4 + 3 + 3) * n2 * n2 * 8 + (64 << 20)
+    handle = C.c_void_p()
+    assert smd.lib().smd_plan_create(C.byref(pb), None, ws, C.byref(handle)) == abi.MS_ERR_INVALID_ARG
+    assert smd.lib().smd_set_probe(None, None, None) == abi.MS_ERR_INVALID_ARG
