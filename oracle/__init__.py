@@ -69,6 +69,7 @@ def lib():
         L.orc_layer_step.argtypes = [C.POINTER(Problem), P, P, P, C.c_int, C.c_int, P, P]
         L.orc_probe_step.argtypes = [C.POINTER(Problem), P, P, P, P, C.c_long, C.c_int, P, P]
         L.orc_full_step.argtypes = [C.POINTER(Problem), P, P, P, C.c_int, C.c_double, P, P]
+        L.orc_position_grad.argtypes = [C.POINTER(Problem), P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -207,6 +208,16 @@ class Model:
 
     def loss(self, probe, slices, measured, subset=None):
         return self.loss_grad(probe, slices, measured, subset, want_slices=False, want_probe=False)[0]
+
+    def position_grad(self, probe, slices, measured):
+        """Returns (loss, dL/dposition (S, 2), curvature bound (S, 2)), y then x."""
+        pr, sl, ms = _c128(probe), _c128(slices), _f64(measured)
+        g = np.empty((self.n_pos, 2))
+        c = np.empty((self.n_pos, 2))
+        loss = np.zeros(1)
+        _check(lib().orc_position_grad(C.byref(self.pb), _ptr(pr), _ptr(sl), _ptr(ms), _ptr(g), _ptr(c), _ptr(loss)),
+               "position_grad")
+        return float(loss[0]), g, c
 
     def layer_step(self, probe, slices, measured, layer, k_steps=1):
         """Returns (new slices, loss before the last step, step size of the last step)."""

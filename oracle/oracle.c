@@ -365,8 +365,29 @@ typedef struct {
     double complex *gs;    /* slice gradient accumulator (M x H x W or H x W) */
     double complex *gp;    /* probe gradient accumulator (n x n)              */
     double *w;             /* overlap accumulator (H x W)                     */
+    double *gpos, *cpos;   /* per-position gradient and curvature bound (S x 2), each s written once */
+    double tprod;          /* prod_m max |t_m|^2 (for cpos)                   */
     double loss;
 } accum;
+
+/* Derivative of the shifted probe P(y, x) = p(y - fy, x - fx) of orc_shift in its shift along
+ * `axis` (0: fy, 1: fx): the phase ramp e^{-2 pi i (k_y fy + k_x fx) / n} differentiated,
+ * i.e. multiplied by -2 pi i k / n with the same signed frequencies. */
+static void shift_derivative(const double complex *p, int n, double fy, double fx, int axis, double complex *out)
+{
+    size_t n2 = (size_t)n * n;
+    memcpy(out, p, sizeof(double complex) * n2);
+    orc_fft2d(out, n, -1);
+    for (int y = 0; y < n; ++y) {
+        for (int x = 0; x < n; ++x) {
+            double ky = (double)signed_k(y, n), kx = (double)signed_k(x, n);
+            double ph = -2.0 * PI * (ky * fy + kx * fx) / (double)n;
+            double k = axis == 0 ? ky : kx;
+            out[(size_t)y * n + x] *= (cos(ph) + I * sin(ph)) * (-2.0 * PI * I * k / (double)n);
+        }
+    }
+    ifft2_normalised(out, n);
+}
 
 static void loss_grad_one(const model *md, long s, const double complex *probe, const double complex *slices,
                           const double *measured, int layer, int want_slices, int want_probe, accum *ac,
@@ -437,15 +458,54 @@ static void loss_grad_one(const model *md, long s, const double complex *probe, 
         if (m > 0) propagate(g, md->h + (size_t)(m - 1) * n2, n, 1);
     }
     if (want_probe && m_stop == 0) {
-        orc_unshift(g, n, fy, fx, tmp);
-        for (size_t k = 0; k < n2; ++k) ac->gp[k] += tmp[k];
+        /* g = dL/dconj(P^s), the gradient with respect to the shifted probe */
+        if (ac->gpos) {
+            /* the window sits at origin + (fy, fx): moving the position moves the probe's shift, so
+             * dL/dp = 2 Re sum conj(g) dP^s/df; the second derivative along an axis is at most
+             * 2 ||Q||^2 ||dP^s/df||^2 with ||Q||^2 <= N^2 prod_m max |t_m|^2 (every G_m unitary) */
+            for (int axis = 0; axis < 2; ++axis) {
+                shift_derivative(probe, n, fy, fx, axis, tmp);
+                double gr = 0.0, nrm = 0.0;
+                for (size_t k = 0; k < n2; ++k) {
+                    gr += creal(conj(g[k]) * tmp[k]);
+                    nrm += creal(tmp[k]) * creal(tmp[k]) + cimag(tmp[k]) * cimag(tmp[k]);
+                }
+                ac->gpos[2 * s + axis] = 2.0 * gr;
+                if (ac->cpos) ac->cpos[2 * s + axis] = 2.0 * (double)n2 * ac->tprod * nrm;
+            }
+        }
+        if (ac->gp) {
+            orc_unshift(g, n, fy, fx, tmp);
+            for (size_t k = 0; k < n2; ++k) ac->gp[k] += tmp[k];
+        }
     }
 }
+
+static int loss_grad_impl(const orc_problem *pb, const double complex *probe, const double complex *slices,
+                          const double *measured, const long *subset, long n_subset, int layer,
+                          double complex *grad_slices, double complex *grad_probe, double *overlap,
+                          double *grad_pos, double *curv_pos, double *loss);
 
 int orc_loss_grad(const orc_problem *pb, const double complex *probe, const double complex *slices,
                   const double *measured, const long *subset, long n_subset, int layer,
                   double complex *grad_slices, double complex *grad_probe, double *overlap,
                   double *loss)
+{
+    return loss_grad_impl(pb, probe, slices, measured, subset, n_subset, layer, grad_slices, grad_probe, overlap,
+                          NULL, NULL, loss);
+}
+
+int orc_position_grad(const orc_problem *pb, const double complex *probe, const double complex *slices,
+                      const double *measured, double *grad_pos, double *curv_pos, double *loss)
+{
+    if (!grad_pos) return -1;
+    return loss_grad_impl(pb, probe, slices, measured, NULL, 0, -1, NULL, NULL, NULL, grad_pos, curv_pos, loss);
+}
+
+static int loss_grad_impl(const orc_problem *pb, const double complex *probe, const double complex *slices,
+                          const double *measured, const long *subset, long n_subset, int layer,
+                          double complex *grad_slices, double complex *grad_probe, double *overlap,
+                          double *grad_pos, double *curv_pos, double *loss)
 {
     if (check_problem(pb) || !probe || !slices || !measured) return -1;
     if (layer >= pb->n_slices) return -1;
@@ -463,11 +523,25 @@ int orc_loss_grad(const orc_problem *pb, const double complex *probe, const doub
     int nt = pb->n_threads > 0 ? pb->n_threads : omp_get_max_threads();
     accum *acc = (accum *)calloc((size_t)nt, sizeof(accum));
     int bad = (acc == NULL);
+    double tprod = 1.0;
+    if (curv_pos)
+        for (int m = 0; m < M; ++m) {
+            double mx = 0.0;
+            for (size_t i = 0; i < hw; ++i) {
+                double complex v = slices[(size_t)m * hw + i];
+                double a = creal(v) * creal(v) + cimag(v) * cimag(v);
+                if (a > mx) mx = a;
+            }
+            tprod *= mx;
+        }
     if (!bad) {
 #pragma omp parallel num_threads(nt)
         {
             int t = omp_get_thread_num();
             accum *ac = &acc[t];
+            ac->gpos = grad_pos;
+            ac->cpos = curv_pos;
+            ac->tprod = tprod;
             ac->gs = grad_slices ? (double complex *)calloc(gsz, sizeof(double complex)) : NULL;
             ac->gp = grad_probe ? (double complex *)calloc(n2, sizeof(double complex)) : NULL;
             ac->w = (overlap && layer >= 0) ? (double *)calloc(hw, sizeof(double)) : NULL;
@@ -488,7 +562,7 @@ int orc_loss_grad(const orc_problem *pb, const double complex *probe, const doub
                 for (long i = lo; i < hi; ++i) {
                     long s = subset ? subset[i] : i;
                     loss_grad_one(&md, s, probe, slices, measured, layer, grad_slices != NULL,
-                                  grad_probe != NULL, ac, psi, far, tp, g, tmp);
+                                  grad_probe != NULL || grad_pos != NULL, ac, psi, far, tp, g, tmp);
                 }
             free(psi); free(far); free(tp); free(g); free(tmp);
         }

@@ -112,6 +112,15 @@ int orc_loss_grad(const orc_problem *pb, const double complex *probe, const doub
                   double complex *grad_slices, double complex *grad_probe, double *overlap,
                   double *loss);
 
+/* Gradient of the loss with respect to every scan position (row f4: the positions of an
+ * experiment deviate from the raster, Sec. 6).  A position is the window's corner plus a
+ * sub-pixel shift of the probe (orc_shift), so grad_pos[s] (S x 2, y then x) is
+ * 2 Re sum conj(dL/dconj(P^s)) dP^s/df along each axis.  curv_pos (S x 2, may be NULL)
+ * receives 2 N^2 prod_m max|t_m|^2 ||dP^s/df||^2, which bounds the second derivative of the
+ * quadratic model along that axis.  loss may be NULL. */
+int orc_position_grad(const orc_problem *pb, const double complex *probe, const double complex *slices,
+                      const double *measured, double *grad_pos, double *curv_pos, double *loss);
+
 /* K amplitude-flow steps on slice `layer` (Algorithm 1, inner loop), in place.
  * loss_out: loss at the iterate before the last step; mu_out: its step size.
  * With the Poisson objective the step is half the amplitude-flow step: near the
