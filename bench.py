@@ -312,6 +312,16 @@ def main():
         plan.adjoint(probe, sl2, measured, grad_slices=gs, grad_probe=gp, loss=end)
         extras["sweep_loss_after"] = end.item()
         extras["pass_model_bytes"] = pass_bytes(geo)
+        # scan-position gradient and curvature bound over all positions (a probe-mode pass)
+        gpos = torch.empty((geo.n_pos, 2), dtype=torch.float64, device=dev)
+        cpos = torch.empty_like(gpos)
+        plan.position_grad(probe, slices, measured, gpos, cpos)
+        torch.cuda.synchronize()
+        t0p = time.perf_counter()
+        for _ in range(3):
+            plan.position_grad(probe, slices, measured, gpos, cpos)
+        torch.cuda.synchronize()
+        extras["position_grad_ms"] = (time.perf_counter() - t0p) * 1e3 / 3
         log("bench: Algorithm 2 (sparse matrix decomposition) at N = 32 and 64")
         extras["algorithm2"] = [algorithm2_benchmark(32, 3, oracle_check=not args.no_cpu_baseline),
                                 algorithm2_benchmark(64, 3)]

@@ -80,7 +80,9 @@ typedef struct ms_plan ms_plan;
 
 /* Workspace bytes for `pb`.  budget_bytes = 0 processes all positions in one
  * batch; otherwise positions are processed in the largest batches that fit
- * the budget (MS_ERR_BUDGET if not even one position fits). */
+ * the budget (MS_ERR_BUDGET if not even one position fits).  Positions that share
+ * a sub-pixel offset share one shifted probe (a shift class); at most 4096 classes
+ * (MS_ERR_UNSUPPORTED beyond), each adding about 37 N^2 8 bytes. */
 ms_status ms_workspace_size(const ms_problem *pb, size_t budget_bytes, size_t *ws_bytes);
 
 /* Builds a plan: copies the host arrays, derives patch origins, probe shift
@@ -180,6 +182,26 @@ ms_status ms_full_step(ms_plan *plan, hipStream_t stream, int32_t k_steps, doubl
 ms_status ms_probe_step(ms_plan *plan, hipStream_t stream, int32_t k_steps, ms_c64 *probe,
                         const ms_c64 *slices, const float *measured, const int64_t *subset,
                         int64_t n_subset, double *loss_out, double *mu_out);
+
+/* Gradient of the loss with respect to every scan position (the outlook of Sec. 6: scan
+ * positions deviate from the ideal raster).  Position s is the window corner plus a
+ * sub-pixel shift of the probe, P^s = F^{-1}(F p o e^{-2 pi i (k_y f_y + k_x f_x)/N}) with
+ * signed k, so
+ *   grad_pos[s] = 2 Re sum_pixels conj(dL/dconj(P^s)) dP^s/df    (y, then x),
+ * dP^s/df the ramp differentiated (times -2 pi i k / N).  curv_pos[s] (or NULL) receives
+ * 2 N^2 prod_m max|t_m|^2 ||dP^s/df||^2 per axis, a bound on the second derivative of the
+ * quadratic model (||Q||^2 <= N^2 prod_m max|t_m|^2 since every G_m is unitary), so that
+ * -grad/curv is a step that the model cannot make worse.  grad_pos, curv_pos: device
+ * double [S][2]; loss_out (device double or NULL): the loss.  Both execution paths. */
+ms_status ms_position_grad(ms_plan *plan, hipStream_t stream, const ms_c64 *probe, const ms_c64 *slices,
+                           const float *measured, double *grad_pos, double *curv_pos, double *loss_out);
+
+/* One refinement step of the scan positions: positions (device double [S][2], in/out, the
+ * plan's positions on entry) <- positions - step_scale * grad_pos / curv_pos (per axis; an
+ * axis with zero curvature stays).  step_scale > 0; 1 is the majorised step.  The plan keeps
+ * its own positions: build a new plan from the returned ones.  loss_out as above. */
+ms_status ms_position_step(ms_plan *plan, hipStream_t stream, double step_scale, const ms_c64 *probe,
+                           const ms_c64 *slices, const float *measured, double *positions, double *loss_out);
 
 /* Timing of the dominant kernel (the fused per-position multislice kernel).
  * After ms_profile_begin, the next max_launches launches of that kernel made

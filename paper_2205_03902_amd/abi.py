@@ -23,7 +23,7 @@ MS_OBJECTIVE_AMPLITUDE, MS_OBJECTIVE_POISSON = 0, 1
 # every entry point declared in include/ms.h
 SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
            "ms_plan_set_path", "ms_plan_set_objective",
-           "ms_make_probe", "ms_make_probe_aberrated", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_profile_begin",
+           "ms_make_probe", "ms_make_probe_aberrated", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_position_grad", "ms_position_step", "ms_profile_begin",
            "ms_profile_end", "ms_last_error")
 
 
@@ -80,6 +80,10 @@ def lib():
         L.ms_full_step.argtypes = [P, P, I32, D, P, P, P, P, P]
         L.ms_probe_step.restype = I32
         L.ms_probe_step.argtypes = [P, P, I32, P, P, P, P, I64, P, P]
+        L.ms_position_grad.restype = I32
+        L.ms_position_grad.argtypes = [P, P, P, P, P, P, P, P]
+        L.ms_position_step.restype = I32
+        L.ms_position_step.argtypes = [P, P, D, P, P, P, P, P]
         L.ms_profile_begin.restype = I32
         L.ms_profile_begin.argtypes = [P, I32]
         L.ms_profile_end.restype = I32
@@ -153,6 +157,22 @@ class Plan:
         self._h = handle
         self.batch = lib().ms_plan_batch(handle)
         self.shift_classes = lib().ms_plan_shift_classes(handle)
+        self.budget_bytes = int(budget_bytes)
+        self._path, self._objective = MS_PATH_AUTO, MS_OBJECTIVE_AMPLITUDE
+
+    def positions(self):
+        """The scan positions (S, 2) this plan was built from (host float64 copy)."""
+        return self._keep[0].copy()
+
+    def with_positions(self, positions):
+        """A plan of the same geometry, path and objective at other scan positions."""
+        pb = self.pb
+        plan = Plan(self.n, self.obj_h, self.obj_w, self.n_slices, positions, self._keep[1][: max(self.n_slices - 1, 0)],
+                    pb.pixel_size, pb.wavelength, pb.tilt_y, pb.tilt_x, budget_bytes=self.budget_bytes,
+                    device=self.device)
+        plan.set_path(self._path)
+        plan.set_objective(self._objective)
+        return plan
 
     @classmethod
     def from_geometry(cls, geo, positions=None, budget_bytes=0, device=None):
@@ -195,10 +215,12 @@ class Plan:
     def set_path(self, path: int):
         """MS_PATH_AUTO, MS_PATH_FUSED or MS_PATH_LINES (see include/ms.h)."""
         _check(lib().ms_plan_set_path(self._h, int(path)), "ms_plan_set_path")
+        self._path = int(path)
 
     def set_objective(self, objective: int):
         """MS_OBJECTIVE_AMPLITUDE or MS_OBJECTIVE_POISSON (see include/ms.h)."""
         _check(lib().ms_plan_set_objective(self._h, int(objective)), "ms_plan_set_objective")
+        self._objective = int(objective)
 
     # -- kernel timing ---------------------------------------------------------
     def profile_begin(self, max_launches: int):
@@ -287,3 +309,30 @@ class Plan:
         _check(lib().ms_probe_step(self._h, self._stream(), int(k_steps), _ptr(probe), _ptr(slices), _ptr(measured),
                                    None if sub is None else sub.ctypes.data, n_sub, _ptr(loss), _ptr(mu)),
                "ms_probe_step")
+
+    def _positions(self, t, name):
+        self._expect(t, (self.n_pos, 2), _torch().float64, name)
+
+    def position_grad(self, probe, slices, measured, grad=None, curv=None, loss=None):
+        """dL/dposition and the curvature bound per axis, device float64 [S, 2] each (y, x)."""
+        torch = _torch()
+        self._probe(probe)
+        self._slices(slices)
+        self._patterns(measured)
+        grad = torch.empty((self.n_pos, 2), dtype=torch.float64, device=self.device) if grad is None else grad
+        curv = torch.empty((self.n_pos, 2), dtype=torch.float64, device=self.device) if curv is None else curv
+        self._positions(grad, "grad")
+        self._positions(curv, "curv")
+        _check(lib().ms_position_grad(self._h, self._stream(), _ptr(probe), _ptr(slices), _ptr(measured), _ptr(grad),
+                                      _ptr(curv), _ptr(loss)), "ms_position_grad")
+        return grad, curv
+
+    def position_step(self, positions, probe, slices, measured, step_scale: float = 1.0, loss=None):
+        """positions: device float64 [S, 2] holding this plan's positions; updated in place."""
+        self._probe(probe)
+        self._slices(slices)
+        self._patterns(measured)
+        self._positions(positions, "positions")
+        _check(lib().ms_position_step(self._h, self._stream(), float(step_scale), _ptr(probe), _ptr(slices),
+                                      _ptr(measured), _ptr(positions), _ptr(loss)), "ms_position_step")
+        return positions

@@ -661,4 +661,59 @@ __global__ __launch_bounds__(256) void sum_classes_kernel(const float2 *in, int 
 
 __global__ void copy_scalar_kernel(const double *src, double *dst) { *dst = *src; }
 
+// Position gradient of one batch: block b takes position s = pos_list[b] of class c,
+//   grad[s] = 2 Re sum conj(g_b) dP_c (y, x),  g_b the probe patch dL/dconj(P^s),
+//   curv[s] = 2 nn prod_m maxt2[m] ||dP_c||^2,
+// dprobe = [dP/df_y for every class][dP/df_x for every class].  FP64 sums, fixed order.
+__global__ __launch_bounds__(256) void position_grad_kernel(const float2 *patch, const int *pos_list,
+                                                            const int4 *pos_info, const float2 *dprobe,
+                                                            long long class_plane, int nn, const float *maxt2,
+                                                            int M, double *grad, double *curv)
+{
+    __shared__ double red[4][256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int s = pos_list[b];
+    const int c = pos_info[s].z;
+    const float2 *g = patch + (size_t)b * nn;
+    const float2 *dy = dprobe + (size_t)c * nn;
+    const float2 *dx = dprobe + class_plane + (size_t)c * nn;
+    double gy = 0.0, gx = 0.0, ny = 0.0, nx = 0.0;
+    for (int i = t; i < nn; i += 256) {
+        const float2 a = g[i], u = dy[i], v = dx[i];
+        gy += (double)a.x * u.x + (double)a.y * u.y;
+        gx += (double)a.x * v.x + (double)a.y * v.y;
+        ny += (double)u.x * u.x + (double)u.y * u.y;
+        nx += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    red[0][t] = gy;
+    red[1][t] = gx;
+    red[2][t] = ny;
+    red[3][t] = nx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[q][t] += red[q][t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        grad[2 * (size_t)s] = 2.0 * red[0][0];
+        grad[2 * (size_t)s + 1] = 2.0 * red[1][0];
+        if (curv) {
+            double tp = 1.0;
+            for (int m = 0; m < M; ++m) tp *= (double)maxt2[m];
+            curv[2 * (size_t)s] = 2.0 * (double)nn * tp * red[2][0];
+            curv[2 * (size_t)s + 1] = 2.0 * (double)nn * tp * red[3][0];
+        }
+    }
+}
+
+// positions <- positions - scale grad / curv per coordinate (unchanged where curv is 0).
+__global__ __launch_bounds__(256) void position_update_kernel(double *pos, const double *grad, const double *curv,
+                                                              long long count, double scale)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long long)gridDim.x * 256)
+        if (curv[i] > 0.0) pos[i] -= scale * grad[i] / curv[i];
+}
+
 }  // namespace imsp

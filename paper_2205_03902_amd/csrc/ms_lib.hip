@@ -29,7 +29,9 @@ ms_status fail(ms_status st, const std::string &msg)
 }
 
 constexpr int kMaxBlocks = 256;    // partial-maximum blocks per segment
-constexpr int kMaxClasses = 256;   // distinct sub-pixel probe shifts per plan
+// Distinct sub-pixel probe shifts per plan.  A raster has a few; refined positions have one per
+// position.  The class tables and partial sums take about (2 kChunks + 5) C N^2 8 bytes.
+constexpr int kMaxClasses = 4096;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -234,7 +236,8 @@ size_t tile_entries(const HostPlan &hp)
 
 // Workspace layout.  Every region is 256-byte aligned.
 struct Layout {
-    size_t tw, hy, hx, gap_table, ry, rx, ident, pos_info, pos_list, sub_list;
+    size_t tw, hy, hx, gap_table, ry, rx, ident, dry, drx, zero_ident, dprobe, pgrad, pcurv;
+    size_t pos_info, pos_list, sub_list;
     size_t class_probe, class_acc, class_tmp, gp, layer_g, layer_w, maxt2, partial, maxw, scal;
     size_t full_g, full_w, maxw_all, mu_all;
     size_t tile_off, tile_list, class_off, class_list, sub_class_off, sub_class_list;
@@ -258,6 +261,12 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     L.ry = take(C * n * 8);
     L.rx = take(C * n * 8);
     L.ident = take(C * 4);
+    L.dry = take(C * n * 8);
+    L.drx = take(C * n * 8);
+    L.zero_ident = take(C * 4);
+    L.dprobe = take(2 * C * NN * 8);
+    L.pgrad = take(S * 2 * 8);
+    L.pcurv = take(S * 2 * 8);
     L.pos_info = take(S * 16);
     L.pos_list = take(S * 4);
     L.sub_list = take(S * 4);
@@ -493,6 +502,27 @@ void class_probes(ms_plan *p, const ms_c64 *probe, hipStream_t st)
                   hp.C, st);
 }
 
+// Derivatives of the shifted probes in their shifts, dP_c/df_y then dP_c/df_x, into dprobe.
+void class_probe_derivatives(ms_plan *p, const ms_c64 *probe, hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
+    const long long plane = (long long)hp.C * hp.n * hp.n;
+    float2 *dy = p->at<float2>(p->L.dprobe), *dx = dy + plane;
+    const float2 *in = reinterpret_cast<const float2 *>(probe);
+    const int *none = p->at<int>(p->L.zero_ident);
+    const float2 *tw = p->at<float2>(p->L.tw);
+    if (p->lines) {
+        float2 *tmp = p->at<float2>(p->L.class_tmp);
+        line_filter(hp.n, true, false, in, 0, tmp, p->at<float2>(p->L.rx), none, tw, hp.C, st);
+        line_filter(hp.n, false, false, tmp, (long long)hp.n * hp.n, dy, p->at<float2>(p->L.dry), none, tw, hp.C, st);
+        line_filter(hp.n, true, false, in, 0, tmp, p->at<float2>(p->L.drx), none, tw, hp.C, st);
+        line_filter(hp.n, false, false, tmp, (long long)hp.n * hp.n, dx, p->at<float2>(p->L.ry), none, tw, hp.C, st);
+        return;
+    }
+    launch_filter(hp.n, false, in, 0, dy, p->at<float2>(p->L.dry), p->at<float2>(p->L.rx), none, tw, hp.C, st);
+    launch_filter(hp.n, false, in, 0, dx, p->at<float2>(p->L.ry), p->at<float2>(p->L.drx), none, tw, hp.C, st);
+}
+
 // max |t_m|^2 of every slice into maxt2[M].
 void slice_maxima(ms_plan *p, const ms_c64 *slices, hipStream_t st)
 {
@@ -685,8 +715,8 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
                 hx[(size_t)g * n + i] = make_float2((float)(std::cos(px) / n), (float)(std::sin(px) / n));
             }
         }
-        std::vector<float2> ry((size_t)C * n), rx((size_t)C * n);
-        std::vector<int> ident(C);
+        std::vector<float2> ry((size_t)C * n), rx((size_t)C * n), dry((size_t)C * n), drx((size_t)C * n);
+        std::vector<int> ident(C), zero_ident(C, 0);
         for (int c = 0; c < C; ++c) {
             ident[c] = (hp.cls_fy[c] == 0.0 && hp.cls_fx[c] == 0.0) ? 1 : 0;
             for (int i = 0; i < n; ++i) {
@@ -694,6 +724,10 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
                 double ax = -2.0 * PI * freq(i) * hp.cls_fx[c] / n;
                 ry[(size_t)c * n + i] = make_float2((float)(std::cos(ay) / n), (float)(std::sin(ay) / n));
                 rx[(size_t)c * n + i] = make_float2((float)(std::cos(ax) / n), (float)(std::sin(ax) / n));
+                // the ramp differentiated in its shift: times -2 pi i k / N
+                const double th = 2.0 * PI * freq(i) / n;
+                dry[(size_t)c * n + i] = make_float2((float)(th * std::sin(ay) / n), (float)(-th * std::cos(ay) / n));
+                drx[(size_t)c * n + i] = make_float2((float)(th * std::sin(ax) / n), (float)(-th * std::cos(ax) / n));
             }
         }
         std::vector<int> pos_list(hp.S);
@@ -707,6 +741,8 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
                   up(p->L.hx, hx.data(), hx.size() * 8) && up(p->L.ry, ry.data(), ry.size() * 8) &&
                   up(p->L.gap_table, hp.gap_table.data(), hp.gap_table.size() * 4) &&
                   up(p->L.rx, rx.data(), rx.size() * 8) && up(p->L.ident, ident.data(), ident.size() * 4) &&
+                  up(p->L.dry, dry.data(), dry.size() * 8) && up(p->L.drx, drx.data(), drx.size() * 8) &&
+                  up(p->L.zero_ident, zero_ident.data(), zero_ident.size() * 4) &&
                   up(p->L.pos_info, hp.pos_info.data(), hp.pos_info.size() * 16) &&
                   up(p->L.pos_list, pos_list.data(), pos_list.size() * 4) &&
                   up(p->L.tile_off, hp.tile_off.data(), hp.tile_off.size() * 4) &&
@@ -1117,6 +1153,64 @@ ms_status ms_probe_step(ms_plan *p, hipStream_t st, int32_t k_steps, ms_c64 *pro
         update_kernel<<<(nn + 255) / 256, 256, 0, st>>>(reinterpret_cast<float2 *>(probe), gp, nn, mu);
     }
     return check_hip("ms_probe_step");
+}
+
+// Probe-mode passes over every batch, then the per-position gradient (and curvature bound).
+static ms_status position_pass(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c64 *slices,
+                               const float *measured, double *grad, double *curv, double *loss_out)
+{
+    const HostPlan &hp = p->hp;
+    const int nn = hp.n * hp.n;
+    slice_maxima(p, slices, st);
+    class_probes(p, probe, st);
+    class_probe_derivatives(p, probe, st);
+    FusedParams fp = fused_params(p, slices, measured);
+    double *total = p->at<double>(p->L.scal) + 1;
+    const int *list = p->at<int>(p->L.pos_list);
+    for (int b = 0; b < hp.nb; ++b) {
+        const int64_t s0 = (int64_t)b * hp.B;
+        const int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
+        fp.pos_list = list + s0;
+        launch_fused(p, kProbe, fp, count, st);
+        int n_loss;
+        const double *lsrc = loss_entries(p, count, &n_loss);
+        loss_sum_kernel<<<1, 256, 0, st>>>(lsrc, n_loss, total, b > 0);
+        position_grad_kernel<<<count, 256, 0, st>>>(p->at<float2>(p->L.probe_patch), list + s0,
+                                                    p->at<int4>(p->L.pos_info), p->at<float2>(p->L.dprobe),
+                                                    (long long)hp.C * nn, nn, p->at<float>(p->L.maxt2), hp.M, grad,
+                                                    curv);
+    }
+    if (loss_out) copy_scalar_kernel<<<1, 1, 0, st>>>(total, loss_out);
+    return MS_OK;
+}
+
+ms_status ms_position_grad(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c64 *slices,
+                           const float *measured, double *grad_pos, double *curv_pos, double *loss_out)
+{
+    g_err.clear();
+    if (!p || !probe || !slices || !measured || !grad_pos) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    if (!aligned8(probe) || !aligned8(slices) || !aligned8(grad_pos) || !aligned8(curv_pos) || !aligned8(loss_out) ||
+        ((uintptr_t)measured & 3))
+        return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
+    position_pass(p, st, probe, slices, measured, grad_pos, curv_pos, loss_out);
+    return check_hip("ms_position_grad");
+}
+
+ms_status ms_position_step(ms_plan *p, hipStream_t st, double step_scale, const ms_c64 *probe, const ms_c64 *slices,
+                           const float *measured, double *positions, double *loss_out)
+{
+    g_err.clear();
+    if (!p || !probe || !slices || !measured || !positions) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    if (!(step_scale > 0.0) || !std::isfinite(step_scale)) return fail(MS_ERR_INVALID_ARG, "step_scale must be > 0");
+    if (!aligned8(probe) || !aligned8(slices) || !aligned8(positions) || !aligned8(loss_out) ||
+        ((uintptr_t)measured & 3))
+        return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
+    double *grad = p->at<double>(p->L.pgrad), *curv = p->at<double>(p->L.pcurv);
+    position_pass(p, st, probe, slices, measured, grad, curv, loss_out);
+    const long long count = 2 * (long long)p->hp.S;
+    position_update_kernel<<<(int)std::min<long long>(1024, (count + 255) / 256), 256, 0, st>>>(positions, grad, curv,
+                                                                                               count, step_scale);
+    return check_hip("ms_position_step");
 }
 
 }  // extern "C"

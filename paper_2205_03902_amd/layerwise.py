@@ -48,3 +48,44 @@ def reconstruct(plan: Plan, probe: torch.Tensor, slices: torch.Tensor, measured:
     secs = time.perf_counter() - t0
     h = buf[:i].cpu().numpy()
     return History(loss=h[:, 0].tolist(), mu=h[:, 1].tolist(), kind=kinds, seconds=secs)
+
+
+def refine_positions(plan: Plan, probe: torch.Tensor, slices: torch.Tensor, measured: torch.Tensor, passes: int,
+                     step_scale: float = 1.0, positions=None, adaptive: bool = True):
+    """Scan-position refinement at fixed probe and slices, `passes` gradient passes in all.
+
+    Each pass is one ms_position_step: the loss at the plan's positions and the step
+    -scale grad / curv from them.  With `adaptive`, a step whose new positions lower the loss
+    is accepted and the next scale doubled; one that raises it is undone and the step retaken
+    from the accepted positions at half the scale.  The plan's geometry is host data, so new
+    positions are read back and a plan of those positions is built (same geometry, path and
+    objective).  positions: the plan's positions (default: those it was built from).
+    Returns (plan of the accepted positions, those positions (device float64 [S, 2]), the
+    accepted losses in order)."""
+    import numpy as np
+    if positions is None:
+        positions = plan.positions()
+    dev = plan.device
+    pos_a = torch.as_tensor(np.asarray(positions, dtype=np.float64).reshape(-1, 2), device=dev).clone()
+    lbuf = torch.zeros(1, dtype=torch.float64, device=dev)
+    scale = float(step_scale)
+    plan_a = plan
+    cand = pos_a.clone()
+    plan_a.position_step(cand, probe, slices, measured, scale, loss=lbuf)
+    loss_a = lbuf.item()
+    losses = [loss_a]
+    for _ in range(int(passes) - 1):
+        plan_c = plan_a.with_positions(cand.cpu().numpy())
+        nxt = cand.clone()
+        next_scale = 2.0 * scale if adaptive else scale
+        plan_c.position_step(nxt, probe, slices, measured, next_scale, loss=lbuf)
+        loss_c = lbuf.item()
+        if loss_c <= loss_a or not adaptive:
+            plan_a, pos_a, loss_a, scale = plan_c, cand, loss_c, next_scale
+            losses.append(loss_c)
+            cand = nxt
+        else:
+            scale *= 0.5
+            cand = pos_a.clone()
+            plan_a.position_step(cand, probe, slices, measured, scale, loss=lbuf)
+    return plan_a, pos_a, losses

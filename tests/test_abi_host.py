@@ -51,7 +51,7 @@ def test_workspace_size_accepts_a_valid_problem():
     (dict(n=8), abi.MS_ERR_INVALID_ARG),
     (dict(n=512, obj_h=512, obj_w=512), abi.MS_ERR_INVALID_ARG),
     # more distinct sub-pixel offsets than the plan keeps shifted probes for
-    (dict(positions=np.stack([np.arange(300) * 0.001, np.zeros(300)], axis=1)), abi.MS_ERR_UNSUPPORTED),
+    (dict(positions=np.stack([np.arange(4100) * 1e-4, np.zeros(4100)], axis=1)), abi.MS_ERR_UNSUPPORTED),
     # more distinct slice distances than the fused kernel keeps in LDS at this window size
     (dict(n_slices=6, dz=np.array([1.0, 2.0, 3.0, 4.0, 5.0])), abi.MS_ERR_UNSUPPORTED),
     (dict(obj_h=16), abi.MS_ERR_INVALID_ARG),
