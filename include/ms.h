@@ -82,7 +82,7 @@ typedef struct ms_plan ms_plan;
  * batch; otherwise positions are processed in the largest batches that fit
  * the budget (MS_ERR_BUDGET if not even one position fits).  Positions that share
  * a sub-pixel offset share one shifted probe (a shift class); at most 4096 classes
- * (MS_ERR_UNSUPPORTED beyond), each adding about 37 N^2 8 bytes. */
+ * (MS_ERR_UNSUPPORTED beyond), each adding about 21 N^2 8 bytes. */
 ms_status ms_workspace_size(const ms_problem *pb, size_t budget_bytes, size_t *ws_bytes);
 
 /* Builds a plan: copies the host arrays, derives patch origins, probe shift
