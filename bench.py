@@ -102,16 +102,13 @@ def cpu_baseline(geo, n_sample: int):
                       f"{secs:.2f} s wall, FP64"}
 
 
-FP32_MFMA_PEAK = 157.3e12   # flop/s, MI355X dense FP32 matrix peak (the complex GEMMs of Algorithm 2)
-
-
 def algorithm2_benchmark(n: int, m: int, iterations: int = 3, a_steps: int = 5, oracle_check: bool = False):
     """Algorithm 2 (sparse matrix decomposition) on the full-field model: an N x N object, a
     probe moved by integer shifts on an 8 x 8 grid (S = 64), M slices.  Measurements come from
     the multislice forward of the layer-wise path (the two models agree for integer shifts of a
     periodic object).  Reports ms per iteration (A estimate with `a_steps` steps, one
     decomposition pass, the next A; the probe matrix and its norm are set up before the timed
-    region) and the GEMM rate against the FP32 matrix peak."""
+    region), with the iteration's byte model and its GEMM flops."""
     import numpy as np
     import torch
 
@@ -138,11 +135,20 @@ def algorithm2_benchmark(n: int, m: int, iterations: int = 3, a_steps: int = 5, 
     torch.cuda.synchronize()
     secs = (time.perf_counter() - t0) / iterations
     n2 = n * n
-    macs = a_steps * 4 * n2 * n2 * S + (4 * (m - 1) + 2 * m) * n2 ** 3
+    # The dense formulation would spend 8 (4 a S N^4 + (4(M-1) + 2M) N^6) flops per iteration;
+    # here only the two N^4 S products with the probe matrix per estimate step are GEMMs, every
+    # G and F product is an FFT propagation of the N^2 images of a matrix.
+    gemm_flops = a_steps * 2 * 8 * n2 * n2 * S
+    matrix = n2 * n2 * 8
+    # bytes: per estimate step A read twice and written once; per decomposition 5 (M - 1)
+    # image passes (compose old, suffixes, V, compose new, next A) reading and writing a matrix,
+    # the gradient's column sums reading V and S_l per layer, X and the trace sums
+    model_bytes = a_steps * 3 * matrix + (5 * (m - 1) * 2 + 2 * m + 2 + 2) * matrix
     res = {"n": n, "slices": m, "positions": S, "iterations": iterations, "a_steps": a_steps,
-           "ms_per_iteration": secs * 1e3, "gemm_tflops": 8 * macs / secs / 1e12,
-           "frac_of_fp32_matrix_peak": 8 * macs / secs / FP32_MFMA_PEAK,
-           "flops_per_iteration": 8 * macs, "matrix_loss": [float(h) for h in hist.cpu().numpy()]}
+           "ms_per_iteration": secs * 1e3, "gemm_flops_per_iteration": gemm_flops,
+           "model_bytes_per_iteration": model_bytes, "model_gb_per_s": model_bytes / secs / 1e9,
+           "dense_equivalent_flops_per_iteration": 8 * (a_steps * 4 * n2 * n2 * S + (4 * (m - 1) + 2 * m) * n2 ** 3),
+           "matrix_loss": [float(h) for h in hist.cpu().numpy()]}
     if oracle_check:
         from oracle import smd as osmd
         import oracle

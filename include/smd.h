@@ -3,8 +3,7 @@
  * Algorithm 2 works on the full-field model of Sec. 2.2: the object is as large as the
  * N x N window, positions are integer shifts, and the whole specimen is the dense N^2 x N^2
  * transfer matrix A_M = O_M G_{M-1} ... G_1 O_1 (O_m = diag(t_m), G_m = F_2D^{-1} diag(h_m)
- * F_2D, h_m the propagator of eq. fresnel_element).  Dense matrices make it practical only
- * for small windows (N <= 64 here).  One iteration of Algorithm 2 is
+ * F_2D, h_m the propagator of eq. fresnel_element).  One iteration of Algorithm 2 is
  *   smd_estimate   amplitude-flow steps on A (eq. Opt_Prob_Matrix):
  *                  A <- A - mu F^H ((|F A P| - sqrt(I)) o F A P / |F A P|) P^H,
  *                  mu = 1 / (N^2 ||P||^2) with ||P|| the spectral norm of the probe matrix
@@ -17,15 +16,20 @@
  *                  Frobenius norm; then the least-squares lambda = Tr(A~^H A_hat) / Tr(A~^H A~)
  *                  (eq. Update Lambda) with A~ = O_M prod G_m O_m;
  *   smd_compose    A = lambda A~ for the next iteration.
- * The result of the algorithm is lambda^(1/M) O_m.
+ * The result of the algorithm is lambda^(1/M) O_m (smd_result).
  *
- * Matrices are row-major complex float (interleaved), device pointers unless marked.
- * Images in FFT order as in ms.h; measured intensities [S][N][N].  The dense products are
- * rocBLAS complex GEMMs on the plan's stream (rocBLAS works in a slice of the caller's
- * workspace); the element-wise, diagonal and reduction steps are kernels of this library.
- * smd_set_probe and smd_decompose synchronise the stream (the spectral norm of P and the new
- * lambda are computed on the host from device reductions); the other calls only enqueue.
- * Errors return a negative status (the ms_status codes of ms.h) with a message in
+ * Data layout.  N^2 x N^2 matrices are complex float (interleaved) in COLUMN-major order:
+ * element (i, j) at j N^2 + i, so that column j -- the image of pixel j through the matrix --
+ * is one contiguous N x N image.  Images, slices [M][N][N] and the probe are in FFT order as
+ * in ms.h; measured intensities [S][N][N].  Device pointers unless marked (host).
+ *
+ * Implementation.  Products with G_m and F_2D never form those matrices: each is one
+ * propagation or 2D DFT of every image of the stored array (in-register line FFTs, the
+ * machinery of the multislice kernels).  The two products with the N^2 x S probe matrix in
+ * smd_estimate are rocBLAS complex GEMMs on the plan's stream (rocBLAS works in a slice of
+ * the workspace).  smd_set_probe and smd_decompose synchronise the stream (the spectral norm of
+ * P and the new lambda are finished on the host from device reductions); the other calls only
+ * enqueue.  Errors return a negative status (the ms_status codes of ms.h) with a message in
  * smd_last_error().
  */
 #ifndef SMD_H
@@ -40,9 +44,9 @@ extern "C" {
 #endif
 
 typedef struct {
-    int32_t n;                  /* window side N: 4, 8, 16, 32 or 64                         */
+    int32_t n;                  /* window side N: 16, 32 or 64                               */
     int32_t n_slices;           /* M >= 1                                                    */
-    int64_t n_pos;              /* S >= 1                                                    */
+    int64_t n_pos;              /* 1 <= S <= N^2                                             */
     const double *positions;    /* (host) S x 2 integer (y, x) shifts                        */
     const double *dz;           /* (host) M - 1 slice distances (A)                          */
     double pixel_size, wavelength;

@@ -378,15 +378,16 @@ struct ScatterParams {
     long long pos_stride;
     const int *tile_off;        // this batch: [kChunks][n_tiles + 1]
     const int4 *entries;        // (batch-local position, origin y, origin x, 0)
-    float2 *partial;            // [nch][n_m][H][W]
-    float *wpartial;            // [nch][n_m][H][W] or null
+    float2 *partial;            // [groups][n_m][H][W]
+    float *wpartial;            // [groups][n_m][H][W] or null
     long long w_stride;
     int H, W, N, tiles_x, n_tiles, m0;
+    int nch, cpb;               // chunks of the batch; consecutive chunks summed per block
 };
 
 __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
 {
-    const int t = blockIdx.x, c = blockIdx.y, mi = blockIdx.z, n_m = gridDim.z;
+    const int t = blockIdx.x, grp = blockIdx.y, mi = blockIdx.z, n_m = gridDim.z;
     const int y = (t / p.tiles_x) * kTileH + (int)(threadIdx.x / kTileW);
     const int x = (t % p.tiles_x) * kTileW + (int)(threadIdx.x % kTileW);
     if (y >= p.H || x >= p.W) return;
@@ -394,10 +395,12 @@ __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
     const float2 *base = p.patches + (size_t)(p.m0 + mi) * NN;
     const bool want_w = p.wpartial != nullptr;
     const float *wbase = want_w ? p.wpatch + (size_t)(p.m0 + mi) * NN : nullptr;
-    const int *off = p.tile_off + (size_t)c * (p.n_tiles + 1);
-    const int e0 = off[t], e1 = off[t + 1];
     float2 acc = make_float2(0.f, 0.f);
     float wacc = 0.f;
+    const int c_end = min(p.nch, (grp + 1) * p.cpb);
+    for (int c = grp * p.cpb; c < c_end; ++c) {
+    const int *off = p.tile_off + (size_t)c * (p.n_tiles + 1);
+    const int e0 = off[t], e1 = off[t + 1];
     for (int e = e0; e < e1; e += kUnroll) {
         int sl[kUnroll], loc[kUnroll];
 #pragma unroll
@@ -428,9 +431,10 @@ __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
             for (int u = 0; u < kUnroll; ++u) wacc += w[u];
         }
     }
+    }
     const size_t HW = (size_t)p.H * p.W, pix = (size_t)y * p.W + x;
-    p.partial[((size_t)c * n_m + mi) * HW + pix] = acc;
-    if (want_w) p.wpartial[((size_t)c * n_m + mi) * HW + pix] = wacc;
+    p.partial[((size_t)grp * n_m + mi) * HW + pix] = acc;
+    if (want_w) p.wpartial[((size_t)grp * n_m + mi) * HW + pix] = wacc;
 }
 
 // out[i] = (accumulate ? out[i] : 0) + sum_{c < nch} partial[c * plane + i], chunks in order.

@@ -29,6 +29,7 @@ ms_status fail(ms_status st, const std::string &msg)
 }
 
 constexpr int kMaxBlocks = 256;    // partial-maximum blocks per segment
+constexpr long long kScatterBlocks = 8192;   // target grid of the scatter pass
 // Distinct sub-pixel probe shifts per plan.  A raster has a few; refined positions have one per
 // position.  The class tables and partial sums take about (kChunks + 5) C N^2 8 bytes.
 constexpr int kMaxClasses = 4096;
@@ -334,6 +335,11 @@ struct ms_plan {
     std::vector<hipEvent_t> ev_start, ev_stop;
     size_t ev_used = 0;
     bool lines = false;   // line kernels instead of the fused per-position kernel
+    // A second stream (default priority) for the probe-gradient reductions, which only read
+    // what the per-position kernel wrote and so run beside the slice scatter; fork and join
+    // through events on the caller's stream.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int objective = MS_OBJECTIVE_AMPLITUDE;
 
     template <typename T>
@@ -488,7 +494,9 @@ void line_filter(int n, bool row, bool conj, const float2 *in, long long in_stri
 void class_probes(ms_plan *p, const ms_c64 *probe, hipStream_t st)
 {
     const HostPlan &hp = p->hp;
-    if (p->lines) {
+    // the line filters spread each class over N/16 workgroups per pass; one workgroup per class
+    // (window_filter_kernel) leaves the GPU nearly idle for a few classes of large windows
+    if (p->lines || hp.n >= 128) {
         // x ramps on rows into class_tmp, then y ramps on columns into class_probe
         line_filter(hp.n, true, false, reinterpret_cast<const float2 *>(probe), 0, p->at<float2>(p->L.class_tmp),
                     p->at<float2>(p->L.rx), p->at<int>(p->L.ident), p->at<float2>(p->L.tw), hp.C, st);
@@ -583,12 +591,20 @@ void scatter(ms_plan *p, int b, int count, int m0, int n_m, float2 *out, float *
     sp.wpartial = wout ? p->at<float>(p->L.wpart) : nullptr;
     sp.w_stride = (long long)hp.M * hp.n * hp.n;
     sp.H = hp.H; sp.W = hp.W; sp.N = hp.n; sp.tiles_x = hp.tiles_x; sp.n_tiles = hp.n_tiles; sp.m0 = m0;
-    scatter_partial_kernel<<<dim3(hp.n_tiles, ch.nch, n_m), 256, 0, st>>>(sp);
+    // Consecutive chunks are summed in one block (in ascending position order, as one longer
+    // chunk) while the grid keeps about kScatterBlocks blocks: fewer partial planes to write
+    // and reduce when many slices are scattered at once.
+    const long long per_group = (long long)hp.n_tiles * n_m;
+    const int groups = (int)std::min<long long>(ch.nch, std::max<long long>(1, (kScatterBlocks + per_group - 1) / per_group));
+    sp.nch = ch.nch;
+    sp.cpb = (ch.nch + groups - 1) / groups;
+    const int ngrp = (ch.nch + sp.cpb - 1) / sp.cpb;
+    scatter_partial_kernel<<<dim3(hp.n_tiles, ngrp, n_m), 256, 0, st>>>(sp);
     const long long plane = (long long)n_m * hp.H * hp.W;
-    chunk_reduce_kernel<float2><<<grid_for(plane), 256, 0, st>>>(sp.partial, ch.nch, plane, out, accumulate);
+    chunk_reduce_kernel<float2><<<grid_for(plane), 256, 0, st>>>(sp.partial, ngrp, plane, out, accumulate);
     if (wout) {
         const long long hw = (long long)hp.H * hp.W;
-        chunk_reduce_kernel<float><<<grid_for(n_m * hw), 256, 0, st>>>(sp.wpartial, ch.nch, n_m * hw, wout,
+        chunk_reduce_kernel<float><<<grid_for(n_m * hw), 256, 0, st>>>(sp.wpartial, ngrp, n_m * hw, wout,
                                                                         accumulate);
     }
 }
@@ -757,6 +773,13 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
         // the per-position tile vectors are no longer needed on the host
         hp.tile_list.clear();
         hp.tile_list.shrink_to_fit();
+        if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess) {
+            hipError_t e = hipGetLastError();
+            ms_plan_destroy(p);
+            return fail(MS_ERR_HIP, std::string("stream or event creation failed: ") + hipGetErrorString(e));
+        }
         *out = p;
         return MS_OK;
     } catch (const std::bad_alloc &) {
@@ -771,6 +794,9 @@ void ms_plan_destroy(ms_plan *plan)
     if (!plan) return;
     for (hipEvent_t e : plan->ev_start) (void)hipEventDestroy(e);
     for (hipEvent_t e : plan->ev_stop) (void)hipEventDestroy(e);
+    if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+    if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
+    if (plan->side) (void)hipStreamDestroy(plan->side);
     delete plan;
 }
 
@@ -941,24 +967,30 @@ ms_status ms_adjoint(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c
     class_probes(p, probe, st);
     FusedParams fp = fused_params(p, slices, measured);
     if (!grad_probe) fp.probe_patch = nullptr;
-    double *total = p->at<double>(p->L.scal) + 1;
     for (int b = 0; b < hp.nb; ++b) {
         int64_t s0 = (int64_t)b * hp.B;
         int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
         fp.pos_list = p->at<int>(p->L.pos_list) + s0;
         launch_fused(p, kAdjoint, fp, count, st);
-        scatter(p, b, count, 0, hp.M, reinterpret_cast<float2 *>(grad_slices), nullptr, b > 0, st);
-        if (grad_probe)
-            class_sums(p, p->at<int>(p->L.class_off) + (size_t)b * kChunks * (hp.C + 1), p->at<int>(p->L.class_list),
-                       count, b > 0, st);
+        // the loss and the probe-gradient reductions read only the per-position outputs: they
+        // run on the side stream while the slice scatter runs here; the next batch (which
+        // overwrites those outputs) and the return wait for them
+        if (hipEventRecord(p->ev_fork, st) != hipSuccess || hipStreamWaitEvent(p->side, p->ev_fork, 0) != hipSuccess)
+            return check_hip("ms_adjoint fork");
         {
             int n_loss;
             const double *lsrc = loss_entries(p, count, &n_loss);
-            loss_sum_kernel<<<1, 256, 0, st>>>(lsrc, n_loss, total, b > 0);
+            loss_sum_kernel<<<1, 256, 0, p->side>>>(lsrc, n_loss, loss_out, b > 0);
         }
+        if (grad_probe) {
+            class_sums(p, p->at<int>(p->L.class_off) + (size_t)b * kChunks * (hp.C + 1), p->at<int>(p->L.class_list),
+                       count, b > 0, p->side);
+            if (b + 1 == hp.nb) probe_gradient(p, reinterpret_cast<float2 *>(grad_probe), p->side);
+        }
+        if (hipEventRecord(p->ev_join, p->side) != hipSuccess) return check_hip("ms_adjoint join");
+        scatter(p, b, count, 0, hp.M, reinterpret_cast<float2 *>(grad_slices), nullptr, b > 0, st);
+        if (hipStreamWaitEvent(st, p->ev_join, 0) != hipSuccess) return check_hip("ms_adjoint join");
     }
-    if (grad_probe) probe_gradient(p, reinterpret_cast<float2 *>(grad_probe), st);
-    copy_scalar_kernel<<<1, 1, 0, st>>>(total, loss_out);
     return check_hip("ms_adjoint");
 }
 

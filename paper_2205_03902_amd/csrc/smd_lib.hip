@@ -1,7 +1,14 @@
-// libimsp: sparse matrix decomposition (Algorithm 2) on dense N^2 x N^2 matrices, behind the
-// C ABI of include/smd.h.  Dense complex products go to rocBLAS (column-major): a row-major
-// product C = op(A) op(B) is the column-major product C^T = op(B)^T op(A)^T, i.e. the same
-// operations with the operands swapped.
+// libimsp: sparse matrix decomposition (Algorithm 2) behind the C ABI of include/smd.h.
+//
+// The matrices are N^2 x N^2 and dense, but every factor between the unknown diagonals is
+// G_m = F^-1 diag(h_m) F: a product with G_m is one propagation of each image of the matrix,
+// and F is one 2D DFT of each image.  Matrices are stored column-major (the transpose in
+// row-major order), so that every such product acts on contiguous images:
+//   A^T = O_1 G_1 O_2 ... G_{M-1} O_M   (every factor is symmetric),
+//   S^T_{l+1} = S^T_l O_l G_l,   V^T_l = V^T_{l+1} conj(O_{l+1}) conj(G_l)   (V_l = R_l^H X),
+// each a right product, i.e. an operation on the rows of the stored array.  The only dense
+// products left are the two N^2 x N^2 x S products with the probe matrix in the A estimate
+// (rocBLAS; a row-major product C = op(A) op(B) is the column-major C^T = op(B)^T op(A)^T).
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
@@ -13,10 +20,13 @@
 #include <string>
 #include <vector>
 
+#include "fft_lines.hpp"
 #include "ms.h"
 #include "smd.h"
 
 namespace {
+
+using imsp::Win;
 
 thread_local std::string s_err;
 
@@ -28,51 +38,120 @@ int32_t sfail(int32_t st, const std::string &msg)
 
 constexpr size_t kAlign = 256;
 constexpr size_t kBlasWorkspace = (size_t)32 << 20;
-constexpr int kRed = 256;   // reduction partials
+constexpr int kRed = 256;        // reduction partials
+constexpr int kDotChunks = 32;   // row chunks of the gradient's column sums
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 unsigned blocks(long long n) { return (unsigned)std::min<long long>(65535, (n + 255) / 256); }
 
 // ---------------------------------------------------------------------------------------
-// kernels
+// Image kernels: one workgroup per N x N image (a row of the stored array), the line-FFT
+// machinery of the multislice kernels (16 complex values per lane, R = N / 16 lanes a line).
 
-__global__ void dft_kernel(float2 *F, int n)
+template <int N>
+__device__ __forceinline__ void stage_tables(float2 *s_tw, const float2 *twg)
 {
-    const long long n2 = (long long)n * n;
-    const double TWO_PI = 6.283185307179586476925286766559;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n2 * n2;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int r = (int)(i / n2), c = (int)(i - (long long)r * n2);
-        const int ky = r / n, kx = r % n, y = c / n, x = c % n;
-        const int ph = (ky * y + kx * x) % n;                 // exact integer phase
-        double s, co;
-        sincos(-TWO_PI * ph / n, &s, &co);
-        F[i] = make_float2((float)co, (float)s);
+    for (int i = threadIdx.x; i < Win<N>::TW_WORDS; i += Win<N>::NT) s_tw[i] = twg[i];
+}
+
+// out_b = post o G(pre o in_b) (CONJ: conj(G)), G = F^-1 diag(h_y (x) h_x) F; hy, hx carry the
+// 1/N of each inverse transform.  pre, post: N x N multipliers or null; pre_conj conjugates pre.
+// in may equal out.
+template <int N, bool CONJ>
+__global__ __launch_bounds__(Win<N>::NT) void image_propagate_kernel(const float2 *in, float2 *out,
+                                                                     const float2 *pre, int pre_conj,
+                                                                     const float2 *post, const float2 *hy,
+                                                                     const float2 *hx, const float2 *twg)
+{
+    using Wn = Win<N>;
+    constexpr int R = Wn::R;
+    __shared__ float2 lds[Wn::LDS_WORDS];
+    __shared__ float2 s_tw[Wn::TW_WORDS];
+    __shared__ float2 s_h[2 * N];
+    const int line = threadIdx.x / R, j = threadIdx.x % R;
+    const size_t base = (size_t)blockIdx.x * N * N;
+    stage_tables<N>(s_tw, twg);
+    for (int i = threadIdx.x; i < N; i += Wn::NT) {
+        s_h[i] = hy[i];
+        s_h[N + i] = hx[i];
+    }
+    float2 v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {   // rows: lane (y = line, j) holds x = j + R k
+        const int x = Wn::nat(j, k);
+        float2 a = in[base + (size_t)line * N + x];
+        if (pre) {
+            const float2 o = pre[line * N + x];
+            a = pre_conj ? imsp::cmulc(a, o) : imsp::cmul(a, o);
+        }
+        v[k] = a;
+    }
+    __syncthreads();
+    float2 *xb = lds + line * Wn::LD;
+    imsp::line_fft_fwd<N>(v, s_tw, xb, j);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const float2 h = s_h[N + Wn::spec(j, i)];
+        v[i] = CONJ ? imsp::cmulc(v[i], h) : imsp::cmul(v[i], h);
+    }
+    imsp::line_fft_inv<N>(v, s_tw, xb, j);
+    imsp::transpose<N, true, false, false>(v, lds, line, j);   // columns: lane (x = line, j) holds y = j + R k
+    imsp::line_fft_fwd<N>(v, s_tw, xb, j);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const float2 h = s_h[Wn::spec(j, i)];
+        v[i] = CONJ ? imsp::cmulc(v[i], h) : imsp::cmul(v[i], h);
+    }
+    imsp::line_fft_inv<N>(v, s_tw, xb, j);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int y = Wn::nat(j, k);
+        float2 r = v[k];
+        if (post) r = imsp::cmul(r, post[y * N + line]);
+        out[base + (size_t)y * N + line] = r;
     }
 }
 
-// T[r][c] = h(q_r) F[r][c], h = exp(-i pi dz lambda q^2) (eq. fresnel_element, no tilt).
-__global__ void h_rows_kernel(const float2 *F, float2 *T, int n, double dz, double lambda, double dx)
+// Unnormalised 2D DFT of every image, natural order in and out: F (INV = false) or
+// F^H = N^2 F^-1 (INV = true).
+template <int N, bool INV>
+__global__ __launch_bounds__(Win<N>::NT) void image_dft_kernel(const float2 *in, float2 *out, const float2 *twg)
 {
-#pragma clang fp contract(off)
-    const long long n2 = (long long)n * n;
-    const double PI = 3.14159265358979323846264338327950288;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n2 * n2;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int r = (int)(i / n2);
-        const int ky = r / n, kx = r % n;
-        const double qy = (double)(ky < n / 2 ? ky : ky - n) / (n * dx);
-        const double qx = (double)(kx < n / 2 ? kx : kx - n) / (n * dx);
-        double s, co;
-        sincos(-PI * dz * lambda * (qy * qy + qx * qx), &s, &co);
-        const float2 f = F[i];
-        const double hr = co, hi = s;
-        T[i] = make_float2((float)(hr * f.x - hi * f.y), (float)(hr * f.y + hi * f.x));
+    using Wn = Win<N>;
+    constexpr int R = Wn::R;
+    __shared__ float2 lds[Wn::LDS_WORDS];
+    __shared__ float2 s_tw[Wn::TW_WORDS];
+    const int line = threadIdx.x / R, j = threadIdx.x % R;
+    const size_t base = (size_t)blockIdx.x * N * N;
+    stage_tables<N>(s_tw, twg);
+    float2 v[16];
+    float2 *xb = lds + line * Wn::LD;
+    if (!INV) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = in[base + (size_t)line * N + Wn::nat(j, k)];   // rows, natural x
+        __syncthreads();
+        imsp::line_fft_fwd<N>(v, s_tw, xb, j);                       // x frequencies, spectral order
+        imsp::transpose<N, true, true, false>(v, lds, line, j);      // lane (kx = line, j) holds y = j + R k
+        imsp::line_fft_fwd<N>(v, s_tw, xb, j);                       // y frequencies, spectral order
+#pragma unroll
+        for (int i = 0; i < 16; ++i) out[base + (size_t)Wn::spec(j, i) * N + line] = v[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = in[base + (size_t)Wn::spec(j, i) * N + line];  // lane kx, spectral ky
+        __syncthreads();
+        imsp::line_fft_inv<N>(v, s_tw, xb, j);                       // natural y
+        imsp::transpose<N, false, false, true>(v, lds, line, j);     // lane (y = line, j) holds spectral kx
+        imsp::line_fft_inv<N>(v, s_tw, xb, j);                       // natural x
+#pragma unroll
+        for (int k = 0; k < 16; ++k) out[base + (size_t)line * N + Wn::nat(j, k)] = v[k];
     }
 }
 
-// P[i][s] = probe[(y - py) mod n][(x - px) mod n], i = (y, x).
-__global__ void probe_matrix_kernel(const float2 *probe, const int2 *pos, float2 *P, int n, long long S)
+// ---------------------------------------------------------------------------------------
+// Element-wise, diagonal and reduction kernels.
+
+// P[i][s] = probe[(y - py) mod n][(x - px) mod n] (i = (y, x)); Pc = conj(P).
+__global__ void probe_matrix_kernel(const float2 *probe, const int2 *pos, float2 *P, float2 *Pc, int n, long long S)
 {
     const long long n2 = (long long)n * n;
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n2 * S;
@@ -81,10 +160,13 @@ __global__ void probe_matrix_kernel(const float2 *probe, const int2 *pos, float2
         const int y = (int)(i / n), x = (int)(i % n);
         const int2 p = pos[s];
         const int yy = ((y - p.x) % n + n) % n, xx = ((x - p.y) % n + n) % n;
-        P[t] = probe[yy * n + xx];
+        const float2 v = probe[yy * n + xx];
+        P[t] = v;
+        Pc[t] = make_float2(v.x, -v.y);
     }
 }
 
+// A = diag(scale d) (d null: the identity times scale).
 __global__ void set_diag_kernel(float2 *A, const float2 *d, long long n2, float2 scale)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n2 * n2;
@@ -99,29 +181,26 @@ __global__ void set_diag_kernel(float2 *A, const float2 *d, long long n2, float2
     }
 }
 
-// out[r][c] = s * d[r] in[r][c] (rows) or s * in[r][c] d[c] (columns).
-__global__ void diag_scale_kernel(float2 *out, const float2 *in, const float2 *d, long long n2, int rows, float2 s)
+// X = lam A - B (FP64 products, one rounding).
+__global__ void axpb_kernel(float2 *X, const float2 *A, const float2 *B, long long count, double lr, double li)
 {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n2 * n2;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (long long)gridDim.x * blockDim.x) {
-        const long long r = i / n2, c = i - r * n2;
-        const float2 e = d[rows ? r : c], v = in[i];
-        const float2 t = make_float2(e.x * v.x - e.y * v.y, e.x * v.y + e.y * v.x);
-        out[i] = make_float2(s.x * t.x - s.y * t.y, s.x * t.y + s.y * t.x);
+        const float2 a = A[i], b = B[i];
+        X[i] = make_float2((float)(lr * a.x - li * a.y - b.x), (float)(lr * a.y + li * a.x - b.y));
     }
 }
 
-// Amplitude residual of Z = F A P against I [S][N^2] (Z is [N^2][S]); FP64 loss partials.
-__global__ __launch_bounds__(256) void smd_residual_kernel(float2 *Z, const float *I, long long n2, long long S,
-                                                         double *part)
+// Amplitude residual of Z^T = (F A P)^T, rows = positions, against I [S][N^2] (same index);
+// FP64 loss partials.
+__global__ __launch_bounds__(256) void smd_residual_kernel(float2 *Z, const float *I, long long count, double *part)
 {
     __shared__ double red[256];
     double acc = 0.0;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n2 * S;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < count;
          t += (long long)gridDim.x * blockDim.x) {
-        const long long k = t / S, s = t - k * S;
         const float2 z = Z[t];
-        const float m = I[s * n2 + k];
+        const float m = I[t];
         const double a = sqrt((double)z.x * z.x + (double)z.y * z.y);
         const double d = sqrt((double)m) - a;
         acc += d * d;
@@ -146,29 +225,20 @@ __global__ void half_sum_kernel(const double *part, int n, double *out)
     *out = 0.5 * s;
 }
 
-// grad[k] = sum_j U[k][j] conj(S[k][j]), FP64 accumulation, one block per k.
-__global__ __launch_bounds__(256) void row_dot_conj_kernel(const float2 *U, const float2 *S, long long n2,
-                                                         double2 *grad)
+// part[c][k] = sum over the rows j of chunk c of V[j][k] conj(S[j][k]) (FP64); V = (R^H X)^T and
+// S = S_l^T as stored, so that sum_c part[c][k] = diag(R^H X S^H)_k.
+__global__ __launch_bounds__(256) void coldot_kernel(const float2 *V, const float2 *S, int n2, int rows, double2 *part)
 {
-    __shared__ double re[256], im[256];
-    const long long k = blockIdx.x;
+    const int k = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+    if (k >= n2) return;
+    const int j0 = c * rows, j1 = min(n2, j0 + rows);
     double ar = 0.0, ai = 0.0;
-    for (long long j = threadIdx.x; j < n2; j += 256) {
-        const float2 u = U[k * n2 + j], s = S[k * n2 + j];
+    for (int jj = j0; jj < j1; ++jj) {
+        const float2 u = V[(size_t)jj * n2 + k], s = S[(size_t)jj * n2 + k];
         ar += (double)u.x * s.x + (double)u.y * s.y;
         ai += (double)u.y * s.x - (double)u.x * s.y;
     }
-    re[threadIdx.x] = ar;
-    im[threadIdx.x] = ai;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            re[threadIdx.x] += re[threadIdx.x + w];
-            im[threadIdx.x] += im[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) grad[k] = make_double2(re[0], im[0]);
+    part[(size_t)c * n2 + k] = make_double2(ar, ai);
 }
 
 // max |d|^2 of each of M diagonals (one block each).
@@ -187,22 +257,32 @@ __global__ __launch_bounds__(256) void peak_kernel(const float2 *d, long long n2
     if (threadIdx.x == 0) peak2[blockIdx.x] = red[0];
 }
 
-// o_new = Proj(o - conj(lambda) / c grad), c = |lambda|^2 prod_{m != l} peak2_m; one block.
-__global__ __launch_bounds__(256) void prox_update_kernel(const float2 *o, const double2 *grad, const double *peak2,
-                                                          int M, int l, double lr, double li, long long n2,
-                                                          float2 *out)
+// o_new = Proj(o - conj(lambda) / c grad), grad[k] = sum_c part[c][k] in chunk order,
+// c = |lambda|^2 prod_{m != l} peak2_m; one block.
+__global__ __launch_bounds__(256) void prox_update_kernel(const float2 *o, const double2 *part, int nparts,
+                                                          const double *peak2, int M, int l, double lr, double li,
+                                                          long long n2, float2 *out)
 {
     __shared__ double red[256];
     double c = lr * lr + li * li;
     for (int m = 0; m < M; ++m)
         if (m != l) c *= peak2[m];
     const double inv = c > 0.0 ? 1.0 / c : 0.0;
-    // conj(lambda) grad
+    auto step = [&](long long k, double &nr, double &ni) {
+        double gr = 0.0, gi = 0.0;
+        for (int q = 0; q < nparts; ++q) {
+            const double2 g = part[(size_t)q * n2 + k];
+            gr += g.x;
+            gi += g.y;
+        }
+        const double tr = lr * gr + li * gi, ti = lr * gi - li * gr;   // conj(lambda) grad
+        nr = (double)o[k].x - inv * tr;
+        ni = (double)o[k].y - inv * ti;
+    };
     double acc = 0.0;
     for (long long k = threadIdx.x; k < n2; k += 256) {
-        const double2 g = grad[k];
-        const double tr = lr * g.x + li * g.y, ti = lr * g.y - li * g.x;
-        const double nr = (double)o[k].x - inv * tr, ni = (double)o[k].y - inv * ti;
+        double nr, ni;
+        step(k, nr, ni);
         acc += nr * nr + ni * ni;
     }
     red[threadIdx.x] = acc;
@@ -214,9 +294,9 @@ __global__ __launch_bounds__(256) void prox_update_kernel(const float2 *o, const
     const double norm = sqrt(red[0]);
     const double sc = norm > 0.0 ? 1.0 / norm : 0.0;
     for (long long k = threadIdx.x; k < n2; k += 256) {
-        const double2 g = grad[k];
-        const double tr = lr * g.x + li * g.y, ti = lr * g.y - li * g.x;
-        out[k] = make_float2((float)(((double)o[k].x - inv * tr) * sc), (float)(((double)o[k].y - inv * ti) * sc));
+        double nr, ni;
+        step(k, nr, ni);
+        out[k] = make_float2((float)(nr * sc), (float)(ni * sc));
     }
 }
 
@@ -270,7 +350,7 @@ struct smd_plan {
     std::vector<double> dz;
     std::vector<int> pos;   // (y, x) pairs
     char *ws = nullptr;
-    size_t F, G, P, T1, T2, X, U, Z, R, pfx, sfx, old, grad, peak, part, scal, posd, blas, total;
+    size_t tw, hprop, P, Pc, Y, Z, W, sfx, old, dot, peak, part, posd, blas, total;
     rocblas_handle h = nullptr;
     double mu_a = 0.0;
     bool ready = false;
@@ -278,6 +358,9 @@ struct smd_plan {
     template <class T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
     size_t mat() const { return (size_t)n2 * n2; }
+    // propagator factors of gap g (h_y then h_x, N each, divided by N)
+    const float2 *hy(int g) const { return at<float2>(hprop) + (size_t)g * 2 * n; }
+    const float2 *hx(int g) const { return hy(g) + n; }
 };
 
 namespace {
@@ -291,22 +374,18 @@ void plan_layout(smd_plan &p)
         return r;
     };
     const size_t mb = p.mat() * 8, sb = (size_t)p.n2 * p.S * 8;
-    p.F = take(mb);
-    p.G = take(mb * std::max(p.M - 1, 1));
+    p.tw = take((size_t)(p.n / 16) * 17 * 8);
+    p.hprop = take((size_t)std::max(p.M - 1, 1) * 2 * p.n * 8);
     p.P = take(sb);
-    p.T1 = take(mb);
-    p.T2 = take(mb);
-    p.X = take(mb);
-    p.U = take(mb);
+    p.Pc = take(sb);
+    p.Y = take(std::max<size_t>(sb, (size_t)p.S * (size_t)p.S * 8));   // also holds the Gram matrix
     p.Z = take(sb);
-    p.R = take(sb);
-    p.pfx = take(mb * p.M);
+    p.W = take(mb);
     p.sfx = take(mb * p.M);
     p.old = take((size_t)p.M * p.n2 * 8);
-    p.grad = take((size_t)p.n2 * 16);
+    p.dot = take((size_t)kDotChunks * p.n2 * 16);
     p.peak = take((size_t)p.M * 8);
     p.part = take((size_t)kRed * 3 * 8);
-    p.scal = take(64);
     p.posd = take((size_t)p.S * 8);
     p.blas = take(kBlasWorkspace);
     p.total = o;
@@ -316,10 +395,10 @@ int32_t check_problem(const smd_problem *pb)
 {
     if (!pb) return sfail(MS_ERR_INVALID_ARG, "problem is NULL");
     const int n = pb->n;
-    if (n != 4 && n != 8 && n != 16 && n != 32 && n != 64)
-        return sfail(MS_ERR_INVALID_ARG, "n must be 4, 8, 16, 32 or 64 (dense N^2 x N^2 matrices)");
+    if (n != 16 && n != 32 && n != 64)
+        return sfail(MS_ERR_INVALID_ARG, "n must be 16, 32 or 64 (N^2 x N^2 matrices)");
     if (pb->n_slices < 1 || pb->n_slices > 16) return sfail(MS_ERR_INVALID_ARG, "n_slices must be in [1, 16]");
-    if (pb->n_pos < 1 || pb->n_pos > 65536) return sfail(MS_ERR_INVALID_ARG, "n_pos must be in [1, 65536]");
+    if (pb->n_pos < 1 || pb->n_pos > (int64_t)n * n) return sfail(MS_ERR_INVALID_ARG, "n_pos must be in [1, N^2]");
     if (!pb->positions || (pb->n_slices > 1 && !pb->dz)) return sfail(MS_ERR_INVALID_ARG, "positions or dz is NULL");
     for (long long s = 0; s < pb->n_pos; ++s)
         for (int c = 0; c < 2; ++c) {
@@ -351,7 +430,7 @@ bool gemm(smd_plan *p, rocblas_operation opA, rocblas_operation opB, int m, int 
                    "rocblas_cgemm");
 }
 
-constexpr rocblas_operation N_ = rocblas_operation_none, H_ = rocblas_operation_conjugate_transpose;
+constexpr rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
 
 int32_t hip_ok(const char *what)
 {
@@ -360,21 +439,57 @@ int32_t hip_ok(const char *what)
     return sfail(MS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// A = scale O_M G_{M-1} ... G_1 O_1 into `out`; uses T1.
-bool compose_into(smd_plan *p, hipStream_t st, const float2 *sl, std::complex<float> scale, float2 *out)
+// Every one of `count` images: out = post o G_g(pre o in) (conj_g: conj(G_g)).
+void propagate_rows(smd_plan *p, hipStream_t st, int g, bool conj_g, const float2 *in, float2 *out, long long count,
+                    const float2 *pre, bool pre_conj, const float2 *post)
+{
+    const float2 *hy = p->hy(g), *hx = p->hx(g), *tw = p->at<float2>(p->tw);
+    const dim3 grid((unsigned)count);
+    const int pc = pre_conj ? 1 : 0;
+    switch (p->n) {
+        case 16:
+            if (conj_g) image_propagate_kernel<16, true><<<grid, Win<16>::NT, 0, st>>>(in, out, pre, pc, post, hy, hx, tw);
+            else image_propagate_kernel<16, false><<<grid, Win<16>::NT, 0, st>>>(in, out, pre, pc, post, hy, hx, tw);
+            break;
+        case 32:
+            if (conj_g) image_propagate_kernel<32, true><<<grid, Win<32>::NT, 0, st>>>(in, out, pre, pc, post, hy, hx, tw);
+            else image_propagate_kernel<32, false><<<grid, Win<32>::NT, 0, st>>>(in, out, pre, pc, post, hy, hx, tw);
+            break;
+        default:
+            if (conj_g) image_propagate_kernel<64, true><<<grid, Win<64>::NT, 0, st>>>(in, out, pre, pc, post, hy, hx, tw);
+            else image_propagate_kernel<64, false><<<grid, Win<64>::NT, 0, st>>>(in, out, pre, pc, post, hy, hx, tw);
+            break;
+    }
+}
+
+// Every one of `count` images: out = F in (inverse: F^H in).
+void dft_rows(smd_plan *p, hipStream_t st, bool inverse, const float2 *in, float2 *out, long long count)
+{
+    const float2 *tw = p->at<float2>(p->tw);
+    const dim3 grid((unsigned)count);
+    switch (p->n) {
+        case 16:
+            if (inverse) image_dft_kernel<16, true><<<grid, Win<16>::NT, 0, st>>>(in, out, tw);
+            else image_dft_kernel<16, false><<<grid, Win<16>::NT, 0, st>>>(in, out, tw);
+            break;
+        case 32:
+            if (inverse) image_dft_kernel<32, true><<<grid, Win<32>::NT, 0, st>>>(in, out, tw);
+            else image_dft_kernel<32, false><<<grid, Win<32>::NT, 0, st>>>(in, out, tw);
+            break;
+        default:
+            if (inverse) image_dft_kernel<64, true><<<grid, Win<64>::NT, 0, st>>>(in, out, tw);
+            else image_dft_kernel<64, false><<<grid, Win<64>::NT, 0, st>>>(in, out, tw);
+            break;
+    }
+}
+
+// A^T = scale O_1 G_1 O_2 ... G_{M-1} O_M into `out` (A column-major).
+void compose_into(smd_plan *p, hipStream_t st, const float2 *sl, std::complex<float> scale, float2 *out)
 {
     const long long n2 = p->n2;
-    const float2 one = make_float2(1.f, 0.f);
-    const float2 sc = make_float2(scale.real(), scale.imag());
-    set_diag_kernel<<<blocks(n2 * n2), 256, 0, st>>>(out, sl, n2, p->M == 1 ? sc : one);
-    for (int m = 1; m < p->M; ++m) {
-        if (!gemm(p, N_, N_, p->n2, p->n2, p->n2, 1.0f, p->at<float2>(p->G) + (size_t)(m - 1) * p->mat(), p->n2, out,
-                  p->n2, 0.0f, p->at<float2>(p->T1), p->n2))
-            return false;
-        diag_scale_kernel<<<blocks(n2 * n2), 256, 0, st>>>(out, p->at<float2>(p->T1), sl + (size_t)m * n2, n2, 1,
-                                                           m + 1 == p->M ? sc : one);
-    }
-    return true;
+    set_diag_kernel<<<blocks(n2 * n2), 256, 0, st>>>(out, sl, n2, make_float2(scale.real(), scale.imag()));
+    for (int g = 0; g + 1 < p->M; ++g)
+        propagate_rows(p, st, g, false, out, out, n2, nullptr, false, sl + (size_t)(g + 1) * n2);
 }
 
 }  // namespace
@@ -410,7 +525,7 @@ int32_t smd_plan_create(const smd_problem *pb, void *workspace, size_t ws_bytes,
     p->S = pb->n_pos;
     p->dx = pb->pixel_size;
     p->lambda = pb->wavelength;
-    p->dz.assign(pb->dz ? pb->dz : nullptr, pb->dz ? pb->dz + std::max(p->M - 1, 0) : nullptr);
+    if (p->M > 1) p->dz.assign(pb->dz, pb->dz + (p->M - 1));
     for (long long i = 0; i < p->S; ++i) {
         p->pos.push_back((int)pb->positions[2 * i]);
         p->pos.push_back((int)pb->positions[2 * i + 1]);
@@ -422,6 +537,30 @@ int32_t smd_plan_create(const smd_problem *pb, void *workspace, size_t ws_bytes,
         return sfail(MS_ERR_BUDGET, "workspace too small: " + std::to_string(need) + " bytes needed");
     }
     p->ws = static_cast<char *>(workspace);
+    // twiddles W_N^{j k1} of lane j (rows of 17) and the propagator of eq. (fresnel_element)
+    // split per axis, exp(-i pi dz lambda q^2) / N, in FP64 rounded once
+    const int n = p->n, R = n / 16;
+    const double PI = 3.14159265358979323846264338327950288;
+    std::vector<float2> tw((size_t)R * 17, make_float2(1.f, 0.f));
+    for (int j = 0; j < R; ++j)
+        for (int k1 = 0; k1 < 16; ++k1) {
+            const double a = -2.0 * PI * (double)(j * k1) / n;
+            tw[(size_t)j * 17 + k1] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+    std::vector<float2> hp((size_t)std::max(p->M - 1, 1) * 2 * n, make_float2(0.f, 0.f));
+    for (int g = 0; g + 1 < p->M; ++g)
+        for (int i = 0; i < n; ++i) {
+            const double q = (double)(i < (n + 1) / 2 ? i : i - n) / ((double)n * p->dx);
+            const double ph = -PI * p->dz[g] * p->lambda * q * q;
+            const float2 h = make_float2((float)(std::cos(ph) / n), (float)(std::sin(ph) / n));
+            hp[(size_t)g * 2 * n + i] = h;        // h_y
+            hp[(size_t)g * 2 * n + n + i] = h;    // h_x
+        }
+    if (hipMemcpy(p->at<char>(p->tw), tw.data(), tw.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->at<char>(p->hprop), hp.data(), hp.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        delete p;
+        return sfail(MS_ERR_HIP, "table upload failed");
+    }
     if (rocblas_create_handle(&p->h) != rocblas_status_success) {
         delete p;
         return sfail(MS_ERR_HIP, "rocblas_create_handle failed");
@@ -443,26 +582,15 @@ int32_t smd_set_probe(smd_plan *p, hipStream_t st, const void *probe)
     if (!p || !probe) return sfail(MS_ERR_INVALID_ARG, "NULL argument");
     rocblas_set_stream(p->h, st);
     const long long n2 = p->n2, S = p->S;
-    const int n = p->n;
-    float2 *F = p->at<float2>(p->F);
-    dft_kernel<<<blocks(n2 * n2), 256, 0, st>>>(F, n);
-    for (int m = 0; m + 1 < p->M; ++m) {
-        h_rows_kernel<<<blocks(n2 * n2), 256, 0, st>>>(F, p->at<float2>(p->T1), n, p->dz[m], p->lambda, p->dx);
-        // G = F^H (diag(h) F) / N^2
-        if (!gemm(p, H_, N_, p->n2, p->n2, p->n2, std::complex<float>(1.0f / (float)n2, 0.f), F, p->n2,
-                  p->at<float2>(p->T1), p->n2, 0.0f, p->at<float2>(p->G) + (size_t)m * p->mat(), p->n2))
-            return MS_ERR_HIP;
-    }
     if (hipMemcpyAsync(p->at<int2>(p->posd), p->pos.data(), (size_t)S * 8, hipMemcpyHostToDevice, st) != hipSuccess)
         return sfail(MS_ERR_HIP, "position upload failed");
     float2 *P = p->at<float2>(p->P);
     probe_matrix_kernel<<<blocks(n2 * S), 256, 0, st>>>(static_cast<const float2 *>(probe), p->at<int2>(p->posd), P,
-                                                          n, S);
-    // Gram matrix P^H P (S x S) into Z (n2 x S >= S x S when S <= n2, else into X / U region)
-    const bool fits = S * S <= (long long)p->mat();
-    float2 *gram = fits ? p->at<float2>(p->X) : nullptr;
-    if (!gram) return sfail(MS_ERR_UNSUPPORTED, "more positions than N^2 x N^2 / S entries");
-    if (!gemm(p, H_, N_, (int)S, (int)S, p->n2, 1.0f, P, (int)S, P, (int)S, 0.0f, gram, (int)S))
+                                                          p->at<float2>(p->Pc), p->n, S);
+    // Gram matrix P^H P (S x S, S <= N^2)
+    float2 *gram = p->at<float2>(p->Y);
+    if (!gemm(p, rocblas_operation_conjugate_transpose, N_, (int)S, (int)S, p->n2, 1.0f, P, (int)S, P, (int)S, 0.0f,
+              gram, (int)S))
         return MS_ERR_HIP;
     std::vector<std::complex<float>> g((size_t)S * S);
     if (hipMemcpyAsync(g.data(), gram, g.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -498,10 +626,8 @@ int32_t smd_compose(smd_plan *p, hipStream_t st, const void *slices, const doubl
 {
     if (!p || !slices || !lambda || !a_out) return sfail(MS_ERR_INVALID_ARG, "NULL argument");
     if (!p->ready) return sfail(MS_ERR_INVALID_ARG, "call smd_set_probe first");
-    rocblas_set_stream(p->h, st);
-    if (!compose_into(p, st, static_cast<const float2 *>(slices),
-                      std::complex<float>((float)lambda[0], (float)lambda[1]), static_cast<float2 *>(a_out)))
-        return MS_ERR_HIP;
+    compose_into(p, st, static_cast<const float2 *>(slices), std::complex<float>((float)lambda[0], (float)lambda[1]),
+                 static_cast<float2 *>(a_out));
     return hip_ok("smd_compose");
 }
 
@@ -512,18 +638,19 @@ int32_t smd_estimate(smd_plan *p, hipStream_t st, const float *measured, void *a
     if (steps < 0) return sfail(MS_ERR_INVALID_ARG, "steps must be >= 0");
     rocblas_set_stream(p->h, st);
     const int n2 = p->n2, S = (int)p->S;
-    float2 *A = static_cast<float2 *>(a), *F = p->at<float2>(p->F), *P = p->at<float2>(p->P);
-    float2 *Z = p->at<float2>(p->Z), *R = p->at<float2>(p->R);
+    float2 *At = static_cast<float2 *>(a), *P = p->at<float2>(p->P), *Pc = p->at<float2>(p->Pc);
+    float2 *Y = p->at<float2>(p->Y), *Z = p->at<float2>(p->Z);
     double *part = p->at<double>(p->part);
     for (int k = 0; k < steps; ++k) {
-        // F (A P): the product with the N^2 x S probe matrix first, 2 N^4 S instead of N^6 + N^4 S
-        if (!gemm(p, N_, N_, n2, S, n2, 1.0f, A, n2, P, S, 0.0f, R, S)) return MS_ERR_HIP;          // A P
-        if (!gemm(p, N_, N_, n2, S, n2, 1.0f, F, n2, R, S, 0.0f, Z, S)) return MS_ERR_HIP;          // F A P
-        smd_residual_kernel<<<kRed, 256, 0, st>>>(Z, measured, n2, S, part);
+        // (A P)^T = P^T A^T, then the DFT of each position's image: Z^T = (F A P)^T
+        if (!gemm(p, T_, N_, S, n2, n2, 1.0f, P, S, At, n2, 0.0f, Y, n2)) return MS_ERR_HIP;
+        dft_rows(p, st, false, Y, Z, S);
+        smd_residual_kernel<<<kRed, 256, 0, st>>>(Z, measured, (long long)S * n2, part);
         if (k == 0 && loss_first) half_sum_kernel<<<1, 1, 0, st>>>(part, kRed, loss_first);
-        if (!gemm(p, H_, N_, n2, S, n2, 1.0f, F, n2, Z, S, 0.0f, R, S)) return MS_ERR_HIP;          // F^H r
-        if (!gemm(p, N_, H_, n2, n2, S, std::complex<float>((float)-p->mu_a, 0.f), R, S, P, S, 1.0f, A, n2))
-            return MS_ERR_HIP;                                                                     // A -= mu (F^H r) P^H
+        dft_rows(p, st, true, Z, Y, S);   // (F^H r)^T
+        // A^T -= mu (F^H r P^H)^T = mu conj(P) (F^H r)^T
+        if (!gemm(p, N_, N_, n2, n2, S, std::complex<float>((float)-p->mu_a, 0.f), Pc, S, Y, n2, 1.0f, At, n2))
+            return MS_ERR_HIP;
     }
     return hip_ok("smd_estimate");
 }
@@ -532,49 +659,34 @@ int32_t smd_decompose(smd_plan *p, hipStream_t st, const void *a_hat, void *slic
 {
     if (!p || !a_hat || !slices || !lambda) return sfail(MS_ERR_INVALID_ARG, "NULL argument");
     if (!p->ready) return sfail(MS_ERR_INVALID_ARG, "call smd_set_probe first");
-    rocblas_set_stream(p->h, st);
     const int n2 = p->n2, M = p->M;
     const long long nn = (long long)n2 * n2;
     const float2 *Ah = static_cast<const float2 *>(a_hat);
     float2 *sl = static_cast<float2 *>(slices);
-    float2 *old = p->at<float2>(p->old);
-    const std::complex<float> lam((float)lambda[0], (float)lambda[1]);
+    float2 *old = p->at<float2>(p->old), *W = p->at<float2>(p->W), *sfx = p->at<float2>(p->sfx);
+    double2 *dot = p->at<double2>(p->dot);
     if (hipMemcpyAsync(old, sl, (size_t)M * n2 * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return sfail(MS_ERR_HIP, "slice copy failed");
     peak_kernel<<<M, 256, 0, st>>>(old, n2, p->at<double>(p->peak));
-    const float2 one = make_float2(1.f, 0.f);
-    float2 *pfx = p->at<float2>(p->pfx), *sfx = p->at<float2>(p->sfx);
-    auto G = [&](int m) { return p->at<float2>(p->G) + (size_t)m * p->mat(); };
-    // suffixes S_0 = I, S_{l+1} = G_l O_l S_l; prefixes R_{M-1} = I, R_l = R_{l+1} O_{l+1} G_l
-    set_diag_kernel<<<blocks(nn), 256, 0, st>>>(sfx, nullptr, n2, one);
-    for (int l = 0; l + 1 < M; ++l) {
-        diag_scale_kernel<<<blocks(nn), 256, 0, st>>>(p->at<float2>(p->T1), sfx + (size_t)l * nn, old + (size_t)l * n2,
-                                                      n2, 1, one);
-        if (!gemm(p, N_, N_, n2, n2, n2, 1.0f, G(l), n2, p->at<float2>(p->T1), n2, 0.0f, sfx + (size_t)(l + 1) * nn, n2))
-            return MS_ERR_HIP;
+    // X^T = lambda A^T(old slices) - A_hat^T: for every layer R_l O_l S_l is the whole matrix
+    compose_into(p, st, old, 1.0f, W);
+    axpb_kernel<<<blocks(nn), 256, 0, st>>>(W, W, Ah, nn, lambda[0], lambda[1]);
+    // suffixes S_l^T: S_0 = I, S^T_{l+1} = S^T_l O_l G_l
+    set_diag_kernel<<<blocks(nn), 256, 0, st>>>(sfx, nullptr, n2, make_float2(1.f, 0.f));
+    for (int l = 0; l + 1 < M; ++l)
+        propagate_rows(p, st, l, false, sfx + (size_t)l * nn, sfx + (size_t)(l + 1) * nn, n2, old + (size_t)l * n2,
+                       false, nullptr);
+    // layers from the last: W holds V_l^T = (R_l^H X)^T, V_{M-1} = X
+    const int rows = (n2 + kDotChunks - 1) / kDotChunks;
+    for (int l = M - 1; l >= 0; --l) {
+        coldot_kernel<<<dim3((n2 + 255) / 256, kDotChunks), 256, 0, st>>>(W, sfx + (size_t)l * nn, n2, rows, dot);
+        prox_update_kernel<<<1, 256, 0, st>>>(old + (size_t)l * n2, dot, kDotChunks, p->at<double>(p->peak), M, l,
+                                              lambda[0], lambda[1], n2, sl + (size_t)l * n2);
+        if (l > 0)   // V^T_{l-1} = V^T_l conj(O_l) conj(G_{l-1})
+            propagate_rows(p, st, l - 1, true, W, W, n2, old + (size_t)l * n2, true, nullptr);
     }
-    set_diag_kernel<<<blocks(nn), 256, 0, st>>>(pfx + (size_t)(M - 1) * nn, nullptr, n2, one);
-    for (int l = M - 2; l >= 0; --l) {
-        diag_scale_kernel<<<blocks(nn), 256, 0, st>>>(p->at<float2>(p->T1), pfx + (size_t)(l + 1) * nn,
-                                                      old + (size_t)(l + 1) * n2, n2, 0, one);
-        if (!gemm(p, N_, N_, n2, n2, n2, 1.0f, p->at<float2>(p->T1), n2, G(l), n2, 0.0f, pfx + (size_t)l * nn, n2))
-            return MS_ERR_HIP;
-    }
-    float2 *X = p->at<float2>(p->X), *U = p->at<float2>(p->U), *Y = p->at<float2>(p->T2);
-    double2 *grad = p->at<double2>(p->grad);
-    for (int l = 0; l < M; ++l) {
-        float2 *Rl = pfx + (size_t)l * nn, *Sl = sfx + (size_t)l * nn;
-        diag_scale_kernel<<<blocks(nn), 256, 0, st>>>(Y, Rl, old + (size_t)l * n2, n2, 0, one);   // R_l O_l
-        if (hipMemcpyAsync(X, Ah, (size_t)nn * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
-            return sfail(MS_ERR_HIP, "copy failed");
-        if (!gemm(p, N_, N_, n2, n2, n2, lam, Y, n2, Sl, n2, -1.0f, X, n2)) return MS_ERR_HIP;   // lambda R O S - A_hat
-        if (!gemm(p, H_, N_, n2, n2, n2, 1.0f, Rl, n2, X, n2, 0.0f, U, n2)) return MS_ERR_HIP;   // R^H X
-        row_dot_conj_kernel<<<n2, 256, 0, st>>>(U, Sl, n2, grad);                               // diag(R^H X S^H)
-        prox_update_kernel<<<1, 256, 0, st>>>(old + (size_t)l * n2, grad, p->at<double>(p->peak), M, l, lambda[0],
-                                              lambda[1], n2, sl + (size_t)l * n2);
-    }
-    float2 *At = a_tilde_out ? static_cast<float2 *>(a_tilde_out) : X;
-    if (!compose_into(p, st, sl, 1.0f, At)) return MS_ERR_HIP;
+    float2 *At = a_tilde_out ? static_cast<float2 *>(a_tilde_out) : W;
+    compose_into(p, st, sl, 1.0f, At);
     double *part = p->at<double>(p->part);
     trace_kernel<<<kRed, 256, 0, st>>>(At, Ah, nn, part);
     std::vector<double> h((size_t)kRed * 3);

@@ -157,11 +157,11 @@ def test_smd_header_declares_the_binding_and_the_library_exports_it():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("kw", [dict(n=12), dict(n=128), dict(n_slices=0), dict(positions=[[0.5, 1.0]]),
-                                dict(wavelength=0.0), dict(dz=[float("nan")])])
+@pytest.mark.parametrize("kw", [dict(n=12), dict(n=8), dict(n=128), dict(n_slices=0), dict(positions=[[0.5, 1.0]]),
+                                dict(positions=[[0, 0]] * 257), dict(wavelength=0.0), dict(dz=[float("nan")])])
 def test_smd_rejects_invalid_problems_without_a_device(kw):
     from paper_2205_03902_amd import smd
-    args = dict(n=8, n_slices=2, positions=[[0, 0], [3, 5]], dz=[2.0], pixel_size=0.2, wavelength=0.0487)
+    args = dict(n=16, n_slices=2, positions=[[0, 0], [3, 5]], dz=[2.0], pixel_size=0.2, wavelength=0.0487)
     args.update(kw)
     pb, keep = smd.make_problem(**args)
     out = C.c_size_t(0)
@@ -174,9 +174,9 @@ def test_smd_workspace_holds_the_dense_matrices():
     pb, keep = smd.make_problem(32, 3, [[0, 0]] * 40, [2.0, 2.0], 0.2, 0.0487)
     ws = smd.workspace_size(pb)
     n2 = 32 * 32
-    # F, G_1..G_2, four scratch matrices, three prefixes and three suffixes
-    assert ws >= (1 + 2 + 4 + 3 + 3) * n2 * n2 * 8
-    assert ws < (1 + 2 + 4 + 3 + 3) * n2 * n2 * 8 + (64 << 20)
+    # one working matrix and the three suffixes; no F or G_m is ever formed
+    assert ws >= (1 + 3) * n2 * n2 * 8
+    assert ws < (1 + 3) * n2 * n2 * 8 + (64 << 20)
     handle = C.c_void_p()
     assert smd.lib().smd_plan_create(C.byref(pb), None, ws, C.byref(handle)) == abi.MS_ERR_INVALID_ARG
     assert smd.lib().smd_set_probe(None, None, None) == abi.MS_ERR_INVALID_ARG

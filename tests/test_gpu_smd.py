@@ -1,7 +1,8 @@
 """GPU parity of the sparse matrix decomposition (Algorithm 2) against the FP64 dense
 reference: the composed transfer matrix, the amplitude-flow steps on A with their loss, one
 decomposition pass (slices, lambda, A~), the lambda^(1/M) result and whole runs of the
-algorithm, at N = 8, 16 and 32 with one to three slices."""
+algorithm, at N = 16 and 32 with one to three slices.  Matrices cross the boundary in
+column-major order: the row-major array the device returns is the transpose."""
 import numpy as np
 import pytest
 
@@ -17,8 +18,10 @@ U32 = 2.0 ** -24
 
 def bar(n, products):
     """Relative (Frobenius) tolerance of a result that went through `products` chained FP32
-    GEMMs with K = N^2 terms each: the rounding error of one such sum grows like sqrt(K) u =
-    N u for terms of random sign, and chained products add their errors; factor 4 of margin."""
+    operators: a GEMM over K = N^2 terms (the estimate's products with the probe matrix) has a
+    rounding error that grows like sqrt(K) u = N u for terms of random sign, a propagation or
+    DFT of each image (the G and F products) about sqrt(log2 N^2) u, less; chained operators
+    add their errors; factor 4 of margin."""
     return 4.0 * products * n * U32
 
 
@@ -70,7 +73,16 @@ def _t(x, dev):
     return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
 
 
-GRID = [(8, 3, 6), (16, 2, 24), (16, 1, 5), (32, 3, 40), (8, 2, 1)]
+def _colmajor(a, dev):
+    """An N^2 x N^2 matrix as the device stores it (column-major: the transpose, row-major)."""
+    return _t(np.asarray(a).T, dev)
+
+
+def _matrix(t):
+    return t.cpu().numpy().T
+
+
+GRID = [(16, 3, 6), (16, 2, 24), (16, 1, 5), (32, 3, 40), (16, 2, 1)]
 
 
 @pytest.mark.parametrize("n,m,s", GRID)
@@ -80,7 +92,7 @@ def test_compose_matches_the_dense_product(dev, n, m, s):
     plan = c.plan(dev)
     plan.set_probe(_t(c.probe, dev))
     lam = 0.8 - 0.3j
-    got = plan.compose(_t(c.start, dev), lam).cpu().numpy()
+    got = _matrix(plan.compose(_t(c.start, dev), lam))
     ref = lam * osmd.compose(c.start.astype(np.complex128), c.gs)
     # G_m = F^H diag(h) F is itself an FP32 product: two per slice step
     print(f"compose rel {rel(got, ref):.3e} bar {bar(n, 2 * m):.3e}")
@@ -94,13 +106,13 @@ def test_estimate_steps_match(dev, n, m, s):
     plan = c.plan(dev)
     plan.set_probe(_t(c.probe, dev))
     a0 = osmd.compose(c.start.astype(np.complex128), c.gs).astype(np.complex64)
-    a = _t(a0, dev)
+    a = _colmajor(a0, dev)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
     plan.estimate(_t(c.measured_images(), dev), a, 5, loss)
     ref, losses = osmd.estimate_a(a0.astype(np.complex128), c.p, c.meas.astype(np.float64), 5)
     assert abs(loss.item() - losses[0]) < bar(n, 2 * m) * losses[0]
-    print(f"estimate rel {rel(a.cpu().numpy(), ref):.3e} bar {bar(n, 2 * m + 4 * 5):.3e}")
-    assert rel(a.cpu().numpy(), ref) < bar(n, 2 * m + 4 * 5)
+    print(f"estimate rel {rel(_matrix(a), ref):.3e} bar {bar(n, 2 * m + 4 * 5):.3e}")
+    assert rel(_matrix(a), ref) < bar(n, 2 * m + 4 * 5)
 
 
 @pytest.mark.parametrize("n,m,s", GRID)
@@ -117,7 +129,7 @@ def test_decompose_pass_matches(dev, n, m, s):
     lam0 = complex(1.3 + 0.2 * rng.standard_normal(), 0.1)
     sl = _t(start, dev)
     at = plan.empty_matrix()
-    lam = plan.decompose(_t(a_hat, dev), sl, lam0, at)
+    lam = plan.decompose(_colmajor(a_hat, dev), sl, lam0, at)
     ref_sl, ref_lam, ref_at = osmd.decompose_pass(a_hat.astype(np.complex128), start.astype(np.complex128), lam0,
                                                   c.gs)
     # prefixes and suffixes: 2 (M - 1) products on G_m; per layer two more; then A~
@@ -126,12 +138,12 @@ def test_decompose_pass_matches(dev, n, m, s):
           f"bar {tol:.3e}")
     assert rel(sl.cpu().numpy(), ref_sl) < tol
     assert abs(lam - ref_lam) < tol * abs(ref_lam)
-    assert rel(at.cpu().numpy(), ref_at) < tol
+    assert rel(_matrix(at), ref_at) < tol
     out = plan.result(sl, lam).cpu().numpy()
     assert rel(out, ref_sl * ref_lam ** (1.0 / m)) < 2 * tol
 
 
-@pytest.mark.parametrize("n,m,s", [(8, 3, 6), (16, 2, 24)])
+@pytest.mark.parametrize("n,m,s", [(16, 3, 6), (16, 2, 24)])
 def test_algorithm2_runs_match(dev, n, m, s):
     from oracle import smd as osmd
     c = case(n, m, s)
@@ -150,7 +162,7 @@ def test_algorithm2_runs_match(dev, n, m, s):
 
 def test_calls_before_set_probe_are_rejected(dev):
     from paper_2205_03902_amd import abi
-    c = case(8, 3, 6)
+    c = case(16, 3, 6)
     plan = c.plan(dev)
     with pytest.raises(abi.MsError):
         plan.compose(_t(c.start, dev))
