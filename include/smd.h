@@ -26,10 +26,10 @@
  * Implementation.  Products with G_m and F_2D never form those matrices: each is one
  * propagation or 2D DFT of every image of the stored array (in-register line FFTs, the
  * machinery of the multislice kernels).  The two products with the N^2 x S probe matrix in
- * smd_estimate are rocBLAS complex GEMMs on the plan's stream (rocBLAS works in a slice of
- * the workspace).  smd_set_probe and smd_decompose synchronise the stream (the spectral norm of
- * P and the new lambda are finished on the host from device reductions); the other calls only
- * enqueue.  Errors return a negative status (the ms_status codes of ms.h) with a message in
+ * smd_estimate are LDS-tiled kernels of this library.  smd_set_probe and smd_decompose
+ * synchronise the stream (the spectral norm of P and the new lambda are finished on the host
+ * from device reductions); the other calls only enqueue.  Errors return a negative status (the
+ * ms_status codes of ms.h) with a message in
  * smd_last_error().
  */
 #ifndef SMD_H

@@ -17,7 +17,6 @@ HEADERS = [os.path.join(ROOT, "include", "ms.h"), os.path.join(ROOT, "include", 
            os.path.join(ROOT, "include", "datagen.h"), os.path.join(PKG, "csrc", "datagen_kernels.hpp"),
            os.path.join(ROOT, "include", "smd.h")]
 ARCH = "gfx950"
-ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 
 def hipcc() -> str:
@@ -31,8 +30,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay disabled in every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"), "-Wall", "-Wno-unused-result"]
-# the dense products of the sparse matrix decomposition are rocBLAS GEMMs
-LINK = ["-L", os.path.join(ROCM, "lib"), "-lrocblas", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+LINK = []
 OBJ_DIR = os.path.join(ROOT, "_build")
 
 

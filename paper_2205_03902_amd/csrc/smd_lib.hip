@@ -8,9 +8,8 @@
 //   S^T_{l+1} = S^T_l O_l G_l,   V^T_l = V^T_{l+1} conj(O_{l+1}) conj(G_l)   (V_l = R_l^H X),
 // each a right product, i.e. an operation on the rows of the stored array.  The only dense
 // products left are the two N^2 x N^2 x S products with the probe matrix in the A estimate
-// (rocBLAS; a row-major product C = op(A) op(B) is the column-major C^T = op(B)^T op(A)^T).
+// (LDS-tiled kernels below).
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -37,8 +36,8 @@ int32_t sfail(int32_t st, const std::string &msg)
 }
 
 constexpr size_t kAlign = 256;
-constexpr size_t kBlasWorkspace = (size_t)32 << 20;
 constexpr int kRed = 256;        // reduction partials
+constexpr int kTraceBlocks = 2048;   // partials of the lambda traces
 constexpr int kDotChunks = 32;   // row chunks of the gradient's column sums
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -145,6 +144,151 @@ __global__ __launch_bounds__(Win<N>::NT) void image_dft_kernel(const float2 *in,
 #pragma unroll
         for (int k = 0; k < 16; ++k) out[base + (size_t)line * N + Wn::nat(j, k)] = v[k];
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// The two products with the probe matrix in the A estimate: N^2 x N^2 by N^2 x S, with S
+// small.  64 x 64 output tiles per workgroup (4 x 4 complex values a lane, spaced 16 apart
+// so that the LDS reads of a wavefront are consecutive or broadcast), K in steps of 16
+// through LDS, FP32 accumulation.
+
+constexpr int kTile = 64, kKStep = 16;
+
+__device__ __forceinline__ void cmac(float2 &acc, float2 a, float2 b)
+{
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(-a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(a.y, b.x, acc.y);
+}
+
+// part[c][s][k] = sum over the rows i of chunk c of P[i][s] At[i][k]   (P: n2 x S, At: n2 x n2).
+// Grid (n2 / 64 column tiles, ceil(S / 64) position tiles, chunks); rows chunk c: [c rows, (c+1) rows).
+__global__ __launch_bounds__(256) void pt_a_partial_kernel(const float2 *P, const float2 *At, int n2, int S, int rows,
+                                                           float2 *part)
+{
+    __shared__ float2 sP[kKStep][kTile];
+    __shared__ float2 sA[kKStep][kTile];
+    const int t = threadIdx.x, ts = t / 16, tk = t % 16;
+    const int k0 = blockIdx.x * kTile, s0 = blockIdx.y * kTile;
+    const int i_begin = blockIdx.z * rows, i_end = min(n2, i_begin + rows);
+    float2 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = make_float2(0.f, 0.f);
+    for (int i0 = i_begin; i0 < i_end; i0 += kKStep) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {   // 16 x 64 of each operand, 4 values a lane
+            const int e = t + 256 * q, r = e / kTile, col = e % kTile, i = i0 + r;
+            const bool in_i = i < i_end;
+            sA[r][col] = in_i ? At[(size_t)i * n2 + k0 + col] : make_float2(0.f, 0.f);
+            sP[r][col] = (in_i && s0 + col < S) ? P[(size_t)i * S + s0 + col] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kKStep; ++r) {
+            float2 pa[4], ab[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) pa[a] = sP[r][ts + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) ab[b] = sA[r][tk + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) cmac(acc[a][b], pa[a], ab[b]);
+        }
+        __syncthreads();
+    }
+    float2 *dst = part + (size_t)blockIdx.z * S * n2;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int s_ = s0 + ts + 16 * a;
+        if (s_ < S)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) dst[(size_t)s_ * n2 + k0 + tk + 16 * b] = acc[a][b];
+    }
+}
+
+// Gram matrix g[s][t] = sum_i conj(P[i][s]) P[i][t] (S x S, FP64 sums); grid (ceil(S / 256), S).
+__global__ __launch_bounds__(256) void gram_kernel(const float2 *P, int n2, int S, double2 *g)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x, s = blockIdx.y;
+    if (t >= S) return;
+    double gr = 0.0, gi = 0.0;
+    for (int i = 0; i < n2; ++i) {
+        const float2 a = P[(size_t)i * S + s], b = P[(size_t)i * S + t];
+        gr += (double)a.x * b.x + (double)a.y * b.y;
+        gi += (double)a.x * b.y - (double)a.y * b.x;
+    }
+    g[(size_t)s * S + t] = make_double2(gr, gi);
+}
+
+// Y[e] = sum_c part[c][e] in chunk order.
+__global__ void chunk_sum_kernel(const float2 *part, int nch, long long count, float2 *Y)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (long long)gridDim.x * blockDim.x) {
+        float2 a = make_float2(0.f, 0.f);
+        for (int c = 0; c < nch; ++c) {
+            const float2 v = part[(size_t)c * count + e];
+            a.x += v.x;
+            a.y += v.y;
+        }
+        Y[e] = a;
+    }
+}
+
+// At[i][k] += alpha sum_s Pc[i][s] Y[s][k]   (Pc: n2 x S, Y: S x n2), alpha real.
+// Grid (n2 / 64 column tiles, n2 / 64 row tiles).
+__global__ __launch_bounds__(256) void rank_update_kernel(float2 *At, const float2 *Pc, const float2 *Y, int n2, int S,
+                                                          float alpha)
+{
+    __shared__ float2 sP[kKStep][kTile];   // [s][i]
+    __shared__ float2 sY[kKStep][kTile];   // [s][k]
+    const int t = threadIdx.x, ti = t / 16, tk = t % 16;
+    const int k0 = blockIdx.x * kTile, i0 = blockIdx.y * kTile;
+    float2 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = make_float2(0.f, 0.f);
+    for (int sb = 0; sb < S; sb += kKStep) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + 256 * q;
+            {   // Y rows sb.., 64 columns
+                const int r = e / kTile, col = e % kTile, s_ = sb + r;
+                sY[r][col] = s_ < S ? Y[(size_t)s_ * n2 + k0 + col] : make_float2(0.f, 0.f);
+            }
+            {   // Pc rows i0.., 16 columns sb..: element (row, s) stored transposed
+                const int row = e / kKStep, r = e % kKStep, s_ = sb + r;
+                sP[r][row] = s_ < S ? Pc[(size_t)(i0 + row) * S + s_] : make_float2(0.f, 0.f);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kKStep; ++r) {
+            float2 pa[4], yb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) pa[a] = sP[r][ti + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) yb[b] = sY[r][tk + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) cmac(acc[a][b], pa[a], yb[b]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const size_t idx = (size_t)(i0 + ti + 16 * a) * n2 + k0 + tk + 16 * b;
+            const float2 v = At[idx];
+            At[idx] = make_float2(fmaf(alpha, acc[a][b].x, v.x), fmaf(alpha, acc[a][b].y, v.y));
+        }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -257,18 +401,21 @@ __global__ __launch_bounds__(256) void peak_kernel(const float2 *d, long long n2
     if (threadIdx.x == 0) peak2[blockIdx.x] = red[0];
 }
 
-// o_new = Proj(o - conj(lambda) / c grad), grad[k] = sum_c part[c][k] in chunk order,
-// c = |lambda|^2 prod_{m != l} peak2_m; one block.
-__global__ __launch_bounds__(256) void prox_update_kernel(const float2 *o, const double2 *part, int nparts,
-                                                          const double *peak2, int M, int l, double lr, double li,
-                                                          long long n2, float2 *out)
+// Proximal step of one layer, before the projection: onew[k] = o[k] - conj(lambda) / c grad[k],
+// grad[k] = sum_c part[c][k] in chunk order, c = |lambda|^2 prod_{m != l} peak2_m (FP64);
+// npart[block] = the block's sum of |onew|^2.
+__global__ __launch_bounds__(256) void prox_step_kernel(const float2 *o, const double2 *part, int nparts,
+                                                        const double *peak2, int M, int l, double lr, double li, int n2,
+                                                        double2 *onew, double *npart)
 {
     __shared__ double red[256];
+    const int k = blockIdx.x * 256 + threadIdx.x;
     double c = lr * lr + li * li;
     for (int m = 0; m < M; ++m)
         if (m != l) c *= peak2[m];
     const double inv = c > 0.0 ? 1.0 / c : 0.0;
-    auto step = [&](long long k, double &nr, double &ni) {
+    double a2 = 0.0;
+    if (k < n2) {
         double gr = 0.0, gi = 0.0;
         for (int q = 0; q < nparts; ++q) {
             const double2 g = part[(size_t)q * n2 + k];
@@ -276,28 +423,30 @@ __global__ __launch_bounds__(256) void prox_update_kernel(const float2 *o, const
             gi += g.y;
         }
         const double tr = lr * gr + li * gi, ti = lr * gi - li * gr;   // conj(lambda) grad
-        nr = (double)o[k].x - inv * tr;
-        ni = (double)o[k].y - inv * ti;
-    };
-    double acc = 0.0;
-    for (long long k = threadIdx.x; k < n2; k += 256) {
-        double nr, ni;
-        step(k, nr, ni);
-        acc += nr * nr + ni * ni;
+        const double nr = (double)o[k].x - inv * tr, ni = (double)o[k].y - inv * ti;
+        onew[k] = make_double2(nr, ni);
+        a2 = nr * nr + ni * ni;
     }
-    red[threadIdx.x] = acc;
+    red[threadIdx.x] = a2;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    const double norm = sqrt(red[0]);
-    const double sc = norm > 0.0 ? 1.0 / norm : 0.0;
-    for (long long k = threadIdx.x; k < n2; k += 256) {
-        double nr, ni;
-        step(k, nr, ni);
-        out[k] = make_float2((float)(nr * sc), (float)(ni * sc));
-    }
+    if (threadIdx.x == 0) npart[blockIdx.x] = red[0];
+}
+
+// The projection: out = onew / ||onew|| (the block sums added in order), rounded once.
+__global__ __launch_bounds__(256) void prox_project_kernel(const double2 *onew, const double *npart, int nblocks,
+                                                           int n2, float2 *out)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n2) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += npart[b];
+    const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    const double2 v = onew[k];
+    out[k] = make_float2((float)(v.x * sc), (float)(v.y * sc));
 }
 
 // Partials of Tr(At^H Ah) (re, im) and Tr(At^H At).
@@ -350,8 +499,7 @@ struct smd_plan {
     std::vector<double> dz;
     std::vector<int> pos;   // (y, x) pairs
     char *ws = nullptr;
-    size_t tw, hprop, P, Pc, Y, Z, W, sfx, old, dot, peak, part, posd, blas, total;
-    rocblas_handle h = nullptr;
+    size_t tw, hprop, P, Pc, Y, Z, W, sfx, old, dot, onew, npart, peak, part, ypart, gram, posd, total;
     double mu_a = 0.0;
     bool ready = false;
 
@@ -364,6 +512,9 @@ struct smd_plan {
 };
 
 namespace {
+
+// Row chunks of the P^T A^T product (split over K for enough workgroups).
+int chunks_of(int n2) { return std::min(16, std::max(1, n2 / 64)); }
 
 void plan_layout(smd_plan &p)
 {
@@ -378,16 +529,19 @@ void plan_layout(smd_plan &p)
     p.hprop = take((size_t)std::max(p.M - 1, 1) * 2 * p.n * 8);
     p.P = take(sb);
     p.Pc = take(sb);
-    p.Y = take(std::max<size_t>(sb, (size_t)p.S * (size_t)p.S * 8));   // also holds the Gram matrix
+    p.Y = take(sb);
     p.Z = take(sb);
     p.W = take(mb);
     p.sfx = take(mb * p.M);
     p.old = take((size_t)p.M * p.n2 * 8);
     p.dot = take((size_t)kDotChunks * p.n2 * 16);
+    p.onew = take((size_t)p.n2 * 16);
+    p.npart = take((size_t)((p.n2 + 255) / 256) * 8);
     p.peak = take((size_t)p.M * 8);
-    p.part = take((size_t)kRed * 3 * 8);
+    p.part = take((size_t)std::max(kRed, kTraceBlocks) * 3 * 8);
+    p.ypart = take((size_t)chunks_of(p.n2) * p.S * p.n2 * 8);
+    p.gram = take((size_t)p.S * p.S * 16);
     p.posd = take((size_t)p.S * 8);
-    p.blas = take(kBlasWorkspace);
     p.total = o;
 }
 
@@ -411,26 +565,6 @@ int32_t check_problem(const smd_problem *pb)
     if (!(pb->pixel_size > 0) || !(pb->wavelength > 0)) return sfail(MS_ERR_INVALID_ARG, "need positive dx, lambda");
     return MS_OK;
 }
-
-bool blas_ok(rocblas_status st, const char *what)
-{
-    if (st == rocblas_status_success) return true;
-    s_err = std::string(what) + ": rocBLAS status " + std::to_string((int)st);
-    return false;
-}
-
-// Row-major C (m x n) = alpha op(A) op(B) + beta C.
-bool gemm(smd_plan *p, rocblas_operation opA, rocblas_operation opB, int m, int n, int k, std::complex<float> alpha,
-          const float2 *A, int lda, const float2 *B, int ldb, std::complex<float> beta, float2 *C, int ldc)
-{
-    const rocblas_float_complex al(alpha.real(), alpha.imag()), be(beta.real(), beta.imag());
-    return blas_ok(rocblas_cgemm(p->h, opB, opA, n, m, k, &al, reinterpret_cast<const rocblas_float_complex *>(B), ldb,
-                                 reinterpret_cast<const rocblas_float_complex *>(A), lda, &be,
-                                 reinterpret_cast<rocblas_float_complex *>(C), ldc),
-                   "rocblas_cgemm");
-}
-
-constexpr rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
 
 int32_t hip_ok(const char *what)
 {
@@ -561,26 +695,18 @@ int32_t smd_plan_create(const smd_problem *pb, void *workspace, size_t ws_bytes,
         delete p;
         return sfail(MS_ERR_HIP, "table upload failed");
     }
-    if (rocblas_create_handle(&p->h) != rocblas_status_success) {
-        delete p;
-        return sfail(MS_ERR_HIP, "rocblas_create_handle failed");
-    }
-    rocblas_set_workspace(p->h, p->at<char>(p->blas), kBlasWorkspace);
     *out = p;
     return MS_OK;
 }
 
 void smd_plan_destroy(smd_plan *p)
 {
-    if (!p) return;
-    if (p->h) rocblas_destroy_handle(p->h);
     delete p;
 }
 
 int32_t smd_set_probe(smd_plan *p, hipStream_t st, const void *probe)
 {
     if (!p || !probe) return sfail(MS_ERR_INVALID_ARG, "NULL argument");
-    rocblas_set_stream(p->h, st);
     const long long n2 = p->n2, S = p->S;
     if (hipMemcpyAsync(p->at<int2>(p->posd), p->pos.data(), (size_t)S * 8, hipMemcpyHostToDevice, st) != hipSuccess)
         return sfail(MS_ERR_HIP, "position upload failed");
@@ -588,12 +714,10 @@ int32_t smd_set_probe(smd_plan *p, hipStream_t st, const void *probe)
     probe_matrix_kernel<<<blocks(n2 * S), 256, 0, st>>>(static_cast<const float2 *>(probe), p->at<int2>(p->posd), P,
                                                           p->at<float2>(p->Pc), p->n, S);
     // Gram matrix P^H P (S x S, S <= N^2)
-    float2 *gram = p->at<float2>(p->Y);
-    if (!gemm(p, rocblas_operation_conjugate_transpose, N_, (int)S, (int)S, p->n2, 1.0f, P, (int)S, P, (int)S, 0.0f,
-              gram, (int)S))
-        return MS_ERR_HIP;
-    std::vector<std::complex<float>> g((size_t)S * S);
-    if (hipMemcpyAsync(g.data(), gram, g.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+    double2 *gram = p->at<double2>(p->gram);
+    gram_kernel<<<dim3((unsigned)((S + 255) / 256), (unsigned)S), 256, 0, st>>>(P, p->n2, (int)S, gram);
+    std::vector<std::complex<double>> g((size_t)S * S);
+    if (hipMemcpyAsync(g.data(), gram, g.size() * 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return sfail(MS_ERR_HIP, "Gram matrix download failed");
     // largest eigenvalue of the Hermitian PSD Gram matrix: power iteration with Rayleigh quotients
@@ -606,7 +730,7 @@ int32_t smd_set_probe(smd_plan *p, hipStream_t st, const void *probe)
         for (auto &x : v) x /= nrm;
         for (long long i = 0; i < S; ++i) {
             std::complex<double> acc = 0.0;
-            for (long long j = 0; j < S; ++j) acc += std::complex<double>(g[(size_t)i * S + j]) * v[j];
+            for (long long j = 0; j < S; ++j) acc += g[(size_t)i * S + j] * v[j];
             w[i] = acc;
         }
         double rq = 0.0;
@@ -636,21 +760,22 @@ int32_t smd_estimate(smd_plan *p, hipStream_t st, const float *measured, void *a
     if (!p || !measured || !a) return sfail(MS_ERR_INVALID_ARG, "NULL argument");
     if (!p->ready) return sfail(MS_ERR_INVALID_ARG, "call smd_set_probe first");
     if (steps < 0) return sfail(MS_ERR_INVALID_ARG, "steps must be >= 0");
-    rocblas_set_stream(p->h, st);
     const int n2 = p->n2, S = (int)p->S;
     float2 *At = static_cast<float2 *>(a), *P = p->at<float2>(p->P), *Pc = p->at<float2>(p->Pc);
     float2 *Y = p->at<float2>(p->Y), *Z = p->at<float2>(p->Z);
     double *part = p->at<double>(p->part);
+    const int nch = chunks_of(n2), rows = n2 / nch;
+    float2 *ypart = p->at<float2>(p->ypart);
     for (int k = 0; k < steps; ++k) {
         // (A P)^T = P^T A^T, then the DFT of each position's image: Z^T = (F A P)^T
-        if (!gemm(p, T_, N_, S, n2, n2, 1.0f, P, S, At, n2, 0.0f, Y, n2)) return MS_ERR_HIP;
+        pt_a_partial_kernel<<<dim3(n2 / kTile, (S + kTile - 1) / kTile, nch), 256, 0, st>>>(P, At, n2, S, rows, ypart);
+        chunk_sum_kernel<<<blocks((long long)S * n2), 256, 0, st>>>(ypart, nch, (long long)S * n2, Y);
         dft_rows(p, st, false, Y, Z, S);
         smd_residual_kernel<<<kRed, 256, 0, st>>>(Z, measured, (long long)S * n2, part);
         if (k == 0 && loss_first) half_sum_kernel<<<1, 1, 0, st>>>(part, kRed, loss_first);
         dft_rows(p, st, true, Z, Y, S);   // (F^H r)^T
         // A^T -= mu (F^H r P^H)^T = mu conj(P) (F^H r)^T
-        if (!gemm(p, N_, N_, n2, n2, S, std::complex<float>((float)-p->mu_a, 0.f), Pc, S, Y, n2, 1.0f, At, n2))
-            return MS_ERR_HIP;
+        rank_update_kernel<<<dim3(n2 / kTile, n2 / kTile), 256, 0, st>>>(At, Pc, Y, n2, S, (float)-p->mu_a);
     }
     return hip_ok("smd_estimate");
 }
@@ -680,21 +805,24 @@ int32_t smd_decompose(smd_plan *p, hipStream_t st, const void *a_hat, void *slic
     const int rows = (n2 + kDotChunks - 1) / kDotChunks;
     for (int l = M - 1; l >= 0; --l) {
         coldot_kernel<<<dim3((n2 + 255) / 256, kDotChunks), 256, 0, st>>>(W, sfx + (size_t)l * nn, n2, rows, dot);
-        prox_update_kernel<<<1, 256, 0, st>>>(old + (size_t)l * n2, dot, kDotChunks, p->at<double>(p->peak), M, l,
-                                              lambda[0], lambda[1], n2, sl + (size_t)l * n2);
+        const int nb = (n2 + 255) / 256;
+        prox_step_kernel<<<nb, 256, 0, st>>>(old + (size_t)l * n2, dot, kDotChunks, p->at<double>(p->peak), M, l,
+                                             lambda[0], lambda[1], n2, p->at<double2>(p->onew), p->at<double>(p->npart));
+        prox_project_kernel<<<nb, 256, 0, st>>>(p->at<double2>(p->onew), p->at<double>(p->npart), nb, n2,
+                                                sl + (size_t)l * n2);
         if (l > 0)   // V^T_{l-1} = V^T_l conj(O_l) conj(G_{l-1})
             propagate_rows(p, st, l - 1, true, W, W, n2, old + (size_t)l * n2, true, nullptr);
     }
     float2 *At = a_tilde_out ? static_cast<float2 *>(a_tilde_out) : W;
     compose_into(p, st, sl, 1.0f, At);
     double *part = p->at<double>(p->part);
-    trace_kernel<<<kRed, 256, 0, st>>>(At, Ah, nn, part);
-    std::vector<double> h((size_t)kRed * 3);
+    trace_kernel<<<kTraceBlocks, 256, 0, st>>>(At, Ah, nn, part);
+    std::vector<double> h((size_t)kTraceBlocks * 3);
     if (hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return sfail(MS_ERR_HIP, "trace download failed");
     double tr = 0.0, ti = 0.0, tt = 0.0;
-    for (int i = 0; i < kRed; ++i) {
+    for (int i = 0; i < kTraceBlocks; ++i) {
         tr += h[3 * i];
         ti += h[3 * i + 1];
         tt += h[3 * i + 2];

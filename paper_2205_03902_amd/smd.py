@@ -1,7 +1,8 @@
 """ctypes binding of the sparse matrix decomposition (include/smd.h, Algorithm 2).
 
-Argument marshalling only: the dense products run as rocBLAS GEMMs and every other
-step in the HIP kernels behind the C ABI; torch provides device memory and the stream.
+Argument marshalling only: every step runs in the HIP kernels behind the C ABI; torch
+provides device memory and the stream.  N^2 x N^2 matrices are column-major on the
+boundary: the row-major tensor a call returns is the matrix transposed.
 """
 from __future__ import annotations
 
@@ -73,7 +74,7 @@ def workspace_size(pb: SmdProblem) -> int:
 
 
 class SmdPlan:
-    """Algorithm 2 on one device (full-field model, N <= 64).  Methods enqueue on torch's
+    """Algorithm 2 on one device (full-field model, N = 16, 32, 64).  Methods enqueue on torch's
     current stream; set_probe and decompose synchronise it."""
 
     def __init__(self, n, n_slices, positions, dz, pixel_size, wavelength, device=None):
