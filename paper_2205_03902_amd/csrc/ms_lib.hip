@@ -494,9 +494,7 @@ void line_filter(int n, bool row, bool conj, const float2 *in, long long in_stri
 void class_probes(ms_plan *p, const ms_c64 *probe, hipStream_t st)
 {
     const HostPlan &hp = p->hp;
-    // the line filters spread each class over N/16 workgroups per pass; one workgroup per class
-    // (window_filter_kernel) leaves the GPU nearly idle for a few classes of large windows
-    if (p->lines || hp.n >= 128) {
+    if (p->lines) {
         // x ramps on rows into class_tmp, then y ramps on columns into class_probe
         line_filter(hp.n, true, false, reinterpret_cast<const float2 *>(probe), 0, p->at<float2>(p->L.class_tmp),
                     p->at<float2>(p->L.rx), p->at<int>(p->L.ident), p->at<float2>(p->L.tw), hp.C, st);
