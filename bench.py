@@ -197,8 +197,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}, WORLD_SIZE {world}): this build "
-              "implements the single-GPU hot path only; multi-GPU position sharding is a design note.",
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}, WORLD_SIZE {world}): the library "
+              "implements the single-GPU hot path; sharding positions over GPUs is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -57,7 +57,7 @@ typedef struct {
 typedef enum {
     MS_OK = 0,
     MS_ERR_INVALID_ARG = -1,   /* a NULL pointer, a bad size, a non-finite parameter    */
-    MS_ERR_UNSUPPORTED = -2,   /* valid problem outside what this build implements     */
+    MS_ERR_UNSUPPORTED = -2,   /* valid problem outside what this library implements   */
     MS_ERR_BUDGET = -3,        /* workspace smaller than ms_workspace_size requires    */
     MS_ERR_HIP = -4            /* the HIP runtime reported an error while enqueueing   */
 } ms_status;
