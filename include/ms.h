@@ -59,7 +59,10 @@ typedef enum {
     MS_ERR_INVALID_ARG = -1,   /* a NULL pointer, a bad size, a non-finite parameter    */
     MS_ERR_UNSUPPORTED = -2,   /* valid problem outside what this library implements   */
     MS_ERR_BUDGET = -3,        /* workspace smaller than ms_workspace_size requires    */
-    MS_ERR_HIP = -4            /* the HIP runtime reported an error while enqueueing   */
+    MS_ERR_HIP = -4,           /* the HIP runtime reported an error while enqueueing   */
+    MS_ERR_NOT_FINITE = -5     /* not returned by this library: the status a caller    */
+                               /* (the Python layer) reports when a device FP64 loss   */
+                               /* it reads back is NaN or infinite                     */
 } ms_status;
 
 /* The problem statement of Sec. 2.1: probe window, slices, scan positions,

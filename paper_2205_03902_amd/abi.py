@@ -17,6 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libimsp.so")
 
 MS_OK, MS_ERR_INVALID_ARG, MS_ERR_UNSUPPORTED, MS_ERR_BUDGET, MS_ERR_HIP = 0, -1, -2, -3, -4
+MS_ERR_NOT_FINITE = -5
 MS_PATH_AUTO, MS_PATH_FUSED, MS_PATH_LINES = 0, 1, 2
 MS_OBJECTIVE_AMPLITUDE, MS_OBJECTIVE_POISSON = 0, 1
 
@@ -92,6 +93,15 @@ def lib():
         L.ms_last_error.argtypes = []
         _lib = L
     return _lib
+
+
+def check_finite(values, what: str):
+    """Raises MsError(MS_ERR_NOT_FINITE) if any loss value read back from the device is NaN or
+    infinite (a diverged iteration: the kernels themselves never fail on such values)."""
+    arr = np.asarray(values, dtype=np.float64).reshape(-1)
+    bad = np.flatnonzero(~np.isfinite(arr))
+    if bad.size:
+        raise MsError(MS_ERR_NOT_FINITE, what, f"loss {arr[bad[0]]} at entry {int(bad[0])} of {arr.size}")
 
 
 def _check(status: int, what: str):

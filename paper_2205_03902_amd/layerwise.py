@@ -14,7 +14,7 @@ from typing import List, Optional
 
 import torch
 
-from .abi import Plan
+from .abi import Plan, check_finite
 
 
 @dataclasses.dataclass
@@ -47,6 +47,7 @@ def reconstruct(plan: Plan, probe: torch.Tensor, slices: torch.Tensor, measured:
     torch.cuda.synchronize(plan.device)
     secs = time.perf_counter() - t0
     h = buf[:i].cpu().numpy()
+    check_finite(h[:, 0], "reconstruct")
     return History(loss=h[:, 0].tolist(), mu=h[:, 1].tolist(), kind=kinds, seconds=secs)
 
 
@@ -73,6 +74,7 @@ def refine_positions(plan: Plan, probe: torch.Tensor, slices: torch.Tensor, meas
     cand = pos_a.clone()
     plan_a.position_step(cand, probe, slices, measured, scale, loss=lbuf)
     loss_a = lbuf.item()
+    check_finite(loss_a, "refine_positions")
     losses = [loss_a]
     for _ in range(int(passes) - 1):
         plan_c = plan_a.with_positions(cand.cpu().numpy())
@@ -80,6 +82,7 @@ def refine_positions(plan: Plan, probe: torch.Tensor, slices: torch.Tensor, meas
         next_scale = 2.0 * scale if adaptive else scale
         plan_c.position_step(nxt, probe, slices, measured, next_scale, loss=lbuf)
         loss_c = lbuf.item()
+        check_finite(loss_c, "refine_positions")
         if loss_c <= loss_a or not adaptive:
             plan_a, pos_a, loss_a, scale = plan_c, cand, loss_c, next_scale
             losses.append(loss_c)

@@ -180,3 +180,14 @@ def test_smd_workspace_holds_the_dense_matrices():
     handle = C.c_void_p()
     assert smd.lib().smd_plan_create(C.byref(pb), None, ws, C.byref(handle)) == abi.MS_ERR_INVALID_ARG
     assert smd.lib().smd_set_probe(None, None, None) == abi.MS_ERR_INVALID_ARG
+
+
+def test_non_finite_losses_are_reported_with_their_status():
+    abi.check_finite([1.0, 2.5e3], "ok")
+    with pytest.raises(abi.MsError) as e:
+        abi.check_finite([1.0, float("nan"), 3.0], "reconstruct")
+    assert e.value.status == abi.MS_ERR_NOT_FINITE and "entry 1" in str(e.value)
+    with pytest.raises(abi.MsError):
+        abi.check_finite(float("inf"), "refine_positions")
+    text = open(os.path.join(ROOT, "include", "ms.h")).read()
+    assert re.search(r"MS_ERR_NOT_FINITE\s*=\s*-5", text)
