@@ -206,6 +206,18 @@ ms_status ms_position_grad(ms_plan *plan, hipStream_t stream, const ms_c64 *prob
 ms_status ms_position_step(ms_plan *plan, hipStream_t stream, double step_scale, const ms_c64 *probe,
                            const ms_c64 *slices, const float *measured, double *positions, double *loss_out);
 
+/* The relative reconstruction error of the experiments (Sec. 5), (1/M) sum_m ||O_m - Ohat_m||_F /
+ * ||O_m||_F, after removing the ambiguities of the model: each estimated slice is first
+ * multiplied by the complex scale alpha_m (phase and amplitude, least squares) that brings it
+ * closest to the reference, so that the error of slice m is
+ *   sqrt(||ref||^2 - |<est, ref>|^2 / ||est||^2) / ||ref||   (1 where est is 0),
+ * with every sum over the pixels where mask > 0 (mask: H x W floats, or NULL for all pixels;
+ * pixels no window covers carry no information).  est, ref: [M][H][W]; hw = H W.  err_out:
+ * device double [M + 1], the error of each slice and then their mean.  FP64 sums in a fixed
+ * order.  No plan is needed. */
+ms_status ms_reconstruction_error(hipStream_t stream, const ms_c64 *est, const ms_c64 *ref, const float *mask,
+                                  int32_t n_slices, int64_t hw, double *err_out);
+
 /* Timing of the dominant kernel (the fused per-position multislice kernel).
  * After ms_profile_begin, the next max_launches launches of that kernel made
  * through `plan` are each bracketed by a pair of HIP events on their stream.

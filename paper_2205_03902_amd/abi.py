@@ -24,7 +24,8 @@ MS_OBJECTIVE_AMPLITUDE, MS_OBJECTIVE_POISSON = 0, 1
 # every entry point declared in include/ms.h
 SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
            "ms_plan_set_path", "ms_plan_set_objective",
-           "ms_make_probe", "ms_make_probe_aberrated", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_position_grad", "ms_position_step", "ms_profile_begin",
+           "ms_make_probe", "ms_make_probe_aberrated", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_position_grad", "ms_position_step", "ms_reconstruction_error",
+           "ms_profile_begin",
            "ms_profile_end", "ms_last_error")
 
 
@@ -85,6 +86,8 @@ def lib():
         L.ms_position_grad.argtypes = [P, P, P, P, P, P, P, P]
         L.ms_position_step.restype = I32
         L.ms_position_step.argtypes = [P, P, D, P, P, P, P, P]
+        L.ms_reconstruction_error.restype = I32
+        L.ms_reconstruction_error.argtypes = [P, P, P, P, I32, I64, P]
         L.ms_profile_begin.restype = I32
         L.ms_profile_begin.argtypes = [P, I32]
         L.ms_profile_end.restype = I32
@@ -93,6 +96,26 @@ def lib():
         L.ms_last_error.argtypes = []
         _lib = L
     return _lib
+
+
+def reconstruction_error(est, ref, mask=None, out=None):
+    """Relative reconstruction error after the per-slice least-squares complex scale
+    (ms_reconstruction_error): device float64 [M + 1], the slices' errors and their mean.
+    est, ref: complex64 (M, H, W) on one device; mask: float32 (H, W) or None."""
+    torch = _torch()
+    if est.shape != ref.shape or est.dim() != 3 or est.dtype != torch.complex64 or ref.dtype != torch.complex64:
+        raise ValueError("est and ref must be complex64 tensors of one shape (M, H, W)")
+    if not (est.is_contiguous() and ref.is_contiguous()) or est.device != ref.device:
+        raise ValueError("est and ref must be contiguous and on one device")
+    M, H, W = est.shape
+    if mask is not None and (mask.shape != (H, W) or mask.dtype != torch.float32 or not mask.is_contiguous()
+                             or mask.device != est.device):
+        raise ValueError("mask must be a contiguous float32 (H, W) tensor on the device of est")
+    out = torch.empty(M + 1, dtype=torch.float64, device=est.device) if out is None else out
+    stream = torch.cuda.current_stream(est.device).cuda_stream
+    _check(lib().ms_reconstruction_error(stream, est.data_ptr(), ref.data_ptr(), _ptr(mask), int(M), int(H * W),
+                                         out.data_ptr()), "ms_reconstruction_error")
+    return out
 
 
 def check_finite(values, what: str):

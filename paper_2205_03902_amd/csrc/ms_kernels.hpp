@@ -712,6 +712,51 @@ __global__ __launch_bounds__(256) void position_grad_kernel(const float2 *patch,
     }
 }
 
+// Relative error of slice m = blockIdx.x after the least-squares complex scale:
+// err[m] = sqrt(||ref||^2 - |<est, ref>|^2 / ||est||^2) / ||ref|| over the masked pixels
+// (1 where est is 0 and ref is not, 0 where ref is 0).  FP64 sums, fixed order.
+__global__ __launch_bounds__(256) void recon_slice_kernel(const float2 *est, const float2 *ref, const float *mask,
+                                                          long long hw, double *err)
+{
+    __shared__ double red[4][256];
+    const int m = blockIdx.x, t = threadIdx.x;
+    const float2 *e = est + (size_t)m * hw, *r = ref + (size_t)m * hw;
+    double xr = 0.0, xi = 0.0, ee = 0.0, rr = 0.0;
+    for (long long i = t; i < hw; i += 256) {
+        if (mask && !(mask[i] > 0.0f)) continue;
+        const float2 a = e[i], b = r[i];
+        xr += (double)a.x * b.x + (double)a.y * b.y;
+        xi += (double)a.x * b.y - (double)a.y * b.x;
+        ee += (double)a.x * a.x + (double)a.y * a.y;
+        rr += (double)b.x * b.x + (double)b.y * b.y;
+    }
+    red[0][t] = xr;
+    red[1][t] = xi;
+    red[2][t] = ee;
+    red[3][t] = rr;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[q][t] += red[q][t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double x2 = red[0][0] * red[0][0] + red[1][0] * red[1][0], e2 = red[2][0], r2 = red[3][0];
+        double v = 0.0;
+        if (r2 > 0.0) v = e2 > 0.0 ? sqrt(fmax(0.0, r2 - x2 / e2) / r2) : 1.0;
+        err[m] = v;
+    }
+}
+
+// err[M] = the mean of err[0 .. M) (in order).
+__global__ void recon_mean_kernel(double *err, int M)
+{
+    double s = 0.0;
+    for (int m = 0; m < M; ++m) s += err[m];
+    err[M] = s / M;
+}
+
 // positions <- positions - scale grad / curv per coordinate (unchanged where curv is 0).
 __global__ __launch_bounds__(256) void position_update_kernel(double *pos, const double *grad, const double *curv,
                                                               long long count, double scale)

@@ -648,6 +648,21 @@ extern "C" {
 
 const char *ms_last_error(void) { return g_err.c_str(); }
 
+ms_status ms_reconstruction_error(hipStream_t st, const ms_c64 *est, const ms_c64 *ref, const float *mask,
+                                  int32_t n_slices, int64_t hw, double *err_out)
+{
+    g_err.clear();
+    if (!est || !ref || !err_out) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    if (n_slices < 1 || n_slices > 4096 || hw < 1 || hw > ((int64_t)1 << 34))
+        return fail(MS_ERR_INVALID_ARG, "n_slices must be in [1, 4096] and hw in [1, 2^34]");
+    if (!aligned8(est) || !aligned8(ref) || !aligned8(err_out) || ((uintptr_t)mask & 3))
+        return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
+    recon_slice_kernel<<<n_slices, 256, 0, st>>>(reinterpret_cast<const float2 *>(est),
+                                                  reinterpret_cast<const float2 *>(ref), mask, hw, err_out);
+    recon_mean_kernel<<<1, 1, 0, st>>>(err_out, n_slices);
+    return check_hip("ms_reconstruction_error");
+}
+
 ms_status ms_workspace_size(const ms_problem *pb, size_t budget_bytes, size_t *ws_bytes)
 {
     try {

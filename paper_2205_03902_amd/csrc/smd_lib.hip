@@ -720,8 +720,15 @@ int32_t smd_set_probe(smd_plan *p, hipStream_t st, const void *probe)
     if (hipMemcpyAsync(g.data(), gram, g.size() * 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return sfail(MS_ERR_HIP, "Gram matrix download failed");
-    // largest eigenvalue of the Hermitian PSD Gram matrix: power iteration with Rayleigh quotients
-    std::vector<std::complex<double>> v((size_t)S, std::complex<double>(1.0, 0.0)), w((size_t)S);
+    // largest eigenvalue of the Hermitian PSD Gram matrix: power iteration with Rayleigh quotients.
+    // The start has golden-ratio phases: on a regular grid of shifts the Gram matrix is
+    // circulant, its eigenvectors are Fourier modes, and the constant vector is one of them
+    // (a power iteration started there never leaves it).
+    std::vector<std::complex<double>> v((size_t)S), w((size_t)S);
+    for (long long i = 0; i < S; ++i) {
+        const double frac = std::fmod(0.6180339887498949 * (double)(i + 1), 1.0);
+        v[i] = std::polar(1.0, 6.283185307179586 * frac);
+    }
     double ev = 0.0;
     for (int it = 0; it < 5000; ++it) {
         double nrm = 0.0;

@@ -191,3 +191,45 @@ def test_full_field_matrix_model_agrees_with_the_multislice_path(dev, n, m):
     total = 0.5 * meas.double().sum().item()
     print(f"matrix loss at the truth {loss.item():.3e} of {total:.3e}")
     assert loss.item() < bar(n, 4 * m) ** 2 * total
+
+
+def test_bench_size_properties(dev):
+    """N = 64, M = 3, S = 64 shifts on an 8 x 8 grid (the size the benchmark times), where the
+    dense reference is too slow: properties that hold at any size.  The model reproduces the
+    multislice path; the normalised truth is a fixed point of a decomposition pass with its
+    scale prod ||t_m|| as lambda; estimate steps from t = 1 never raise the matrix loss."""
+    from paper_2205_03902_amd import abi, smd
+    n, m = 64, 3
+    print(f"[case] smd bench size n={n} M={m}", flush=True)
+    pos = np.array([[y * 8, x * 8] for y in range(8) for x in range(8)], dtype=np.float64)
+    dz = [2.0] * (m - 1)
+    ms = abi.Plan(n, n, n, m, pos, dz, DX, LAM, device=dev)
+    probe = ms.make_probe(0.03, 20.0)
+    truth = _t(synth.unit_phase_field((m, n, n), 17, 0.5) * (1.0 + 0.1 * np.tanh(
+        synth.complex_field((m, n, n), 18).real)).astype(np.float32), dev)
+    meas = ms.forward(probe, truth)
+    plan = smd.SmdPlan(n, m, pos, dz, DX, LAM, device=dev)
+    plan.set_probe(probe)
+    a = plan.compose(truth)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    plan.estimate(meas, a, 1, loss)
+    total = 0.5 * meas.double().sum().item()
+    print(f"matrix loss at the truth {loss.item():.3e} of {total:.3e}")
+    assert loss.item() < bar(n, 4 * m) ** 2 * total
+    norms = torch.linalg.vector_norm(truth.reshape(m, -1).to(torch.complex128), dim=1)
+    unit = (truth / norms.to(torch.complex64)[:, None, None]).contiguous()
+    scale = float(torch.prod(norms).item())
+    sl = unit.clone()
+    lam = plan.decompose(plan.compose(truth), sl, complex(scale, 0.0))
+    tol = bar(n, 4 * m + 2)
+    print(f"fixed point: slices rel {rel(sl.cpu().numpy(), unit.cpu().numpy()):.2e}, lambda rel "
+          f"{abs(lam - scale) / scale:.2e}, bar {tol:.2e}")
+    assert rel(sl.cpu().numpy(), unit.cpu().numpy()) < tol and abs(lam - scale) < tol * scale
+    # the matrix step is amplitude flow with mu <= 1 / ||Q||^2: the matrix loss never rises
+    a = plan.compose(torch.ones_like(truth))
+    losses = torch.zeros(6, dtype=torch.float64, device=dev)
+    for k in range(6):
+        plan.estimate(meas, a, 1, losses[k:k + 1])
+    h = losses.cpu().numpy()
+    print(f"matrix loss over estimate steps {h}")
+    assert np.all(np.isfinite(h)) and np.all(np.diff(h) <= 1e-6 * h[0]), h
