@@ -99,3 +99,21 @@ def test_config1_first_layer_steps(dev, cfg1):
         assert abs(out[0].item() - ref_l) / ref_l < 1e-5
         assert abs(out[1].item() - ref_mu) / ref_mu < 1e-5
         assert rel(s.cpu().numpy(), ref) < 1e-5
+
+
+def test_config1_position_gradient_sampled(dev, cfg1):
+    """The scan-position gradient of all 1024 positions (the benchmark's position_grad pass);
+    each position's gradient depends on its own pattern only, so the oracle recomputes a sample
+    of positions as a problem of its own.  The curvature bound uses the maxima of the whole
+    slices, which both problems share."""
+    import oracle
+    from paper_2205_03902_amd import abi
+    c = cfg1
+    plan = abi.Plan.from_geometry(c.geo, device=dev)
+    g, cv = plan.position_grad(_t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev))
+    pick = np.arange(5, c.geo.n_pos, 101)
+    sub = oracle.Model.from_geometry(c.geo, positions=c.model.positions[pick])
+    _, ref_g, ref_c = sub.position_grad(c.probe, c.start, c.measured[pick])
+    got_g, got_c = g.cpu().numpy()[pick], cv.cpu().numpy()[pick]
+    print(f"config 1 position gradient: rel {rel(got_g, ref_g):.2e}, curvature rel {rel(got_c, ref_c):.2e}")
+    assert rel(got_g, ref_g) < 1e-4 and rel(got_c, ref_c) < 1e-5
