@@ -117,3 +117,22 @@ def test_config1_position_gradient_sampled(dev, cfg1):
     got_g, got_c = g.cpu().numpy()[pick], cv.cpu().numpy()[pick]
     print(f"config 1 position gradient: rel {rel(got_g, ref_g):.2e}, curvature rel {rel(got_c, ref_c):.2e}")
     assert rel(got_g, ref_g) < 1e-4 and rel(got_c, ref_c) < 1e-5
+
+
+def test_config1_full_gradient_step(dev, cfg1):
+    """One full-gradient step of the benchmark's comparison (step scale 1/M) at full size."""
+    from paper_2205_03902_amd import abi
+    c = cfg1
+    M = c.geo.n_slices
+    plan = abi.Plan.from_geometry(c.geo, device=dev)
+    s = _t(c.start, dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    mu = torch.zeros(M, dtype=torch.float64, device=dev)
+    plan.full_step(1, _t(c.probe, dev), s, _t(c.measured, dev), loss=loss, mu=mu, step_scale=1.0 / M)
+    ref_s, ref_l, ref_mu = c.model.full_step(c.probe, c.start, c.measured, 1, step_scale=1.0 / M)
+    got = s.cpu().numpy()
+    print(f"config 1 full step: loss {abs(loss.item() - ref_l) / ref_l:.2e}, "
+          f"step {rel(got - c.start, ref_s - c.start):.2e}")
+    assert abs(loss.item() - ref_l) / ref_l < 1e-5
+    assert np.abs(mu.cpu().numpy() / ref_mu - 1).max() < 1e-5
+    assert rel(got - c.start, ref_s - c.start) < 1e-3
