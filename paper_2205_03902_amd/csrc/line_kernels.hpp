@@ -372,13 +372,20 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LinePa
         float2 *dst = wave + m * NN;
         float *ovl = (mode == kAdjoint && p.full) ? p.overlap_patch + ((size_t)b * M + m) * NN : nullptr;
         if (ROW) {
+            // reads before writes in two halves: vector memory operations retire in issue
+            // order, so interleaved loads would each wait for the stores before them
             const int l2 = opaque(line), j2 = opaque(j);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int idx = l2 * N + Wn::nat(j2, k);
-                const float2 ps = psi[idx];
-                if (ovl) ovl[idx] = cabs2(ps);
-                dst[idx] = cconjmul(ps, v[k]);
+            for (int h = 0; h < 16; h += 8) {
+                float2 ps[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) ps[k] = psi[l2 * N + Wn::nat(j2, h + k)];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int idx = l2 * N + Wn::nat(j2, h + k);
+                    if (ovl) ovl[idx] = cabs2(ps[k]);
+                    dst[idx] = cconjmul(ps[k], v[h + k]);
+                }
             }
         } else {
             float2 g[16];

@@ -86,10 +86,10 @@ __device__ __forceinline__ void store_window_abs2(const float2 (&v)[16], float *
     for (int k = 0; k < 16; ++k) dst[base + window_step<N, ROW>() * k] = cabs2(v[k]);
 }
 
-// v *= T (or conj(T)): the object patch t[(oy + y) mod H][(ox + x) mod W] (Sec. 1.3, 2.1).
-template <int N, bool ROW, bool CONJ>
-__device__ __forceinline__ void apply_patch(float2 (&v)[16], const float2 *slice, int H, int W, int oy,
-                                            int ox, int line, int j)
+// t = the object patch t[(oy + y) mod H][(ox + x) mod W] (Sec. 1.3, 2.1) on this lane's 16 points.
+template <int N, bool ROW>
+__device__ __forceinline__ void load_patch(float2 (&t)[16], const float2 *slice, int H, int W, int oy, int ox,
+                                           int line, int j)
 {
     using Wn = Win<N>;
     constexpr int R = Wn::R;
@@ -106,8 +106,7 @@ __device__ __forceinline__ void apply_patch(float2 (&v)[16], const float2 *slice
         for (int k = 0; k < 16; ++k) {
             const int xx = x0 + R * k;
             const unsigned off = row + (unsigned)(xx >= W ? xx - W : xx);
-            float2 t = slice[off];
-            v[k] = CONJ ? cconjmul(t, v[k]) : cmul(v[k], t);
+            t[k] = slice[off];
         }
     } else {
         int xx = ox + line;
@@ -117,10 +116,27 @@ __device__ __forceinline__ void apply_patch(float2 (&v)[16], const float2 *slice
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const unsigned off = base + step * k - ((y0 + R * k >= H) ? wrap : 0u);
-            float2 t = slice[off];
-            v[k] = CONJ ? cconjmul(t, v[k]) : cmul(v[k], t);
+            t[k] = slice[off];
         }
     }
+}
+
+// v *= t (or conj(t)), pointwise.
+template <bool CONJ>
+__device__ __forceinline__ void mul_patch(float2 (&v)[16], const float2 (&t)[16])
+{
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = CONJ ? cconjmul(t[k], v[k]) : cmul(v[k], t[k]);
+}
+
+// v *= T (or conj(T)) on the window.
+template <int N, bool ROW, bool CONJ>
+__device__ __forceinline__ void apply_patch(float2 (&v)[16], const float2 *slice, int H, int W, int oy,
+                                            int ox, int line, int j)
+{
+    float2 t[16];
+    load_patch<N, ROW>(t, slice, H, W, oy, ox, line, j);
+    mul_patch<CONJ>(v, t);
 }
 
 // One Fresnel propagation V_z (or its adjoint G^H when CONJ), starting in layout ROW
@@ -263,19 +279,25 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
         const float2 *slice = p.slices + (size_t)m * H * W;
         const bool store = (MODE == kAdjoint && m > 0) || (MODE == kLayer && m == p.layer && m > 0);
         if (row) {
+            // the transmission loads go out before this step's stores: the vector memory
+            // counter retires in issue order, so waiting for them does not wait for the stores
+            float2 t[16];
+            load_patch<N, true>(t, slice, H, W, oy, ox, line, j);
             if (store) store_window<N, true>(v, wave + m * NN, line, j);
             if (MODE == kLayer && m == p.layer)
                 store_window_abs2<N, true>(v, p.overlap_patch + ((size_t)b * M + m) * NN, line, j);
-            apply_patch<N, true, false>(v, slice, H, W, oy, ox, line, j);
+            mul_patch<false>(v, t);
             if (m + 1 < M) {
                 const int u = p.gap_table[m] * N;
                 propagate<N, true, false>(v, tw, lds, s_hy + u, s_hx + u, line, j);
             }
         } else {
+            float2 t[16];
+            load_patch<N, false>(t, slice, H, W, oy, ox, line, j);
             if (store) store_window<N, false>(v, wave + m * NN, line, j);
             if (MODE == kLayer && m == p.layer)
                 store_window_abs2<N, false>(v, p.overlap_patch + ((size_t)b * M + m) * NN, line, j);
-            apply_patch<N, false, false>(v, slice, H, W, oy, ox, line, j);
+            mul_patch<false>(v, t);
             if (m + 1 < M) {
                 const int u = p.gap_table[m] * N;
                 propagate<N, false, false>(v, tw, lds, s_hy + u, s_hx + u, line, j);
@@ -326,6 +348,19 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
             const bool row = !(m & 1);
             const float2 *slice = p.slices + (size_t)m * H * W;
             const bool patch = (MODE == kAdjoint) || (MODE == kLayer && m == p.layer);
+            const bool go_on = (m > m_stop) || (MODE != kLayer && m == 0);
+            // Memory order of the step.  Vector memory operations retire in issue order, so a
+            // wait for a load also waits for every store issued before it.  The transmission
+            // loads go out first (they are consumed last); the incident wave is read and the
+            // gradient patch written in two halves, which keeps the live registers within the
+            // budget of 1024 lanes.  The layer mode, whose patch is one slice's, reads the
+            // transmission after the patch instead (no spills in either form).
+            constexpr bool kEarlyT = (MODE != kLayer);
+            float2 t[16];
+            if (kEarlyT && go_on) {
+                if (row) load_patch<N, true>(t, slice, H, W, oy, ox, line, j);
+                else load_patch<N, false>(t, slice, H, W, oy, ox, line, j);
+            }
             if (patch) {
                 const float2 *psi = (m == 0) ? probe : wave + m * NN;
                 float2 *dst = wave + m * NN;
@@ -336,17 +371,24 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
                 const unsigned step = row ? (unsigned)R : (unsigned)(R * N);
                 float *ovl = (MODE == kAdjoint && p.full) ? p.overlap_patch + ((size_t)b * M + m) * NN : nullptr;
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    const unsigned off = base + step * k;
-                    float2 ps = psi[off];
-                    if (ovl) ovl[off] = cabs2(ps);
-                    dst[off] = cconjmul(ps, v[k]);   // dL/d conj(t_m) on the window: conj(psi_m) o g
+                for (int h = 0; h < 16; h += 8) {
+                    float2 ps[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) ps[k] = psi[base + step * (h + k)];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const unsigned off = base + step * (h + k);
+                        if (ovl) ovl[off] = cabs2(ps[k]);
+                        dst[off] = cconjmul(ps[k], v[h + k]);   // dL/d conj(t_m) on the window: conj(psi_m) o g
+                    }
                 }
             }
-            const bool go_on = (m > m_stop) || (MODE != kLayer && m == 0);
             if (!go_on) break;
-            if (row) apply_patch<N, true, true>(v, slice, H, W, oy, ox, line, j);
-            else apply_patch<N, false, true>(v, slice, H, W, oy, ox, line, j);
+            if (!kEarlyT) {
+                if (row) load_patch<N, true>(t, slice, H, W, oy, ox, line, j);
+                else load_patch<N, false>(t, slice, H, W, oy, ox, line, j);
+            }
+            mul_patch<true>(v, t);
             if (m > 0) {
                 // G_{m-1}^H: start on the axis this layout owns (the last one of the forward step)
                 const int u = p.gap_table[m - 1] * N;
