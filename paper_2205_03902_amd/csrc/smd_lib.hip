@@ -148,18 +148,31 @@ __global__ __launch_bounds__(Win<N>::NT) void image_dft_kernel(const float2 *in,
 
 // ---------------------------------------------------------------------------------------
 // The two products with the probe matrix in the A estimate: N^2 x N^2 by N^2 x S, with S
-// small.  64 x 64 output tiles per workgroup (4 x 4 complex values a lane, spaced 16 apart
-// so that the LDS reads of a wavefront are consecutive or broadcast), K in steps of 16
-// through LDS, FP32 accumulation.
+// small.  Both run on the FP32 matrix cores (v_mfma_f32_32x32x2_f32).  A workgroup of four
+// wavefronts owns a 64 x 64 complex output tile, each wavefront a 32 x 32 quarter held as
+// real and imaginary accumulators (16 + 16 registers a lane); a complex product is four
+// real ones, (ar + i ai)(br + i bi) = (ar br - ai bi) + i (ar bi + ai br).  Operands are
+// staged 16 K-rows at a time through LDS.  Matrix-core operand layouts (lane l of 64):
+//   A (32 x 2): A[l % 32][l / 32];  B (2 x 32): B[l / 32][l % 32];
+//   D (32 x 32), register r: D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
 
 constexpr int kTile = 64, kKStep = 16;
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ void cmac(float2 &acc, float2 a, float2 b)
+// acc_re/acc_im (32 x 32 quarter) += A B over the 16 staged K-rows; sa[r][m] holds A[m][r]
+// for this quarter's rows m (64-wide rows, offset m0), sb[r][n] holds B[r][n] (offset n0).
+__device__ __forceinline__ void cmfma_16(f32x16 &acc_re, f32x16 &acc_im, const float2 (*sa)[kTile],
+                                         const float2 (*sb)[kTile], int m0, int n0, int lane)
 {
-    acc.x = fmaf(a.x, b.x, acc.x);
-    acc.x = fmaf(-a.y, b.y, acc.x);
-    acc.y = fmaf(a.x, b.y, acc.y);
-    acc.y = fmaf(a.y, b.x, acc.y);
+#pragma unroll
+    for (int kk = 0; kk < kKStep; kk += 2) {
+        const float2 a = sa[kk + lane / 32][m0 + lane % 32];
+        const float2 b = sb[kk + lane / 32][n0 + lane % 32];
+        acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc_re, 0, 0, 0);
+        acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, acc_re, 0, 0, 0);
+        acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, acc_im, 0, 0, 0);
+        acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, acc_im, 0, 0, 0);
+    }
 }
 
 // part[c][s][k] = sum over the rows i of chunk c of P[i][s] At[i][k]   (P: n2 x S, At: n2 x n2).
@@ -167,46 +180,46 @@ __device__ __forceinline__ void cmac(float2 &acc, float2 a, float2 b)
 __global__ __launch_bounds__(256) void pt_a_partial_kernel(const float2 *P, const float2 *At, int n2, int S, int rows,
                                                            float2 *part)
 {
-    __shared__ float2 sP[kKStep][kTile];
-    __shared__ float2 sA[kKStep][kTile];
-    const int t = threadIdx.x, ts = t / 16, tk = t % 16;
+    __shared__ float2 sP[kKStep][kTile];   // [i][s]
+    __shared__ float2 sA[kKStep][kTile];   // [i][k]
+    const int t = threadIdx.x, w = t / 64, lane = t % 64;
+    const int ms = 32 * (w / 2), nk = 32 * (w % 2);   // this wavefront's quarter (s, k)
     const int k0 = blockIdx.x * kTile, s0 = blockIdx.y * kTile;
     const int i_begin = blockIdx.z * rows, i_end = min(n2, i_begin + rows);
-    float2 acc[4][4];
+    f32x16 acc_re, acc_im;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int r = 0; r < 16; ++r) acc_re[r] = acc_im[r] = 0.f;
+    // 16 x 64 of each operand, 4 values a lane; the next rows are loaded into registers
+    // while the matrix cores work on the staged ones
+    float2 ra[4], rp[4];
+    auto fetch = [&](int i0) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = make_float2(0.f, 0.f);
-    for (int i0 = i_begin; i0 < i_end; i0 += kKStep) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {   // 16 x 64 of each operand, 4 values a lane
+        for (int q = 0; q < 4; ++q) {
             const int e = t + 256 * q, r = e / kTile, col = e % kTile, i = i0 + r;
             const bool in_i = i < i_end;
-            sA[r][col] = in_i ? At[(size_t)i * n2 + k0 + col] : make_float2(0.f, 0.f);
-            sP[r][col] = (in_i && s0 + col < S) ? P[(size_t)i * S + s0 + col] : make_float2(0.f, 0.f);
+            ra[q] = in_i ? At[(size_t)i * n2 + k0 + col] : make_float2(0.f, 0.f);
+            rp[q] = (in_i && s0 + col < S) ? P[(size_t)i * S + s0 + col] : make_float2(0.f, 0.f);
+        }
+    };
+    fetch(i_begin);
+    for (int i0 = i_begin; i0 < i_end; i0 += kKStep) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + 256 * q, r = e / kTile, col = e % kTile;
+            sA[r][col] = ra[q];
+            sP[r][col] = rp[q];
         }
         __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kKStep; ++r) {
-            float2 pa[4], ab[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) pa[a] = sP[r][ts + 16 * a];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) ab[b] = sA[r][tk + 16 * b];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) cmac(acc[a][b], pa[a], ab[b]);
-        }
+        if (i0 + kKStep < i_end) fetch(i0 + kKStep);
+        cmfma_16(acc_re, acc_im, sP, sA, ms, nk, lane);
         __syncthreads();
     }
     float2 *dst = part + (size_t)blockIdx.z * S * n2;
+    const int k = k0 + nk + lane % 32;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int s_ = s0 + ts + 16 * a;
-        if (s_ < S)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) dst[(size_t)s_ * n2 + k0 + tk + 16 * b] = acc[a][b];
+    for (int r = 0; r < 16; ++r) {
+        const int s_ = s0 + ms + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
+        if (s_ < S) dst[(size_t)s_ * n2 + k] = make_float2(acc_re[r], acc_im[r]);
     }
 }
 
@@ -246,49 +259,50 @@ __global__ __launch_bounds__(256) void rank_update_kernel(float2 *At, const floa
 {
     __shared__ float2 sP[kKStep][kTile];   // [s][i]
     __shared__ float2 sY[kKStep][kTile];   // [s][k]
-    const int t = threadIdx.x, ti = t / 16, tk = t % 16;
+    const int t = threadIdx.x, w = t / 64, lane = t % 64;
+    const int mi = 32 * (w / 2), nk = 32 * (w % 2);   // this wavefront's quarter (i, k)
     const int k0 = blockIdx.x * kTile, i0 = blockIdx.y * kTile;
-    float2 acc[4][4];
+    const int k = k0 + nk + lane % 32;
+    // the updated tile is read up front, so that its latency hides behind the products
+    float2 old[16];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int r = 0; r < 16; ++r) old[r] = At[(size_t)(i0 + mi + 8 * (r / 4) + 4 * (lane / 32) + r % 4) * n2 + k];
+    f32x16 acc_re, acc_im;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = make_float2(0.f, 0.f);
-    for (int sb = 0; sb < S; sb += kKStep) {
+    for (int r = 0; r < 16; ++r) acc_re[r] = acc_im[r] = 0.f;
+    float2 ry[4], rp[4];
+    auto fetch = [&](int sb) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = t + 256 * q;
             {   // Y rows sb.., 64 columns
                 const int r = e / kTile, col = e % kTile, s_ = sb + r;
-                sY[r][col] = s_ < S ? Y[(size_t)s_ * n2 + k0 + col] : make_float2(0.f, 0.f);
+                ry[q] = s_ < S ? Y[(size_t)s_ * n2 + k0 + col] : make_float2(0.f, 0.f);
             }
-            {   // Pc rows i0.., 16 columns sb..: element (row, s) stored transposed
+            {   // Pc rows i0.., 16 columns sb..
                 const int row = e / kKStep, r = e % kKStep, s_ = sb + r;
-                sP[r][row] = s_ < S ? Pc[(size_t)(i0 + row) * S + s_] : make_float2(0.f, 0.f);
+                rp[q] = s_ < S ? Pc[(size_t)(i0 + row) * S + s_] : make_float2(0.f, 0.f);
             }
+        }
+    };
+    fetch(0);
+    for (int sb = 0; sb < S; sb += kKStep) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + 256 * q;
+            sY[e / kTile][e % kTile] = ry[q];
+            sP[e % kKStep][e / kKStep] = rp[q];   // element (row, s) stored transposed
         }
         __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kKStep; ++r) {
-            float2 pa[4], yb[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) pa[a] = sP[r][ti + 16 * a];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) yb[b] = sY[r][tk + 16 * b];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) cmac(acc[a][b], pa[a], yb[b]);
-        }
+        if (sb + kKStep < S) fetch(sb + kKStep);
+        cmfma_16(acc_re, acc_im, sP, sY, mi, nk, lane);
         __syncthreads();
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const size_t idx = (size_t)(i0 + ti + 16 * a) * n2 + k0 + tk + 16 * b;
-            const float2 v = At[idx];
-            At[idx] = make_float2(fmaf(alpha, acc[a][b].x, v.x), fmaf(alpha, acc[a][b].y, v.y));
-        }
+    for (int r = 0; r < 16; ++r) {
+        const size_t idx = (size_t)(i0 + mi + 8 * (r / 4) + 4 * (lane / 32) + r % 4) * n2 + k;
+        At[idx] = make_float2(fmaf(alpha, acc_re[r], old[r].x), fmaf(alpha, acc_im[r], old[r].y));
+    }
 }
 
 // ---------------------------------------------------------------------------------------
