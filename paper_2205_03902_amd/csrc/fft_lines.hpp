@@ -159,8 +159,10 @@ struct Win {
     static constexpr int G = 16 / R;        // k1 values per lane after the exchange
     static constexpr int NT = N * R;        // lanes per window
     // LDS: line exchange slots of LD = N + R complex values (stride = R mod 16), and the
-    // N x N transpose tile stored with an XOR swizzle; both are free of bank conflicts for
-    // the 64-bit accesses of a wavefront (32 banks, 16 lanes per cycle).
+    // N x N transpose tiles; all are free of bank conflicts for the 64-bit accesses of a
+    // wavefront (32 banks, 16 lanes per cycle).  In a slot, lane j writes its value k1 at
+    // R k1 + k1 / G + j and reads (u, jj) back at 17 j + R u + jj (the same cell when
+    // k1 = j G + u and jj is the writer): a per-lane base plus a constant on both sides.
     static constexpr int LD = N + R;
     static constexpr int LDS_WORDS = N * LD;            // complex values of LDS per window
     static constexpr int SWZ = (N == 64) ? 5 : 9;       // transpose swizzle multiplier
@@ -194,13 +196,15 @@ __device__ __forceinline__ void line_fft_fwd(float2 (&v)[16], const float2 (&tw)
     if constexpr (R > 1) {
 #pragma unroll
         for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[k1]);
+        float2 *wb = xb + opaque(j);
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) xb[k1 * R + (j ^ (k1 / G))] = v[k1];   // skewed slot
+        for (int k1 = 0; k1 < 16; ++k1) wb[k1 * R + k1 / G] = v[k1];
         wave_sync();
+        const float2 *rb = xb + 17 * opaque(j);
 #pragma unroll
         for (int u = 0; u < G; ++u)
 #pragma unroll
-            for (int jj = 0; jj < R; ++jj) v[u * R + jj] = xb[(j * G + u) * R + (jj ^ j)];
+            for (int jj = 0; jj < R; ++jj) v[u * R + jj] = rb[u * R + jj];
         wave_sync();
 #pragma unroll
         for (int u = 0; u < G; ++u) dft_small<R, false>(&v[u * R]);
@@ -215,13 +219,15 @@ __device__ __forceinline__ void line_fft_inv(float2 (&v)[16], const float2 (&tw)
     if constexpr (R > 1) {
 #pragma unroll
         for (int u = 0; u < G; ++u) dft_small<R, true>(&v[u * R]);
+        float2 *rb = xb + 17 * opaque(j);
 #pragma unroll
         for (int u = 0; u < G; ++u)
 #pragma unroll
-            for (int jj = 0; jj < R; ++jj) xb[(j * G + u) * R + (jj ^ j)] = v[u * R + jj];
+            for (int jj = 0; jj < R; ++jj) rb[u * R + jj] = v[u * R + jj];
         wave_sync();
+        const float2 *wb = xb + opaque(j);
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) v[k1] = xb[k1 * R + (j ^ (k1 / G))];
+        for (int k1 = 0; k1 < 16; ++k1) v[k1] = wb[k1 * R + k1 / G];
         wave_sync();
 #pragma unroll
         for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmulc(v[k1], tw[k1]);
@@ -268,6 +274,34 @@ __device__ __forceinline__ void transpose(float2 (&v)[16], float2 *lds, int line
         int b = SPEC_OUT ? W::spec(j, i) : W::nat(j, i);
         if (FROM_ROW) v[i] = lds[W::tpos(b, line)];
         else v[i] = lds[W::tpos(line, b)];
+    }
+    __syncthreads();
+}
+
+// Natural-order transpose for R >= 4 through the tile T(y, x) = y LD + (x ^ (y mod R)): the
+// xor touches only the bits of x that the lane index fixes, so every access is a per-lane
+// base plus a constant, and both sides are free of bank conflicts.
+template <int N, bool FROM_ROW>
+__device__ __forceinline__ void transpose_nat(float2 (&v)[16], float2 *lds, int line, int j)
+{
+    using W = Win<N>;
+    constexpr int R = W::R, LD = W::LD;
+    static_assert(R >= 4, "the constant-offset tile needs at least 4 lanes a line");
+    line = opaque(line);
+    j = opaque(j);
+    float2 *row_base = lds + line * LD + (j ^ (line % R));   // lane owns row y = line
+    float2 *col_base = lds + j * LD + (line ^ j);            // lane owns column x = line
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (FROM_ROW) row_base[R * i] = v[i];
+        else col_base[R * LD * i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (FROM_ROW) v[i] = col_base[R * LD * i];
+        else v[i] = row_base[R * i];
     }
     __syncthreads();
 }

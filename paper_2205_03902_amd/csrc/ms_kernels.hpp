@@ -158,7 +158,8 @@ __device__ __forceinline__ void propagate(float2 (&v)[16], const float2 *twg, fl
         v[i] = CONJ ? cmulc(v[i], h) : cmul(v[i], h);
     }
     line_fft_inv<N>(v, twg, xb, j);
-    transpose<N, ROW, false, false>(v, lds, line, j);
+    if constexpr (Wn::R >= 4) transpose_nat<N, ROW>(v, lds, line, j);
+    else transpose<N, ROW, false, false>(v, lds, line, j);
     line_fft_fwd<N>(v, twg, xb, j);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
