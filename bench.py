@@ -97,9 +97,22 @@ def cpu_baseline(geo, n_sample: int):
     md.loss_grad(probe, start, meas)
     secs = time.perf_counter() - t0
     return {"value": n_sample * geo.n_slices / secs, "unit": UNIT, "cores": oracle.max_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": f"{n_sample} of {geo.n_pos} positions (evenly spaced), one fwd+adj pass, "
                       f"{secs:.2f} s wall, FP64"}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name, as the kernel reports it."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def coverage_mask(geo, positions):

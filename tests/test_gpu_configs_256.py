@@ -5,7 +5,7 @@ config 2 (512^2 object, 10 slices, 4096 positions, noise free) and config 4 (102
 sample of positions one by one.  Gradients at full size are checked through a property
 that holds at any size (the loss and gradient of a set of positions are the sums over a
 partition of it); the gradient itself is compared with the oracle, and with the oracle's
-finite differences along 16 seeded directions, on a 16-position block of config 2."""
+finite differences along 24 seeded directions, on a 16-position block of config 2."""
 import numpy as np
 import pytest
 
@@ -88,13 +88,13 @@ def test_config2_block_gradient_matches_oracle_and_finite_differences(dev, cfg2)
     ref_l, ref_gs, ref_gp, _ = c.model.loss_grad(c.probe, c.start, c.measured)
     assert abs(loss.item() - ref_l) / ref_l < 1e-5
     assert rel(gs.cpu().numpy(), ref_gs) < 1e-4 and rel(gp.cpu().numpy(), ref_gp) < 1e-4
-    # 16 seeded directions over slices (+) probe: FP64 oracle loss, central difference at
+    # 24 seeded directions over slices (+) probe: FP64 oracle loss, central difference at
     # step 1e-5 (truncation ~ eps^2, rounding ~ 1e-16 |L| / eps, both far below 1e-4)
     g_s = gs.cpu().numpy().astype(np.complex128)
     g_p = gp.cpu().numpy().astype(np.complex128)
     start, probe = c.start.astype(np.complex128), c.probe.astype(np.complex128)
-    s_dirs = synth.complex_directions(start.shape, 16, seed=geo.seed + 2)
-    p_dirs = synth.complex_directions(probe.shape, 16, seed=geo.seed + 7) * 0.01
+    s_dirs = synth.complex_directions(start.shape, 24, seed=geo.seed + 2)
+    p_dirs = synth.complex_directions(probe.shape, 24, seed=geo.seed + 7) * 0.01
     eps = 1e-5
     for d, dp in zip(s_dirs, p_dirs):
         fd = (c.model.loss(probe + eps * dp, start + eps * d, c.measured)
