@@ -29,7 +29,7 @@ ms_status fail(ms_status st, const std::string &msg)
 }
 
 constexpr int kMaxBlocks = 256;    // partial-maximum blocks per segment
-constexpr long long kScatterBlocks = 8192;   // target grid of the scatter pass
+constexpr long long kScatterBlocks = 32768;   // target grid of the scatter pass
 // Distinct sub-pixel probe shifts per plan.  A raster has a few; refined positions have one per
 // position.  The class tables and partial sums take about (kChunks + 5) C N^2 8 bytes.
 constexpr int kMaxClasses = 4096;
