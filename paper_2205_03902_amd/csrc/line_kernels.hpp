@@ -216,12 +216,7 @@ __device__ __forceinline__ double residual_vals(float2 (&v)[16], const float (&m
                 v[i] = make_float2(z.x - k * z.x, z.y - k * z.y);
             }
         } else {
-            const double d = sqrt((double)m) - sqrt(a2d);
-            acc += d * d;
-            if (a2 != 0.0f) {
-                const float k = sqrtf(m) / sqrtf(a2);
-                v[i] = make_float2(z.x - k * z.x, z.y - k * z.y);
-            }
+            acc += amp_residual(m, v[i]);
         }
     }
     return acc;

@@ -186,6 +186,28 @@ __device__ __forceinline__ double block_sum(double x, double *red)
     return t;
 }
 
+// One pixel of the amplitude loss (Sec. 3.2): returns (sqrt(I) - |Psi|)^2 in FP64 and turns z = Psi
+// into the residual Psi - sqrt(I) Psi / |Psi| (Psi itself where Psi = 0: the phase is taken as 0).
+// Both come from d = sqrt(I) - |Psi| = (I - |Psi|^2) / (sqrt(I) + |Psi|) with I - |Psi|^2 formed in
+// FP64, and the residual is Psi (-d / |Psi|): neither cancels when the fit is close (the form
+// Psi - (sqrt(I) / |Psi|) Psi loses the digits that sqrt(I) / |Psi| shares with 1).  The two
+// quotients use the FP32 reciprocal (1 ulp).
+__device__ __forceinline__ double amp_residual(float m, float2 &z)
+{
+    const float a2 = cabs2(z);
+    const float a = sqrtf(a2), sq = sqrtf(m);
+    const double a2d = (double)z.x * (double)z.x + (double)z.y * (double)z.y;
+    if (a2d == 0.0) return (double)m;   // Psi = 0: the term is I itself, the residual Psi
+    // sqrt(I) + |Psi| is 0 only when I = 0 and |Psi|^2 underflows in FP32 (|Psi| < 1e-22)
+    const float den = sq + a;
+    const float d = den > 0.0f ? (float)((double)m - a2d) * __builtin_amdgcn_rcpf(den) : 0.0f;
+    if (a2 != 0.0f) {
+        const float f = -d * __builtin_amdgcn_rcpf(a);
+        z = make_float2(z.x * f, z.y * f);
+    }
+    return (double)d * (double)d;
+}
+
 // Far field (Sec. 2.1) and amplitude residual (Sec. 3.2) on the 2D spectrum held in
 // layout ROW2 (after the forward 2D FFT): r = Psi - sqrt(I) Psi / |Psi|, 0 where Psi = 0.
 // Returns this lane's FP64 share of the loss: sum (sqrt(I) - |Psi|)^2 (amplitude) or, when
@@ -219,19 +241,7 @@ __device__ __forceinline__ double residual(float2 (&v)[16], const float *meas, i
     for (int i = 0; i < 16; ++i) {
         int f = Wn::spec(j, i);
         int fy = ROW2 ? line : f, fx = ROW2 ? f : line;
-        float m = meas[fy * N + fx];
-        float2 z = v[i];
-        float a2 = cabs2(z);
-        float a = sqrtf(a2);
-        float sq = sqrtf(m);
-        double d = sqrt((double)m) - sqrt((double)z.x * (double)z.x + (double)z.y * (double)z.y);
-        acc += d * d;
-        if (a2 == 0.0f) {
-            v[i] = z;   // zero: the phase is taken as 0, so the residual is Psi itself
-        } else {
-            float k = sq / a;
-            v[i] = make_float2(z.x - k * z.x, z.y - k * z.y);
-        }
+        acc += amp_residual(meas[fy * N + fx], v[i]);
     }
     return acc;
 }
