@@ -87,14 +87,23 @@ __device__ __forceinline__ void store_window_abs2(const float2 (&v)[16], float *
 }
 
 // t = the object patch t[(oy + y) mod H][(ox + x) mod W] (Sec. 1.3, 2.1) on this lane's 16 points.
+// inside: the window lies inside the object (oy + N <= H, ox + N <= W), so no index wraps and every
+// load is a per-lane base plus a constant step.
 template <int N, bool ROW>
 __device__ __forceinline__ void load_patch(float2 (&t)[16], const float2 *slice, int H, int W, int oy, int ox,
-                                           int line, int j)
+                                           int line, int j, bool inside = false)
 {
     using Wn = Win<N>;
     constexpr int R = Wn::R;
     line = opaque(line);
     j = opaque(j);
+    if (inside) {
+        const unsigned base = ROW ? (unsigned)((oy + line) * W + ox + j) : (unsigned)((oy + j) * W + ox + line);
+        const unsigned step = ROW ? (unsigned)R : (unsigned)(R * W);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t[k] = slice[base + step * k];
+        return;
+    }
     // 32-bit element offsets (H W <= 2^30): a step of R along the owned axis adds a constant,
     // and crossing the object edge subtracts one period.
     if (ROW) {
@@ -271,6 +280,7 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
     const int4 info = p.pos_info[s];
     const int oy = info.x, ox = info.y, cls = info.z;
     const int H = p.H, W = p.W, M = p.M;
+    const bool inside = (oy + N <= H) && (ox + N <= W);   // the patch does not wrap
 
     // twiddles and propagator factors live in LDS for the whole chain
     stage<N>(s_tw, p.tw, Wn::TW_WORDS);
@@ -293,7 +303,7 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
             // the transmission loads go out before this step's stores: the vector memory
             // counter retires in issue order, so waiting for them does not wait for the stores
             float2 t[16];
-            load_patch<N, true>(t, slice, H, W, oy, ox, line, j);
+            load_patch<N, true>(t, slice, H, W, oy, ox, line, j, inside);
             if (store) store_window<N, true>(v, wave + m * NN, line, j);
             if (MODE == kLayer && m == p.layer)
                 store_window_abs2<N, true>(v, p.overlap_patch + ((size_t)b * M + m) * NN, line, j);
@@ -304,7 +314,7 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
             }
         } else {
             float2 t[16];
-            load_patch<N, false>(t, slice, H, W, oy, ox, line, j);
+            load_patch<N, false>(t, slice, H, W, oy, ox, line, j, inside);
             if (store) store_window<N, false>(v, wave + m * NN, line, j);
             if (MODE == kLayer && m == p.layer)
                 store_window_abs2<N, false>(v, p.overlap_patch + ((size_t)b * M + m) * NN, line, j);
@@ -369,8 +379,8 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
             constexpr bool kEarlyT = (MODE != kLayer);
             float2 t[16];
             if (kEarlyT && go_on) {
-                if (row) load_patch<N, true>(t, slice, H, W, oy, ox, line, j);
-                else load_patch<N, false>(t, slice, H, W, oy, ox, line, j);
+                if (row) load_patch<N, true>(t, slice, H, W, oy, ox, line, j, inside);
+                else load_patch<N, false>(t, slice, H, W, oy, ox, line, j, inside);
             }
             if (patch) {
                 const float2 *psi = (m == 0) ? probe : wave + m * NN;
@@ -396,8 +406,8 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
             }
             if (!go_on) break;
             if (!kEarlyT) {
-                if (row) load_patch<N, true>(t, slice, H, W, oy, ox, line, j);
-                else load_patch<N, false>(t, slice, H, W, oy, ox, line, j);
+                if (row) load_patch<N, true>(t, slice, H, W, oy, ox, line, j, inside);
+                else load_patch<N, false>(t, slice, H, W, oy, ox, line, j, inside);
             }
             mul_patch<true>(v, t);
             if (m > 0) {
