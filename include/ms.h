@@ -93,6 +93,9 @@ ms_status ms_workspace_size(const ms_problem *pb, size_t budget_bytes, size_t *w
  * (device memory of ws_bytes, 256-byte aligned, owned by the caller and kept
  * alive until ms_plan_destroy).  Blocks until the upload is done. */
 ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes, ms_plan **out);
+/* Releases the plan's host data and its internal stream and events.  Work the plan
+ * enqueued still reads and writes the workspace: synchronise the streams it was
+ * called on before freeing the workspace.  NULL is ignored. */
 void ms_plan_destroy(ms_plan *plan);
 
 /* Positions per batch and number of probe shift classes chosen by the plan. */
