@@ -94,7 +94,9 @@ __global__ __launch_bounds__(Win<N>::NT) void image_propagate_kernel(const float
         v[i] = CONJ ? imsp::cmulc(v[i], h) : imsp::cmul(v[i], h);
     }
     imsp::line_fft_inv<N>(v, s_tw, xb, j);
-    imsp::transpose<N, true, false, false>(v, lds, line, j);   // columns: lane (x = line, j) holds y = j + R k
+    // columns: lane (x = line, j) holds y = j + R k
+    if constexpr (R >= 4) imsp::transpose_nat<N, true>(v, lds, line, j);
+    else imsp::transpose<N, true, false, false>(v, lds, line, j);
     imsp::line_fft_fwd<N>(v, s_tw, xb, j);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
