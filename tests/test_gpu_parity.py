@@ -96,6 +96,29 @@ def test_layer_step(dev, n, layer):
     assert np.array_equal(got[others], c.start[others])
 
 
+@pytest.mark.parametrize("n", [32, 64])
+def test_algorithm1_sweeps_match_the_oracle(dev, n):
+    """Two sweeps of Algorithm 1 through the Python driver (every layer in order, Gauss-Seidel,
+    then a probe step) against the oracle's driver: the loss of every step within 1e-5, and
+    the slices and probe after the 2 (M + 1) chained steps within 1e-4 (each step adds about
+    1e-6 of FP32 rounding to its iterate, and later steps carry the earlier ones)."""
+    import oracle
+    from paper_2205_03902_amd import layerwise
+    c = case_for(n)
+    plan = _plan(c, dev)
+    p0 = (c.probe * np.exp(0.05j)).astype(np.complex64)
+    p_t, s_t = _t(p0, dev), _t(c.start, dev)
+    hist = layerwise.reconstruct(plan, p_t, s_t, _t(c.measured, dev), sweeps=2, k_steps=1, probe_steps=1)
+    ref_s, ref_p, ref_h = oracle.layerwise(c.model, p0, c.start, c.measured, sweeps=2, k_steps=1, probe_steps=1)
+    assert hist.kind == ([f"layer{m}" for m in range(c.geo.n_slices)] + ["probe"]) * 2
+    assert len(ref_h) == len(hist.loss)
+    el = max(abs(a - b) / b for a, b in zip(hist.loss, ref_h))
+    es, ep = rel(s_t.cpu().numpy(), ref_s), rel(p_t.cpu().numpy(), ref_p)
+    print(f"n={n}: losses {el:.2e} slices {es:.2e} probe {ep:.2e}")
+    assert all(b2 <= b1 for b1, b2 in zip(hist.loss, hist.loss[1:])), hist.loss
+    assert el < TOL_FWD and es < TOL_GRAD and ep < TOL_GRAD
+
+
 @pytest.mark.parametrize("subset", [None, [0, 4, 8], [4]])
 def test_probe_step(dev, subset):
     c = case_for(32)
