@@ -38,7 +38,7 @@ int32_t sfail(int32_t st, const std::string &msg)
 constexpr size_t kAlign = 256;
 constexpr int kRed = 256;        // reduction partials
 constexpr int kTraceBlocks = 2048;   // partials of the lambda traces
-constexpr int kDotChunks = 32;   // row chunks of the gradient's column sums
+constexpr int kDotChunks = 64;   // row chunks of the gradient's column sums
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 unsigned blocks(long long n) { return (unsigned)std::min<long long>(65535, (n + 255) / 256); }
@@ -393,10 +393,21 @@ __global__ __launch_bounds__(256) void coldot_kernel(const float2 *V, const floa
     if (k >= n2) return;
     const int j0 = c * rows, j1 = min(n2, j0 + rows);
     double ar = 0.0, ai = 0.0;
-    for (int jj = j0; jj < j1; ++jj) {
-        const float2 u = V[(size_t)jj * n2 + k], s = S[(size_t)jj * n2 + k];
-        ar += (double)u.x * s.x + (double)u.y * s.y;
-        ai += (double)u.y * s.x - (double)u.x * s.y;
+    // eight rows of loads in flight, summed in row order
+    constexpr int kU = 8;
+    for (int jb = j0; jb < j1; jb += kU) {
+        float2 u[kU], w[kU];
+#pragma unroll
+        for (int q = 0; q < kU; ++q) {
+            const bool in = jb + q < j1;
+            u[q] = in ? V[(size_t)(jb + q) * n2 + k] : make_float2(0.f, 0.f);
+            w[q] = in ? S[(size_t)(jb + q) * n2 + k] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < kU; ++q) {
+            ar += (double)u[q].x * w[q].x + (double)u[q].y * w[q].y;
+            ai += (double)u[q].y * w[q].x - (double)u[q].x * w[q].y;
+        }
     }
     part[(size_t)c * n2 + k] = make_double2(ar, ai);
 }
