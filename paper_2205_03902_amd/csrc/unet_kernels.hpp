@@ -659,4 +659,37 @@ __global__ void mse_grad_kernel(const float *__restrict__ y, const float *__rest
     *reinterpret_cast<uint4 *>(gy + p * 8) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
+// 1x1 convolution to a few FP32 channels (the network's head): one lane per pixel reads its C
+// bf16 channels (16-byte pieces), the weights (bf16 [cout][kpad]) and bias sit in LDS as FP32,
+// sums in FP32.  cout <= kHeadMax, C a multiple of 8 and at most kHeadC.
+constexpr int kHeadMax = 8, kHeadC = 64;
+
+__global__ __launch_bounds__(256) void head_kernel(const uint16_t *in, int C, const uint16_t *w, int kpad,
+                                                   const float *bias, int cout, float *out, long long pixels)
+{
+    __shared__ float sw[kHeadMax][kHeadC];
+    __shared__ float sb[kHeadMax];
+    for (int i = threadIdx.x; i < cout * C; i += 256) sw[i / C][i % C] = bf2f(w[(size_t)(i / C) * kpad + i % C]);
+    for (int i = threadIdx.x; i < cout; i += 256) sb[i] = bias ? bias[i] : 0.0f;
+    __syncthreads();
+    const long long px = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (px >= pixels) return;
+    float acc[kHeadMax];
+#pragma unroll
+    for (int o = 0; o < kHeadMax; ++o) acc[o] = 0.0f;
+    const uint4 *src = reinterpret_cast<const uint4 *>(in + px * C);
+    for (int c8 = 0; c8 < C / 8; ++c8) {
+        const uint4 v = src[c8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float x = bf2f(bf_at(v, e));
+#pragma unroll
+            for (int o = 0; o < kHeadMax; ++o)
+                if (o < cout) acc[o] = fmaf(sw[o][c8 * 8 + e], x, acc[o]);
+        }
+    }
+    float *dst = out + px * cout;
+    for (int o = 0; o < cout; ++o) dst[o] = acc[o] + sb[o];
+}
+
 }  // namespace unet

@@ -314,6 +314,13 @@ void layer_forward(const un_net &n, int li, int batch, int level, const uint16_t
         a.g = gather_of(in0, c0, nullptr, 0, hlg, wlg, 1, 1);
         a.o = up_map(ly.info.cout, hlg, wlg);
     } else {
+        if (ly.info.kind == UN_CONV1X1 && !in1 && ly.info.cout <= kHeadMax && c0 % 8 == 0 && c0 <= kHeadC) {
+            // the head: a per-pixel kernel (a GEMM of a few columns is all pipeline start-up)
+            const long long px = n.pixels(batch, level);
+            head_kernel<<<(unsigned)((px + 255) / 256), 256, 0, st>>>(in0, c0, a.w, a.kpad, a.bias, ly.info.cout,
+                                                                       static_cast<float *>(out), px);
+            return;
+        }
         a.g = gather_of(in0, c0, in1, c1, hlg, wlg, ly.info.taps, 1);
         a.o = plain_map(ly.info.cout, ly.info.cout, hlg, wlg);
         a.relu = ly.info.kind == UN_CONV3X3;
