@@ -659,9 +659,126 @@ __global__ void mse_grad_kernel(const float *__restrict__ y, const float *__rest
     *reinterpret_cast<uint4 *>(gy + p * 8) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
+// Direct 3x3 convolution (stride 1, zero padding 1) to 32 output channels, for the layers at
+// full resolution: the implicit GEMM gathers every input pixel's channels once per tap (nine
+// times) through L2, this kernel stages a (TH + 2) x 18 halo of input pixels and the layer's
+// weights in LDS once per TH x 16 output tile and reads the nine shifted A fragments from there.
+// Inputs: C = c0 + c1 channels per pixel (a second source is the skip of a concatenation),
+// weights bf16 [32][kpad] with k = tap * C + channel (tap-major, the GEMM's order).  Each of the
+// four wavefronts owns TH / 4 output rows (TH * 4 pixels = TH / 8 row blocks of 32).
+struct Conv3Args {
+    const uint16_t *src0, *src1;   // NHWC bf16
+    int c0, c1;                    // channels of each source (c1 = 0: one source)
+    int h_log, w_log;              // image height / width (log2)
+    const uint16_t *w;             // [32][kpad]
+    int kpad;
+    const float *bias;             // [32] or null
+    int relu;
+    uint16_t *dst;                 // NHWC bf16, 32 channels
+};
+
+template <int TH, int C, int TY>
+__global__ __launch_bounds__(kThreads) void conv3x3_kernel(const Conv3Args a)
+{
+    constexpr int TW = 16, HW = TW + 2, HP = (TH + 2) * HW;   // halo width and pixels
+    constexpr int LDH = C + 8;                                // bf16 per halo pixel (bank padding)
+    constexpr int K = 9 * C, LDW = K + 8;                     // weight row stride
+    constexpr int FM = TH / 8;                                // 32-pixel blocks per wavefront
+    __shared__ __attribute__((aligned(16))) uint16_t halo[HP * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t wl[32 * LDW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int x0 = blockIdx.x * TW, b = blockIdx.z;
+    const int H = 1 << a.h_log, W = 1 << a.w_log;
+    for (int q = tid; q < 32 * (K / 8); q += kThreads) {
+        const int n = q / (K / 8), k = (q % (K / 8)) * 8;
+        *reinterpret_cast<uint4 *>(&wl[n * LDW + k]) = *reinterpret_cast<const uint4 *>(a.w + (long long)n * a.kpad + k);
+    }
+    // this lane's A row: pixel p = i 32 + lane % 32 of the wavefront's rows
+    const int r0 = wave * (TH / 4);
+    int hbase[FM];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        const int p = i * 32 + (lane & 31);
+        hbase[i] = ((r0 + p / TW) * HW + p % TW) * LDH + (lane >> 5) * 8;
+    }
+    const uint16_t *wrow = wl + (lane & 31) * LDW + (lane >> 5) * 8;
+    const int co = lane & 31;
+    const float bias = a.bias ? a.bias[co] : 0.0f;
+    // TY tiles along y share the staged weights; the next tile's halo is loaded into
+    // registers (16-byte pieces of 8 channels, zeros outside the image) while the matrix
+    // cores work on the current one
+    constexpr int NQ = HP * (C / 8), NCH = (NQ + kThreads - 1) / kThreads;
+    uint4 rh[NCH];
+    auto fetch = [&](int y0) {
+#pragma unroll
+        for (int r = 0; r < NCH; ++r) {
+            const int q = tid + r * kThreads;
+            rh[r] = make_uint4(0u, 0u, 0u, 0u);
+            if (q < NQ) {
+                const int pix = q / (C / 8), ch = (q % (C / 8)) * 8;
+                const int y = y0 - 1 + pix / HW, x = x0 - 1 + pix % HW;
+                if (y >= 0 && y < H && x >= 0 && x < W) {
+                    const long long gp = ((long long)((b << a.h_log) + y) << a.w_log) + x;
+                    rh[r] = ch < a.c0 ? *reinterpret_cast<const uint4 *>(a.src0 + gp * a.c0 + ch)
+                                      : *reinterpret_cast<const uint4 *>(a.src1 + gp * a.c1 + (ch - a.c0));
+                }
+            }
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int r = 0; r < NCH; ++r) {
+            const int q = tid + r * kThreads;
+            if (q < NQ) *reinterpret_cast<uint4 *>(&halo[(q / (C / 8)) * LDH + (q % (C / 8)) * 8]) = rh[r];
+        }
+    };
+    fetch(blockIdx.y * TY * TH);
+    put();
+    __syncthreads();
+    for (int ty = 0; ty < TY; ++ty) {
+        const int y0 = (blockIdx.y * TY + ty) * TH;
+        if (ty + 1 < TY) fetch(y0 + TH);
+
+        f32x16 acc[FM];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][e] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int shift = ((t / 3) * HW + t % 3) * LDH;
+#pragma unroll
+            for (int kc = 0; kc < C / 16; ++kc) {
+                const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(wrow + t * C + kc * 16);
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(&halo[hbase[i] + shift + kc * 16]);
+                    acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc[i], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int p = i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                const int y = y0 + r0 + p / TW, x = x0 + p % TW;
+                float val = acc[i][e] + bias;
+                if (a.relu) val = fmaxf(val, 0.0f);
+                a.dst[((((long long)(b << a.h_log) + y) << a.w_log) + x) * 32 + co] = f2bf(val);
+            }
+        if (ty + 1 < TY) {
+            __syncthreads();   // every wavefront is done with this tile's halo
+            put();
+            __syncthreads();
+        }
+    }
+}
+
 // 1x1 convolution to a few FP32 channels (the network's head): one lane per pixel reads its C
 // bf16 channels (16-byte pieces), the weights (bf16 [cout][kpad]) and bias sit in LDS as FP32,
-// sums in FP32.  cout <= kHeadMax, C a multiple of 8 and at most kHeadC.
+// sums in FP32.  cout <= kHeadMax, C a multiple of 8 and at most kHeadC.  (Four lanes per pixel,
+// each reading a quarter of it so that a wavefront's loads are consecutive, measured slower.)
 constexpr int kHeadMax = 8, kHeadC = 64;
 
 __global__ __launch_bounds__(256) void head_kernel(const uint16_t *in, int C, const uint16_t *w, int kpad,

@@ -321,6 +321,24 @@ void layer_forward(const un_net &n, int li, int batch, int level, const uint16_t
                                                                        static_cast<float *>(out), px);
             return;
         }
+        const int cin = c0 + (in1 ? c1 : 0);
+        if (ly.info.kind == UN_CONV3X3 && ly.info.cout == 32 && (cin == 32 || cin == 64) && c0 % 16 == 0 &&
+            (in1 ? c1 : 0) % 16 == 0 && hlg >= 6 && wlg >= 4) {
+            // full-resolution layers: direct convolution from an LDS halo (see conv3x3_kernel)
+            Conv3Args c{};
+            c.src0 = in0; c.src1 = in1; c.c0 = c0; c.c1 = in1 ? c1 : 0;
+            c.h_log = hlg; c.w_log = wlg;
+            c.w = a.w; c.kpad = a.kpad; c.bias = a.bias; c.relu = 1;
+            c.dst = static_cast<uint16_t *>(out);
+            if (cin == 32) {   // 16-row tiles, four per workgroup
+                const dim3 grid(1u << (wlg - 4), 1u << (hlg - 6), (unsigned)batch);
+                conv3x3_kernel<16, 32, 4><<<grid, kThreads, 0, st>>>(c);
+            } else {           // 8-row tiles, four per workgroup
+                const dim3 grid(1u << (wlg - 4), 1u << (hlg - 5), (unsigned)batch);
+                conv3x3_kernel<8, 64, 4><<<grid, kThreads, 0, st>>>(c);
+            }
+            return;
+        }
         a.g = gather_of(in0, c0, in1, c1, hlg, wlg, ly.info.taps, 1);
         a.o = plain_map(ly.info.cout, ly.info.cout, hlg, wlg);
         a.relu = ly.info.kind == UN_CONV3X3;
