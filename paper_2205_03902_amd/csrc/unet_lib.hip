@@ -296,6 +296,32 @@ OutMap up_map(int cout, int h_log_in, int w_log_in)
     return o;
 }
 
+// Whether a 3x3 convolution to `cout` channels from c0 (+ c1) input channels on a 2^hl x 2^wl
+// image runs as the direct convolution (conv3x3_kernel).
+bool direct_conv_fits(int cout, int c0, int c1, int hl, int wl)
+{
+    const int cin = c0 + c1;
+    return cout == 32 && (cin == 32 || cin == 64) && c0 % 16 == 0 && c1 % 16 == 0 && hl >= 6 && wl >= 4;
+}
+
+void direct_conv(const uint16_t *in0, int c0, const uint16_t *in1, int c1, int hl, int wl, int batch,
+                 const uint16_t *w, int kpad, const float *bias, int relu, const uint16_t *mask, uint16_t *out,
+                 hipStream_t st)
+{
+    Conv3Args c{};
+    c.src0 = in0; c.src1 = in1; c.c0 = c0; c.c1 = c1;
+    c.h_log = hl; c.w_log = wl;
+    c.w = w; c.kpad = kpad; c.bias = bias; c.relu = relu; c.mask = mask;
+    c.dst = out;
+    if (c0 + c1 == 32) {   // 16-row tiles, four per workgroup
+        const dim3 grid(1u << (wl - 4), 1u << (hl - 6), (unsigned)batch);
+        conv3x3_kernel<16, 32, 4><<<grid, kThreads, 0, st>>>(c);
+    } else {               // 8-row tiles, four per workgroup
+        const dim3 grid(1u << (wl - 4), 1u << (hl - 5), (unsigned)batch);
+        conv3x3_kernel<8, 64, 4><<<grid, kThreads, 0, st>>>(c);
+    }
+}
+
 // Forward of one layer.  in0 / in1: inputs (in1 the skip of a concatenation); level: image
 // level of the input (for the transposed convolution, the coarser one).
 void layer_forward(const un_net &n, int li, int batch, int level, const uint16_t *in0, int c0, const uint16_t *in1,
@@ -321,22 +347,9 @@ void layer_forward(const un_net &n, int li, int batch, int level, const uint16_t
                                                                        static_cast<float *>(out), px);
             return;
         }
-        const int cin = c0 + (in1 ? c1 : 0);
-        if (ly.info.kind == UN_CONV3X3 && ly.info.cout == 32 && (cin == 32 || cin == 64) && c0 % 16 == 0 &&
-            (in1 ? c1 : 0) % 16 == 0 && hlg >= 6 && wlg >= 4) {
-            // full-resolution layers: direct convolution from an LDS halo (see conv3x3_kernel)
-            Conv3Args c{};
-            c.src0 = in0; c.src1 = in1; c.c0 = c0; c.c1 = in1 ? c1 : 0;
-            c.h_log = hlg; c.w_log = wlg;
-            c.w = a.w; c.kpad = a.kpad; c.bias = a.bias; c.relu = 1;
-            c.dst = static_cast<uint16_t *>(out);
-            if (cin == 32) {   // 16-row tiles, four per workgroup
-                const dim3 grid(1u << (wlg - 4), 1u << (hlg - 6), (unsigned)batch);
-                conv3x3_kernel<16, 32, 4><<<grid, kThreads, 0, st>>>(c);
-            } else {           // 8-row tiles, four per workgroup
-                const dim3 grid(1u << (wlg - 4), 1u << (hlg - 5), (unsigned)batch);
-                conv3x3_kernel<8, 64, 4><<<grid, kThreads, 0, st>>>(c);
-            }
+        if (ly.info.kind == UN_CONV3X3 && direct_conv_fits(ly.info.cout, c0, in1 ? c1 : 0, hlg, wlg)) {
+            direct_conv(in0, c0, in1, in1 ? c1 : 0, hlg, wlg, batch, a.w, a.kpad, a.bias, 1, nullptr,
+                        static_cast<uint16_t *>(out), st);
             return;
         }
         a.g = gather_of(in0, c0, in1, c1, hlg, wlg, ly.info.taps, 1);
@@ -401,6 +414,12 @@ void layer_data_grad(const un_net &n, int li, int batch, int level, const uint16
     a.kpad = ly.d_k;
     if (ly.info.kind == UN_UPCONV2X2) a.g = gather_of(gy, ly.G, nullptr, 0, hlg + 1, wlg + 1, 4, 2);
     else a.g = gather_of(gy, ly.G, nullptr, 0, hlg, wlg, ly.info.taps, 1);
+    if (ly.info.kind == UN_CONV3X3 && !dst1 && d0c == ly.d_rows && direct_conv_fits(ly.d_rows, ly.G, 0, hlg, wlg)) {
+        // the same convolution of the output gradient with the flipped weights, masked
+        direct_conv(gy, ly.G, nullptr, 0, hlg, wlg, batch, a.w, a.kpad, nullptr, 0, mask,
+                    static_cast<uint16_t *>(dst0), st);
+        return;
+    }
     a.o = plain_map(ly.d_rows, ly.d_rows, hlg, wlg);
     a.mask = mask;
     a.dst0 = dst0;
