@@ -659,9 +659,10 @@ __global__ void mse_grad_kernel(const float *__restrict__ y, const float *__rest
     *reinterpret_cast<uint4 *>(gy + p * 8) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
-// Direct 3x3 convolution (stride 1, zero padding 1) to 32 output channels, for the layers at
-// full resolution (forward passes, and the data gradients of the 32 -> 32 layers, which are the
-// same convolution of the output gradient with the flipped weights and a ReLU mask): the implicit GEMM gathers every input pixel's channels once per tap (nine
+// Direct 3x3 convolution (stride 1, zero padding 1) to 32 output channels (a layer with 64 takes
+// two launches, one per half), for the two finest levels (forward passes, and the data gradients
+// of the layers whose input has as many channels as their output, which are the same convolution
+// of the output gradient with the flipped weights and a ReLU mask): the implicit GEMM gathers every input pixel's channels once per tap (nine
 // times) through L2, this kernel stages a (TH + 2) x 18 halo of input pixels and the layer's
 // weights in LDS once per TH x 16 output tile and reads the nine shifted A fragments from there.
 // Inputs: C = c0 + c1 channels per pixel (a second source is the skip of a concatenation),
@@ -675,8 +676,9 @@ struct Conv3Args {
     int kpad;
     const float *bias;             // [32] or null
     int relu;
-    const uint16_t *mask;          // [pixels][32] bf16: output *= (mask > 0), or null (data gradients)
-    uint16_t *dst;                 // NHWC bf16, 32 channels
+    const uint16_t *mask;          // [pixels][ldd] bf16: output *= (mask > 0), or null (data gradients)
+    uint16_t *dst;                 // NHWC bf16 with ldd channels a pixel; this launch writes 32 of them
+    int ldd;                       // channels per output pixel (32, or 64 when two launches split them)
 };
 
 template <int TH, int C, int TY>
@@ -765,7 +767,7 @@ __global__ __launch_bounds__(kThreads) void conv3x3_kernel(const Conv3Args a)
             for (int e = 0; e < 16; ++e) {
                 const int p = i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
                 const int y = y0 + r0 + p / TW, x = x0 + p % TW;
-                const long long d = ((((long long)(b << a.h_log) + y) << a.w_log) + x) * 32 + co;
+                const long long d = ((((long long)(b << a.h_log) + y) << a.w_log) + x) * a.ldd + co;
                 float val = acc[i][e] + bias;
                 if (a.relu) val = fmaxf(val, 0.0f);
                 if (a.mask && !(bf2f(a.mask[d]) > 0.0f)) val = 0.0f;
