@@ -659,14 +659,15 @@ __global__ void mse_grad_kernel(const float *__restrict__ y, const float *__rest
     *reinterpret_cast<uint4 *>(gy + p * 8) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
-// Direct 3x3 convolution (stride 1, zero padding 1) to 32 output channels (a layer with 64 takes
-// two launches, one per half), for the two finest levels (forward passes, and the data gradients
-// of the layers whose input has as many channels as their output, which are the same convolution
-// of the output gradient with the flipped weights and a ReLU mask): the implicit GEMM gathers every input pixel's channels once per tap (nine
-// times) through L2, this kernel stages a (TH + 2) x 18 halo of input pixels and the layer's
-// weights in LDS once per TH x 16 output tile and reads the nine shifted A fragments from there.
-// Inputs: C = c0 + c1 channels per pixel (a second source is the skip of a concatenation),
-// weights bf16 [32][kpad] with k = tap * C + channel (tap-major, the GEMM's order).  Each of the
+// Direct 3x3 convolution (stride 1, zero padding 1) to 32 output channels, for the two finest
+// levels: forward passes, and the data gradients whose output is not split over a concatenation
+// (the same convolution of the output gradient with the flipped weights, and a ReLU mask).  A
+// layer with 64 output channels takes two launches, one per half.  The implicit GEMM gathers
+// every input pixel's channels once per tap (nine times) through L2; this kernel stages the
+// layer's weights once per workgroup and a (TH + 2) x 18 halo of input pixels per TH x 16 output
+// tile in LDS, and reads the nine shifted A fragments from there.  Inputs: C = c0 + c1 channels
+// per pixel (a second source is the skip of a concatenation); weights bf16 [32][kpad] with
+// k = tap * C + channel (tap-major, the GEMM's order, so the sums are the GEMM's).  Each of the
 // four wavefronts owns TH / 4 output rows (TH * 4 pixels = TH / 8 row blocks of 32).
 struct Conv3Args {
     const uint16_t *src0, *src1;   // NHWC bf16
