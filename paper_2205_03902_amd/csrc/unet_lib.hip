@@ -297,26 +297,32 @@ OutMap up_map(int cout, int h_log_in, int w_log_in)
 }
 
 // Whether a 3x3 convolution to `cout` channels from c0 (+ c1) input channels on a 2^hl x 2^wl
-// image runs as the direct convolution (conv3x3_kernel, 32 output channels a launch).
+// image runs as the direct convolution (conv3x3_kernel, 32 output channels a launch). Four launches
+// (128 channels) pay only from 128 x 128 up: at 64 x 64 each launch has too few workgroups to fill
+// the chip and the implicit GEMM is faster.
 bool direct_conv_fits(int cout, int c0, int c1, int hl, int wl)
 {
     const int cin = c0 + c1;
-    return (cout == 32 || cout == 64) && (cin == 32 || cin == 64) && c0 % 16 == 0 && c1 % 16 == 0 && hl >= 6 &&
-           wl >= 4;
+    return cout % 32 == 0 && (cout <= 64 || (cout <= 128 && hl >= 7)) && (cin == 32 || cin == 64) &&
+           c0 % 16 == 0 && c1 % 16 == 0 && hl >= 6 && wl >= 4;
 }
 
+// Output channels [0, d0c) go to out0 (d0c a pixel, masked by mask if given), the rest to out1
+// (cout - d0c a pixel): the split of a concatenation's gradient.
 void direct_conv(const uint16_t *in0, int c0, const uint16_t *in1, int c1, int hl, int wl, int batch, int cout,
-                 const uint16_t *w, int kpad, const float *bias, int relu, const uint16_t *mask, uint16_t *out,
-                 hipStream_t st)
+                 const uint16_t *w, int kpad, const float *bias, int relu, const uint16_t *mask, uint16_t *out0,
+                 int d0c, uint16_t *out1, hipStream_t st)
 {
     for (int h = 0; h < cout / 32; ++h) {   // 32 output channels a launch
+        const bool first = h * 32 < d0c;
         Conv3Args c{};
         c.src0 = in0; c.src1 = in1; c.c0 = c0; c.c1 = c1;
         c.h_log = hl; c.w_log = wl;
         c.w = w + (size_t)h * 32 * kpad; c.kpad = kpad;
         c.bias = bias ? bias + h * 32 : nullptr; c.relu = relu;
-        c.mask = mask ? mask + h * 32 : nullptr;
-        c.dst = out + h * 32; c.ldd = cout;
+        c.mask = (mask && first) ? mask + h * 32 : nullptr;
+        c.dst = first ? out0 + h * 32 : out1 + (h * 32 - d0c);
+        c.ldd = first ? d0c : cout - d0c;
         if (c0 + c1 == 32) {   // 16-row tiles, four per workgroup
             const dim3 grid(1u << (wl - 4), 1u << (hl - 6), (unsigned)batch);
             conv3x3_kernel<16, 32, 4><<<grid, kThreads, 0, st>>>(c);
@@ -354,7 +360,7 @@ void layer_forward(const un_net &n, int li, int batch, int level, const uint16_t
         }
         if (ly.info.kind == UN_CONV3X3 && direct_conv_fits(ly.info.cout, c0, in1 ? c1 : 0, hlg, wlg)) {
             direct_conv(in0, c0, in1, in1 ? c1 : 0, hlg, wlg, batch, ly.info.cout, a.w, a.kpad, a.bias, 1, nullptr,
-                        static_cast<uint16_t *>(out), st);
+                        static_cast<uint16_t *>(out), ly.info.cout, nullptr, st);
             return;
         }
         a.g = gather_of(in0, c0, in1, c1, hlg, wlg, ly.info.taps, 1);
@@ -419,10 +425,12 @@ void layer_data_grad(const un_net &n, int li, int batch, int level, const uint16
     a.kpad = ly.d_k;
     if (ly.info.kind == UN_UPCONV2X2) a.g = gather_of(gy, ly.G, nullptr, 0, hlg + 1, wlg + 1, 4, 2);
     else a.g = gather_of(gy, ly.G, nullptr, 0, hlg, wlg, ly.info.taps, 1);
-    if (ly.info.kind == UN_CONV3X3 && !dst1 && d0c == ly.d_rows && direct_conv_fits(ly.d_rows, ly.G, 0, hlg, wlg)) {
-        // the same convolution of the output gradient with the flipped weights, masked
+    if (ly.info.kind == UN_CONV3X3 && d0c % 32 == 0 && d0c + (dst1 ? d1c : 0) == ly.d_rows &&
+        direct_conv_fits(ly.d_rows, ly.G, 0, hlg, wlg)) {
+        // the same convolution of the output gradient with the flipped weights, masked, the
+        // channels of a concatenation split over its two sources
         direct_conv(gy, ly.G, nullptr, 0, hlg, wlg, batch, ly.d_rows, a.w, a.kpad, nullptr, 0, mask,
-                    static_cast<uint16_t *>(dst0), st);
+                    static_cast<uint16_t *>(dst0), d0c, static_cast<uint16_t *>(dst1), st);
         return;
     }
     a.o = plain_map(ly.d_rows, ly.d_rows, hlg, wlg);

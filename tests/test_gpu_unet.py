@@ -55,7 +55,12 @@ def _nchw(t):
     return t.permute(0, 3, 1, 2).double().cpu().numpy()
 
 
-CASES = [(3, 2, 8, 3, 16, 32, 2, 1), (6, 6, 16, 4, 32, 32, 2, 2), (8, 1, 8, 1, 8, 16, 3, 3)]
+# (in, out, base, levels, height, width, batch, seed). The last two reach the direct 3x3
+# convolution, which takes images of 64 rows and more: 32 channels at 128 x 64 (two row tiles,
+# the concatenation's 64 input channels, its gradient split 32 / 32 over the two sources) and
+# 64 channels at 128 x 128 (two 32-channel launches a layer, the gradient split 64 / 64).
+CASES = [(3, 2, 8, 3, 16, 32, 2, 1), (6, 6, 16, 4, 32, 32, 2, 2), (8, 1, 8, 1, 8, 16, 3, 3),
+         (6, 6, 32, 2, 128, 64, 2, 4), (4, 3, 64, 2, 128, 128, 1, 6)]
 
 
 @pytest.mark.parametrize("case", CASES)
