@@ -200,6 +200,33 @@ def copy_calibration():
     log(f"copy calibration: read {a.numel() * 4 / 1024:.0f} KiB, wrote {b.numel() * 4 / 1024:.0f} KiB")
 
 
+def device_record():
+    """What the device reports about itself, and the HBM rate a plain device copy reaches: the
+    measured ceiling beside the published 8 TB/s for the HBM-bound kernels."""
+    import torch
+    prop = torch.cuda.get_device_properties(0)
+    n = 1 << 28                      # 1 GiB of float32 each way
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    rec = {"name": prop.name, "compute_units": prop.multi_processor_count,
+           "hbm_gib": round(prop.total_memory / 2 ** 30, 1),
+           "copy_GB_s": round(2 * n * 4 / sec / 1e9, 1), "copy_bytes": 2 * n * 4}
+    del a, b
+    torch.cuda.empty_cache()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,6 +337,7 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        extras["device"] = device_record()
         # one forward pass
         torch.cuda.synchronize()
         f0 = time.perf_counter()

@@ -660,9 +660,10 @@ __global__ void mse_grad_kernel(const float *__restrict__ y, const float *__rest
 }
 
 // Direct 3x3 convolution (stride 1, zero padding 1) to 32 output channels, for the two finest
-// levels: forward passes, and the data gradients whose output is not split over a concatenation
-// (the same convolution of the output gradient with the flipped weights, and a ReLU mask).  A
-// layer with 64 output channels takes two launches, one per half.  The implicit GEMM gathers
+// levels: forward passes and data gradients (the same convolution of the output gradient with
+// the flipped weights, and a ReLU mask).  A layer with 64 or 128 output channels takes one
+// launch per 32; a gradient split over a concatenation's two sources sends each launch to its
+// source.  The implicit GEMM gathers
 // every input pixel's channels once per tap (nine times) through L2; this kernel stages the
 // layer's weights once per workgroup and a (TH + 2) x 18 halo of input pixels per TH x 16 output
 // tile in LDS, and reads the nine shifted A fragments from there.  Inputs: C = c0 + c1 channels
@@ -679,7 +680,7 @@ struct Conv3Args {
     int relu;
     const uint16_t *mask;          // [pixels][ldd] bf16: output *= (mask > 0), or null (data gradients)
     uint16_t *dst;                 // NHWC bf16 with ldd channels a pixel; this launch writes 32 of them
-    int ldd;                       // channels per output pixel (32, or 64 when two launches split them)
+    int ldd;                       // channels per output pixel (a multiple of 32: one launch per 32)
 };
 
 template <int TH, int C, int TY>
