@@ -238,7 +238,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the sweep and forward timings")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
-                    help="positions per batch (0 = all at once); sets the plan's workspace budget")
+                    help="about this many positions per batch (0 = all at once): sets the plan's workspace "
+                         "budget; the log reports the batch the plan chose")
     ap.add_argument("--no-time-to-loss", action="store_true",
                     help="skip the learned-initialisation run (generation, training, time to loss)")
     ap.add_argument("--ttl-train", type=int, default=1000, help="training specimens of the time-to-loss run")
@@ -277,8 +278,11 @@ def main():
         pb, keep = abi.make_problem(geo.n, geo.obj_h, geo.obj_w, geo.n_slices, geo.positions(), geo.gaps(),
                                     geo.pixel_size, geo.wavelength)
         full = abi.workspace_size(pb)
-        n2 = geo.n * geo.n
-        per_pos = geo.n_slices * n2 * 8 + n2 * 8 + n2 * 4 + 8
+        # bytes a position adds, as the library counts them: the mean over the problem against
+        # a one-position problem (a second position alone also adds shift classes and partials)
+        p1, keep1 = abi.make_problem(geo.n, geo.obj_h, geo.obj_w, geo.n_slices, geo.positions()[:1],
+                                     geo.gaps(), geo.pixel_size, geo.wavelength)
+        per_pos = (full - abi.workspace_size(p1)) // max(geo.n_pos - 1, 1)
         budget = full - (geo.n_pos - args.batch) * per_pos
     plan = abi.Plan.from_geometry(geo, budget_bytes=budget, device=dev)
     log(f"bench: {plan.batch} positions per batch")
