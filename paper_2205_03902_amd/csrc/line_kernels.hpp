@@ -83,10 +83,13 @@ __device__ __forceinline__ void gstore(const float2 (&v)[16], float2 *dst, int l
 // Column-resident launches move their 16 columns of an image through LDS, so that global
 // accesses are rows of 16 consecutive columns (128 contiguous bytes) instead of 32-byte pieces
 // of 16 rows per wavefront.  Column c of the tile lives at c * LD (the line's own exchange
-// region) with its rows XOR-swizzled by 4 ((c / 2) mod 4): the row-wise fill and the
-// column-wise reads then each spread over all banks.  tile_fill / tile_drain are collective
-// (every lane of the workgroup calls them; they synchronise the workgroup).
-__device__ __forceinline__ int tile_swz(int c) { return 4 * ((c >> 1) & 3); }
+// region) with its rows XOR-swizzled by c (the low four bits of the row index; a row stays in
+// its block of 16).  The 16 lanes that fill one row then hit 16 distinct bank pairs whatever
+// LD mod 16 is, and the lanes of one column read 16 distinct rows mod 16: no bank conflicts at
+// N = 64, 128, 256 (with 4 * ((c / 2) mod 4) the fill and drain were 4-way conflicted).
+// tile_fill / tile_drain are collective (every lane of the workgroup calls them; they
+// synchronise the workgroup).
+__device__ __forceinline__ int tile_swz(int c) { return c & 15; }
 
 template <int N, class F>
 __device__ __forceinline__ void tile_fill(float2 *tile, F load)
