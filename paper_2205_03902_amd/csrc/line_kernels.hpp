@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LinePa
     constexpr size_t NN = (size_t)N * N;
     __shared__ float2 xbuf[kLinesPerGroup * Wn::LD];
     __shared__ float2 s_tw[Wn::TW_WORDS];
-    __shared__ float2 s_h[2 * N];
+    __shared__ float2 s_h[N];
     __shared__ double red[(NT + 63) / 64];
 
     const int tid = threadIdx.x;
@@ -295,8 +295,9 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LinePa
     const float2 *probe = p.class_probe + (size_t)cls * NN;
     const float2 *hown = ROW ? p.hx : p.hy;
 
-    // tables for this launch: twiddles, the own-axis factor of the gap that is finished
-    // (s_h) and of the gap that is started (s_h + N)
+    // tables for this launch: twiddles, and the own-axis factor of the gap that is finished,
+    // later replaced by that of the gap that is started (one table of N: with 4 workgroups of
+    // this kernel a CU's LDS holds, not 3)
     for (int i = tid; i < Wn::TW_WORDS; i += NT) s_tw[i] = p.tw[i];
     int g_fin = -1, g_start = -1;
     if (stage == kStageForward) {
@@ -306,10 +307,19 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LinePa
         g_fin = (m + 1 < M) ? m : -1;
         g_start = m - 1;
     }
-    if (g_fin >= 0)
-        for (int i = tid; i < N; i += NT) s_h[i] = hown[p.gap_table[g_fin] * N + i];
-    if (g_start >= 0)
-        for (int i = tid; i < N; i += NT) s_h[N + i] = hown[p.gap_table[g_start] * N + i];
+    auto load_h = [&](int g) {
+        for (int i = tid; i < N; i += NT) s_h[i] = hown[p.gap_table[g] * N + i];
+    };
+    // before the second propagation of a launch: every lane is done with the first table
+    auto next_h = [&]() {
+        if (g_fin >= 0) {
+            __syncthreads();
+            load_h(g_start);
+            __syncthreads();
+        }
+    };
+    if (g_fin >= 0) load_h(g_fin);
+    else if (g_start >= 0) load_h(g_start);
     __syncthreads();
 
     const LinePos q{line, lloc, j, (int)blockIdx.x * kLinesPerGroup};
@@ -328,7 +338,8 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LinePa
             line_store_abs2<N, ROW, false>(v, p.overlap_patch + ((size_t)b * M + m) * NN, q, xbuf);
         line_patch<N, ROW, false>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, q, xbuf);
         if (m + 1 < M) {
-            prop_axis<N, false>(v, s_tw, xb, s_h + N, j);
+            next_h();
+            prop_axis<N, false>(v, s_tw, xb, s_h, j);
             line_store<N, ROW, false>(v, A, q, xbuf);
         } else {
             if (mode == kForward && p.exit_waves) line_store<N, ROW, false>(v, p.exit_waves + (size_t)s * NN, q, xbuf);
@@ -398,7 +409,8 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LinePa
     if (!go_on) return;
     line_patch<N, ROW, true>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, q, xbuf);
     if (m > 0) {
-        prop_axis<N, true>(v, s_tw, xb, s_h + N, j);
+        next_h();
+        prop_axis<N, true>(v, s_tw, xb, s_h, j);
         line_store<N, ROW, false>(v, A, q, xbuf);
     } else if (p.probe_patch) {
         line_store<N, ROW, false>(v, p.probe_patch + (size_t)b * NN, q, xbuf);
