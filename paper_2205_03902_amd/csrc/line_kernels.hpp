@@ -97,8 +97,15 @@ __device__ __forceinline__ void tile_fill(float2 *tile, F load)
     constexpr int RP = kLinesPerGroup * Win<N>::R / 16;
     const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4, sw = tile_swz(c);
     __syncthreads();
-#pragma unroll 4
-    for (int r = r0; r < N; r += RP) tile[c * Win<N>::LD + (r ^ sw)] = load(r, c);
+    constexpr int K = N / RP, G = K < 8 ? K : 8;   // G loads in flight before their LDS writes
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += G) {
+        float2 buf[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) buf[k] = load(r0 + (k0 + k) * RP, c);
+#pragma unroll
+        for (int k = 0; k < G; ++k) tile[c * Win<N>::LD + ((r0 + (k0 + k) * RP) ^ sw)] = buf[k];
+    }
     __syncthreads();
 }
 
@@ -269,7 +276,9 @@ __device__ __forceinline__ double group_sum(double x, double *red)
 }
 
 template <int N, bool ROW>
-__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R) void line_kernel(LineParams p, int stage)
+// At least 4 waves a SIMD (128 VGPRs): four workgroups a CU, as the LDS allows.  The column
+// kernel gives up a few registers to spills for it, and for 8 tile loads in flight.
+__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(LineParams p, int stage)
 {
     using Wn = Win<N>;
     constexpr int R = Wn::R;
