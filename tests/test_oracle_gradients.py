@@ -146,3 +146,82 @@ def test_step_size_equals_inverse_spectral_norm_for_unit_slices(orc, layer):
     qn2b = np.linalg.norm(_dense_q(f2, gs, parts, layer), 2) ** 2
     _, _, mu2 = md.layer_step(probe, sl2, meas, layer, 1)
     assert mu2 * qn2b <= 1 + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# The probe's measurement matrix Q_p (Sec. 3.5): Psi^s = F O_M G_{M-1} ... G_1 O_1 Sh_s p, Sh_s the
+# sub-pixel shift of the probe (a phase ramp on its spectrum), stacked over the positions of a subset.
+
+def _dense_shift(n, fy, fx):
+    """N^2 x N^2 sub-pixel shift: F^{-1} diag(exp(-2 pi i (k_y f_y + k_x f_x) / N)) F, k signed with the
+    Nyquist bin at -N/2, written from the definition (no library FFT)."""
+    k = np.array([i if i < n // 2 else i - n for i in range(n)], dtype=float)
+    f1 = np.exp(-2j * np.pi * np.outer(np.arange(n), np.arange(n)) / n)
+    f2 = np.kron(f1, f1)
+    ramp = np.exp(-2j * np.pi * (np.add.outer(k * fy, k * fx)) / n).reshape(-1)
+    return (np.conj(f2) / (n * n)) @ np.diag(ramp) @ f2
+
+
+def _dense_qp(orc, n, obj, slices, pos, dz, subset):
+    f1 = np.exp(-2j * np.pi * np.outer(np.arange(n), np.arange(n)) / n)
+    f2 = np.kron(f1, f1)
+    gs = [(np.conj(f2) / (n * n)) @ np.diag(orc.propagator(n, 0.2, 0.0487, d).reshape(-1)) @ f2 for d in dz]
+    blocks = []
+    for s in subset:
+        py, px = pos[s]
+        iy, ix = int(np.floor(py)), int(np.floor(px))
+        idx = np.array([((iy + i) % obj) * obj + (ix + j) % obj for i in range(n) for j in range(n)])
+        r = np.diag(slices[0].reshape(-1)[idx])
+        for m in range(1, len(slices)):
+            r = np.diag(slices[m].reshape(-1)[idx]) @ gs[m - 1] @ r
+        blocks.append(f2 @ r @ _dense_shift(n, py - iy, px - ix))
+    return np.vstack(blocks)
+
+
+@pytest.mark.parametrize("subset", [None, [2], [0, 3, 4]])
+def test_probe_step_size_equals_inverse_spectral_norm_for_unit_slices(orc, subset):
+    """For unit-modulus slices Q_p^H Q_p = N^2 |subset| I, so the probe step
+    mu_p = 1 / (N^2 |subset| prod_m max|t_m|^2) is exactly ||Q_p||^{-2} (Sec. 3.2 step rule applied to the
+    probe step of Sec. 3.5); with a slice of non-unit modulus it is smaller than ||Q_p||^{-2}."""
+    n, obj, m = 4, 6, 3
+    rng = np.random.default_rng(40 + (0 if subset is None else len(subset)))
+    pos = np.array([[0.0, 0.0], [1.5, 2.0], [4.0, 5.5], [5.25, 1.0], [2.0, 3.75]])
+    dz = [2.0, 3.0]
+    sub = list(range(len(pos))) if subset is None else subset
+    sl = np.exp(1j * rng.uniform(0, 2, (m, obj, obj)))
+    probe = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    meas = rng.uniform(0, 4, (len(pos), n, n))
+    md = orc.Model(n, obj, obj, m, pos, np.array(dz), 0.2, 0.0487)
+    qn2 = np.linalg.norm(_dense_qp(orc, n, obj, sl, pos, dz, sub), 2) ** 2
+    assert abs(qn2 / (n * n * len(sub)) - 1) < 1e-12
+    _, _, mu = md.probe_step(probe, sl, meas, subset, 1)
+    assert abs(mu * qn2 - 1) < 1e-10
+    sl2 = sl.copy()
+    sl2[1] *= rng.uniform(0.2, 1.3, (obj, obj))
+    qn2b = np.linalg.norm(_dense_qp(orc, n, obj, sl2, pos, dz, sub), 2) ** 2
+    _, _, mu2 = md.probe_step(probe, sl2, meas, subset, 1)
+    assert mu2 * qn2b <= 1 + 1e-12
+    assert mu2 * qn2b < 0.999          # strictly below: the bound is not tight here
+
+
+def test_probe_gradient_equals_dense_amplitude_flow(orc):
+    """dL/d conj(p) = Q_p^H (Q_p p - sqrt(y) o phase(Q_p p)) (Sec. 3.2, Sec. 3.5), with sub-pixel shifts
+    and general complex slices."""
+    n, obj, m = 4, 6, 3
+    rng = np.random.default_rng(50)
+    pos = np.array([[0.0, 0.0], [1.5, 2.0], [4.0, 5.5], [5.25, 1.0]])
+    dz = [2.0, 3.0]
+    sl = rng.standard_normal((m, obj, obj)) + 1j * rng.standard_normal((m, obj, obj))
+    probe = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    meas = rng.uniform(0, 4, (len(pos), n, n))
+    md = orc.Model(n, obj, obj, m, pos, np.array(dz), 0.2, 0.0487)
+    for sub in ([0, 1, 2, 3], [1, 3]):
+        q = _dense_qp(orc, n, obj, sl, pos, dz, sub)
+        qz = q @ probe.reshape(-1)
+        y = meas[sub].reshape(-1)
+        phase = qz / np.abs(qz)
+        grad = np.conj(q.T) @ (qz - phase * np.sqrt(y))
+        loss = np.sum((np.sqrt(y) - np.abs(qz)) ** 2)
+        l2, _, gp, _ = md.loss_grad(probe, sl, meas, subset=sub, want_slices=False)
+        assert abs(l2 - loss) < 1e-10 * loss
+        assert np.abs(gp.reshape(-1) - grad).max() < 1e-10 * np.abs(grad).max()
