@@ -8,6 +8,10 @@ deterministic scatter of the per-position gradients into every slice, the
 probe-gradient reduction and the FP64 loss.  The metric counts
 S * M position-slice forward+adjoint updates per step.
 
+The headline workload is the largest single-GPU one: 256 x 256 windows, a
+1024 x 1024 object of 12 slices and 16384 scan positions (line kernels).  The
+128 x 128 workload (fused kernel) is reported beside it.
+
 Prints ONE JSON line.  Also reported (outside the timed region): one
 Algorithm 1 sweep (M layer steps and one probe step) and one forward pass.
 """
@@ -28,29 +32,34 @@ METRIC = "position-slice fwd+adjoint updates/s; time-to-loss, learned init vs pl
 UNIT = "position-slice fwd+adjoint updates/s"
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 ALU_PEAK = 78.6e12           # FP32 FMA flop/s without packed FP32: 256 CU x 64 lanes x 2 x 2.4 GHz
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_adjoint_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2205_03902_amd", "csrc", f)
-                  for f in ("ms_kernels.hpp", "fft_lines.hpp")]
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2205_03902_amd", "csrc")
+# the sources of each per-position kernel family (a traffic record is valid for these only)
+KERNEL_SOURCES = {"fused": ["ms_kernels.hpp", "fft_lines.hpp"],
+                  "lines": ["line_kernels.hpp", "ms_kernels.hpp", "fft_lines.hpp"]}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(family: str) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
+    for f in KERNEL_SOURCES[family]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def model_per_launch(geo):
-    """Algorithmic bytes and flops of one fused adjoint launch over all positions.
+    """Algorithmic bytes and flops of the per-position kernels of one adjoint pass over all
+    positions (one fused launch, or the 2M + 1 line launches).
 
     Bytes per position: measured intensities 4 N^2, incident waves stored and
     reloaded 2 (M-1) 8 N^2, slice-gradient patches M 8 N^2, probe-gradient
-    patch 8 N^2 (object-patch gathers are cache reuse and not counted).
+    patch 8 N^2 (object-patch gathers are cache reuse and not counted; so is the
+    half-propagated window the line kernels pass between their launches, which a
+    window held on chip would not need).
     Flops per position: (4M - 2) 2D FFTs of 10 N^2 log2 N, plus 30 N^2 M
     pointwise (transmission, propagator, gradient products) and 20 N^2 for the
     modulus residual.
@@ -68,20 +77,29 @@ def pass_bytes(geo):
     return (32 * n2 * geo.n_slices + 4 * n2) * geo.n_pos + 24 * geo.obj_h * geo.obj_w * geo.n_slices
 
 
-def traffic_record():
-    """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernel source."""
+def traffic_file(geo, family: str) -> str:
+    return os.path.join(PROFILES, f"{family}_adjoint_traffic_{geo.name}.json")
+
+
+def traffic_record(geo, family: str):
+    """HBM bytes per pass of the per-position kernels, measured with rocprofv3 counters on this
+    workload and on the current kernel sources; None for any other workload, path or source."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(geo, family)) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("workload") != geo.name or rec.get("family") != family:
         return None
-    return rec.get("bytes_per_launch")
+    if rec.get("kernel_source_hash") != kernel_source_hash(family):
+        return None
+    return rec.get("bytes_per_pass")
 
 
-def cpu_baseline(geo, n_sample: int):
-    """The FP64 oracle on a sample of the same workload (one fwd+adj pass over n_sample positions)."""
+def cpu_baseline(geo, n_sample: int, truth=None):
+    """The FP64 oracle on a sample of the same workload (one fwd+adj pass over n_sample evenly
+    spaced positions).  The rate is per position-slice update, so it carries over to the whole
+    workload linearly (each position's chain is independent; the scatter is a small part)."""
     import numpy as np
 
     import oracle
@@ -90,16 +108,21 @@ def cpu_baseline(geo, n_sample: int):
     pick = np.linspace(0, geo.n_pos - 1, n_sample).round().astype(int)
     md = oracle.Model.from_geometry(geo, positions=pos[pick])
     probe = oracle.probe(geo.n, geo.pixel_size, geo.wavelength, geo.alpha, geo.defocus)
-    truth = synth.transmissions(synth.specimen(geo))
-    meas = synth.poisson_counts(md.forward(probe, truth), geo.dose, geo.seed + 1)
+    if truth is None:
+        truth = synth.transmissions(synth.specimen(geo))
+    meas = md.forward(probe, truth)
+    if geo.dose > 0:
+        meas = synth.poisson_counts(meas, geo.dose, geo.seed + 1)
     start = np.ones_like(truth)
     t0 = time.perf_counter()
     md.loss_grad(probe, start, meas)
     secs = time.perf_counter() - t0
+    sample = (f"{n_sample} of {geo.n_pos} positions (evenly spaced), one fwd+adj pass, {secs:.2f} s wall, FP64")
+    if n_sample < geo.n_pos:
+        sample += (f"; the whole pass extrapolated linearly: {secs * geo.n_pos / n_sample:.0f} s")
     return {"value": n_sample * geo.n_slices / secs, "unit": UNIT, "cores": oracle.max_threads(),
-            "kind": "oracle", "cpu": cpu_model(),
-            "sample": f"{n_sample} of {geo.n_pos} positions (evenly spaced), one fwd+adj pass, "
-                      f"{secs:.2f} s wall, FP64"}
+            "kind": "oracle", "cpu": cpu_model(), "sample": sample,
+            "extrapolated": n_sample < geo.n_pos}
 
 
 def cpu_model() -> str:
@@ -227,24 +250,107 @@ def device_record():
     return rec
 
 
+def time_adjoint(geo, steps: int, warmup: int, dev, batch: int = 0):
+    """Plan, inputs and `steps` timed adjoint passes of one workload.  Inputs are resident in HBM
+    before the timed region: the probe and measured patterns are made on the GPU (the probe of
+    the 10 %-longer defocus is the start, slices t = 1)."""
+    import torch
+    from paper_2205_03902_amd import abi, datagen, synth
+    log(f"bench: {geo.name} N={geo.n} H=W={geo.obj_h} M={geo.n_slices} S={geo.n_pos}")
+    budget = 0
+    if batch and batch < geo.n_pos:
+        # workspace of a plan whose batches hold `batch` positions
+        pb, keep = abi.make_problem(geo.n, geo.obj_h, geo.obj_w, geo.n_slices, geo.positions(), geo.gaps(),
+                                    geo.pixel_size, geo.wavelength)
+        full = abi.workspace_size(pb)
+        # bytes a position adds, as the library counts them: the mean over the problem against
+        # a one-position problem (a second position alone also adds shift classes and partials)
+        p1, keep1 = abi.make_problem(geo.n, geo.obj_h, geo.obj_w, geo.n_slices, geo.positions()[:1],
+                                     geo.gaps(), geo.pixel_size, geo.wavelength)
+        per_pos = (full - abi.workspace_size(p1)) // max(geo.n_pos - 1, 1)
+        budget = full - (geo.n_pos - batch) * per_pos
+    plan = abi.Plan.from_geometry(geo, budget_bytes=budget, device=dev)
+    log(f"bench: {plan.batch} positions per batch")
+    probe_true = plan.make_probe(geo.alpha, geo.defocus)
+    truth_np = synth.transmissions(synth.specimen(geo))
+    truth = torch.from_numpy(truth_np).to(dev)
+    inten = plan.forward(probe_true, truth)
+    measured = datagen.poisson(inten, geo.dose, seed=geo.seed + 1, stream_id=0) if geo.dose > 0 else inten
+    del inten
+    slices = torch.ones((geo.n_slices, geo.obj_h, geo.obj_w), dtype=torch.complex64, device=dev)
+    probe = plan.make_probe(geo.alpha, 1.1 * geo.defocus)
+    gs = torch.empty_like(slices)
+    gp = torch.empty_like(probe)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        plan.adjoint(probe, slices, measured, grad_slices=gs, grad_probe=gp, loss=loss)
+    torch.cuda.synchronize()
+    # HIP events on the stream every launch is enqueued on
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.profile_begin(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.adjoint(probe, slices, measured, grad_slices=gs, grad_probe=gp, loss=loss)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms, launches = plan.profile_end()
+    ms = e0.elapsed_time(e1) / steps
+    kern = kern_ms / max(launches, 1)
+    family = "lines" if geo.n > 128 else "fused"
+    log(f"bench: {steps} steps, {ms:.3f} ms/step (events), {wall * 1e3 / steps:.3f} ms/step (wall), "
+        f"{family} kernels {kern:.3f} ms per pass x {launches}, loss {loss.item():.6e}")
+    return {"plan": plan, "probe": probe, "slices": slices, "measured": measured, "truth": truth,
+            "truth_np": truth_np, "gs": gs, "gp": gp, "ms": ms, "kernel_ms": kern, "family": family,
+            "loss": loss.item(), "batch": plan.batch}
+
+
+def roofline(geo, family: str, kernel_ms: float):
+    """Roofline record of the per-position kernels of one pass (the dominant kernel family)."""
+    byt, flo = model_per_launch(geo)
+    k_s = kernel_ms * 1e-3
+    hbm = {"bound": "hbm", "achieved": byt / k_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    hbm["frac"] = hbm["achieved"] / hbm["peak"]
+    alu = {"bound": "alu", "achieved": flo / k_s / 1e12, "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s"}
+    alu["frac"] = alu["achieved"] / alu["peak"]
+    roof = dict(alu if alu["frac"] >= hbm["frac"] else hbm)
+    other = hbm if roof["bound"] == "alu" else alu
+    roof["traffic"] = traffic_record(geo, family)
+    if family == "fused":
+        roof["kernel"] = f"fused_kernel<{geo.n}, adjoint> (one launch per pass)"
+    else:
+        roof["kernel"] = (f"line_kernel<{geo.n}, row|column> (the {2 * geo.n_slices + 1} launches of one pass, "
+                          f"timed together)")
+    roof["kernel_ms"] = kernel_ms
+    roof["other"] = {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    roof["algorithmic_bytes_per_launch"] = byt
+    roof["algorithmic_flops_per_launch"] = flo
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=1, help="workload geometry (0..4)")
+    ap.add_argument("--config", type=int, default=4, help="workload geometry (0..4); 4 is the headline")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="positions in the oracle's timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the sweep and forward timings")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 128 x 128 workload's line")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
                     help="about this many positions per batch (0 = all at once): sets the plan's workspace "
                          "budget; the log reports the batch the plan chose")
     ap.add_argument("--no-time-to-loss", action="store_true",
                     help="skip the learned-initialisation run (generation, training, time to loss)")
-    ap.add_argument("--ttl-train", type=int, default=1000, help="training specimens of the time-to-loss run")
-    ap.add_argument("--ttl-test", type=int, default=20, help="held-out specimens of the time-to-loss run")
-    ap.add_argument("--ttl-epochs", type=int, default=12, help="training epochs of the time-to-loss run")
+    ap.add_argument("--ttl-train", type=int, default=2000, help="training specimens of the time-to-loss run")
+    ap.add_argument("--ttl-test", type=int, default=100, help="held-out specimens of the time-to-loss run")
+    ap.add_argument("--ttl-epochs", type=int, default=20, help="training epochs of the time-to-loss run")
     ap.add_argument("--algorithm2-only", type=int, default=0, metavar="N",
                     help="time only Algorithm 2 at window N (M = 3) and print its JSON")
     args = ap.parse_args()
@@ -266,78 +372,19 @@ def main():
         print(json.dumps(algorithm2_benchmark(args.algorithm2_only, 3)), flush=True)
         return
 
-    from paper_2205_03902_amd import abi, configs, datagen, layerwise, synth
+    from paper_2205_03902_amd import configs, layerwise
+    from paper_2205_03902_amd import abi
     geo = configs.CONFIGS[args.config]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log(f"bench: {geo.name} N={geo.n} H=W={geo.obj_h} M={geo.n_slices} S={geo.n_pos}")
 
-    budget = 0
-    if args.batch and args.batch < geo.n_pos:
-        # workspace of a plan whose batches hold args.batch positions
-        pb, keep = abi.make_problem(geo.n, geo.obj_h, geo.obj_w, geo.n_slices, geo.positions(), geo.gaps(),
-                                    geo.pixel_size, geo.wavelength)
-        full = abi.workspace_size(pb)
-        # bytes a position adds, as the library counts them: the mean over the problem against
-        # a one-position problem (a second position alone also adds shift classes and partials)
-        p1, keep1 = abi.make_problem(geo.n, geo.obj_h, geo.obj_w, geo.n_slices, geo.positions()[:1],
-                                     geo.gaps(), geo.pixel_size, geo.wavelength)
-        per_pos = (full - abi.workspace_size(p1)) // max(geo.n_pos - 1, 1)
-        budget = full - (geo.n_pos - args.batch) * per_pos
-    plan = abi.Plan.from_geometry(geo, budget_bytes=budget, device=dev)
-    log(f"bench: {plan.batch} positions per batch")
-    probe_true = plan.make_probe(geo.alpha, geo.defocus)
-    truth = torch.from_numpy(synth.transmissions(synth.specimen(geo))).to(dev)
-    inten = plan.forward(probe_true, truth)
-    if geo.dose > 0:
-        measured = datagen.poisson(inten, geo.dose, seed=geo.seed + 1, stream_id=0)
-    else:
-        measured = inten
-    # plain start (identity slices) and the 10 %-longer-defocus probe start
-    slices = torch.ones((geo.n_slices, geo.obj_h, geo.obj_w), dtype=torch.complex64, device=dev)
-    probe = plan.make_probe(geo.alpha, 1.1 * geo.defocus)
-    gs = torch.empty_like(slices)
-    gp = torch.empty_like(probe)
-    loss = torch.empty(1, dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
-
-    for _ in range(args.warmup):
-        plan.adjoint(probe, slices, measured, grad_slices=gs, grad_probe=gp, loss=loss)
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    plan.profile_begin(args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        plan.adjoint(probe, slices, measured, grad_slices=gs, grad_probe=gp, loss=loss)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms, launches = plan.profile_end()
-    ms = e0.elapsed_time(e1) / args.steps
-    log(f"bench: {args.steps} steps, {ms:.3f} ms/step (events), {wall * 1e3 / args.steps:.3f} ms/step (wall), "
-        f"fused kernel {kern_ms / max(launches, 1):.3f} ms x {launches}, loss {loss.item():.6e}")
-
+    run = time_adjoint(geo, args.steps, args.warmup, dev, args.batch)
+    plan, probe, slices, measured = run["plan"], run["probe"], run["slices"], run["measured"]
+    gs, gp, truth = run["gs"], run["gp"], run["truth"]
+    ms = run["ms"]
+    batch = run["batch"]
     value = geo.n_pos * geo.n_slices / (ms * 1e-3)
-    byt, flo = model_per_launch(geo)
-    k_s = kern_ms / max(launches, 1) * 1e-3
-    hbm = {"bound": "hbm", "achieved": byt / k_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
-    hbm["frac"] = hbm["achieved"] / hbm["peak"]
-    alu = {"bound": "alu", "achieved": flo / k_s / 1e12, "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s"}
-    alu["frac"] = alu["achieved"] / alu["peak"]
-    roof = dict(alu if alu["frac"] >= hbm["frac"] else hbm)
-    other = hbm if roof["bound"] == "alu" else alu
-    traffic = traffic_record()
-    roof["traffic"] = traffic
-    roof["kernel"] = f"fused_kernel<{geo.n}, adjoint>" if geo.n <= 128 else \
-        f"line_kernel<{geo.n}> (all launches of one adjoint pass)"
-    roof["kernel_ms"] = kern_ms / max(launches, 1)
-    roof["other"] = {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
-    roof["algorithmic_bytes_per_launch"] = byt
-    roof["algorithmic_flops_per_launch"] = flo
+    roof = roofline(geo, run["family"], run["kernel_ms"])
 
     extras = {}
     if not args.no_extras:
@@ -359,9 +406,10 @@ def main():
         # pixels some window covers, before and after the sweep
         cover = coverage_mask(geo, geo.positions())
         mask_t = torch.from_numpy(cover).to(dev)
-        e0 = abi.reconstruction_error(slices, truth, mask_t)
-        e1 = abi.reconstruction_error(sl, truth, mask_t)
-        extras["recon_error_start_after_sweep"] = [e0[-1].item(), e1[-1].item()]
+        r0 = abi.reconstruction_error(slices, truth, mask_t)
+        r1 = abi.reconstruction_error(sl, truth, mask_t)
+        extras["recon_error_start_after_sweep"] = [r0[-1].item(), r1[-1].item()]
+        del sl, pr
         # the full-gradient (Jacobi) variant from the same start: 4 steps against one sweep,
         # with the layer steps as they are and averaged (step scale 1/M)
         end = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -378,10 +426,12 @@ def main():
             extras[f"{tag}_ms"] = (time.perf_counter() - t0f) * 1e3 / 4
             plan.adjoint(probe, sl, measured, grad_slices=gs, grad_probe=gp, loss=end)
             extras[f"{tag}_losses"] = [x.item() for x in losses] + [end.item()]
+            del sl
         sl2 = slices.clone()
-        h2 = layerwise.reconstruct(plan, probe.clone(), sl2, measured, sweeps=1)
+        layerwise.reconstruct(plan, probe.clone(), sl2, measured, sweeps=1)
         plan.adjoint(probe, sl2, measured, grad_slices=gs, grad_probe=gp, loss=end)
         extras["sweep_loss_after"] = end.item()
+        del sl2
         extras["pass_model_bytes"] = pass_bytes(geo)
         # scan-position gradient and curvature bound over all positions (a probe-mode pass)
         gpos = torch.empty((geo.n_pos, 2), dtype=torch.float64, device=dev)
@@ -397,13 +447,28 @@ def main():
         extras["algorithm2"] = [algorithm2_benchmark(32, 3, cpu_baseline=not args.no_cpu_baseline),
                                 algorithm2_benchmark(64, 3)]
 
+    truth_np = run["truth_np"]
+    del run, plan, probe, slices, measured, gs, gp, truth
+    torch.cuda.empty_cache()
+    if not args.no_secondary and args.config != 1:
+        # the 128 x 128 workload on the fused kernel, beside the headline
+        g1 = configs.CFG1
+        r1 = time_adjoint(g1, args.steps, args.warmup, dev)
+        extras["cfg1"] = {"workload": f"{g1.name}: {g1.n}x{g1.n} window, {g1.obj_h}x{g1.obj_w} object, "
+                                      f"{g1.n_slices} slices, {g1.n_pos} positions",
+                          "value": g1.n_pos * g1.n_slices / (r1["ms"] * 1e-3), "unit": UNIT,
+                          "ms_per_step": r1["ms"], "roofline": roofline(g1, r1["family"], r1["kernel_ms"])}
+        del r1
+        torch.cuda.empty_cache()
+
     out = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{geo.name}: {geo.n}x{geo.n} window, {geo.obj_h}x{geo.obj_w} object, "
                                   f"{geo.n_slices} slices, {geo.n_pos} positions",
                       "n": geo.n, "obj": geo.obj_h, "slices": geo.n_slices, "positions": geo.n_pos,
-                      "parallelism": "single GPU, positions in one batch"},
+                      "parallelism": "single GPU, " + ("positions in one batch" if batch == geo.n_pos
+                                                       else f"{batch} positions per batch")},
            "roofline": roof}
     out.update(extras)
     if not args.no_time_to_loss:
@@ -412,12 +477,12 @@ def main():
         res = learned_init.main(["--train", str(args.ttl_train), "--test", str(args.ttl_test),
                                  "--epochs", str(args.ttl_epochs)], log=log)
         out["time_to_loss"] = dict(res["time_to_loss"], workload=res["workload"], train=res["train"],
-                                   epochs=res["epochs"], sweeps=res["sweeps"], generation_s=res["generation_s"],
-                                   training_s=res["training_s"], heldout_loss=res["heldout_loss"][-1:],
-                                   unet=res["unet"])
+                                   test=args.ttl_test, epochs=res["epochs"], sweeps=res["sweeps"],
+                                   generation_s=res["generation_s"], training_s=res["training_s"],
+                                   heldout_loss=res["heldout_loss"][-1:], unet=res["unet"])
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(geo, min(args.cpu_sample, geo.n_pos))
+        out["cpu_baseline"] = cpu_baseline(geo, min(args.cpu_sample, geo.n_pos), truth=truth_np)
     print(json.dumps(out), flush=True)
 
 

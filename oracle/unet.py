@@ -36,7 +36,7 @@ def conv2d(x, w, b=None, pad=1):
     for u in range(kh):
         for v in range(kw):
             patch = xp[:, :, u:u + ho, v:v + wo]                       # (n, c, ho, wo)
-            y += np.einsum("oc,ncij->noij", w[:, :, u, v], patch)
+            y += np.einsum("oc,ncij->noij", w[:, :, u, v], patch, optimize=True)
     if b is not None:
         y += b[None, :, None, None]
     return y
@@ -53,8 +53,8 @@ def conv2d_backward(x, w, dy, pad=1):
     for u in range(kh):
         for v in range(kw):
             patch = xp[:, :, u:u + ho, v:v + wo]
-            dw[:, :, u, v] = np.einsum("noij,ncij->oc", dy, patch)
-            dxp[:, :, u:u + ho, v:v + wo] += np.einsum("oc,noij->ncij", w[:, :, u, v], dy)
+            dw[:, :, u, v] = np.einsum("noij,ncij->oc", dy, patch, optimize=True)
+            dxp[:, :, u:u + ho, v:v + wo] += np.einsum("oc,noij->ncij", w[:, :, u, v], dy, optimize=True)
     dx = dxp[:, :, pad:pad + h, pad:pad + wd]
     db = dy.sum(axis=(0, 2, 3))
     return dx, dw, db
@@ -89,7 +89,7 @@ def conv_transpose2(x, w, b=None):
     y = np.zeros((n, cout, 2 * h, 2 * wd))
     for u in range(2):
         for v in range(2):
-            y[:, :, u::2, v::2] = np.einsum("co,ncij->noij", w[:, :, u, v], x)
+            y[:, :, u::2, v::2] = np.einsum("co,ncij->noij", w[:, :, u, v], x, optimize=True)
     if b is not None:
         y += b[None, :, None, None]
     return y
@@ -101,8 +101,8 @@ def conv_transpose2_backward(x, w, dy):
     for u in range(2):
         for v in range(2):
             g = dy[:, :, u::2, v::2]
-            dx += np.einsum("co,noij->ncij", w[:, :, u, v], g)
-            dw[:, :, u, v] = np.einsum("ncij,noij->co", x, g)
+            dx += np.einsum("co,noij->ncij", w[:, :, u, v], g, optimize=True)
+            dw[:, :, u, v] = np.einsum("ncij,noij->co", x, g, optimize=True)
     return dx, dw, dy.sum(axis=(0, 2, 3))
 
 

@@ -138,3 +138,25 @@ def test_config4_full_size_forward_and_batched_adjoint(dev):
     ls, _, _ = sub_plan.adjoint(p, s, ms)
     ref = sub.loss(probe, start, ms.cpu().numpy())
     assert abs(ls.item() - ref) / ref < 1e-5
+
+
+def test_config4_block_gradients_match_the_oracle(dev):
+    """Config 4's 12-slice chain on the line kernels against the FP64 oracle: loss, every slice
+    gradient and the probe gradient of a 16-position block (a 4 x 4 piece of the raster in the
+    object's interior, plus windows moved across the object's edges so that the patches wrap)."""
+    from paper_2205_03902_amd import abi, configs
+    geo = configs.CFG4
+    pos = geo.positions()
+    block = pos[[8256, 8257, 8258, 8259, 8384, 8385, 8386, 8387, 8512, 8513, 8514, 8515, 8640, 8641, 8642, 8643]]
+    block[3] = (geo.obj_h - 100.0, geo.obj_w - 37.0)      # wraps through the bottom-right corner
+    block[12] = (-20.0, 500.0)                             # wraps through the top edge
+    print(f"[case] config 4 block: 16 positions, M={geo.n_slices}", flush=True)
+    c = make_case(geo, positions=block)
+    plan = abi.Plan.from_geometry(geo, positions=block, device=dev)
+    loss, gs, gp = plan.adjoint(_t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev))
+    ref_l, ref_gs, ref_gp, _ = c.model.loss_grad(c.probe, c.start, c.measured)
+    el, egs, egp = abs(loss.item() - ref_l) / ref_l, rel(gs.cpu().numpy(), ref_gs), rel(gp.cpu().numpy(), ref_gp)
+    per_slice = [rel(gs[m].cpu().numpy(), ref_gs[m]) for m in range(geo.n_slices)]
+    print(f"config 4 block: loss {el:.2e} grad slices {egs:.2e} (worst slice {max(per_slice):.2e}) probe {egp:.2e}")
+    assert el < 1e-5 and egs < 1e-4 and egp < 1e-4
+    assert max(per_slice) < 1e-4

@@ -61,7 +61,7 @@ def test_lines_layer_and_probe_steps(dev, n):
     plan = _plan(c, dev)
     p, m = _t(c.probe, dev), _t(c.measured, dev)
     out = torch.zeros(2, dtype=torch.float64, device=dev)
-    for layer in (0, c.geo.n_slices - 1):
+    for layer in range(c.geo.n_slices):            # first, middle and last layer
         s = _t(c.start, dev)
         plan.layer_step(layer, 1, p, s, m, loss=out[0:1], mu=out[1:2])
         ref_s, ref_l, ref_mu = c.model.layer_step(c.probe, c.start, c.measured, layer, 1)
