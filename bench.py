@@ -250,10 +250,11 @@ def device_record():
     return rec
 
 
-def time_adjoint(geo, steps: int, warmup: int, dev, batch: int = 0):
+def time_adjoint(geo, steps: int, warmup: int, dev, batch: int = 0, checkpoint_every: int = 0):
     """Plan, inputs and `steps` timed adjoint passes of one workload.  Inputs are resident in HBM
     before the timed region: the probe and measured patterns are made on the GPU (the probe of
-    the 10 %-longer defocus is the start, slices t = 1)."""
+    the 10 %-longer defocus is the start, slices t = 1).  checkpoint_every: which incident waves
+    the adjoint stores (1 all, M none; 0 all unless a batch budget is set)."""
     import torch
     from paper_2205_03902_amd import abi, datagen, synth
     log(f"bench: {geo.name} N={geo.n} H=W={geo.obj_h} M={geo.n_slices} S={geo.n_pos}")
@@ -269,8 +270,9 @@ def time_adjoint(geo, steps: int, warmup: int, dev, batch: int = 0):
                                      geo.gaps(), geo.pixel_size, geo.wavelength)
         per_pos = (full - abi.workspace_size(p1)) // max(geo.n_pos - 1, 1)
         budget = full - (geo.n_pos - batch) * per_pos
-    plan = abi.Plan.from_geometry(geo, budget_bytes=budget, device=dev)
-    log(f"bench: {plan.batch} positions per batch")
+    plan = abi.Plan.from_geometry(geo, budget_bytes=budget, device=dev, checkpoint_every=checkpoint_every)
+    log(f"bench: {plan.batch} positions per batch, incident waves stored every {plan.checkpoint_every} slices, "
+        f"workspace {plan.workspace_bytes / 2 ** 30:.1f} GiB")
     probe_true = plan.make_probe(geo.alpha, geo.defocus)
     truth_np = synth.transmissions(synth.specimen(geo))
     truth = torch.from_numpy(truth_np).to(dev)
@@ -289,7 +291,9 @@ def time_adjoint(geo, steps: int, warmup: int, dev, batch: int = 0):
     # HIP events on the stream every launch is enqueued on
     stream = torch.cuda.current_stream(dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    plan.profile_begin(steps)
+    # one timed region per batch for every wave stored, M + 1 per batch when waves are recomputed
+    n_batches = -(-geo.n_pos // plan.batch)
+    plan.profile_begin(steps * n_batches * (geo.n_slices + 2))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
@@ -300,13 +304,14 @@ def time_adjoint(geo, steps: int, warmup: int, dev, batch: int = 0):
     wall = time.perf_counter() - t0
     kern_ms, launches = plan.profile_end()
     ms = e0.elapsed_time(e1) / steps
-    kern = kern_ms / max(launches, 1)
+    kern = kern_ms / steps
     family = "lines" if geo.n > 128 else "fused"
     log(f"bench: {steps} steps, {ms:.3f} ms/step (events), {wall * 1e3 / steps:.3f} ms/step (wall), "
-        f"{family} kernels {kern:.3f} ms per pass x {launches}, loss {loss.item():.6e}")
+        f"{family} kernels {kern:.3f} ms per pass ({launches} timed regions), loss {loss.item():.6e}")
     return {"plan": plan, "probe": probe, "slices": slices, "measured": measured, "truth": truth,
             "truth_np": truth_np, "gs": gs, "gp": gp, "ms": ms, "kernel_ms": kern, "family": family,
-            "loss": loss.item(), "batch": plan.batch}
+            "loss": loss.item(), "batch": plan.batch, "checkpoint_every": plan.checkpoint_every,
+            "workspace_bytes": plan.workspace_bytes}
 
 
 def roofline(geo, family: str, kernel_ms: float):
@@ -341,7 +346,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024, help="positions in the oracle's timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the sweep and forward timings")
-    ap.add_argument("--no-secondary", action="store_true", help="skip the 128 x 128 workload's line")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 128 x 128 workload and the recomputed-wave run of the 10-slice workload")
+    ap.add_argument("--checkpoint-every", type=int, default=0,
+                    help="incident waves the adjoint stores: 1 all, k every k-th, >= M none (0: all unless --batch)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
                     help="about this many positions per batch (0 = all at once): sets the plan's workspace "
@@ -378,7 +386,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    run = time_adjoint(geo, args.steps, args.warmup, dev, args.batch)
+    run = time_adjoint(geo, args.steps, args.warmup, dev, args.batch, args.checkpoint_every)
     plan, probe, slices, measured = run["plan"], run["probe"], run["slices"], run["measured"]
     gs, gp, truth = run["gs"], run["gp"], run["truth"]
     ms = run["ms"]
@@ -460,6 +468,22 @@ def main():
                           "ms_per_step": r1["ms"], "roofline": roofline(g1, r1["family"], r1["kernel_ms"])}
         del r1
         torch.cuda.empty_cache()
+    if not args.no_secondary and args.config != 2:
+        # the 10-slice 256 x 256 workload with every incident wave stored and with none (each
+        # recomputed from the probe during the adjoint)
+        g2 = configs.CFG2
+        legs = {}
+        for k in (1, g2.n_slices):
+            r2 = time_adjoint(g2, max(3, args.steps // 4), 1, dev, checkpoint_every=k)
+            legs[f"checkpoint_every_{k}"] = {"ms_per_step": r2["ms"], "kernel_ms": r2["kernel_ms"],
+                                             "value": g2.n_pos * g2.n_slices / (r2["ms"] * 1e-3),
+                                             "workspace_gib": r2["workspace_bytes"] / 2 ** 30,
+                                             "loss": r2["loss"]}
+            del r2
+            torch.cuda.empty_cache()
+        extras["cfg2_waves_stored_vs_recomputed"] = dict(
+            workload=f"{g2.name}: {g2.n}x{g2.n} window, {g2.obj_h}x{g2.obj_w} object, {g2.n_slices} slices, "
+                     f"{g2.n_pos} positions", unit=UNIT, **legs)
 
     out = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",

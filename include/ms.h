@@ -77,13 +77,30 @@ typedef struct {
     double pixel_size;         /* real-space sampling dx (Angstrom), q = k / (N dx)     */
     double wavelength;         /* lambda (Angstrom)                                     */
     double tilt_y, tilt_x;     /* illumination tilts theta_y, theta_x (rad)             */
+    int32_t checkpoint_every;  /* incident waves kept for the adjoint, see below          */
 } ms_problem;
+
+/* Incident waves.  The adjoint of slice m (Sec. 3.2 pulled back through the chain of Sec. 2.1)
+ * needs the wave psi_m incident on slice m at every position of a batch.  checkpoint_every = k:
+ *   k = 1      every psi_m is stored during the forward chain (M N^2 complex values a position);
+ *   1 < k < M  only psi_k, psi_2k, ... are stored (psi_0 is the shifted probe itself); during the
+ *              adjoint, psi_m is recomputed from the nearest stored wave below it by running the
+ *              forward chain again from there (m mod k slices), and each slice's gradient patches
+ *              are scattered before the next slice is taken;
+ *   k >= M     nothing is stored: every psi_m is recomputed from the probe;
+ *   k = 0      automatic: 1, unless the workspace budget of ms_workspace_size / the workspace given
+ *              to ms_plan_create cannot hold every position's waves at once; then the smallest k
+ *              whose waves fit with all positions in one batch, and only if k = M does not fit
+ *              are positions split into batches.
+ * A larger k trades memory (floor((M - 1) / k) + 1 waves a position instead of M) for the
+ * recomputed propagations (about M (k - 1) / 2 slice steps a position instead of none).  All values give
+ * the same results up to rounding.  k < 0 returns MS_ERR_INVALID_ARG. */
 
 typedef struct ms_plan ms_plan;
 
 /* Workspace bytes for `pb`.  budget_bytes = 0 processes all positions in one
- * batch; otherwise positions are processed in the largest batches that fit
- * the budget (MS_ERR_BUDGET if not even one position fits).  Positions that share
+ * batch; otherwise the wave storage (checkpoint_every, above) and then the batch
+ * size are chosen to fit the budget (MS_ERR_BUDGET if not even one position fits).  Positions that share
  * a sub-pixel offset share one shifted probe (a shift class); at most 4096 classes
  * (MS_ERR_UNSUPPORTED beyond), each adding about 21 N^2 8 bytes. */
 ms_status ms_workspace_size(const ms_problem *pb, size_t budget_bytes, size_t *ws_bytes);
@@ -98,9 +115,11 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
  * called on before freeing the workspace.  NULL is ignored. */
 void ms_plan_destroy(ms_plan *plan);
 
-/* Positions per batch and number of probe shift classes chosen by the plan. */
+/* Positions per batch, number of probe shift classes and the wave checkpoint interval k
+ * (1 = every wave stored; M = none) chosen by the plan. */
 int64_t ms_plan_batch(const ms_plan *plan);
 int32_t ms_plan_shift_classes(const ms_plan *plan);
+int32_t ms_plan_checkpoint_every(const ms_plan *plan);
 
 /* How the per-position multislice chain is executed.  MS_PATH_FUSED keeps each
  * N x N window of one position in one workgroup for the whole chain (N <= 128);

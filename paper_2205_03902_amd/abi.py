@@ -23,7 +23,7 @@ MS_OBJECTIVE_AMPLITUDE, MS_OBJECTIVE_POISSON = 0, 1
 
 # every entry point declared in include/ms.h
 SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
-           "ms_plan_set_path", "ms_plan_set_objective",
+           "ms_plan_checkpoint_every", "ms_plan_set_path", "ms_plan_set_objective",
            "ms_make_probe", "ms_make_probe_aberrated", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_position_grad", "ms_position_step", "ms_reconstruction_error",
            "ms_profile_begin",
            "ms_profile_end", "ms_last_error")
@@ -39,7 +39,7 @@ class MsProblem(C.Structure):
     _fields_ = [("n", C.c_int32), ("obj_h", C.c_int32), ("obj_w", C.c_int32), ("n_slices", C.c_int32),
                 ("n_pos", C.c_int64), ("positions", C.c_void_p), ("dz", C.c_void_p),
                 ("pixel_size", C.c_double), ("wavelength", C.c_double),
-                ("tilt_y", C.c_double), ("tilt_x", C.c_double)]
+                ("tilt_y", C.c_double), ("tilt_x", C.c_double), ("checkpoint_every", C.c_int32)]
 
 
 _lib = None
@@ -64,6 +64,8 @@ def lib():
         L.ms_plan_batch.argtypes = [P]
         L.ms_plan_shift_classes.restype = I32
         L.ms_plan_shift_classes.argtypes = [P]
+        L.ms_plan_checkpoint_every.restype = I32
+        L.ms_plan_checkpoint_every.argtypes = [P]
         L.ms_plan_set_path.restype = I32
         L.ms_plan_set_path.argtypes = [P, I32]
         L.ms_plan_set_objective.restype = I32
@@ -132,14 +134,17 @@ def _check(status: int, what: str):
         raise MsError(status, what, lib().ms_last_error().decode())
 
 
-def make_problem(n, obj_h, obj_w, n_slices, positions, dz, pixel_size, wavelength, tilt_y=0.0, tilt_x=0.0):
-    """Returns (MsProblem, keepalive) with host arrays owned by the caller's keepalive tuple."""
+def make_problem(n, obj_h, obj_w, n_slices, positions, dz, pixel_size, wavelength, tilt_y=0.0, tilt_x=0.0,
+                 checkpoint_every=0):
+    """Returns (MsProblem, keepalive) with host arrays owned by the caller's keepalive tuple.
+    checkpoint_every: which incident waves the adjoint stores (1 all, k every k-th, >= M none,
+    0 chosen from the workspace budget; include/ms.h)."""
     pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
     dzs = np.ascontiguousarray(np.asarray(dz, dtype=np.float64).reshape(-1))
     if dzs.size == 0:
         dzs = np.zeros(1)
     pb = MsProblem(int(n), int(obj_h), int(obj_w), int(n_slices), pos.shape[0], pos.ctypes.data, dzs.ctypes.data,
-                   float(pixel_size), float(wavelength), float(tilt_y), float(tilt_x))
+                   float(pixel_size), float(wavelength), float(tilt_y), float(tilt_x), int(checkpoint_every))
     return pb, (pos, dzs)
 
 
@@ -174,12 +179,12 @@ class Plan:
     """
 
     def __init__(self, n, obj_h, obj_w, n_slices, positions, dz, pixel_size, wavelength,
-                 tilt_y=0.0, tilt_x=0.0, budget_bytes: int = 0, device=None):
+                 tilt_y=0.0, tilt_x=0.0, budget_bytes: int = 0, device=None, checkpoint_every: int = 0):
         torch = _torch()
         self.device = _indexed(torch.device(device if device is not None else "cuda"))
         self.n, self.obj_h, self.obj_w, self.n_slices = int(n), int(obj_h), int(obj_w), int(n_slices)
         self.pb, self._keep = make_problem(n, obj_h, obj_w, n_slices, positions, dz, pixel_size, wavelength,
-                                           tilt_y, tilt_x)
+                                           tilt_y, tilt_x, checkpoint_every)
         self.n_pos = self.pb.n_pos
         ws = workspace_size(self.pb, budget_bytes)
         with torch.cuda.device(self.device):
@@ -190,6 +195,8 @@ class Plan:
         self._h = handle
         self.batch = lib().ms_plan_batch(handle)
         self.shift_classes = lib().ms_plan_shift_classes(handle)
+        self.checkpoint_every = lib().ms_plan_checkpoint_every(handle)
+        self.workspace_bytes = ws
         self.budget_bytes = int(budget_bytes)
         self._path, self._objective = MS_PATH_AUTO, MS_OBJECTIVE_AMPLITUDE
 
@@ -202,16 +209,16 @@ class Plan:
         pb = self.pb
         plan = Plan(self.n, self.obj_h, self.obj_w, self.n_slices, positions, self._keep[1][: max(self.n_slices - 1, 0)],
                     pb.pixel_size, pb.wavelength, pb.tilt_y, pb.tilt_x, budget_bytes=self.budget_bytes,
-                    device=self.device)
+                    device=self.device, checkpoint_every=pb.checkpoint_every)
         plan.set_path(self._path)
         plan.set_objective(self._objective)
         return plan
 
     @classmethod
-    def from_geometry(cls, geo, positions=None, budget_bytes=0, device=None):
+    def from_geometry(cls, geo, positions=None, budget_bytes=0, device=None, checkpoint_every=0):
         pos = geo.positions() if positions is None else positions
         return cls(geo.n, geo.obj_h, geo.obj_w, geo.n_slices, pos, geo.gaps(), geo.pixel_size, geo.wavelength,
-                   budget_bytes=budget_bytes, device=device)
+                   budget_bytes=budget_bytes, device=device, checkpoint_every=checkpoint_every)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -39,16 +39,28 @@ struct LineParams {
     const float *measured;       // [S][N][N]
     float *intensity;            // [S][N][N] (forward mode)
     float2 *exit_waves;          // [S][N][N] or null
-    float2 *A;                   // [count][N][N] half-propagated window
-    float2 *waves;               // [count][M][N][N] incident waves, then gradient patches (or null)
+    float2 *A;                   // [count][N][N] half-propagated window, read and written in place
     float2 *probe_patch;         // [count][N][N] or null
-    float *overlap_patch;        // [count][M][N][N]: |psi_m|^2 (layer mode: the layer; full: every slice)
     double *loss_part;           // [count][N / 16]
     int H, W, M, m;
-    int mode;                    // kForward / kAdjoint / kLayer / kProbe
-    int layer;                   // layer mode: the slice whose gradient is wanted
+    int mode;                    // kForward: intensities in the far-field launch; otherwise the residual
     int objective;               // 0 amplitude, 1 Poisson deviance
-    int full;                    // adjoint mode: also write |psi_m|^2 of every slice
+    // Per-launch destinations, each [count] x stride elements (null: not used by this launch).
+    // Forward launch of slice m:
+    const float2 *restart;       //   psi_m read from here (m > 0) instead of finishing the propagation in A
+    long long restart_stride;
+    float2 *psi_out;             //   psi_m stored here
+    long long psi_out_stride;
+    int stop_after_psi;          //   the launch ends once psi_m is stored (recomputing a wave)
+    // Forward (layer mode) or adjoint (full-step overlap) launch of slice m:
+    float *ovl_out;              //   |psi_m|^2
+    long long ovl_stride;
+    // Adjoint launch of slice m:
+    const float2 *psi_in;        //   psi_m (null: the shifted probe, m = 0)
+    long long psi_in_stride;
+    float2 *patch_out;           //   dL/d conj(t_m) on the window, conj(psi_m) o g (may alias psi_in)
+    long long patch_stride;
+    int go_on;                   //   after the patch: conj(t_m), then G_{m-1}^H into A, or the probe patch
 };
 
 // Global-memory window access for a line group in either layout: lane (line, j) owns
@@ -297,10 +309,8 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
     const int4 info = p.pos_info[s];
     const int oy = info.x, ox = info.y, cls = info.z;
     const int M = p.M, m = p.m;
-    const int mode = p.mode;
     float2 *xb = xbuf + lloc * Wn::LD;
     float2 *A = p.A + (size_t)b * NN;
-    float2 *wave = p.waves ? p.waves + (size_t)b * M * NN : nullptr;
     const float2 *probe = p.class_probe + (size_t)cls * NN;
     const float2 *hown = ROW ? p.hx : p.hy;
 
@@ -308,13 +318,14 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
     // later replaced by that of the gap that is started (one table of N: with 4 workgroups of
     // this kernel a CU's LDS holds, not 3)
     for (int i = tid; i < Wn::TW_WORDS; i += NT) s_tw[i] = p.tw[i];
+    const bool restart = (stage == kStageForward) && p.restart && m > 0;
     int g_fin = -1, g_start = -1;
     if (stage == kStageForward) {
-        g_fin = m - 1;
-        g_start = (m + 1 < M) ? m : -1;
+        g_fin = (m > 0 && !restart) ? m - 1 : -1;
+        g_start = (m + 1 < M && !p.stop_after_psi) ? m : -1;
     } else if (stage == kStageAdjoint) {
         g_fin = (m + 1 < M) ? m : -1;
-        g_start = m - 1;
+        g_start = (m > 0 && p.go_on) ? m - 1 : -1;
     }
     auto load_h = [&](int g) {
         for (int i = tid; i < N; i += NT) s_h[i] = hown[p.gap_table[g] * N + i];
@@ -334,24 +345,26 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
     const LinePos q{line, lloc, j, (int)blockIdx.x * kLinesPerGroup};
     float2 v[16];
     if (stage == kStageForward) {
-        // ---- psi_m: the probe, or the propagation of gap m-1 finished along this axis ----
+        // ---- psi_m: the probe, a stored wave, or the propagation of gap m-1 finished along this axis ----
         if (m == 0) {
             line_load<N, ROW, false>(v, probe, q, xbuf);
+        } else if (restart) {
+            line_load<N, ROW, false>(v, p.restart + (size_t)b * p.restart_stride, q, xbuf);
         } else {
             line_load<N, ROW, false>(v, A, q, xbuf);
             prop_axis<N, false>(v, s_tw, xb, s_h, j);
         }
-        const bool store = (mode == kAdjoint && m > 0) || (mode == kLayer && m == p.layer && m > 0);
-        if (store) line_store<N, ROW, false>(v, wave + m * NN, q, xbuf);
-        if (mode == kLayer && m == p.layer)
-            line_store_abs2<N, ROW, false>(v, p.overlap_patch + ((size_t)b * M + m) * NN, q, xbuf);
+        if (p.psi_out) line_store<N, ROW, false>(v, p.psi_out + (size_t)b * p.psi_out_stride, q, xbuf);
+        if (p.ovl_out) line_store_abs2<N, ROW, false>(v, p.ovl_out + (size_t)b * p.ovl_stride, q, xbuf);
+        if (p.stop_after_psi) return;
         line_patch<N, ROW, false>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, q, xbuf);
         if (m + 1 < M) {
             next_h();
             prop_axis<N, false>(v, s_tw, xb, s_h, j);
             line_store<N, ROW, false>(v, A, q, xbuf);
         } else {
-            if (mode == kForward && p.exit_waves) line_store<N, ROW, false>(v, p.exit_waves + (size_t)s * NN, q, xbuf);
+            if (p.mode == kForward && p.exit_waves)
+                line_store<N, ROW, false>(v, p.exit_waves + (size_t)s * NN, q, xbuf);
             line_fft_fwd<N>(v, s_tw, xb, j);
             line_store<N, ROW, true>(v, A, q, xbuf);    // spectral along this axis, at natural frequency
         }
@@ -362,7 +375,7 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
         // line index = frequency along the first axis (natural); FFT along this axis
         line_load<N, ROW, false>(v, A, q, xbuf);
         line_fft_fwd<N>(v, s_tw, xb, j);
-        if (mode == kForward) {
+        if (p.mode == kForward) {
             line_store_abs2<N, ROW, true>(v, p.intensity + (size_t)s * NN, q, xbuf);
             return;
         }
@@ -383,12 +396,10 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
         line_load<N, ROW, false>(v, A, q, xbuf);
         prop_axis<N, true>(v, s_tw, xb, s_h, j);
     }
-    const int m_stop = (mode == kLayer) ? p.layer : 0;
-    const bool patch = (mode == kAdjoint) || (mode == kLayer && m == p.layer);
-    if (patch) {
-        const float2 *psi = (m == 0) ? probe : wave + m * NN;
-        float2 *dst = wave + m * NN;
-        float *ovl = (mode == kAdjoint && p.full) ? p.overlap_patch + ((size_t)b * M + m) * NN : nullptr;
+    if (p.patch_out) {
+        const float2 *psi = p.psi_in ? p.psi_in + (size_t)b * p.psi_in_stride : probe;
+        float2 *dst = p.patch_out + (size_t)b * p.patch_stride;
+        float *ovl = p.ovl_out ? p.ovl_out + (size_t)b * p.ovl_stride : nullptr;
         if (ROW) {
             // reads before writes in two halves: vector memory operations retire in issue
             // order, so interleaved loads would each wait for the stores before them
@@ -414,8 +425,7 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
             line_store<N, false, false>(g, dst, q, xbuf);
         }
     }
-    const bool go_on = (m > m_stop) || (mode != kLayer && m == 0);
-    if (!go_on) return;
+    if (!p.go_on) return;
     line_patch<N, ROW, true>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, q, xbuf);
     if (m > 0) {
         next_h();

@@ -23,7 +23,8 @@ enum Mode : int {
     kForward = 0,   // intensities (and exit waves)
     kAdjoint = 1,   // loss, gradient patches of every slice and of the probe
     kLayer = 2,     // loss, gradient patch of one slice and its overlap patch
-    kProbe = 3      // loss and probe gradient patch
+    kProbe = 3,     // loss and probe gradient patch
+    kReplay = 4     // adjoint with recomputed incident waves: one slice's gradient patch a launch
 };
 
 struct FusedParams {
@@ -38,13 +39,21 @@ struct FusedParams {
     const float *measured;       // [S][N][N]
     float *intensity;            // [S][N][N]
     float2 *exit_waves;          // [S][N][N] or null
-    float2 *waves;               // [count][M][N][N] incident waves, then gradient patches
+    float2 *waves;               // per position wave_stride elements: incident waves, then gradient patches
+                                 //   adjoint: slot m = psi_m; layer: slot 0 = psi_layer;
+                                 //   replay: slots 0 .. nck-1 = psi_ck, psi_2ck, ..., slot nck = work
+    long long wave_stride;
     float2 *probe_patch;         // [count][N][N] or null
-    float *overlap_patch;        // [count][M][N][N]: |psi_m|^2 of slice m (layer mode: the layer; full: all)
+    float *overlap_patch;        // per position ovl_stride elements: |psi_m|^2 (adjoint with full: slot m;
+                                 //   layer and replay: slot 0)
+    long long ovl_stride;
     double *loss_pos;            // [count]
     int H, W, M, layer;
     int objective;               // 0 amplitude, 1 Poisson deviance
-    int full;                    // adjoint mode: also write |psi_m|^2 of every slice
+    int full;                    // adjoint and replay modes: also write |psi_m|^2 of the patch's slice
+    int ck;                      // replay: psi_m stored for m = ck, 2 ck, ... (ck >= 2)
+    int seg;                     // replay: the slice whose patch this launch writes (M - 1 first)
+    float2 *park;                // replay: [count][N][N] adjoint state between launches
 };
 
 // Incident-wave load/store in natural [y][x] order from either layout, with 32-bit element
@@ -262,6 +271,21 @@ __device__ __forceinline__ void stage(float2 *dst, const float2 *src, int n)
     for (int i = threadIdx.x; i < n; i += Win<N>::NT) dst[i] = src[i];
 }
 
+// Where psi_m goes in the forward chain (null: not stored).  wave: this position's wave region.
+template <int MODE>
+__device__ __forceinline__ float2 *forward_store(const FusedParams &p, float2 *wave, int m, size_t NN)
+{
+    if (m == 0) return nullptr;                                   // psi_0 is the shifted probe
+    if (MODE == kAdjoint) return wave + m * NN;
+    if (MODE == kLayer) return m == p.layer ? wave : nullptr;
+    if (MODE == kReplay) {
+        const int nck = (p.M - 1) / p.ck;
+        if (m % p.ck == 0) return wave + (size_t)(m / p.ck - 1) * NN;
+        if (m == p.M - 1) return wave + (size_t)nck * NN;         // the head launch's own slice
+    }
+    return nullptr;
+}
+
 template <int N, int MODE>
 __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4))) void fused_kernel(FusedParams p)
 {
@@ -289,69 +313,75 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
     __syncthreads();
     const float2 *tw = s_tw;
 
-    float2 *wave = p.waves ? p.waves + (size_t)b * M * NN : nullptr;
+    float2 *wave = p.waves ? p.waves + (size_t)b * p.wave_stride : nullptr;
     const float2 *probe = p.class_probe + (size_t)cls * NN;
-    float2 v[16];
-    load_window<N, true>(v, probe, line, j);
-
-    // ---- forward multislice: E_1 = P^s o X_1, E_m = V(E_{m-1}) o X_m (Sec. 2.1) ----
-    for (int m = 0; m < M; ++m) {
-        const bool row = !(m & 1);
-        const float2 *slice = p.slices + (size_t)m * H * W;
-        const bool store = (MODE == kAdjoint && m > 0) || (MODE == kLayer && m == p.layer && m > 0);
-        if (row) {
-            // the transmission loads go out before this step's stores: the vector memory
-            // counter retires in issue order, so waiting for them does not wait for the stores
-            float2 t[16];
-            load_patch<N, true>(t, slice, H, W, oy, ox, line, j, inside);
-            if (store) store_window<N, true>(v, wave + m * NN, line, j);
-            if (MODE == kLayer && m == p.layer)
-                store_window_abs2<N, true>(v, p.overlap_patch + ((size_t)b * M + m) * NN, line, j);
-            mul_patch<false>(v, t);
-            if (m + 1 < M) {
-                const int u = p.gap_table[m] * N;
-                propagate<N, true, false>(v, tw, lds, s_hy + u, s_hx + u, line, j);
-            }
-        } else {
-            float2 t[16];
-            load_patch<N, false>(t, slice, H, W, oy, ox, line, j, inside);
-            if (store) store_window<N, false>(v, wave + m * NN, line, j);
-            if (MODE == kLayer && m == p.layer)
-                store_window_abs2<N, false>(v, p.overlap_patch + ((size_t)b * M + m) * NN, line, j);
-            mul_patch<false>(v, t);
-            if (m + 1 < M) {
-                const int u = p.gap_table[m] * N;
-                propagate<N, false, false>(v, tw, lds, s_hy + u, s_hx + u, line, j);
-            }
-        }
-    }
-
-    // ---- far field Psi = F E_M ----
-    const bool rowM = !((M - 1) & 1);
     float2 *xb = lds + line * Wn::LD;
-    if constexpr (MODE == kForward) {
-        if (p.exit_waves) {
-            float2 *ew = p.exit_waves + (size_t)s * NN;
-            if (rowM) store_window<N, true>(v, ew, line, j);
-            else store_window<N, false>(v, ew, line, j);
-        }
-    }
-    line_fft_fwd<N>(v, tw, xb, j);
-    if (rowM) transpose<N, true, true, false>(v, lds, line, j);
-    else transpose<N, false, true, false>(v, lds, line, j);
-    line_fft_fwd<N>(v, tw, xb, j);
-    // now layout !rowM; line = frequency along the first axis, registers spectral along the second
+    float2 v[16];
+    // Replay launches after the first: the adjoint of slice seg alone, from the state the
+    // previous launch parked, with psi_seg recomputed from the nearest stored wave below it.
+    const bool head = (MODE != kReplay) || (p.seg == M - 1);
+    const int m_stop = (MODE == kLayer) ? p.layer : (MODE == kReplay ? p.seg : 0);
+    int m_hi = M - 1;
 
-    if constexpr (MODE == kForward) {
-        float *out = p.intensity + (size_t)s * NN;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            int f = Wn::spec(j, i);
-            int fy = rowM ? f : line, fx = rowM ? line : f;
-            out[fy * N + fx] = cabs2(v[i]);
+    if (head) {
+        load_window<N, true>(v, probe, line, j);
+
+        // ---- forward multislice: E_1 = P^s o X_1, E_m = V(E_{m-1}) o X_m (Sec. 2.1) ----
+        for (int m = 0; m < M; ++m) {
+            const bool row = !(m & 1);
+            const float2 *slice = p.slices + (size_t)m * H * W;
+            float2 *st = forward_store<MODE>(p, wave, m, NN);
+            float *ovl = (MODE == kLayer && m == p.layer) ? p.overlap_patch + (size_t)b * p.ovl_stride : nullptr;
+            if (row) {
+                // the transmission loads go out before this step's stores: the vector memory
+                // counter retires in issue order, so waiting for them does not wait for the stores
+                float2 t[16];
+                load_patch<N, true>(t, slice, H, W, oy, ox, line, j, inside);
+                if (st) store_window<N, true>(v, st, line, j);
+                if (ovl) store_window_abs2<N, true>(v, ovl, line, j);
+                mul_patch<false>(v, t);
+                if (m + 1 < M) {
+                    const int u = p.gap_table[m] * N;
+                    propagate<N, true, false>(v, tw, lds, s_hy + u, s_hx + u, line, j);
+                }
+            } else {
+                float2 t[16];
+                load_patch<N, false>(t, slice, H, W, oy, ox, line, j, inside);
+                if (st) store_window<N, false>(v, st, line, j);
+                if (ovl) store_window_abs2<N, false>(v, ovl, line, j);
+                mul_patch<false>(v, t);
+                if (m + 1 < M) {
+                    const int u = p.gap_table[m] * N;
+                    propagate<N, false, false>(v, tw, lds, s_hy + u, s_hx + u, line, j);
+                }
+            }
         }
-        return;
-    } else {
+
+        // ---- far field Psi = F E_M ----
+        const bool rowM = !((M - 1) & 1);
+        if constexpr (MODE == kForward) {
+            if (p.exit_waves) {
+                float2 *ew = p.exit_waves + (size_t)s * NN;
+                if (rowM) store_window<N, true>(v, ew, line, j);
+                else store_window<N, false>(v, ew, line, j);
+            }
+        }
+        line_fft_fwd<N>(v, tw, xb, j);
+        if (rowM) transpose<N, true, true, false>(v, lds, line, j);
+        else transpose<N, false, true, false>(v, lds, line, j);
+        line_fft_fwd<N>(v, tw, xb, j);
+        // now layout !rowM; line = frequency along the first axis, registers spectral along the second
+
+        if constexpr (MODE == kForward) {
+            float *out = p.intensity + (size_t)s * NN;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                int f = Wn::spec(j, i);
+                int fy = rowM ? f : line, fx = rowM ? line : f;
+                out[fy * N + fx] = cabs2(v[i]);
+            }
+            return;
+        }
         const float *meas = p.measured + (size_t)s * NN;
         double part = rowM ? residual<N, false>(v, meas, line, j, p.objective)
                            : residual<N, true>(v, meas, line, j, p.objective);
@@ -363,13 +393,46 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
         if (rowM) transpose<N, false, false, true>(v, lds, line, j);
         else transpose<N, true, false, true>(v, lds, line, j);
         line_fft_inv<N>(v, tw, xb, j);
+    } else if constexpr (MODE == kReplay) {
+        // psi_seg from the stored wave psi_c (or the probe at c = 0), c = seg - seg mod ck
+        const int seg = p.seg, c = seg - seg % p.ck;
+        const int nck = (M - 1) / p.ck;
+        if (c < seg) {
+            const float2 *src = (c == 0) ? probe : wave + (size_t)(c / p.ck - 1) * NN;
+            if (!(c & 1)) load_window<N, true>(v, src, line, j);
+            else load_window<N, false>(v, src, line, j);
+            for (int m = c; m < seg; ++m) {
+                const bool row = !(m & 1);
+                const float2 *slice = p.slices + (size_t)m * H * W;
+                const int u = p.gap_table[m] * N;
+                float2 t[16];
+                if (row) {
+                    load_patch<N, true>(t, slice, H, W, oy, ox, line, j, inside);
+                    mul_patch<false>(v, t);
+                    propagate<N, true, false>(v, tw, lds, s_hy + u, s_hx + u, line, j);
+                } else {
+                    load_patch<N, false>(t, slice, H, W, oy, ox, line, j, inside);
+                    mul_patch<false>(v, t);
+                    propagate<N, false, false>(v, tw, lds, s_hy + u, s_hx + u, line, j);
+                }
+            }
+            float2 *work = wave + (size_t)nck * NN;
+            if (!(seg & 1)) store_window<N, true>(v, work, line, j);
+            else store_window<N, false>(v, work, line, j);
+        }
+        const float2 *pk = p.park + (size_t)b * NN;
+        if (!(seg & 1)) load_window<N, true>(v, pk, line, j);
+        else load_window<N, false>(v, pk, line, j);
+        m_hi = seg;
+    }
 
-        const int m_stop = (MODE == kLayer) ? p.layer : 0;
-        for (int m = M - 1; m >= m_stop; --m) {
+    if constexpr (MODE != kForward) {
+        int m = m_hi;
+        for (; m >= m_stop; --m) {
             const bool row = !(m & 1);
             const float2 *slice = p.slices + (size_t)m * H * W;
-            const bool patch = (MODE == kAdjoint) || (MODE == kLayer && m == p.layer);
-            const bool go_on = (m > m_stop) || (MODE != kLayer && m == 0);
+            const bool patch = (MODE == kAdjoint) || (MODE == kReplay) || (MODE == kLayer && m == p.layer);
+            const bool go_on = (m > m_stop) || (MODE != kLayer && m == 0) || (MODE == kReplay);
             // Memory order of the step.  Vector memory operations retire in issue order, so a
             // wait for a load also waits for every store issued before it.  The transmission
             // loads go out first (they are consumed last); the incident wave is read and the
@@ -383,14 +446,27 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
                 else load_patch<N, false>(t, slice, H, W, oy, ox, line, j, inside);
             }
             if (patch) {
-                const float2 *psi = (m == 0) ? probe : wave + m * NN;
-                float2 *dst = wave + m * NN;
+                const float2 *psi;
+                float2 *dst;
+                float *ovl = nullptr;
+                if constexpr (MODE == kReplay) {
+                    const int nck = (M - 1) / p.ck;
+                    dst = wave + (size_t)nck * NN;
+                    psi = (m == 0) ? probe : (m % p.ck == 0 ? wave + (size_t)(m / p.ck - 1) * NN : dst);
+                    if (p.full) ovl = p.overlap_patch + (size_t)b * p.ovl_stride;
+                } else if constexpr (MODE == kLayer) {
+                    dst = wave;
+                    psi = (m == 0) ? probe : wave;
+                } else {
+                    dst = wave + m * NN;
+                    psi = (m == 0) ? probe : dst;
+                    if (MODE == kAdjoint && p.full) ovl = p.overlap_patch + (size_t)b * p.ovl_stride + m * NN;
+                }
                 // 32-bit element offsets from the window base (N^2 < 2^31): one address
                 // register per access instead of a 64-bit pointer each
                 const int l2 = opaque(line), j2 = opaque(j);
                 const unsigned base = row ? (unsigned)(l2 * N + j2) : (unsigned)(j2 * N + l2);
                 const unsigned step = row ? (unsigned)R : (unsigned)(R * N);
-                float *ovl = (MODE == kAdjoint && p.full) ? p.overlap_patch + ((size_t)b * M + m) * NN : nullptr;
 #pragma unroll
                 for (int h = 0; h < 16; h += 8) {
                     float2 ps[8];
@@ -416,8 +492,18 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
                 if (row) propagate<N, true, true>(v, tw, lds, s_hy + u, s_hx + u, line, j);
                 else propagate<N, false, true>(v, tw, lds, s_hy + u, s_hx + u, line, j);
             }
+            if (MODE == kReplay) break;                  // one slice a launch
         }
-        if constexpr (MODE == kAdjoint || MODE == kProbe) {
+        if constexpr (MODE == kReplay) {
+            if (m_stop > 0) {
+                // park the state for the launch of slice m_stop - 1, in that slice's layout
+                float2 *pk = p.park + (size_t)b * NN;
+                if (!((m_stop - 1) & 1)) store_window<N, true>(v, pk, line, j);
+                else store_window<N, false>(v, pk, line, j);
+                return;
+            }
+        }
+        if constexpr (MODE == kAdjoint || MODE == kProbe || MODE == kReplay) {
             if (p.probe_patch) store_window<N, true>(v, p.probe_patch + (size_t)b * NN, line, j);
         }
     }
@@ -436,15 +522,15 @@ constexpr int kChunks = 16;  // chunks per batch
 constexpr int kUnroll = 8;   // patch loads in flight per lane
 
 struct ScatterParams {
-    const float2 *patches;      // patch of (position b, slice m): patches + b * pos_stride + m * N * N
-    const float *wpatch;        // overlap patch of (position b, slice m): wpatch + b * w_stride + m * N * N
+    const float2 *patches;      // patch of (position b, slice i of the launch): patches + b * pos_stride + i * N * N
+    const float *wpatch;        // overlap patch of (position b, slice i): wpatch + b * w_stride + i * N * N
     long long pos_stride;
     const int *tile_off;        // this batch: [kChunks][n_tiles + 1]
     const int4 *entries;        // (batch-local position, origin y, origin x, 0)
     float2 *partial;            // [groups][n_m][H][W]
     float *wpartial;            // [groups][n_m][H][W] or null
     long long w_stride;
-    int H, W, N, tiles_x, n_tiles, m0;
+    int H, W, N, tiles_x, n_tiles;
     int nch, cpb;               // chunks of the batch; consecutive chunks summed per block
 };
 
@@ -455,9 +541,9 @@ __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
     const int x = (t % p.tiles_x) * kTileW + (int)(threadIdx.x % kTileW);
     if (y >= p.H || x >= p.W) return;
     const size_t NN = (size_t)p.N * p.N;
-    const float2 *base = p.patches + (size_t)(p.m0 + mi) * NN;
+    const float2 *base = p.patches + (size_t)mi * NN;
     const bool want_w = p.wpartial != nullptr;
-    const float *wbase = want_w ? p.wpatch + (size_t)(p.m0 + mi) * NN : nullptr;
+    const float *wbase = want_w ? p.wpatch + (size_t)mi * NN : nullptr;
     float2 acc = make_float2(0.f, 0.f);
     float wacc = 0.f;
     const int c_end = min(p.nch, (grp + 1) * p.cpb);

@@ -66,6 +66,7 @@ ms_status validate(const ms_problem *pb)
             return fail(MS_ERR_INVALID_ARG, "position " + std::to_string(i / 2) + " is not finite or too large");
     for (int m = 0; m + 1 < pb->n_slices; ++m)
         if (!std::isfinite(pb->dz[m])) return fail(MS_ERR_INVALID_ARG, "dz is not finite");
+    if (pb->checkpoint_every < 0) return fail(MS_ERR_INVALID_ARG, "checkpoint_every must be >= 0");
     return MS_OK;
 }
 
@@ -73,6 +74,7 @@ ms_status validate(const ms_problem *pb)
 // batches and scatter lists.
 struct HostPlan {
     int n = 0, H = 0, W = 0, M = 0, C = 0;
+    int K = 1;                                // incident waves stored every K slices (1: all)
     int64_t S = 0, B = 0;
     int nb = 0, tiles_x = 0, tiles_y = 0, n_tiles = 0;
     std::vector<int4> pos_info;
@@ -235,6 +237,13 @@ size_t tile_entries(const HostPlan &hp)
     return total;
 }
 
+// Stored incident waves per position: all M with K = 1; otherwise the checkpoints psi_K,
+// psi_2K, ... (floor((M - 1) / K) of them) and one work slot, which holds the recomputed wave
+// of the slice being taken and then its gradient patch.
+int checkpoints(int M, int K) { return K > 1 ? (M - 1) / K : 0; }
+int wave_slots(int M, int K) { return K > 1 ? checkpoints(M, K) + 1 : M; }
+int overlap_slots(int M, int K) { return K > 1 ? 1 : M; }
+
 // Workspace layout.  Every region is 256-byte aligned.
 struct Layout {
     size_t tw, hy, hx, gap_table, ry, rx, ident, dry, drx, zero_ident, dprobe, pgrad, pcurv;
@@ -243,7 +252,7 @@ struct Layout {
     size_t full_g, full_w, maxw_all, mu_all;
     size_t tile_off, tile_list, class_off, class_list, sub_class_off, sub_class_list;
     size_t spart, wpart, cpart;
-    size_t waves, probe_patch, overlap, loss_pos, half, loss_part, energy;
+    size_t waves, probe_patch, overlap, loss_pos, half, replay, loss_part, energy;
     size_t total;
 };
 
@@ -295,13 +304,16 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     L.spart = take(nch * M * HW * 8);
     L.wpart = take(nch * M * HW * 4);
     L.cpart = take(nch * C * NN * 8);
-    L.waves = take((size_t)B * M * NN * 8);
+    L.waves = take((size_t)B * wave_slots(hp.M, hp.K) * NN * 8);
     L.probe_patch = take((size_t)B * NN * 8);
-    L.overlap = take((size_t)B * M * NN * 4);
+    L.overlap = take((size_t)B * overlap_slots(hp.M, hp.K) * NN * 4);
     L.loss_pos = take((size_t)B * 8);
-    // line kernels: the half-propagated window per position and per-line-group partials
+    // line kernels: the half-propagated window per position (and a second one for recomputed
+    // waves), per-line-group partials; recomputation on the fused kernel parks its adjoint
+    // state in the first
     const bool lines_possible = hp.n >= 32;
-    L.half = take(lines_possible ? (size_t)B * NN * 8 : 0);
+    L.half = take((lines_possible || hp.K > 1) ? (size_t)B * NN * 8 : 0);
+    L.replay = take((lines_possible && hp.K > 1) ? (size_t)B * NN * 8 : 0);
     L.loss_part = take(lines_possible ? (size_t)B * (n / 16) * 8 : 0);
     L.energy = take((n / 16) * 8);
     L.total = o;
@@ -319,6 +331,31 @@ int64_t choose_batch(const HostPlan &hp, size_t n_entries, size_t budget)
         else hi = mid;
     }
     return lo;
+}
+
+// Wave storage and batch: a requested interval k (>= M means none stored) is kept and only
+// the batch adapts to the budget; k = 0 takes every wave (K = 1) unless the budget cannot hold
+// all positions that way, then the smallest K whose waves fit all positions, and only when K = M
+// does not fit either, smaller batches.  Sets hp.K; returns the batch (0 if nothing fits).
+int64_t choose_storage(HostPlan &hp, size_t n_entries, size_t budget, int k_req)
+{
+    if (hp.M < 2) {
+        hp.K = 1;
+        return choose_batch(hp, n_entries, budget);
+    }
+    if (k_req > 0) {
+        hp.K = std::min(k_req, hp.M);
+        return choose_batch(hp, n_entries, budget);
+    }
+    hp.K = 1;
+    if (budget == 0) return hp.S;
+    for (int k = 1; k <= hp.M; ++k) {
+        if (k > 1 && k < hp.M && wave_slots(hp.M, k) == wave_slots(hp.M, k - 1)) continue;
+        hp.K = k;
+        if (make_layout(hp, hp.S, n_entries).total <= budget) return hp.S;
+    }
+    hp.K = hp.M;
+    return choose_batch(hp, n_entries, budget);
 }
 
 }  // namespace
@@ -344,6 +381,10 @@ struct ms_plan {
 
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    // elements per position of the wave and overlap regions
+    long long wave_stride() const { return (long long)wave_slots(hp.M, hp.K) * hp.n * hp.n; }
+    long long ovl_stride() const { return (long long)overlap_slots(hp.M, hp.K) * hp.n * hp.n; }
+    bool recompute() const { return hp.K > 1; }
 };
 
 namespace {
@@ -363,6 +404,7 @@ void launch_fused_n(int mode, const FusedParams &fp, int count, hipStream_t st)
         case kForward: fused_kernel<N, kForward><<<grid, block, 0, st>>>(fp); break;
         case kAdjoint: fused_kernel<N, kAdjoint><<<grid, block, 0, st>>>(fp); break;
         case kLayer: fused_kernel<N, kLayer><<<grid, block, 0, st>>>(fp); break;
+        case kReplay: fused_kernel<N, kReplay><<<grid, block, 0, st>>>(fp); break;
         default: fused_kernel<N, kProbe><<<grid, block, 0, st>>>(fp); break;
     }
 }
@@ -396,9 +438,8 @@ void launch_line_n(int n, bool row, const LineParams &lp, int stage, int count, 
     }
 }
 
-// Forward launches m = 0..M-1 (layout of slice m: rows for even m), the far-field launch
-// in the other layout, then (unless forward-only) the adjoint launches m = M-1 .. m_stop.
-void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream_t st)
+// Line-kernel parameters shared by every launch of one batch (per-launch fields cleared).
+LineParams line_params(ms_plan *p, const FusedParams &fp, int mode)
 {
     const HostPlan &hp = p->hp;
     LineParams lp{};
@@ -406,34 +447,161 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
     lp.tw = fp.tw; lp.hy = fp.hy; lp.hx = fp.hx; lp.gap_table = fp.gap_table;
     lp.measured = fp.measured; lp.intensity = fp.intensity; lp.exit_waves = fp.exit_waves;
     lp.A = p->at<float2>(p->L.half);
-    lp.waves = fp.waves; lp.probe_patch = fp.probe_patch; lp.overlap_patch = fp.overlap_patch;
+    lp.probe_patch = fp.probe_patch;
     lp.loss_part = p->at<double>(p->L.loss_part);
-    lp.H = hp.H; lp.W = hp.W; lp.M = hp.M; lp.mode = mode; lp.layer = fp.layer;
+    lp.H = hp.H; lp.W = hp.W; lp.M = hp.M;
+    lp.mode = mode;
     lp.objective = fp.objective;
-    lp.full = fp.full;
+    return lp;
+}
+
+// Forward launches m = 0..M-1 (layout of slice m: rows for even m), the far-field launch
+// in the other layout, then (unless forward-only) the adjoint launches m = M-1 .. m_stop.
+// Every wave the mode needs is stored (K = 1 layout; the layer mode uses slot 0).
+void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
     const int M = hp.M;
+    const long long NN = (long long)hp.n * hp.n;
+    float2 *waves = fp.waves;
+    LineParams lp = line_params(p, fp, mode);
     for (int m = 0; m < M; ++m) {
         lp.m = m;
+        lp.psi_out = nullptr;
+        lp.ovl_out = nullptr;
+        if (m > 0 && mode == kAdjoint) { lp.psi_out = waves + m * NN; lp.psi_out_stride = fp.wave_stride; }
+        if (m > 0 && mode == kLayer && m == fp.layer) { lp.psi_out = waves; lp.psi_out_stride = fp.wave_stride; }
+        if (mode == kLayer && m == fp.layer) { lp.ovl_out = fp.overlap_patch; lp.ovl_stride = fp.ovl_stride; }
         launch_line_n(hp.n, (m & 1) == 0, lp, kStageForward, count, st);
     }
+    lp.psi_out = nullptr;
+    lp.ovl_out = nullptr;
     lp.m = M - 1;
     launch_line_n(hp.n, ((M - 1) & 1) != 0, lp, kStageFar, count, st);
     if (mode == kForward) return;
     const int m_stop = (mode == kLayer) ? fp.layer : 0;
     for (int m = M - 1; m >= m_stop; --m) {
         lp.m = m;
+        lp.patch_out = nullptr;
+        lp.psi_in = nullptr;
+        lp.ovl_out = nullptr;
+        if (mode == kAdjoint) {
+            lp.patch_out = waves + m * NN;
+            lp.psi_in = m > 0 ? waves + m * NN : nullptr;
+            if (fp.full) { lp.ovl_out = fp.overlap_patch + m * NN; lp.ovl_stride = fp.ovl_stride; }
+        } else if (mode == kLayer && m == fp.layer) {
+            lp.patch_out = waves;
+            lp.psi_in = m > 0 ? waves : nullptr;
+        }
+        lp.patch_stride = lp.psi_in_stride = fp.wave_stride;
+        lp.go_on = (m > m_stop) || (mode != kLayer);
         launch_line_n(hp.n, (m & 1) == 0, lp, kStageAdjoint, count, st);
     }
 }
 
+// Event pair around a group of per-position launches, while profiling is on.
+struct TimedRegion {
+    ms_plan *p;
+    hipStream_t st;
+    bool on;
+    TimedRegion(ms_plan *plan, hipStream_t stream) : p(plan), st(stream), on(plan->ev_used < plan->ev_start.size())
+    {
+        if (on) (void)hipEventRecord(p->ev_start[p->ev_used], st);
+    }
+    ~TimedRegion()
+    {
+        if (on) (void)hipEventRecord(p->ev_stop[p->ev_used++], st);
+    }
+};
+
 // All per-position work of one batch, with optional timing.
 void launch_fused(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream_t st)
 {
-    const bool timed = p->ev_used < p->ev_start.size();
-    if (timed) (void)hipEventRecord(p->ev_start[p->ev_used], st);
+    TimedRegion t(p, st);
     if (p->lines) run_lines(p, mode, fp, count, st);
     else launch_fused_raw(p->hp.n, mode, fp, count, st);
-    if (timed) (void)hipEventRecord(p->ev_stop[p->ev_used++], st);
+}
+
+void scatter(ms_plan *p, int b, int count, const float2 *patches, long long pos_stride, const float *wpatch,
+             long long w_stride, int n_m, float2 *out, float *wout, int accumulate, hipStream_t st);
+
+// Adjoint of one batch with recomputed incident waves (K > 1): the forward chain stores psi_K,
+// psi_2K, ... and the head slice M - 1; then, slice by slice from M - 1 down to 0, the wave of the
+// slice is recomputed from the nearest stored one below (or the probe), its gradient patch written
+// to the work slot and scattered into g (and |psi|^2 into w when the step sizes need it) before
+// the next slice overwrites the slot.  Each slice's launches are one timed region.
+void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t st, float2 *g, float *w,
+                       int accumulate)
+{
+    const HostPlan &hp = p->hp;
+    const int M = hp.M, K = hp.K, nck = checkpoints(M, K);
+    const long long NN = (long long)hp.n * hp.n, hw = (long long)hp.H * hp.W;
+    float2 *waves = fp.waves;
+    float2 *work = waves + nck * NN;
+    auto ck_slot = [&](int m) { return waves + (long long)(m / K - 1) * NN; };
+    const float *ovl = w ? fp.overlap_patch : nullptr;
+    fp.full = w ? 1 : 0;
+    if (!p->lines) {
+        for (int seg = M - 1; seg >= 0; --seg) {
+            fp.seg = seg;
+            {
+                TimedRegion t(p, st);
+                launch_fused_raw(hp.n, kReplay, fp, count, st);
+            }
+            scatter(p, b, count, work, fp.wave_stride, ovl, fp.ovl_stride, 1, g + seg * hw, w ? w + seg * hw : nullptr,
+                    accumulate, st);
+        }
+        return;
+    }
+    LineParams lp = line_params(p, fp, kAdjoint);
+    float2 *R = p->at<float2>(p->L.replay);
+    {
+        TimedRegion t(p, st);
+        for (int m = 0; m < M; ++m) {
+            lp.m = m;
+            lp.psi_out = nullptr;
+            if (m > 0 && m % K == 0) lp.psi_out = ck_slot(m);
+            else if (m == M - 1) lp.psi_out = work;
+            lp.psi_out_stride = fp.wave_stride;
+            launch_line_n(hp.n, (m & 1) == 0, lp, kStageForward, count, st);
+        }
+        lp.psi_out = nullptr;
+        lp.m = M - 1;
+        launch_line_n(hp.n, ((M - 1) & 1) != 0, lp, kStageFar, count, st);
+    }
+    lp.patch_out = work;
+    lp.patch_stride = lp.psi_in_stride = fp.wave_stride;
+    lp.go_on = 1;
+    if (w) { lp.ovl_out = fp.overlap_patch; lp.ovl_stride = fp.ovl_stride; }
+    for (int m = M - 1; m >= 0; --m) {
+        TimedRegion t(p, st);
+        if (m < M - 1 && m % K != 0) {
+            // psi_m again: from the stored wave psi_c (or the probe), the forward launches c .. m
+            // in the second half-propagation buffer, the last one ending at psi_m in the work slot
+            const int c = m - m % K;
+            LineParams rp = lp;
+            rp.A = R;
+            rp.patch_out = nullptr;
+            rp.psi_in = nullptr;
+            rp.ovl_out = nullptr;
+            rp.probe_patch = nullptr;
+            rp.go_on = 0;
+            for (int mm = c; mm <= m; ++mm) {
+                rp.m = mm;
+                rp.restart = (mm == c && c > 0) ? ck_slot(c) : nullptr;
+                rp.restart_stride = fp.wave_stride;
+                rp.psi_out = (mm == m) ? work : nullptr;
+                rp.psi_out_stride = fp.wave_stride;
+                rp.stop_after_psi = (mm == m) ? 1 : 0;
+                launch_line_n(hp.n, (mm & 1) == 0, rp, kStageForward, count, st);
+            }
+        }
+        lp.m = m;
+        lp.psi_in = (m == 0) ? nullptr : (m % K == 0 ? ck_slot(m) : work);
+        launch_line_n(hp.n, (m & 1) == 0, lp, kStageAdjoint, count, st);
+        scatter(p, b, count, work, fp.wave_stride, ovl, fp.ovl_stride, 1, g + m * hw, w ? w + m * hw : nullptr,
+                accumulate, st);
+    }
 }
 
 // Per-position losses of the last batch: where they are and how many.
@@ -560,6 +728,11 @@ FusedParams fused_params(ms_plan *p, const ms_c64 *slices, const float *measured
     fp.H = hp.H; fp.W = hp.W; fp.M = hp.M; fp.layer = 0;
     fp.objective = p->objective;
     fp.full = 0;
+    fp.wave_stride = p->wave_stride();
+    fp.ovl_stride = p->ovl_stride();
+    fp.ck = hp.K;
+    fp.seg = hp.M - 1;
+    fp.park = p->at<float2>(p->L.half);
     return fp;
 }
 
@@ -572,23 +745,24 @@ double step_norm(const ms_plan *p)
 
 int grid_for(long long count) { return (int)std::max<long long>(1, std::min<long long>(8192, (count + 255) / 256)); }
 
-// Gradient patches of batch b (slices m0 .. m0 + n_m - 1) into out (n_m x H x W), and the
-// overlap patches into wout if given; accumulate adds to what out already holds.
-void scatter(ms_plan *p, int b, int count, int m0, int n_m, float2 *out, float *wout, int accumulate,
-             hipStream_t st)
+// Gradient patches of batch b for n_m consecutive slices into out (n_m x H x W), and the
+// overlap patches into wout if given; accumulate adds to what out already holds.  patches:
+// slice i of position a at patches + a * pos_stride + i * N^2 (wpatch likewise with w_stride).
+void scatter(ms_plan *p, int b, int count, const float2 *patches, long long pos_stride, const float *wpatch,
+             long long w_stride, int n_m, float2 *out, float *wout, int accumulate, hipStream_t st)
 {
     const HostPlan &hp = p->hp;
     const Chunking ch = chunking(count);
     ScatterParams sp{};
-    sp.patches = p->at<float2>(p->L.waves);
-    sp.wpatch = p->at<float>(p->L.overlap);
-    sp.pos_stride = (long long)hp.M * hp.n * hp.n;
+    sp.patches = patches;
+    sp.wpatch = wpatch;
+    sp.pos_stride = pos_stride;
     sp.tile_off = p->at<int>(p->L.tile_off) + (size_t)b * kChunks * (hp.n_tiles + 1);
     sp.entries = p->at<int4>(p->L.tile_list);
     sp.partial = p->at<float2>(p->L.spart);
     sp.wpartial = wout ? p->at<float>(p->L.wpart) : nullptr;
-    sp.w_stride = (long long)hp.M * hp.n * hp.n;
-    sp.H = hp.H; sp.W = hp.W; sp.N = hp.n; sp.tiles_x = hp.tiles_x; sp.n_tiles = hp.n_tiles; sp.m0 = m0;
+    sp.w_stride = w_stride;
+    sp.H = hp.H; sp.W = hp.W; sp.N = hp.n; sp.tiles_x = hp.tiles_x; sp.n_tiles = hp.n_tiles;
     // Consecutive chunks are summed in one block (in ascending position order, as one longer
     // chunk) while the grid keeps about kScatterBlocks blocks: fewer partial planes to write
     // and reduce when many slices are scattered at once.
@@ -677,7 +851,7 @@ ms_status ms_workspace_size(const ms_problem *pb, size_t budget_bytes, size_t *w
         if ((int)hp.dz_unique.size() > table_capacity(hp.n))
             return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(table_capacity(hp.n)) + " distinct slice distances");
         size_t ne = tile_entries(hp);
-        int64_t B = choose_batch(hp, ne, budget_bytes);
+        int64_t B = choose_storage(hp, ne, budget_bytes, pb->checkpoint_every);
         if (B < 1) return fail(MS_ERR_BUDGET, "budget too small for a single position");
         *ws_bytes = make_layout(hp, B, ne).total;
         return MS_OK;
@@ -709,7 +883,7 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
             return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(table_capacity(hp.n)) + " distinct slice distances");
         }
         size_t ne = tile_entries(hp);
-        int64_t B = choose_batch(hp, ne, ws_bytes);
+        int64_t B = choose_storage(hp, ne, ws_bytes, pb->checkpoint_every);
         if (B < 1) { delete p; return fail(MS_ERR_BUDGET, "workspace too small for a single position"); }
         build_lists(hp, B);
         p->L = make_layout(hp, B, ne);
@@ -862,6 +1036,8 @@ int64_t ms_plan_batch(const ms_plan *plan) { return plan ? plan->hp.B : 0; }
 
 int32_t ms_plan_shift_classes(const ms_plan *plan) { return plan ? plan->hp.C : 0; }
 
+int32_t ms_plan_checkpoint_every(const ms_plan *plan) { return plan ? plan->hp.K : 0; }
+
 ms_status ms_plan_set_objective(ms_plan *p, int32_t objective)
 {
     g_err.clear();
@@ -984,7 +1160,10 @@ ms_status ms_adjoint(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c
         int64_t s0 = (int64_t)b * hp.B;
         int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
         fp.pos_list = p->at<int>(p->L.pos_list) + s0;
-        launch_fused(p, kAdjoint, fp, count, st);
+        if (p->recompute())
+            adjoint_recompute(p, fp, b, count, st, reinterpret_cast<float2 *>(grad_slices), nullptr, b > 0);
+        else
+            launch_fused(p, kAdjoint, fp, count, st);
         // the loss and the probe-gradient reductions read only the per-position outputs: they
         // run on the side stream while the slice scatter runs here; the next batch (which
         // overwrites those outputs) and the return wait for them
@@ -1001,7 +1180,9 @@ ms_status ms_adjoint(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c
             if (b + 1 == hp.nb) probe_gradient(p, reinterpret_cast<float2 *>(grad_probe), p->side);
         }
         if (hipEventRecord(p->ev_join, p->side) != hipSuccess) return check_hip("ms_adjoint join");
-        scatter(p, b, count, 0, hp.M, reinterpret_cast<float2 *>(grad_slices), nullptr, b > 0, st);
+        if (!p->recompute())
+            scatter(p, b, count, fp.waves, fp.wave_stride, nullptr, 0, hp.M, reinterpret_cast<float2 *>(grad_slices),
+                    nullptr, b > 0, st);
         if (hipStreamWaitEvent(st, p->ev_join, 0) != hipSuccess) return check_hip("ms_adjoint join");
     }
     return check_hip("ms_adjoint");
@@ -1035,7 +1216,7 @@ ms_status ms_layer_step(ms_plan *p, hipStream_t st, int32_t layer, int32_t k_ste
             int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
             fp.pos_list = p->at<int>(p->L.pos_list) + s0;
             launch_fused(p, kLayer, fp, count, st);
-            scatter(p, b, count, layer, 1, g, w, b > 0, st);
+            scatter(p, b, count, fp.waves, fp.wave_stride, fp.overlap_patch, fp.ovl_stride, 1, g, w, b > 0, st);
             {
                 int n_loss;
                 const double *lsrc = loss_entries(p, count, &n_loss);
@@ -1086,8 +1267,12 @@ ms_status ms_full_step(ms_plan *p, hipStream_t st, int32_t k_steps, double step_
             int64_t s0 = (int64_t)b * hp.B;
             int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
             fp.pos_list = p->at<int>(p->L.pos_list) + s0;
-            launch_fused(p, kAdjoint, fp, count, st);
-            scatter(p, b, count, 0, M, g, w, b > 0, st);
+            if (p->recompute()) {
+                adjoint_recompute(p, fp, b, count, st, g, w, b > 0);
+            } else {
+                launch_fused(p, kAdjoint, fp, count, st);
+                scatter(p, b, count, fp.waves, fp.wave_stride, fp.overlap_patch, fp.ovl_stride, M, g, w, b > 0, st);
+            }
             int n_loss;
             const double *lsrc = loss_entries(p, count, &n_loss);
             loss_sum_kernel<<<1, 256, 0, st>>>(lsrc, n_loss, total, b > 0);

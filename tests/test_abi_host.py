@@ -46,6 +46,34 @@ def test_workspace_size_accepts_a_valid_problem():
     assert 0 < ws_small <= ws // 2
 
 
+def test_checkpoint_interval_sets_the_wave_storage():
+    """checkpoint_every = k keeps floor((M - 1) / k) stored waves and one work slot a position instead
+    of M; k = 0 takes the smallest k whose waves fit the budget with every position in one batch,
+    and only below the k = M footprint cuts the positions into batches."""
+    geo = configs.CFG4
+    args = dict(n=geo.n, obj_h=geo.obj_h, obj_w=geo.obj_w, n_slices=geo.n_slices, positions=geo.positions(),
+                dz=geo.gaps(), pixel_size=geo.pixel_size, wavelength=geo.wavelength)
+    ws = {}
+    for k in (1, 2, 3, 4, 12, 40):
+        pb, keep = abi.make_problem(checkpoint_every=k, **args)
+        ws[k] = abi.workspace_size(pb)
+    assert ws[1] > ws[2] > ws[3] > ws[4] > ws[12] == ws[40]
+    # one position's waves: 12 slots of 256^2 complex64 against 1 slot (+ the recomputation buffers)
+    per_slot = geo.n_pos * geo.n * geo.n * 8
+    assert ws[1] - ws[12] > 9 * per_slot
+    pb, keep = abi.make_problem(checkpoint_every=0, **args)
+    assert abi.workspace_size(pb) == ws[1]                      # no budget: every wave
+    assert abi.workspace_size(pb, budget_bytes=ws[1]) == ws[1]
+    assert abi.workspace_size(pb, budget_bytes=ws[3]) == ws[3]   # k = 2 does not fit, k = 3 does
+    assert abi.workspace_size(pb, budget_bytes=ws[3] - 1) == ws[4]
+    small = abi.workspace_size(pb, budget_bytes=ws[12] // 2)     # batches, no wave stored
+    assert small <= ws[12] // 2
+    pb, keep = abi.make_problem(checkpoint_every=-1, **args)
+    with pytest.raises(abi.MsError) as e:
+        abi.workspace_size(pb)
+    assert e.value.status == abi.MS_ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("kw, status", [
     (dict(n=24), abi.MS_ERR_INVALID_ARG),
     (dict(n=8), abi.MS_ERR_INVALID_ARG),
