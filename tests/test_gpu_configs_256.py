@@ -111,8 +111,8 @@ def test_config4_full_size_forward_and_batched_adjoint(dev):
     probe = oracle.probe(geo.n, geo.pixel_size, geo.wavelength, geo.alpha, geo.defocus).astype(np.complex64)
     truth = synth.transmissions(synth.specimen(geo))
     start = synth.unit_phase_field(truth.shape, geo.seed + 3, 0.3)
-    # a 16 GiB budget splits the scan into batches
-    plan = abi.Plan.from_geometry(geo, budget_bytes=16 << 30, device=dev)
+    # with every wave stored, a 16 GiB budget splits the scan into batches
+    plan = abi.Plan.from_geometry(geo, budget_bytes=16 << 30, device=dev, checkpoint_every=1)
     assert plan.batch < geo.n_pos
     p = _t(probe, dev)
     inten = plan.forward(p, _t(start, dev))

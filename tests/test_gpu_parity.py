@@ -26,7 +26,9 @@ def dev():
 
 def _plan(case, dev, budget=0):
     from paper_2205_03902_amd import abi
-    return abi.Plan.from_geometry(case.geo, positions=case.model.positions, budget_bytes=budget, device=dev)
+    # every wave stored: a budget then splits the positions into batches
+    return abi.Plan.from_geometry(case.geo, positions=case.model.positions, budget_bytes=budget, device=dev,
+                                  checkpoint_every=1)
 
 
 def _t(x, dev):

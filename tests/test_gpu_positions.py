@@ -37,7 +37,9 @@ def _t(x, dev):
 
 def _plan(c, dev, path, budget=0):
     from paper_2205_03902_amd import abi
-    plan = abi.Plan.from_geometry(c.geo, positions=c.model.positions, budget_bytes=budget, device=dev)
+    # every wave stored: a budget then splits the positions into batches
+    plan = abi.Plan.from_geometry(c.geo, positions=c.model.positions, budget_bytes=budget, device=dev,
+                                  checkpoint_every=1)
     plan.set_path(path)
     return plan
 
