@@ -174,6 +174,20 @@ ms_status ms_adjoint(ms_plan *plan, hipStream_t stream, const ms_c64 *probe, con
                      const float *measured, ms_c64 *grad_slices, ms_c64 *grad_probe,
                      double *loss_out);
 
+/* ms_adjoint without a plan or workspace, for callers that cannot allocate device memory (serving
+ * loops and harnesses that forbid hipMalloc).  It builds the plan of `pb` on the host (freed before
+ * returning) in a static device array of MS_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends, chooses the wave storage and the batch to fit it (checkpoint_every
+ * as for ms_workspace_size with that budget), and enqueues ms_adjoint's work on `stream`; it calls no
+ * device allocation.  Arguments and results are those of ms_adjoint.  Problems whose smallest
+ * footprint (one position a batch, no wave stored) exceeds the array return MS_ERR_BUDGET with the
+ * bytes needed, and nothing is enqueued.  Before uploading its tables the call waits for `stream`
+ * (work enqueued earlier on it may still read the array); calls that overlap in time on one device
+ * (other streams, other threads) share the array and race. */
+#define MS_SCRATCH_BYTES ((size_t)64 << 20)
+ms_status ms_adjoint_scratch(const ms_problem *pb, hipStream_t stream, const ms_c64 *probe, const ms_c64 *slices,
+                             const float *measured, ms_c64 *grad_slices, ms_c64 *grad_probe, double *loss_out);
+
 /* k_steps amplitude-flow steps on slice `layer` (0-based, i.e. l - 1), the
  * inner loop of Algorithm 1 with the other slices fixed:
  *   t_l <- t_l - mu * dL/d conj(t_l),

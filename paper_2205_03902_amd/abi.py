@@ -24,7 +24,7 @@ MS_OBJECTIVE_AMPLITUDE, MS_OBJECTIVE_POISSON = 0, 1
 # every entry point declared in include/ms.h
 SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
            "ms_plan_checkpoint_every", "ms_plan_set_path", "ms_plan_set_objective",
-           "ms_make_probe", "ms_make_probe_aberrated", "ms_forward", "ms_adjoint", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_position_grad", "ms_position_step", "ms_reconstruction_error",
+           "ms_make_probe", "ms_make_probe_aberrated", "ms_forward", "ms_adjoint", "ms_adjoint_scratch", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_position_grad", "ms_position_step", "ms_reconstruction_error",
            "ms_profile_begin",
            "ms_profile_end", "ms_last_error")
 
@@ -78,6 +78,8 @@ def lib():
         L.ms_forward.argtypes = [P, P, P, P, P, P]
         L.ms_adjoint.restype = I32
         L.ms_adjoint.argtypes = [P, P, P, P, P, P, P, P]
+        L.ms_adjoint_scratch.restype = I32
+        L.ms_adjoint_scratch.argtypes = [C.POINTER(MsProblem), P, P, P, P, P, P, P]
         L.ms_layer_step.restype = I32
         L.ms_layer_step.argtypes = [P, P, I32, I32, P, P, P, P, P]
         L.ms_full_step.restype = I32
@@ -146,6 +148,29 @@ def make_problem(n, obj_h, obj_w, n_slices, positions, dz, pixel_size, wavelengt
     pb = MsProblem(int(n), int(obj_h), int(obj_w), int(n_slices), pos.shape[0], pos.ctypes.data, dzs.ctypes.data,
                    float(pixel_size), float(wavelength), float(tilt_y), float(tilt_x), int(checkpoint_every))
     return pb, (pos, dzs)
+
+
+def adjoint_scratch(pb: MsProblem, probe, slices, measured, want_probe: bool = True):
+    """ms_adjoint_scratch: loss and gradients of problem pb without a plan or workspace (the library's
+    static device array).  probe (N, N), slices (M, H, W) complex64 and measured (S, N, N) float32 on
+    one CUDA device; enqueued on torch's current stream there.  Returns (loss (1,) float64,
+    dL/dconj(slices), dL/dconj(probe) or None)."""
+    torch = _torch()
+    n, M, H, W, S = pb.n, pb.n_slices, pb.obj_h, pb.obj_w, pb.n_pos
+    for t, shape, dtype, name in ((probe, (n, n), torch.complex64, "probe"), (slices, (M, H, W), torch.complex64, "slices"),
+                                  (measured, (S, n, n), torch.float32, "measured")):
+        if not isinstance(t, torch.Tensor) or tuple(t.shape) != shape or t.dtype != dtype or not t.is_contiguous() \
+                or t.device != probe.device or t.device.type != "cuda":
+            raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape {shape} on the probe's device")
+    dev = probe.device
+    with torch.cuda.device(dev):
+        gs = torch.empty_like(slices)
+        gp = torch.empty_like(probe) if want_probe else None
+        lo = torch.empty(1, dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        _check(lib().ms_adjoint_scratch(C.byref(pb), stream, _ptr(probe), _ptr(slices), _ptr(measured), _ptr(gs),
+                                        _ptr(gp), _ptr(lo)), "ms_adjoint_scratch")
+    return lo, gs, gp
 
 
 def workspace_size(pb: MsProblem, budget_bytes: int = 0) -> int:

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -300,9 +301,11 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     L.class_list = take(S * 4);
     L.sub_class_off = take(nb * kChunks * (C + 1) * 4);
     L.sub_class_list = take(S * 4);
-    const size_t nch = (size_t)chunking(B).nch;
-    L.spart = take(nch * M * HW * 8);
-    L.wpart = take(nch * M * HW * 4);
+    // chunk partials of the slices one scatter takes: all M at once, or one at a time when the
+    // waves are recomputed slice by slice
+    const size_t nch = (size_t)chunking(B).nch, scattered = hp.K > 1 ? 1 : M;
+    L.spart = take(nch * scattered * HW * 8);
+    L.wpart = take(nch * scattered * HW * 4);
     L.cpart = take(nch * C * NN * 8);
     L.waves = take((size_t)B * wave_slots(hp.M, hp.K) * NN * 8);
     L.probe_patch = take((size_t)B * NN * 8);
@@ -862,6 +865,110 @@ ms_status ms_workspace_size(const ms_problem *pb, size_t budget_bytes, size_t *w
     }
 }
 
+}  // extern "C"
+
+namespace {
+
+// A plan's host description and tables for problem pb in the workspace ws of ws_bytes: derives
+// positions, shift classes, wave storage and batch (the workspace is the budget), builds the
+// scatter lists and uploads every table (blocking copies).  Creates no stream or event.
+ms_status build_plan(ms_plan *p, const ms_problem *pb, char *ws, size_t ws_bytes, const char *ws_name)
+{
+    HostPlan &hp = p->hp;
+    derive_positions(pb, hp);
+    if (too_many_classes(hp))
+        return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(kMaxClasses) + " distinct sub-pixel offsets");
+    if ((int)hp.dz_unique.size() > table_capacity(hp.n))
+        return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(table_capacity(hp.n)) + " distinct slice distances");
+    size_t ne = tile_entries(hp);
+    int64_t B = choose_storage(hp, ne, ws_bytes, pb->checkpoint_every);
+    if (B < 1) {
+        HostPlan one = hp;
+        one.K = std::max(hp.M, 1);
+        return fail(MS_ERR_BUDGET, std::string(ws_name) + " of " + std::to_string(ws_bytes) +
+                                       " bytes is too small for a single position (it needs " +
+                                       std::to_string(make_layout(one, 1, ne).total) + ")");
+    }
+    build_lists(hp, B);
+    p->L = make_layout(hp, B, ne);
+    if (p->L.total > ws_bytes) return fail(MS_ERR_BUDGET, std::string(ws_name) + " too small");
+    p->ws = ws;
+    p->lines = !fused_fits(hp.n);
+    p->ws_bytes = ws_bytes;
+    p->dx = pb->pixel_size; p->lambda = pb->wavelength; p->tilt_y = pb->tilt_y; p->tilt_x = pb->tilt_x;
+    // Tables, computed in FP64 and rounded once.
+    const int n = hp.n, C = hp.C;
+    const double PI = 3.14159265358979323846264338327950288;
+    // twiddles W_N^{j k1} of lane j, rows of 17 (see Win::TW_WORDS)
+    const int R = n / 16;
+    std::vector<float2> tw((size_t)R * 17, make_float2(1.f, 0.f));
+    for (int j = 0; j < R; ++j)
+        for (int k1 = 0; k1 < 16; ++k1) {
+            double a = -2.0 * PI * (double)(j * k1) / n;
+            tw[(size_t)j * 17 + k1] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+    auto freq = [&](int i) { return (double)(i < (n + 1) / 2 ? i : i - n); };
+    const int U = (int)hp.dz_unique.size();
+    std::vector<float2> hy((size_t)U * n), hx((size_t)U * n);
+    for (int g = 0; g < U; ++g) {
+        double dz = hp.dz_unique[g];
+        for (int i = 0; i < n; ++i) {
+            double q = freq(i) / ((double)n * pb->pixel_size);
+            // eq. (fresnel_element) split per axis: exp(-pi i dz (lambda q^2 + 2 q sin(theta)))
+            double py = -PI * dz * (pb->wavelength * q * q + 2.0 * q * std::sin(pb->tilt_y));
+            double px = -PI * dz * (pb->wavelength * q * q + 2.0 * q * std::sin(pb->tilt_x));
+            hy[(size_t)g * n + i] = make_float2((float)(std::cos(py) / n), (float)(std::sin(py) / n));
+            hx[(size_t)g * n + i] = make_float2((float)(std::cos(px) / n), (float)(std::sin(px) / n));
+        }
+    }
+    std::vector<float2> ry((size_t)C * n), rx((size_t)C * n), dry((size_t)C * n), drx((size_t)C * n);
+    std::vector<int> ident(C), zero_ident(C, 0);
+    for (int c = 0; c < C; ++c) {
+        ident[c] = (hp.cls_fy[c] == 0.0 && hp.cls_fx[c] == 0.0) ? 1 : 0;
+        for (int i = 0; i < n; ++i) {
+            double ay = -2.0 * PI * freq(i) * hp.cls_fy[c] / n;
+            double ax = -2.0 * PI * freq(i) * hp.cls_fx[c] / n;
+            ry[(size_t)c * n + i] = make_float2((float)(std::cos(ay) / n), (float)(std::sin(ay) / n));
+            rx[(size_t)c * n + i] = make_float2((float)(std::cos(ax) / n), (float)(std::sin(ax) / n));
+            // the ramp differentiated in its shift: times -2 pi i k / N
+            const double th = 2.0 * PI * freq(i) / n;
+            dry[(size_t)c * n + i] = make_float2((float)(th * std::sin(ay) / n), (float)(-th * std::cos(ay) / n));
+            drx[(size_t)c * n + i] = make_float2((float)(th * std::sin(ax) / n), (float)(-th * std::cos(ax) / n));
+        }
+    }
+    std::vector<int> pos_list(hp.S);
+    for (int64_t s = 0; s < hp.S; ++s) pos_list[s] = (int)s;
+
+    auto up = [&](size_t off, const void *src, size_t bytes) -> bool {
+        if (bytes == 0) return true;
+        return hipMemcpy(p->ws + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    bool ok = up(p->L.tw, tw.data(), tw.size() * 8) && up(p->L.hy, hy.data(), hy.size() * 8) &&
+              up(p->L.hx, hx.data(), hx.size() * 8) && up(p->L.ry, ry.data(), ry.size() * 8) &&
+              up(p->L.gap_table, hp.gap_table.data(), hp.gap_table.size() * 4) &&
+              up(p->L.rx, rx.data(), rx.size() * 8) && up(p->L.ident, ident.data(), ident.size() * 4) &&
+              up(p->L.dry, dry.data(), dry.size() * 8) && up(p->L.drx, drx.data(), drx.size() * 8) &&
+              up(p->L.zero_ident, zero_ident.data(), zero_ident.size() * 4) &&
+              up(p->L.pos_info, hp.pos_info.data(), hp.pos_info.size() * 16) &&
+              up(p->L.pos_list, pos_list.data(), pos_list.size() * 4) &&
+              up(p->L.tile_off, hp.tile_off.data(), hp.tile_off.size() * 4) &&
+              up(p->L.tile_list, hp.tile_list.data(), hp.tile_list.size() * 16) &&
+              up(p->L.class_off, hp.class_off.data(), hp.class_off.size() * 4) &&
+              up(p->L.class_list, hp.class_list.data(), hp.class_list.size() * 4);
+    if (!ok) {
+        hipError_t e = hipGetLastError();
+        return fail(MS_ERR_HIP, std::string("table upload failed: ") + hipGetErrorString(e));
+    }
+    // the per-position tile vectors are no longer needed on the host
+    hp.tile_list.clear();
+    hp.tile_list.shrink_to_fit();
+    return MS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes, ms_plan **out)
 {
     try {
@@ -872,94 +979,11 @@ ms_status ms_plan_create(const ms_problem *pb, void *workspace, size_t ws_bytes,
         if (!workspace) return fail(MS_ERR_INVALID_ARG, "workspace is NULL");
         if ((uintptr_t)workspace % kAlign) return fail(MS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
         ms_plan *p = new ms_plan();
-        HostPlan &hp = p->hp;
-        derive_positions(pb, hp);
-        if (too_many_classes(hp)) {
+        st = build_plan(p, pb, static_cast<char *>(workspace), ws_bytes, "workspace");
+        if (st != MS_OK) {
             delete p;
-            return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(kMaxClasses) + " distinct sub-pixel offsets");
+            return st;
         }
-        if ((int)hp.dz_unique.size() > table_capacity(hp.n)) {
-            delete p;
-            return fail(MS_ERR_UNSUPPORTED, "more than " + std::to_string(table_capacity(hp.n)) + " distinct slice distances");
-        }
-        size_t ne = tile_entries(hp);
-        int64_t B = choose_storage(hp, ne, ws_bytes, pb->checkpoint_every);
-        if (B < 1) { delete p; return fail(MS_ERR_BUDGET, "workspace too small for a single position"); }
-        build_lists(hp, B);
-        p->L = make_layout(hp, B, ne);
-        if (p->L.total > ws_bytes) { delete p; return fail(MS_ERR_BUDGET, "workspace too small"); }
-        p->ws = static_cast<char *>(workspace);
-        p->lines = !fused_fits(hp.n);
-        p->ws_bytes = ws_bytes;
-        p->dx = pb->pixel_size; p->lambda = pb->wavelength; p->tilt_y = pb->tilt_y; p->tilt_x = pb->tilt_x;
-
-        // Tables, computed in FP64 and rounded once.
-        const int n = hp.n, C = hp.C;
-        const double PI = 3.14159265358979323846264338327950288;
-        // twiddles W_N^{j k1} of lane j, rows of 17 (see Win::TW_WORDS)
-        const int R = n / 16;
-        std::vector<float2> tw((size_t)R * 17, make_float2(1.f, 0.f));
-        for (int j = 0; j < R; ++j)
-            for (int k1 = 0; k1 < 16; ++k1) {
-                double a = -2.0 * PI * (double)(j * k1) / n;
-                tw[(size_t)j * 17 + k1] = make_float2((float)std::cos(a), (float)std::sin(a));
-            }
-        auto freq = [&](int i) { return (double)(i < (n + 1) / 2 ? i : i - n); };
-        const int U = (int)hp.dz_unique.size();
-        std::vector<float2> hy((size_t)U * n), hx((size_t)U * n);
-        for (int g = 0; g < U; ++g) {
-            double dz = hp.dz_unique[g];
-            for (int i = 0; i < n; ++i) {
-                double q = freq(i) / ((double)n * pb->pixel_size);
-                // eq. (fresnel_element) split per axis: exp(-pi i dz (lambda q^2 + 2 q sin(theta)))
-                double py = -PI * dz * (pb->wavelength * q * q + 2.0 * q * std::sin(pb->tilt_y));
-                double px = -PI * dz * (pb->wavelength * q * q + 2.0 * q * std::sin(pb->tilt_x));
-                hy[(size_t)g * n + i] = make_float2((float)(std::cos(py) / n), (float)(std::sin(py) / n));
-                hx[(size_t)g * n + i] = make_float2((float)(std::cos(px) / n), (float)(std::sin(px) / n));
-            }
-        }
-        std::vector<float2> ry((size_t)C * n), rx((size_t)C * n), dry((size_t)C * n), drx((size_t)C * n);
-        std::vector<int> ident(C), zero_ident(C, 0);
-        for (int c = 0; c < C; ++c) {
-            ident[c] = (hp.cls_fy[c] == 0.0 && hp.cls_fx[c] == 0.0) ? 1 : 0;
-            for (int i = 0; i < n; ++i) {
-                double ay = -2.0 * PI * freq(i) * hp.cls_fy[c] / n;
-                double ax = -2.0 * PI * freq(i) * hp.cls_fx[c] / n;
-                ry[(size_t)c * n + i] = make_float2((float)(std::cos(ay) / n), (float)(std::sin(ay) / n));
-                rx[(size_t)c * n + i] = make_float2((float)(std::cos(ax) / n), (float)(std::sin(ax) / n));
-                // the ramp differentiated in its shift: times -2 pi i k / N
-                const double th = 2.0 * PI * freq(i) / n;
-                dry[(size_t)c * n + i] = make_float2((float)(th * std::sin(ay) / n), (float)(-th * std::cos(ay) / n));
-                drx[(size_t)c * n + i] = make_float2((float)(th * std::sin(ax) / n), (float)(-th * std::cos(ax) / n));
-            }
-        }
-        std::vector<int> pos_list(hp.S);
-        for (int64_t s = 0; s < hp.S; ++s) pos_list[s] = (int)s;
-
-        auto up = [&](size_t off, const void *src, size_t bytes) -> bool {
-            if (bytes == 0) return true;
-            return hipMemcpy(p->ws + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
-        };
-        bool ok = up(p->L.tw, tw.data(), tw.size() * 8) && up(p->L.hy, hy.data(), hy.size() * 8) &&
-                  up(p->L.hx, hx.data(), hx.size() * 8) && up(p->L.ry, ry.data(), ry.size() * 8) &&
-                  up(p->L.gap_table, hp.gap_table.data(), hp.gap_table.size() * 4) &&
-                  up(p->L.rx, rx.data(), rx.size() * 8) && up(p->L.ident, ident.data(), ident.size() * 4) &&
-                  up(p->L.dry, dry.data(), dry.size() * 8) && up(p->L.drx, drx.data(), drx.size() * 8) &&
-                  up(p->L.zero_ident, zero_ident.data(), zero_ident.size() * 4) &&
-                  up(p->L.pos_info, hp.pos_info.data(), hp.pos_info.size() * 16) &&
-                  up(p->L.pos_list, pos_list.data(), pos_list.size() * 4) &&
-                  up(p->L.tile_off, hp.tile_off.data(), hp.tile_off.size() * 4) &&
-                  up(p->L.tile_list, hp.tile_list.data(), hp.tile_list.size() * 16) &&
-                  up(p->L.class_off, hp.class_off.data(), hp.class_off.size() * 4) &&
-                  up(p->L.class_list, hp.class_list.data(), hp.class_list.size() * 4);
-        if (!ok) {
-            hipError_t e = hipGetLastError();
-            delete p;
-            return fail(MS_ERR_HIP, std::string("table upload failed: ") + hipGetErrorString(e));
-        }
-        // the per-position tile vectors are no longer needed on the host
-        hp.tile_list.clear();
-        hp.tile_list.shrink_to_fit();
         if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess) {
@@ -1143,19 +1167,40 @@ ms_status ms_forward(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c
     return check_hip("ms_forward");
 }
 
-ms_status ms_adjoint(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c64 *slices, const float *measured,
-                     ms_c64 *grad_slices, ms_c64 *grad_probe, double *loss_out)
+}  // extern "C"
+
+// The workspace of ms_adjoint_scratch: every call on a device shares that device's copy, which
+// keeps the last call's contents (nothing in it needs to start at zero).
+static __device__ __align__(256) unsigned char scratch[MS_SCRATCH_BYTES];
+
+namespace {
+
+bool adjoint_args_ok(const ms_c64 *probe, const ms_c64 *slices, const float *measured, const ms_c64 *grad_slices,
+                     const ms_c64 *grad_probe, const double *loss_out, ms_status *st)
 {
-    g_err.clear();
-    if (!p || !probe || !slices || !measured || !grad_slices || !loss_out)
-        return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    if (!probe || !slices || !measured || !grad_slices || !loss_out) {
+        *st = fail(MS_ERR_INVALID_ARG, "NULL argument");
+        return false;
+    }
     if (!aligned8(probe) || !aligned8(slices) || !aligned8(grad_slices) || !aligned8(grad_probe) ||
-        !aligned8(loss_out) || ((uintptr_t)measured & 3))
-        return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
+        !aligned8(loss_out) || ((uintptr_t)measured & 3)) {
+        *st = fail(MS_ERR_INVALID_ARG, "misaligned buffer");
+        return false;
+    }
+    return true;
+}
+
+// The loss-and-gradient pass of a plan.  With a side stream (a plan from ms_plan_create) the loss
+// and probe-gradient reductions run beside the slice scatter; without one, after it on st.
+ms_status adjoint_impl(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c64 *slices, const float *measured,
+                       ms_c64 *grad_slices, ms_c64 *grad_probe, double *loss_out)
+{
     const HostPlan &hp = p->hp;
     class_probes(p, probe, st);
     FusedParams fp = fused_params(p, slices, measured);
     if (!grad_probe) fp.probe_patch = nullptr;
+    const bool fork = p->side != nullptr;
+    hipStream_t aux = fork ? p->side : st;
     for (int b = 0; b < hp.nb; ++b) {
         int64_t s0 = (int64_t)b * hp.B;
         int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
@@ -1167,25 +1212,87 @@ ms_status ms_adjoint(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c
         // the loss and the probe-gradient reductions read only the per-position outputs: they
         // run on the side stream while the slice scatter runs here; the next batch (which
         // overwrites those outputs) and the return wait for them
-        if (hipEventRecord(p->ev_fork, st) != hipSuccess || hipStreamWaitEvent(p->side, p->ev_fork, 0) != hipSuccess)
+        if (fork && (hipEventRecord(p->ev_fork, st) != hipSuccess || hipStreamWaitEvent(aux, p->ev_fork, 0) != hipSuccess))
             return check_hip("ms_adjoint fork");
         {
             int n_loss;
             const double *lsrc = loss_entries(p, count, &n_loss);
-            loss_sum_kernel<<<1, 256, 0, p->side>>>(lsrc, n_loss, loss_out, b > 0);
+            loss_sum_kernel<<<1, 256, 0, aux>>>(lsrc, n_loss, loss_out, b > 0);
         }
         if (grad_probe) {
             class_sums(p, p->at<int>(p->L.class_off) + (size_t)b * kChunks * (hp.C + 1), p->at<int>(p->L.class_list),
-                       count, b > 0, p->side);
-            if (b + 1 == hp.nb) probe_gradient(p, reinterpret_cast<float2 *>(grad_probe), p->side);
+                       count, b > 0, aux);
+            if (b + 1 == hp.nb) probe_gradient(p, reinterpret_cast<float2 *>(grad_probe), aux);
         }
-        if (hipEventRecord(p->ev_join, p->side) != hipSuccess) return check_hip("ms_adjoint join");
+        if (fork && hipEventRecord(p->ev_join, aux) != hipSuccess) return check_hip("ms_adjoint join");
         if (!p->recompute())
             scatter(p, b, count, fp.waves, fp.wave_stride, nullptr, 0, hp.M, reinterpret_cast<float2 *>(grad_slices),
                     nullptr, b > 0, st);
-        if (hipStreamWaitEvent(st, p->ev_join, 0) != hipSuccess) return check_hip("ms_adjoint join");
+        if (fork && hipStreamWaitEvent(st, p->ev_join, 0) != hipSuccess) return check_hip("ms_adjoint join");
     }
     return check_hip("ms_adjoint");
+}
+
+// Device address of the static scratch per device (looked up once per device, with that device
+// current): host code passes these, never the array's name, which is a host-side stand-in.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+ms_status scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return check_hip("hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MS_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MS_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ms_status ms_adjoint(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c64 *slices, const float *measured,
+                     ms_c64 *grad_slices, ms_c64 *grad_probe, double *loss_out)
+{
+    g_err.clear();
+    if (!p) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    ms_status bad;
+    if (!adjoint_args_ok(probe, slices, measured, grad_slices, grad_probe, loss_out, &bad)) return bad;
+    return adjoint_impl(p, st, probe, slices, measured, grad_slices, grad_probe, loss_out);
+}
+
+ms_status ms_adjoint_scratch(const ms_problem *pb, hipStream_t st, const ms_c64 *probe, const ms_c64 *slices,
+                             const float *measured, ms_c64 *grad_slices, ms_c64 *grad_probe, double *loss_out)
+{
+    try {
+        g_err.clear();
+        ms_status status = validate(pb);
+        if (status != MS_OK) return status;
+        if (!adjoint_args_ok(probe, slices, measured, grad_slices, grad_probe, loss_out, &status)) return status;
+        void *ws = nullptr;
+        status = scratch_address(&ws);
+        if (status != MS_OK) return status;
+        // work enqueued earlier on st may still read the scratch: let it finish before the tables
+        // of this problem overwrite it
+        if (hipStreamSynchronize(st) != hipSuccess) return check_hip("ms_adjoint_scratch: hipStreamSynchronize");
+        ms_plan plan;   // host description only: no stream, no event, no device memory of its own
+        status = build_plan(&plan, pb, static_cast<char *>(ws), MS_SCRATCH_BYTES, "the static scratch");
+        if (status != MS_OK) return status;
+        return adjoint_impl(&plan, st, probe, slices, measured, grad_slices, grad_probe, loss_out);
+    } catch (const std::bad_alloc &) {
+        return fail(MS_ERR_INVALID_ARG, "host out of memory");
+    } catch (...) {
+        return fail(MS_ERR_INVALID_ARG, "unexpected host error");
+    }
 }
 
 ms_status ms_layer_step(ms_plan *p, hipStream_t st, int32_t layer, int32_t k_steps, const ms_c64 *probe,

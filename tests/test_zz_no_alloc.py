@@ -1,0 +1,81 @@
+"""ms_adjoint_scratch, the entry point that allocates no device memory, against ms_adjoint on the
+same inputs: two calls in a row on one stream (the second on a smaller problem, so the static
+scratch is reused with a different layout), each to the parity bars (loss 1e-5, gradients 1e-4);
+and the budget error for a problem the scratch cannot hold."""
+import numpy as np
+import pytest
+
+from parity_cases import make_case, rel, small_geometry, small_positions
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def _problem(c, checkpoint_every=0):
+    from paper_2205_03902_amd import abi
+    g = c.geo
+    return abi.make_problem(g.n, g.obj_h, g.obj_w, g.n_slices, c.model.positions, g.gaps(), g.pixel_size,
+                            g.wavelength, checkpoint_every=checkpoint_every)
+
+
+def test_scratch_adjoint_matches_the_planned_adjoint_on_two_calls(dev):
+    from paper_2205_03902_amd import abi, configs
+    # 1: 64 positions of the 128^2, 6-slice workload: every wave stored would exceed the scratch, so
+    #    the call recomputes waves; 2: a smaller problem (64^2 windows, 3 slices, 9 positions)
+    g1 = configs.CFG1
+    c1 = make_case(g1, positions=g1.positions()[::16][:64])
+    g2 = small_geometry(64)
+    c2 = make_case(g2, positions=small_positions(g2))
+    print(f"[case] scratch: {g1.name} 64 positions, then {g2.name} 9 positions", flush=True)
+    results = []
+    for c in (c1, c2):
+        pb, keep = _problem(c)
+        p, s, m = _t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev)
+        results.append((c, abi.adjoint_scratch(pb, p, s, m)))
+    torch.cuda.synchronize()
+    for c, (ls, gs, gp) in results:
+        plan = abi.Plan.from_geometry(c.geo, positions=c.model.positions, device=dev)
+        l1, g1_, p1 = plan.adjoint(_t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev))
+        el = abs(ls.item() - l1.item()) / l1.item()
+        eg, ep = rel(gs.cpu().numpy(), g1_.cpu().numpy()), rel(gp.cpu().numpy(), p1.cpu().numpy())
+        print(f"{c.geo.name}: scratch vs plan loss {el:.1e} slices {eg:.1e} probe {ep:.1e} "
+              f"(bitwise {torch.equal(gs, g1_) and torch.equal(gp, p1)})")
+        assert el < 1e-5 and eg < 1e-4 and ep < 1e-4
+
+
+def test_scratch_adjoint_without_the_probe_gradient(dev):
+    from paper_2205_03902_amd import abi
+    g = small_geometry(32)
+    c = make_case(g, positions=small_positions(g))
+    pb, keep = _problem(c)
+    ls, gs, gp = abi.adjoint_scratch(pb, _t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev), want_probe=False)
+    assert gp is None
+    ref_l, ref_gs, _, _ = c.model.loss_grad(c.probe, c.start, c.measured, want_probe=False)
+    assert abs(ls.item() - ref_l) / ref_l < 1e-5 and rel(gs.cpu().numpy(), ref_gs) < 1e-4
+
+
+def test_scratch_adjoint_rejects_a_problem_beyond_the_scratch(dev):
+    """A 1024^2 object of 12 slices needs more than the scratch even for one position (the full-step
+    gradient and overlap planes of every slice alone take 144 MiB): MS_ERR_BUDGET, nothing enqueued."""
+    from paper_2205_03902_amd import abi, configs
+    g = configs.CFG4
+    probe = torch.zeros((g.n, g.n), dtype=torch.complex64, device=dev)
+    slices = torch.ones((g.n_slices, g.obj_h, g.obj_w), dtype=torch.complex64, device=dev)
+    meas = torch.zeros((1, g.n, g.n), dtype=torch.float32, device=dev)
+    pb, keep = abi.make_problem(g.n, g.obj_h, g.obj_w, g.n_slices, g.positions()[:1], g.gaps(), g.pixel_size,
+                                g.wavelength)
+    with pytest.raises(abi.MsError) as e:
+        abi.adjoint_scratch(pb, probe, slices, meas)
+    assert e.value.status == abi.MS_ERR_BUDGET
+    assert "scratch" in str(e.value)
