@@ -243,16 +243,23 @@ ms_status ms_position_step(ms_plan *plan, hipStream_t stream, double step_scale,
                            const ms_c64 *slices, const float *measured, double *positions, double *loss_out);
 
 /* The relative reconstruction error of the experiments (Sec. 5), (1/M) sum_m ||O_m - Ohat_m||_F /
- * ||O_m||_F, after removing the ambiguities of the model: each estimated slice is first
- * multiplied by the complex scale alpha_m (phase and amplitude, least squares) that brings it
- * closest to the reference, so that the error of slice m is
- *   sqrt(||ref||^2 - |<est, ref>|^2 / ||est||^2) / ||ref||   (1 where est is 0),
- * with every sum over the pixels where mask > 0 (mask: H x W floats, or NULL for all pixels;
- * pixels no window covers carry no information).  est, ref: [M][H][W]; hw = H W.  err_out:
- * device double [M + 1], the error of each slice and then their mean.  FP64 sums in a fixed
- * order.  No plan is needed. */
+ * ||O_m||_F, after removing the ambiguities of the model.  Intensities do not change when every
+ * slice is translated together (and the probe the other way), so the estimate is first translated
+ * periodically by the integer d = (d_y, d_x), |d_y|, |d_x| <= max_shift, Ohat_d[y][x] =
+ * Ohat[(y - d_y) mod H][(x - d_x) mod W]; each translated slice is then multiplied by the complex
+ * scale alpha_m (phase and amplitude, least squares) that brings it closest to the reference, so that
+ * the error of slice m is
+ *   sqrt(||ref||^2 - |<est_d, ref>|^2 / ||est_d||^2) / ||ref||   (1 where est_d is 0),
+ * with every sum over the reference pixels where mask > 0 (mask: H x W floats, or NULL for all
+ * pixels; pixels no window covers carry no information).  The translation taken is the one with the
+ * smallest mean error, the first minimum when d_y and then d_x run upwards; max_shift = 0 compares
+ * without translation.  est, ref: [M][H][W]; max_shift in [0, 64] and below H and W.  work: device
+ * double [(2 max_shift + 1)^2 (M + 1)] (overwritten).  err_out: device double [M + 1], the error of
+ * each slice and then their mean, at that translation; shift_out: device int32 [2] (d_y, d_x) or NULL.
+ * FP64 sums in a fixed order.  No plan is needed. */
 ms_status ms_reconstruction_error(hipStream_t stream, const ms_c64 *est, const ms_c64 *ref, const float *mask,
-                                  int32_t n_slices, int64_t hw, double *err_out);
+                                  int32_t n_slices, int32_t obj_h, int32_t obj_w, int32_t max_shift, double *work,
+                                  double *err_out, int32_t *shift_out);
 
 /* Timing of the dominant kernel (the fused per-position multislice kernel).
  * After ms_profile_begin, the next max_launches launches of that kernel made

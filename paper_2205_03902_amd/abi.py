@@ -91,7 +91,7 @@ def lib():
         L.ms_position_step.restype = I32
         L.ms_position_step.argtypes = [P, P, D, P, P, P, P, P]
         L.ms_reconstruction_error.restype = I32
-        L.ms_reconstruction_error.argtypes = [P, P, P, P, I32, I64, P]
+        L.ms_reconstruction_error.argtypes = [P, P, P, P, I32, I32, I32, I32, P, P, P]
         L.ms_profile_begin.restype = I32
         L.ms_profile_begin.argtypes = [P, I32]
         L.ms_profile_end.restype = I32
@@ -102,23 +102,25 @@ def lib():
     return _lib
 
 
-def reconstruction_error(est, ref, mask=None, out=None):
-    """Relative reconstruction error after the per-slice least-squares complex scale
-    (ms_reconstruction_error): device float64 [M + 1], the slices' errors and their mean.
-    est, ref: complex64 (M, H, W) on one device; mask: float32 (H, W) or None."""
+def reconstruction_error(est, ref, mask=None, out=None, max_shift: int = 0, shift=None):
+    """The relative reconstruction error of Sec. 5 after the model's ambiguities
+    (ms_reconstruction_error): device float64 [M + 1], the slices' errors and their mean, at the
+    best common translation |d| <= max_shift of the estimate (written to `shift`, a device int32 [2],
+    if given).  est, ref: complex64 (M, H, W); mask: float32 (H, W) or None."""
     torch = _torch()
-    if est.shape != ref.shape or est.dim() != 3 or est.dtype != torch.complex64 or ref.dtype != torch.complex64:
-        raise ValueError("est and ref must be complex64 tensors of one shape (M, H, W)")
-    if not (est.is_contiguous() and ref.is_contiguous()) or est.device != ref.device:
-        raise ValueError("est and ref must be contiguous and on one device")
     M, H, W = est.shape
-    if mask is not None and (mask.shape != (H, W) or mask.dtype != torch.float32 or not mask.is_contiguous()
-                             or mask.device != est.device):
-        raise ValueError("mask must be a contiguous float32 (H, W) tensor on the device of est")
-    out = torch.empty(M + 1, dtype=torch.float64, device=est.device) if out is None else out
-    stream = torch.cuda.current_stream(est.device).cuda_stream
-    _check(lib().ms_reconstruction_error(stream, est.data_ptr(), ref.data_ptr(), _ptr(mask), int(M), int(H * W),
-                                         out.data_ptr()), "ms_reconstruction_error")
+    if ref.shape != est.shape or est.dtype != torch.complex64 or ref.dtype != torch.complex64:
+        raise ValueError("est and ref must be complex64 tensors of one shape (M, H, W)")
+    if mask is not None and (tuple(mask.shape) != (H, W) or mask.dtype != torch.float32):
+        raise ValueError("mask must be float32 (H, W)")
+    if out is None:
+        out = torch.empty(M + 1, dtype=torch.float64, device=est.device)
+    side = 2 * int(max_shift) + 1
+    work = torch.empty(side * side * (M + 1), dtype=torch.float64, device=est.device)
+    stream = _torch().cuda.current_stream(est.device).cuda_stream
+    _check(lib().ms_reconstruction_error(stream, est.data_ptr(), ref.data_ptr(), _ptr(mask), int(M), int(H), int(W),
+                                         int(max_shift), work.data_ptr(), out.data_ptr(), _ptr(shift)),
+           "ms_reconstruction_error")
     return out
 
 

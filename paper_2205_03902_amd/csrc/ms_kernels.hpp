@@ -861,19 +861,29 @@ __global__ __launch_bounds__(256) void position_grad_kernel(const float2 *patch,
     }
 }
 
-// Relative error of slice m = blockIdx.x after the least-squares complex scale:
-// err[m] = sqrt(||ref||^2 - |<est, ref>|^2 / ||est||^2) / ||ref|| over the masked pixels
-// (1 where est is 0 and ref is not, 0 where ref is 0).  FP64 sums, fixed order.
-__global__ __launch_bounds__(256) void recon_slice_kernel(const float2 *est, const float2 *ref, const float *mask,
-                                                          long long hw, double *err)
+// Relative reconstruction error of the experiments (Sec. 5) at every translation tried.  Block
+// (k, m) takes slice m of the estimate translated by d_k (periodically: est[(y - d_y) mod H]
+// [(x - d_x) mod W] at reference pixel (y, x)), and over the reference pixels where mask > 0 forms in
+// FP64, in a fixed order, <est_d, ref>, ||est_d||^2 and ||ref||^2; the error with the least-squares
+// complex scale is sqrt(||ref||^2 - |<est_d, ref>|^2 / ||est_d||^2) / ||ref|| (1 where est_d is 0).
+// d_k = (k / (2 r + 1) - r, k mod (2 r + 1) - r), r = max_shift < min(H, W).  err: [n_shifts][M + 1].
+__global__ __launch_bounds__(256) void recon_shift_kernel(const float2 *est, const float2 *ref, const float *mask,
+                                                          int H, int W, int max_shift, int M, double *err)
 {
     __shared__ double red[4][256];
-    const int m = blockIdx.x, t = threadIdx.x;
+    const int k = blockIdx.x, m = blockIdx.y, t = threadIdx.x;
+    const int side = 2 * max_shift + 1;
+    const int dy = k / side - max_shift, dx = k % side - max_shift;
+    const long long hw = (long long)H * W;
     const float2 *e = est + (size_t)m * hw, *r = ref + (size_t)m * hw;
     double xr = 0.0, xi = 0.0, ee = 0.0, rr = 0.0;
     for (long long i = t; i < hw; i += 256) {
         if (mask && !(mask[i] > 0.0f)) continue;
-        const float2 a = e[i], b = r[i];
+        const int y = (int)(i / W), x = (int)(i - (long long)y * W);
+        int ys = y - dy, xs = x - dx;
+        if (ys < 0) ys += H; else if (ys >= H) ys -= H;
+        if (xs < 0) xs += W; else if (xs >= W) xs -= W;
+        const float2 a = e[(size_t)ys * W + xs], b = r[i];
         xr += (double)a.x * b.x + (double)a.y * b.y;
         xi += (double)a.x * b.y - (double)a.y * b.x;
         ee += (double)a.x * a.x + (double)a.y * a.y;
@@ -894,16 +904,28 @@ __global__ __launch_bounds__(256) void recon_slice_kernel(const float2 *est, con
         const double x2 = red[0][0] * red[0][0] + red[1][0] * red[1][0], e2 = red[2][0], r2 = red[3][0];
         double v = 0.0;
         if (r2 > 0.0) v = e2 > 0.0 ? sqrt(fmax(0.0, r2 - x2 / e2) / r2) : 1.0;
-        err[m] = v;
+        err[(size_t)k * (M + 1) + m] = v;
     }
 }
 
-// err[M] = the mean of err[0 .. M) (in order).
-__global__ void recon_mean_kernel(double *err, int M)
+// Mean error over the slices of every translation (slices in order), then the translation with the
+// smallest mean, the first one in the order of k: its errors and mean into out[M + 1] and d into
+// shift (if not null).  One thread.
+__global__ void recon_select_kernel(double *err, int n_shifts, int M, int max_shift, double *out, int *shift)
 {
-    double s = 0.0;
-    for (int m = 0; m < M; ++m) s += err[m];
-    err[M] = s / M;
+    int best = 0;
+    for (int k = 0; k < n_shifts; ++k) {
+        double s = 0.0;
+        for (int m = 0; m < M; ++m) s += err[(size_t)k * (M + 1) + m];
+        err[(size_t)k * (M + 1) + M] = s / M;
+        if (err[(size_t)k * (M + 1) + M] < err[(size_t)best * (M + 1) + M]) best = k;
+    }
+    for (int m = 0; m <= M; ++m) out[m] = err[(size_t)best * (M + 1) + m];
+    if (shift) {
+        const int side = 2 * max_shift + 1;
+        shift[0] = best / side - max_shift;
+        shift[1] = best % side - max_shift;
+    }
 }
 
 // positions <- positions - scale grad / curv per coordinate (unchanged where curv is 0).

@@ -826,17 +826,23 @@ extern "C" {
 const char *ms_last_error(void) { return g_err.c_str(); }
 
 ms_status ms_reconstruction_error(hipStream_t st, const ms_c64 *est, const ms_c64 *ref, const float *mask,
-                                  int32_t n_slices, int64_t hw, double *err_out)
+                                  int32_t n_slices, int32_t obj_h, int32_t obj_w, int32_t max_shift, double *work,
+                                  double *err_out, int32_t *shift_out)
 {
     g_err.clear();
-    if (!est || !ref || !err_out) return fail(MS_ERR_INVALID_ARG, "NULL argument");
-    if (n_slices < 1 || n_slices > 4096 || hw < 1 || hw > ((int64_t)1 << 34))
-        return fail(MS_ERR_INVALID_ARG, "n_slices must be in [1, 4096] and hw in [1, 2^34]");
-    if (!aligned8(est) || !aligned8(ref) || !aligned8(err_out) || ((uintptr_t)mask & 3))
+    if (!est || !ref || !err_out || !work) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    if (n_slices < 1 || n_slices > 4096 || obj_h < 1 || obj_w < 1 || (int64_t)obj_h * obj_w > ((int64_t)1 << 30))
+        return fail(MS_ERR_INVALID_ARG, "n_slices must be in [1, 4096] and obj_h obj_w in [1, 2^30]");
+    if (max_shift < 0 || max_shift > 64 || max_shift >= obj_h || max_shift >= obj_w)
+        return fail(MS_ERR_INVALID_ARG, "max_shift must be in [0, 64] and below the object's sides");
+    if (!aligned8(est) || !aligned8(ref) || !aligned8(err_out) || !aligned8(work) || ((uintptr_t)mask & 3) ||
+        ((uintptr_t)shift_out & 3))
         return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
-    recon_slice_kernel<<<n_slices, 256, 0, st>>>(reinterpret_cast<const float2 *>(est),
-                                                  reinterpret_cast<const float2 *>(ref), mask, hw, err_out);
-    recon_mean_kernel<<<1, 1, 0, st>>>(err_out, n_slices);
+    const int side = 2 * max_shift + 1, n_shifts = side * side;
+    recon_shift_kernel<<<dim3(n_shifts, n_slices), 256, 0, st>>>(reinterpret_cast<const float2 *>(est),
+                                                                  reinterpret_cast<const float2 *>(ref), mask, obj_h,
+                                                                  obj_w, max_shift, n_slices, work);
+    recon_select_kernel<<<1, 1, 0, st>>>(work, n_shifts, n_slices, max_shift, err_out, shift_out);
     return check_hip("ms_reconstruction_error");
 }
 

@@ -274,3 +274,25 @@ def test_reconstruction_error_matches_the_oracle(dev):
         errs, mean = metrics.reconstruction_error(est, ref, mk)
         got = abi.reconstruction_error(_t(est, dev), _t(ref, dev), None if mk is None else _t(mk, dev)).cpu().numpy()
         assert np.abs(got[:3] - errs).max() < 1e-9 and abs(got[3] - mean) < 1e-9, (got, errs)
+
+
+def test_translation_aligned_reconstruction_error_matches_the_oracle(dev):
+    """With a common translation of the estimate's slices searched over |d| <= max_shift: the same
+    translation and errors as the oracle's brute-force search, on a translated, rescaled and
+    perturbed copy (with and without a mask) and on an untranslated one."""
+    from oracle import metrics
+    from paper_2205_03902_amd import abi, synth
+    ref = synth.complex_field((3, 70, 90), 33)
+    base = (ref * np.array([0.8 * np.exp(0.4j), 1.2, -1j])[:, None, None]
+            + 0.05 * synth.complex_field((3, 70, 90), 34))
+    mask = np.zeros((70, 90), dtype=np.float32)
+    mask[5:60, 10:80] = 1.0
+    for s, r in (((3, -5), 6), ((0, 0), 2), ((-2, 1), 3)):
+        est = np.roll(base, s, axis=(1, 2)).astype(np.complex64)
+        for mk in (None, mask):
+            errs, mean, d = metrics.reconstruction_error_aligned(est, ref, mk, max_shift=r)
+            sh = torch.zeros(2, dtype=torch.int32, device=dev)
+            got = abi.reconstruction_error(_t(est, dev), _t(ref, dev), None if mk is None else _t(mk, dev),
+                                           max_shift=r, shift=sh).cpu().numpy()
+            assert tuple(sh.cpu().numpy()) == d == (-s[0], -s[1])
+            assert np.abs(got[:3] - errs).max() < 1e-9 and abs(got[3] - mean) < 1e-9, (got, errs)

@@ -47,3 +47,41 @@ def test_mask_excludes_pixels_and_zero_estimate_is_error_one():
     assert np.all(errs < 1e-14)
     errs, mean = metrics.reconstruction_error(np.zeros_like(ref), ref)
     assert np.all(errs == 1.0) and mean == 1.0
+
+
+def test_translated_copies_are_aligned_back():
+    """Every slice translated together (periodically) by s: the aligned error is zero at d = -s, and
+    with a per-slice complex scale as well; max_shift = 0 is the unaligned metric."""
+    ref = _ref((3, 24, 20), 7)
+    for s in [(3, -2), (-4, 4), (0, 1)]:
+        est = np.roll(ref, s, axis=(1, 2)) * np.array([0.8j, 1.5 * np.exp(0.3j), -1.1])[:, None, None]
+        errs, mean, d = metrics.reconstruction_error_aligned(est, ref, max_shift=4)
+        assert d == (-s[0], -s[1])
+        assert np.all(errs < 1e-14) and mean < 1e-14
+        e0, m0 = metrics.reconstruction_error(est, ref)
+        assert m0 > 0.5                                            # unaligned, the copy looks wrong
+        e1, m1, d1 = metrics.reconstruction_error_aligned(est, ref, max_shift=0)
+        assert d1 == (0, 0) and m1 == m0 and np.array_equal(e1, e0)
+
+
+def test_aligned_error_of_a_noisy_translated_copy_is_the_noise_error():
+    """A translated copy plus a perturbation orthogonal to the reference: the best translation is the
+    true one and its error is the closed form of the perturbation alone."""
+    ref = _ref((1, 16, 16), 11)
+    d = 0.2 * synth.complex_field((1, 16, 16), 12).astype(np.complex128)
+    d -= np.vdot(ref, d) / np.vdot(ref, ref) * ref
+    est = np.roll(ref + d, (2, -3), axis=(1, 2))
+    errs, mean, sh = metrics.reconstruction_error_aligned(est, ref, max_shift=3)
+    r2, d2 = np.vdot(ref, ref).real, np.vdot(d, d).real
+    assert sh == (-2, 3)
+    assert abs(errs[0] - np.sqrt(d2 / (r2 + d2))) < 1e-13
+
+
+def test_alignment_uses_the_mask_of_the_reference_frame():
+    ref = _ref((2, 12, 12), 13)
+    mask = np.zeros((12, 12), dtype=np.float32)
+    mask[3:9, 2:10] = 1.0
+    est = np.roll(ref, (1, 1), axis=(1, 2))
+    est[:, 0, 0] = 50.0                  # lands at (0 - 1, 0 - 1) mod 12 = (11, 11) after alignment: unmasked
+    errs, mean, sh = metrics.reconstruction_error_aligned(est, ref, mask, max_shift=2)
+    assert sh == (-1, -1) and mean < 1e-14
