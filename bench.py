@@ -211,6 +211,40 @@ def algorithm2_benchmark(n: int, m: int, iterations: int = 3, a_steps: int = 5, 
     return res
 
 
+def unet_forward_benchmark(reps: int, batch: int = 16):
+    """The learned initialisation's network alone: 4 levels, 32 base channels, 256^2 crops of 6 slices,
+    He-initialised, forward passes at `batch` on a seeded input; HIP events over `reps` passes, and the
+    flops of every layer (for per-dispatch counters)."""
+    import numpy as np
+    import torch
+    from paper_2205_03902_amd.unet import UNet, to_nhwc_bf16
+    dev = torch.device("cuda:0")
+    net = UNet(6, 6, base=32, levels=4, height=256, width=256, max_batch=batch, device=dev)
+    net.init_he(seed=7)
+    rng = np.random.Generator(np.random.PCG64(8))
+    x = to_nhwc_bf16(torch.from_numpy(rng.standard_normal((batch, 6, 256, 256)).astype(np.float32)).to(dev), net.in_pad)
+    out = torch.empty((batch, 256, 256, 6), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        net.forward(x, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        net.forward(x, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    layers = {}
+    for name, shp in net.shapes().items():
+        level = int(name[3]) if name.startswith(("enc", "dec")) else 0
+        px = (256 >> level) ** 2
+        k = shp[2] * shp[3]
+        layers[name] = {"shape": list(shp), "pixels": px,
+                        "gflop": batch * 2.0 * px * shp[0] * shp[1] * (1 if k == 4 and name.endswith("up") else k) / 1e9}
+    f = net.flops_per_sample() * batch
+    return {"batch": batch, "reps": reps, "forward_ms": ms, "forward_tflops": f / ms * 1e-9,
+            "gflop_per_pass": f / 1e9, "layers": layers}
+
+
 def copy_calibration():
     """A plain device copy of known size, for scaling HBM traffic counters."""
     import torch
@@ -359,6 +393,9 @@ def main():
     ap.add_argument("--ttl-train", type=int, default=2000, help="training specimens of the time-to-loss run")
     ap.add_argument("--ttl-test", type=int, default=100, help="held-out specimens of the time-to-loss run")
     ap.add_argument("--ttl-epochs", type=int, default=20, help="training epochs of the time-to-loss run")
+    ap.add_argument("--unet-only", type=int, default=0, metavar="REPS",
+                    help="time only the network's forward pass (256^2 crops of 6 slices, batch 16) REPS times "
+                         "and print its JSON with the flops of every layer")
     ap.add_argument("--algorithm2-only", type=int, default=0, metavar="N",
                     help="time only Algorithm 2 at window N (M = 3) and print its JSON")
     args = ap.parse_args()
@@ -373,6 +410,11 @@ def main():
     import torch
     if args.copy_calibration:
         copy_calibration()
+        return
+
+    if args.unet_only:
+        torch.cuda.set_device(0)
+        print(json.dumps(unet_forward_benchmark(args.unet_only)), flush=True)
         return
 
     if args.algorithm2_only:
@@ -410,13 +452,16 @@ def main():
         h = layerwise.reconstruct(plan, pr, sl, measured, sweeps=1, k_steps=1, probe_steps=1)
         extras["sweep_ms"] = h.seconds * 1e3
         extras["sweep_losses"] = [h.loss[0], h.loss[-1]]
-        # the paper's relative reconstruction error (per-slice complex scale removed) over the
-        # pixels some window covers, before and after the sweep
+        # the paper's relative reconstruction error over the pixels some window covers, before and
+        # after the sweep (which also steps the probe), after a common translation of the slices
+        # (|d| <= 4 px) and a complex scale per slice
         cover = coverage_mask(geo, geo.positions())
         mask_t = torch.from_numpy(cover).to(dev)
-        r0 = abi.reconstruction_error(slices, truth, mask_t)
-        r1 = abi.reconstruction_error(sl, truth, mask_t)
+        shift = torch.zeros(2, dtype=torch.int32, device=dev)
+        r0 = abi.reconstruction_error(slices, truth, mask_t, max_shift=4)
+        r1 = abi.reconstruction_error(sl, truth, mask_t, max_shift=4, shift=shift)
         extras["recon_error_start_after_sweep"] = [r0[-1].item(), r1[-1].item()]
+        extras["recon_error_shift_after_sweep"] = [int(v) for v in shift.cpu().tolist()]
         del sl, pr
         # the full-gradient (Jacobi) variant from the same start: 4 steps against one sweep,
         # with the layer steps as they are and averaged (step scale 1/M)
