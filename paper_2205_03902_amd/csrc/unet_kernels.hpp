@@ -669,7 +669,10 @@ __global__ void mse_grad_kernel(const float *__restrict__ y, const float *__rest
 // tile in LDS, and reads the nine shifted A fragments from there.  Inputs: C = c0 + c1 channels
 // per pixel (a second source is the skip of a concatenation); weights bf16 [32][kpad] with
 // k = tap * C + channel (tap-major, the GEMM's order, so the sums are the GEMM's).  Each of the
-// four wavefronts owns TH / 4 output rows (TH * 4 pixels = TH / 8 row blocks of 32).
+// four wavefronts owns TH / 4 output rows (TH * 4 pixels = TH / 8 row blocks of 32).  With C = 8
+// (the network's input, 6 channels padded to 8) one matrix-core step of K = 16 takes two taps,
+// the lower half of the lanes the first and the upper half the second, and the ninth tap pairs
+// with the weights' zero padding (k in [72, 80)).
 struct Conv3Args {
     const uint16_t *src0, *src1;   // NHWC bf16
     int c0, c1;                    // channels of each source (c1 = 0: one source)
@@ -689,14 +692,15 @@ __global__ __launch_bounds__(kThreads) void conv3x3_kernel(const Conv3Args a)
     constexpr int TW = 16, HW = TW + 2, HP = (TH + 2) * HW;   // halo width and pixels
     constexpr int LDH = C + 8;                                // bf16 per halo pixel (bank padding)
     constexpr int K = 9 * C, LDW = K + 8;                     // weight row stride
+    constexpr int KW = C == 8 ? 80 : K;                       // weight columns staged (C = 8: with the pad)
     constexpr int FM = TH / 8;                                // 32-pixel blocks per wavefront
     __shared__ __attribute__((aligned(16))) uint16_t halo[HP * LDH];
     __shared__ __attribute__((aligned(16))) uint16_t wl[32 * LDW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int x0 = blockIdx.x * TW, b = blockIdx.z;
     const int H = 1 << a.h_log, W = 1 << a.w_log;
-    for (int q = tid; q < 32 * (K / 8); q += kThreads) {
-        const int n = q / (K / 8), k = (q % (K / 8)) * 8;
+    for (int q = tid; q < 32 * (KW / 8); q += kThreads) {
+        const int n = q / (KW / 8), k = (q % (KW / 8)) * 8;
         *reinterpret_cast<uint4 *>(&wl[n * LDW + k]) = *reinterpret_cast<const uint4 *>(a.w + (long long)n * a.kpad + k);
     }
     // this lane's A row: pixel p = i 32 + lane % 32 of the wavefront's rows
@@ -705,7 +709,7 @@ __global__ __launch_bounds__(kThreads) void conv3x3_kernel(const Conv3Args a)
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int p = i * 32 + (lane & 31);
-        hbase[i] = ((r0 + p / TW) * HW + p % TW) * LDH + (lane >> 5) * 8;
+        hbase[i] = ((r0 + p / TW) * HW + p % TW) * LDH + (C == 8 ? 0 : (lane >> 5) * 8);
     }
     const uint16_t *wrow = wl + (lane & 31) * LDW + (lane >> 5) * 8;
     const int co = lane & 31;
@@ -750,16 +754,30 @@ __global__ __launch_bounds__(kThreads) void conv3x3_kernel(const Conv3Args a)
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][e] = 0.0f;
+        if constexpr (C == 8) {
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int shift = ((t / 3) * HW + t % 3) * LDH;
-#pragma unroll
-            for (int kc = 0; kc < C / 16; ++kc) {
-                const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(wrow + t * C + kc * 16);
+            for (int tp = 0; tp < 5; ++tp) {
+                const int t = min(2 * tp + (lane >> 5), 8);     // this lane half's tap (the pad reads tap 8)
+                const int shift = ((t / 3) * HW + t % 3) * LDH;
+                const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(wrow + tp * 16);
 #pragma unroll
                 for (int i = 0; i < FM; ++i) {
-                    const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(&halo[hbase[i] + shift + kc * 16]);
+                    const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(&halo[hbase[i] + shift]);
                     acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc[i], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int shift = ((t / 3) * HW + t % 3) * LDH;
+#pragma unroll
+                for (int kc = 0; kc < C / 16; ++kc) {
+                    const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(wrow + t * C + kc * 16);
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) {
+                        const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(&halo[hbase[i] + shift + kc * 16]);
+                        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc[i], 0, 0, 0);
+                    }
                 }
             }
         }

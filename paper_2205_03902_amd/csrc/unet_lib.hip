@@ -227,6 +227,10 @@ void gemm(const GemmArgs &a, hipStream_t st)
         gemm_kernel<128, 32, 4, 1><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 32)), kThreads, 0, st>>>(a);
     } else if (N <= 64) {
         gemm_kernel<128, 64, 2, 2><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 64)), kThreads, 0, st>>>(a);
+    } else if (cdiv(M, 128) * cdiv(N, 128) < 1024) {
+        // the coarse levels: 128 x 64 tiles double the workgroups of a grid that would leave CUs
+        // with one or two (the same sums: each output's K order does not depend on the tiling)
+        gemm_kernel<128, 64, 2, 2><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 64)), kThreads, 0, st>>>(a);
     } else {
         gemm_kernel<128, 128, 2, 2><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 128)), kThreads, 0, st>>>(a);
     }
@@ -303,8 +307,9 @@ OutMap up_map(int cout, int h_log_in, int w_log_in)
 bool direct_conv_fits(int cout, int c0, int c1, int hl, int wl)
 {
     const int cin = c0 + c1;
-    return cout % 32 == 0 && (cout <= 64 || (cout <= 128 && hl >= 7)) && (cin == 32 || cin == 64) &&
-           c0 % 16 == 0 && c1 % 16 == 0 && hl >= 6 && wl >= 4;
+    const bool wide = (cin == 32 || cin == 64) && c0 % 16 == 0 && c1 % 16 == 0;
+    const bool narrow = cin == 8 && c1 == 0;   // the input layer: up to 8 channels, two taps a step
+    return cout % 32 == 0 && (cout <= 64 || (cout <= 128 && hl >= 7)) && (wide || narrow) && hl >= 6 && wl >= 4;
 }
 
 // Output channels [0, d0c) go to out0 (d0c a pixel, masked by mask if given), the rest to out1
@@ -323,7 +328,10 @@ void direct_conv(const uint16_t *in0, int c0, const uint16_t *in1, int c1, int h
         c.mask = (mask && first) ? mask + h * 32 : nullptr;
         c.dst = first ? out0 + h * 32 : out1 + (h * 32 - d0c);
         c.ldd = first ? d0c : cout - d0c;
-        if (c0 + c1 == 32) {   // 16-row tiles, four per workgroup
+        if (c0 + c1 == 8) {    // 16-row tiles, four per workgroup
+            const dim3 grid(1u << (wl - 4), 1u << (hl - 6), (unsigned)batch);
+            conv3x3_kernel<16, 8, 4><<<grid, kThreads, 0, st>>>(c);
+        } else if (c0 + c1 == 32) {   // 16-row tiles, four per workgroup
             const dim3 grid(1u << (wl - 4), 1u << (hl - 6), (unsigned)batch);
             conv3x3_kernel<16, 32, 4><<<grid, kThreads, 0, st>>>(c);
         } else {               // 8-row tiles, four per workgroup
