@@ -34,14 +34,8 @@ constexpr int kBK = 32;         // K (or pixels, for weight gradients) per pipel
 constexpr int kLDK = 40;        // LDS row stride in bf16: 80 B, so that 16-byte reads of
                                 // consecutive rows by 8 lanes cover all banks once
 
-// Round to nearest even; NaN stays NaN.
-__device__ __forceinline__ uint16_t f2bf(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// Round to nearest even (the hardware conversion, one v_cvt_pk_bf16_f32); NaN stays NaN.
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
 
@@ -243,24 +237,55 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const GemmArgs a)
         if (n >= a.o.n_total) continue;
         const int t = n / a.o.nout, co = n - t * a.o.nout;
         const float bias = a.bias ? a.bias[co] : 0.0f;
+        if (a.out_f32) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int m = m0 + wm * TM + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                    if (m >= a.r.m_total || co >= a.d0c) continue;
+                    int b, y, x;
+                    decode(m, a.r.ho_log, a.r.wo_log, b, y, x);
+                    const long long d = dest_pixel(a.o, b, y, x, t);
+                    float val = acc[i][j][e] + bias;
+                    if (a.relu) val = fmaxf(val, 0.0f);
+                    if (a.mask && !(bf2f(a.mask[d * a.d0c + co]) > 0.0f)) val = 0.0f;
+                    static_cast<float *>(a.dst0)[d * a.d0c + co] = val;
+                }
+            }
+            continue;
+        }
+        // bf16 outputs: elements e and e + 1 are consecutive rows (pixels) of column n; lanes n and
+        // n ^ 1 (channels co and co ^ 1 of one tap: nout, d0c and d1c are even) swap one of them so
+        // that each writes both channels of one pixel as a 32-bit word
+        const bool odd = co & 1;
+        uint16_t *dst = co < a.d0c ? static_cast<uint16_t *>(a.dst0) : static_cast<uint16_t *>(a.dst1);
+        const int ldd = co < a.d0c ? a.d0c : a.d1c;
+        const int cd = (co < a.d0c ? co : co - a.d0c) & ~1;
+        const bool masked = a.mask && co < a.d0c;
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int m = m0 + wm * TM + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+            for (int e = 0; e < 16; e += 2) {
+                float v0 = acc[i][j][e] + bias, v1 = acc[i][j][e + 1] + bias;
+                if (a.relu) {
+                    v0 = fmaxf(v0, 0.0f);
+                    v1 = fmaxf(v1, 0.0f);
+                }
+                const float got = __shfl_xor(odd ? v0 : v1, 1, 64);
+                float lo = odd ? got : v0, hi = odd ? v1 : got;
+                const int ee = odd ? e + 1 : e;
+                const int m = m0 + wm * TM + i * 32 + 8 * (ee >> 2) + 4 * (lane >> 5) + (ee & 3);
                 if (m >= a.r.m_total) continue;
                 int b, y, x;
                 decode(m, a.r.ho_log, a.r.wo_log, b, y, x);
-                const long long d = dest_pixel(a.o, b, y, x, t);
-                float val = acc[i][j][e] + bias;
-                if (a.relu) val = fmaxf(val, 0.0f);
-                if (co < a.d0c) {
-                    if (a.mask && !(bf2f(a.mask[d * a.d0c + co]) > 0.0f)) val = 0.0f;
-                    if (a.out_f32) static_cast<float *>(a.dst0)[d * a.d0c + co] = val;
-                    else static_cast<uint16_t *>(a.dst0)[d * a.d0c + co] = f2bf(val);
-                } else {
-                    static_cast<uint16_t *>(a.dst1)[d * a.d1c + (co - a.d0c)] = f2bf(val);
+                const long long d = dest_pixel(a.o, b, y, x, t) * ldd + cd;
+                if (masked) {
+                    const uint32_t mk = *reinterpret_cast<const uint32_t *>(a.mask + d);
+                    if (!(bf2f(mk & 0xffffu) > 0.0f)) lo = 0.0f;
+                    if (!(bf2f(mk >> 16) > 0.0f)) hi = 0.0f;
                 }
+                *reinterpret_cast<uint32_t *>(dst + d) = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
             }
         }
     }
@@ -781,17 +806,30 @@ __global__ __launch_bounds__(kThreads) void conv3x3_kernel(const Conv3Args a)
                 }
             }
         }
+        // Elements e and e + 1 of a lane are pixels x and x + 1 of its channel co; lanes co and co ^ 1
+        // swap one of them so that each writes both channels of one pixel as a 32-bit word.
+        const bool odd = co & 1;
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int p = i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+            for (int e = 0; e < 16; e += 2) {
+                float v0 = acc[i][e] + bias, v1 = acc[i][e + 1] + bias;
+                if (a.relu) {
+                    v0 = fmaxf(v0, 0.0f);
+                    v1 = fmaxf(v1, 0.0f);
+                }
+                const float got = __shfl_xor(odd ? v0 : v1, 1, 64);
+                float lo = odd ? got : v0, hi = odd ? v1 : got;      // channels co & ~1 and (co & ~1) + 1
+                const int ee = odd ? e + 1 : e;
+                const int p = i * 32 + 8 * (ee >> 2) + 4 * (lane >> 5) + (ee & 3);
                 const int y = y0 + r0 + p / TW, x = x0 + p % TW;
-                const long long d = ((((long long)(b << a.h_log) + y) << a.w_log) + x) * a.ldd + co;
-                float val = acc[i][e] + bias;
-                if (a.relu) val = fmaxf(val, 0.0f);
-                if (a.mask && !(bf2f(a.mask[d]) > 0.0f)) val = 0.0f;
-                a.dst[d] = f2bf(val);
+                const long long d = ((((long long)(b << a.h_log) + y) << a.w_log) + x) * a.ldd + (co & ~1);
+                if (a.mask) {
+                    const uint32_t m = *reinterpret_cast<const uint32_t *>(a.mask + d);
+                    if (!(bf2f(m & 0xffffu) > 0.0f)) lo = 0.0f;
+                    if (!(bf2f(m >> 16) > 0.0f)) hi = 0.0f;
+                }
+                *reinterpret_cast<uint32_t *>(a.dst + d) = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
             }
         if (ty + 1 < TY) {
             __syncthreads();   // every wavefront is done with this tile's halo
