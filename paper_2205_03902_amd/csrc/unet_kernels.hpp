@@ -840,30 +840,37 @@ __global__ __launch_bounds__(kThreads) void conv3x3_kernel(const Conv3Args a)
 }
 
 // 1x1 convolution to a few FP32 channels (the network's head): one lane per pixel reads its C
-// bf16 channels (16-byte pieces), the weights (bf16 [cout][kpad]) and bias sit in LDS as FP32,
-// sums in FP32.  cout <= kHeadMax, C a multiple of 8 and at most kHeadC.  (Four lanes per pixel,
-// each reading a quarter of it so that a wavefront's loads are consecutive, measured slower.)
+// bf16 channels (16-byte pieces, all issued before the first is used: with C a run-time bound
+// the loads went out one at a time and a wavefront's lines were fetched again between them), the
+// weights (bf16 [cout][kpad]) and bias sit in LDS as FP32, sums in FP32.  cout <= kHeadMax,
+// C = 8 C8 <= kHeadC.  (Four lanes per pixel, each reading a quarter of it so that a wavefront's
+// loads are consecutive, measured slower.)
 constexpr int kHeadMax = 8, kHeadC = 64;
 
-__global__ __launch_bounds__(256) void head_kernel(const uint16_t *in, int C, const uint16_t *w, int kpad,
+template <int C8>
+__global__ __launch_bounds__(256) void head_kernel(const uint16_t *in, const uint16_t *w, int kpad,
                                                    const float *bias, int cout, float *out, long long pixels)
 {
-    __shared__ float sw[kHeadMax][kHeadC];
+    constexpr int C = 8 * C8;
+    __shared__ float sw[kHeadMax][C];
     __shared__ float sb[kHeadMax];
     for (int i = threadIdx.x; i < cout * C; i += 256) sw[i / C][i % C] = bf2f(w[(size_t)(i / C) * kpad + i % C]);
     for (int i = threadIdx.x; i < cout; i += 256) sb[i] = bias ? bias[i] : 0.0f;
     __syncthreads();
     const long long px = (long long)blockIdx.x * 256 + threadIdx.x;
     if (px >= pixels) return;
+    const uint4 *src = reinterpret_cast<const uint4 *>(in + px * C);
+    uint4 v[C8];
+#pragma unroll
+    for (int c8 = 0; c8 < C8; ++c8) v[c8] = src[c8];
     float acc[kHeadMax];
 #pragma unroll
     for (int o = 0; o < kHeadMax; ++o) acc[o] = 0.0f;
-    const uint4 *src = reinterpret_cast<const uint4 *>(in + px * C);
-    for (int c8 = 0; c8 < C / 8; ++c8) {
-        const uint4 v = src[c8];
+#pragma unroll
+    for (int c8 = 0; c8 < C8; ++c8) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const float x = bf2f(bf_at(v, e));
+            const float x = bf2f(bf_at(v[c8], e));
 #pragma unroll
             for (int o = 0; o < kHeadMax; ++o)
                 if (o < cout) acc[o] = fmaf(sw[o][c8 * 8 + e], x, acc[o]);

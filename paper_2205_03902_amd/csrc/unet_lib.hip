@@ -359,11 +359,21 @@ void layer_forward(const un_net &n, int li, int batch, int level, const uint16_t
         a.g = gather_of(in0, c0, nullptr, 0, hlg, wlg, 1, 1);
         a.o = up_map(ly.info.cout, hlg, wlg);
     } else {
-        if (ly.info.kind == UN_CONV1X1 && !in1 && ly.info.cout <= kHeadMax && c0 % 8 == 0 && c0 <= kHeadC) {
+        if (ly.info.kind == UN_CONV1X1 && !in1 && ly.info.cout <= kHeadMax && c0 > 0 && c0 % 8 == 0 && c0 <= kHeadC) {
             // the head: a per-pixel kernel (a GEMM of a few columns is all pipeline start-up)
             const long long px = n.pixels(batch, level);
-            head_kernel<<<(unsigned)((px + 255) / 256), 256, 0, st>>>(in0, c0, a.w, a.kpad, a.bias, ly.info.cout,
-                                                                       static_cast<float *>(out), px);
+            const unsigned blocks = (unsigned)((px + 255) / 256);
+            float *y = static_cast<float *>(out);
+            switch (c0 / 8) {
+            case 1: head_kernel<1><<<blocks, 256, 0, st>>>(in0, a.w, a.kpad, a.bias, ly.info.cout, y, px); break;
+            case 2: head_kernel<2><<<blocks, 256, 0, st>>>(in0, a.w, a.kpad, a.bias, ly.info.cout, y, px); break;
+            case 3: head_kernel<3><<<blocks, 256, 0, st>>>(in0, a.w, a.kpad, a.bias, ly.info.cout, y, px); break;
+            case 4: head_kernel<4><<<blocks, 256, 0, st>>>(in0, a.w, a.kpad, a.bias, ly.info.cout, y, px); break;
+            case 5: head_kernel<5><<<blocks, 256, 0, st>>>(in0, a.w, a.kpad, a.bias, ly.info.cout, y, px); break;
+            case 6: head_kernel<6><<<blocks, 256, 0, st>>>(in0, a.w, a.kpad, a.bias, ly.info.cout, y, px); break;
+            case 7: head_kernel<7><<<blocks, 256, 0, st>>>(in0, a.w, a.kpad, a.bias, ly.info.cout, y, px); break;
+            default: head_kernel<8><<<blocks, 256, 0, st>>>(in0, a.w, a.kpad, a.bias, ly.info.cout, y, px); break;
+            }
             return;
         }
         if (ly.info.kind == UN_CONV3X3 && direct_conv_fits(ly.info.cout, c0, in1 ? c1 : 0, hlg, wlg)) {
