@@ -342,7 +342,8 @@ def time_adjoint(geo, steps: int, warmup: int, dev, batch: int = 0, checkpoint_e
     family = "lines" if geo.n > 128 else "fused"
     log(f"bench: {steps} steps, {ms:.3f} ms/step (events), {wall * 1e3 / steps:.3f} ms/step (wall), "
         f"{family} kernels {kern:.3f} ms per pass ({launches} timed regions), loss {loss.item():.6e}")
-    return {"plan": plan, "probe": probe, "slices": slices, "measured": measured, "truth": truth,
+    return {"plan": plan, "probe": probe, "probe_true": probe_true, "slices": slices, "measured": measured,
+            "truth": truth,
             "truth_np": truth_np, "gs": gs, "gp": gp, "ms": ms, "kernel_ms": kern, "family": family,
             "loss": loss.item(), "batch": plan.batch, "checkpoint_every": plan.checkpoint_every,
             "workspace_bytes": plan.workspace_bytes}
@@ -446,6 +447,8 @@ def main():
             plan.forward(probe, slices)
         torch.cuda.synchronize()
         extras["forward_ms"] = (time.perf_counter() - f0) * 1e3 / 3
+        probe_start_err = (torch.linalg.vector_norm(probe - run["probe_true"]) /
+                           torch.linalg.vector_norm(run["probe_true"])).item()
         # one Algorithm 1 sweep: M layer steps and one probe step over all positions
         sl = slices.clone()
         pr = probe.clone()
@@ -485,6 +488,22 @@ def main():
         plan.adjoint(probe, sl2, measured, grad_slices=gs, grad_probe=gp, loss=end)
         extras["sweep_loss_after"] = end.item()
         del sl2
+        # the workload's whole reconstruction: its layer-wise sweeps (30 for the 16384-position
+        # workload), each followed by a probe step over all positions (joint probe estimation), from
+        # t = 1 and the 1.1x-defocus probe; the final loss and the aligned error against the truth
+        sl3, pr3 = slices.clone(), probe.clone()
+        hr = layerwise.reconstruct(plan, pr3, sl3, measured, sweeps=geo.iterations, probe_steps=1)
+        shift3 = torch.zeros(2, dtype=torch.int32, device=dev)
+        r3 = abi.reconstruction_error(sl3, truth, mask_t, max_shift=4, shift=shift3)
+        probe_true_err = (torch.linalg.vector_norm(pr3 - run["probe_true"]) /
+                          torch.linalg.vector_norm(run["probe_true"])).item()
+        extras["reconstruction"] = {"sweeps": geo.iterations, "probe_steps_per_sweep": 1, "seconds": hr.seconds,
+                                    "loss_first_last": [hr.loss[0], hr.loss[-1]],
+                                    "loss_never_rises": bool(all(b <= a * (1 + 1e-6) for a, b in
+                                                                 zip(hr.loss, hr.loss[1:]))),
+                                    "recon_error": r3[-1].item(), "recon_shift": [int(v) for v in shift3.cpu().tolist()],
+                                    "probe_rel_error_start_end": [probe_start_err, probe_true_err]}
+        del sl3, pr3
         extras["pass_model_bytes"] = pass_bytes(geo)
         # scan-position gradient and curvature bound over all positions (a probe-mode pass)
         gpos = torch.empty((geo.n_pos, 2), dtype=torch.float64, device=dev)
