@@ -19,11 +19,13 @@ LIB_PATH = os.path.join(PKG, "libimsp.so")
 MS_OK, MS_ERR_INVALID_ARG, MS_ERR_UNSUPPORTED, MS_ERR_BUDGET, MS_ERR_HIP = 0, -1, -2, -3, -4
 MS_ERR_NOT_FINITE = -5
 MS_PATH_AUTO, MS_PATH_FUSED, MS_PATH_LINES = 0, 1, 2
+MS_BANDS_NONE, MS_BANDS_ROWS, MS_BANDS_ALL = 0, 1, 2
 MS_OBJECTIVE_AMPLITUDE, MS_OBJECTIVE_POISSON = 0, 1
 
 # every entry point declared in include/ms.h
 SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
-           "ms_plan_checkpoint_every", "ms_plan_set_path", "ms_plan_set_objective",
+           "ms_plan_checkpoint_every", "ms_plan_set_path", "ms_plan_set_bands", "ms_plan_has_bands",
+           "ms_plan_set_objective",
            "ms_make_probe", "ms_make_probe_aberrated", "ms_forward", "ms_adjoint", "ms_adjoint_scratch", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_position_grad", "ms_position_step", "ms_reconstruction_error",
            "ms_profile_begin",
            "ms_profile_end", "ms_last_error")
@@ -68,6 +70,10 @@ def lib():
         L.ms_plan_checkpoint_every.argtypes = [P]
         L.ms_plan_set_path.restype = I32
         L.ms_plan_set_path.argtypes = [P, I32]
+        L.ms_plan_set_bands.restype = I32
+        L.ms_plan_set_bands.argtypes = [P, I32]
+        L.ms_plan_has_bands.restype = I32
+        L.ms_plan_has_bands.argtypes = [P]
         L.ms_plan_set_objective.restype = I32
         L.ms_plan_set_objective.argtypes = [P, I32]
         L.ms_make_probe.restype = I32
@@ -223,9 +229,10 @@ class Plan:
         self.batch = lib().ms_plan_batch(handle)
         self.shift_classes = lib().ms_plan_shift_classes(handle)
         self.checkpoint_every = lib().ms_plan_checkpoint_every(handle)
+        self.has_bands = int(lib().ms_plan_has_bands(handle))   # bit 0 row launches, bit 1 column launches
         self.workspace_bytes = ws
         self.budget_bytes = int(budget_bytes)
-        self._path, self._objective = MS_PATH_AUTO, MS_OBJECTIVE_AMPLITUDE
+        self._path, self._objective, self._bands = MS_PATH_AUTO, MS_OBJECTIVE_AMPLITUDE, MS_BANDS_ALL
 
     def positions(self):
         """The scan positions (S, 2) this plan was built from (host float64 copy)."""
@@ -239,6 +246,7 @@ class Plan:
                     device=self.device, checkpoint_every=pb.checkpoint_every)
         plan.set_path(self._path)
         plan.set_objective(self._objective)
+        plan.set_bands(self._bands)
         return plan
 
     @classmethod
@@ -283,6 +291,11 @@ class Plan:
         """MS_PATH_AUTO, MS_PATH_FUSED or MS_PATH_LINES (see include/ms.h)."""
         _check(lib().ms_plan_set_path(self._h, int(path)), "ms_plan_set_path")
         self._path = int(path)
+
+    def set_bands(self, mode: int):
+        """MS_BANDS_ALL, MS_BANDS_ROWS or MS_BANDS_NONE (see include/ms.h)."""
+        _check(lib().ms_plan_set_bands(self._h, int(mode)), "ms_plan_set_bands")
+        self._bands = int(mode)
 
     def set_objective(self, objective: int):
         """MS_OBJECTIVE_AMPLITUDE or MS_OBJECTIVE_POISSON (see include/ms.h)."""

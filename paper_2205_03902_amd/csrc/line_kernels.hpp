@@ -132,6 +132,18 @@ __device__ __forceinline__ void tile_drain(const float2 *tile, F store)
     __syncthreads();
 }
 
+// Tile index of register i (natural or spectral order) under the swizzle sw.  The swizzle acts
+// on the low four bits, which hold the lane's part of the index, so the index is one of 16 / R
+// per-lane bases plus a multiple of 16 known at compile time (16 R times a register's index
+// would otherwise be 16 addresses kept live).
+template <int N, bool SPEC>
+__device__ __forceinline__ int tile_idx(int j, int i, int sw)
+{
+    constexpr int R = Win<N>::R, G = Win<N>::G;
+    if (SPEC) return ((j * G + i / R) ^ sw) + 16 * (i % R);
+    return ((j + R * (i % G)) ^ sw) + 16 * (i / G);
+}
+
 template <int N, bool SPEC>
 __device__ __forceinline__ void tile_get(float2 (&v)[16], const float2 *tile, int lloc, int j)
 {
@@ -139,7 +151,7 @@ __device__ __forceinline__ void tile_get(float2 (&v)[16], const float2 *tile, in
     const float2 *col = tile + lloc * Wn::LD;
     const int sw = tile_swz(lloc);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = col[(SPEC ? Wn::spec(j, i) : Wn::nat(j, i)) ^ sw];
+    for (int i = 0; i < 16; ++i) v[i] = col[tile_idx<N, SPEC>(j, i, sw)];
 }
 
 template <int N, bool SPEC>
@@ -149,7 +161,7 @@ __device__ __forceinline__ void tile_put(const float2 (&v)[16], float2 *tile, in
     float2 *col = tile + lloc * Wn::LD;
     const int sw = tile_swz(lloc);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) col[(SPEC ? Wn::spec(j, i) : Wn::nat(j, i)) ^ sw] = v[i];
+    for (int i = 0; i < 16; ++i) col[tile_idx<N, SPEC>(j, i, sw)] = v[i];
 }
 
 // Where this lane's line is: (line) for row launches; for column launches also the
@@ -433,6 +445,129 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
         line_store<N, ROW, false>(v, A, q, xbuf);
     } else if (p.probe_patch) {
         line_store<N, ROW, false>(v, p.probe_patch + (size_t)b * NN, q, xbuf);
+    }
+}
+
+// ---- band sums of the adjoint's gradient patches ----
+//
+// The gradient of slice m (Sec. 3.2) sums, over positions, the patch conj(psi_m) o g placed at the
+// window's origin.  Windows of one scan column (one origin x) overlap row for row: a workgroup of a
+// row launch that takes 16 object rows, rather than 16 window rows, for every position of such a
+// band sums the band's patches on those rows in registers and writes one (N + spread) x N band
+// image instead of N x N values per position.  Column launches do the same with 16 object columns
+// for the positions of one scan row whose origins x agree modulo 16, so that the columns a
+// workgroup takes are an aligned group of 16 in every member's window (row launches need no such
+// alignment: a row is one contiguous piece whatever its index).  The scatter then reads bands.
+//
+// Workgroup w takes band rows (row launches) or band columns (column launches) u0 .. u0 + 15 of
+// band `band`, u counted from the band's first origin along the cross axis; member i (origin
+// delta_i further along) holds them as window lines u0 + l - delta_i.  For column launches every
+// member covers all 16 (u0 - delta_i is a multiple of 16 in [0, N)); for row launches lines outside
+// the window are computed on a clamped index and neither stored nor summed.
+struct BandParams {
+    const int4 *wg;              // per workgroup: (band, first member, end member, u0)
+    const int *mem;              // batch-local position of each member
+    const int *delta;            // each member's origin minus the band's first, along the cross axis
+    float2 *band;                // [bands] x band_stride
+    long long band_stride;
+    int ld;                      // row pitch of a band image: N (row launches) or N + spread (column launches)
+};
+
+// Adjoint launch of slice m over band workgroups (1D grid); otherwise the adjoint stage of
+// line_kernel for each member in turn, with both propagation tables kept in LDS.
+template <int N, bool ROW>
+__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, ROW ? 3 : 2) void line_band_kernel(LineParams p, BandParams bp)
+{
+    using Wn = Win<N>;
+    constexpr int R = Wn::R;
+    constexpr int NT = kLinesPerGroup * R;
+    constexpr size_t NN = (size_t)N * N;
+    __shared__ float2 xbuf[kLinesPerGroup * Wn::LD];
+    __shared__ float2 s_tw[Wn::TW_WORDS];
+    __shared__ float2 s_hf[N], s_hs[N];
+
+    const int tid = threadIdx.x;
+    const int M = p.M, m = p.m;
+    const float2 *hown = ROW ? p.hx : p.hy;
+    const int g_fin = (m + 1 < M) ? m : -1;
+    const int g_start = (m > 0 && p.go_on) ? m - 1 : -1;
+    for (int i = tid; i < Wn::TW_WORDS; i += NT) s_tw[i] = p.tw[i];
+    if (g_fin >= 0)
+        for (int i = tid; i < N; i += NT) s_hf[i] = hown[p.gap_table[g_fin] * N + i];
+    if (g_start >= 0)
+        for (int i = tid; i < N; i += NT) s_hs[i] = hown[p.gap_table[g_start] * N + i];
+    __syncthreads();
+
+    const int4 w = bp.wg[blockIdx.x];
+    float2 acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = make_float2(0.f, 0.f);
+    for (int i = w.y; i < w.z; ++i) {
+        // the lane's line and place, hidden from the optimiser each member: the LDS and global
+        // addresses derived from them are recomputed where used rather than hoisted out of the
+        // loop and kept live (which spilled most of them)
+        const int lloc = opaque(tid / R), j = opaque(tid % R);
+        float2 *xb = xbuf + lloc * Wn::LD;
+        const int b = bp.mem[i];
+        const int4 info = p.pos_info[p.pos_list[b]];
+        const int l0 = w.w - bp.delta[i];            // window line of lloc = 0
+        const int wl = l0 + lloc;
+        const bool valid = !ROW || (unsigned)wl < (unsigned)N;
+        const LinePos q{valid ? wl : 0, lloc, j, l0};
+        float2 *A = p.A + (size_t)b * NN;
+        float2 v[16];
+        if (m + 1 == M) {
+            line_load<N, ROW, true>(v, A, q, xbuf);
+            line_fft_inv<N>(v, s_tw, xb, j);
+        } else {
+            line_load<N, ROW, false>(v, A, q, xbuf);
+            prop_axis<N, true>(v, s_tw, xb, s_hf, j);
+        }
+        {
+            // acc += conj(psi_m) o g, psi_m read element by element (through the LDS tile for columns)
+            const float2 *psi = p.psi_in ? p.psi_in + (size_t)b * p.psi_in_stride
+                                         : p.class_probe + (size_t)info.z * NN;
+            if (ROW) {
+                if (valid) {
+                    const int l2 = opaque(q.line), j2 = opaque(j);
+#pragma unroll
+                    for (int k = 0; k < 16; ++k)
+                        acc[k] = cadd(acc[k], cconjmul(psi[l2 * N + Wn::nat(j2, k)], v[k]));
+                }
+            } else {
+                tile_fill<N>(xbuf, [&](int r, int c) { return psi[r * N + q.c0 + c]; });
+                const float2 *col = xbuf + lloc * Wn::LD;
+                const int sw = tile_swz(lloc);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) acc[k] = cadd(acc[k], cconjmul(col[tile_idx<N, false>(j, k, sw)], v[k]));
+            }
+        }
+        if (!p.go_on) continue;
+        line_patch<N, ROW, true>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, info.x, info.y, q, xbuf);
+        float2 *dst = nullptr;
+        if (m > 0) {
+            prop_axis<N, true>(v, s_tw, xb, s_hs, j);
+            dst = A;
+        } else if (p.probe_patch) {
+            dst = p.probe_patch + (size_t)b * NN;
+        }
+        if (dst) {
+            if (ROW) {
+                if (valid) gstore<N, true, false>(v, dst, q.line, j);
+            } else {
+                line_store<N, false, false>(v, dst, q, xbuf);
+            }
+        }
+    }
+    float2 *band = bp.band + (size_t)w.x * bp.band_stride;
+    const int lloc = tid / R, j = tid % R;
+    if (ROW) {
+        const int row = w.w + lloc;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) band[(size_t)row * bp.ld + Wn::nat(j, k)] = acc[k];
+    } else {
+        tile_put<N, false>(acc, xbuf, lloc, j);
+        tile_drain<N>(xbuf, [&](int r, int c, float2 x) { band[(size_t)r * bp.ld + w.w + c] = x; });
     }
 }
 

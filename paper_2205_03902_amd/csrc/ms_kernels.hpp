@@ -521,14 +521,22 @@ constexpr int kTileH = 4;
 constexpr int kChunks = 16;  // chunks per batch
 constexpr int kUnroll = 8;   // patch loads in flight per lane
 
+// The images scattered are per-position patches (N x N) or band images of several positions (see
+// line_band_kernel): an entry (image, origin y, origin x, extent) covers N rows and N + extent
+// columns of the object (N + extent rows and N columns for vertical bands), element (y, x) of the
+// image at y * ld + x.  Slices m0 + i of even and odd index (row and column launches) have images,
+// lists and geometry of their own (the same for patches).
 struct ScatterParams {
-    const float2 *patches;      // patch of (position b, slice i of the launch): patches + b * pos_stride + i * N * N
-    const float *wpatch;        // overlap patch of (position b, slice i): wpatch + b * w_stride + i * N * N
-    long long pos_stride;
-    const int *tile_off;        // this batch: [kChunks][n_tiles + 1]
-    const int4 *entries;        // (batch-local position, origin y, origin x, 0)
+    // image e of slice i of the launch: patches + e * pos_stride + i * slice_stride, per parity
+    const float2 *patches0, *patches1;
+    long long pos_stride0, pos_stride1, slice_stride0, slice_stride1;
+    const float *wpatch;        // overlap patch of (position e, slice i): wpatch + e * w_stride + i * N * N
+    const int *tile_off0, *tile_off1;    // this batch: [kChunks][n_tiles + 1]
+    const int4 *entries0, *entries1;
+    int ld0, ld1, vert0, vert1;
+    int m0;                     // slice index of i = 0
     float2 *partial;            // [groups][n_m][H][W]
-    float *wpartial;            // [groups][n_m][H][W] or null
+    float *wpartial;            // [groups][n_m][H][W] or null (patches only)
     long long w_stride;
     int H, W, N, tiles_x, n_tiles;
     int nch, cpb;               // chunks of the batch; consecutive chunks summed per block
@@ -541,14 +549,20 @@ __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
     const int x = (t % p.tiles_x) * kTileW + (int)(threadIdx.x % kTileW);
     if (y >= p.H || x >= p.W) return;
     const size_t NN = (size_t)p.N * p.N;
-    const float2 *base = p.patches + (size_t)mi * NN;
+    const bool odd = ((p.m0 + mi) & 1) != 0;
+    const int *tile_off = odd ? p.tile_off1 : p.tile_off0;
+    const int4 *entries = odd ? p.entries1 : p.entries0;
+    const int ld = odd ? p.ld1 : p.ld0;
+    const int vert = odd ? p.vert1 : p.vert0;
+    const long long pos_stride = odd ? p.pos_stride1 : p.pos_stride0;
+    const float2 *base = odd ? p.patches1 + (size_t)mi * p.slice_stride1 : p.patches0 + (size_t)mi * p.slice_stride0;
     const bool want_w = p.wpartial != nullptr;
     const float *wbase = want_w ? p.wpatch + (size_t)mi * NN : nullptr;
     float2 acc = make_float2(0.f, 0.f);
     float wacc = 0.f;
     const int c_end = min(p.nch, (grp + 1) * p.cpb);
     for (int c = grp * p.cpb; c < c_end; ++c) {
-    const int *off = p.tile_off + (size_t)c * (p.n_tiles + 1);
+    const int *off = tile_off + (size_t)c * (p.n_tiles + 1);
     const int e0 = off[t], e1 = off[t + 1];
     for (int e = e0; e < e1; e += kUnroll) {
         int sl[kUnroll], loc[kUnroll];
@@ -557,19 +571,20 @@ __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
             loc[u] = -1;
             sl[u] = 0;
             if (e + u < e1) {
-                const int4 en = p.entries[e + u];
+                const int4 en = entries[e + u];
                 int ly = y - en.y;
                 if (ly < 0) ly += p.H;
                 int lx = x - en.z;
                 if (lx < 0) lx += p.W;
                 sl[u] = en.x;
-                if (ly < p.N && lx < p.N) loc[u] = ly * p.N + lx;
+                const int rows = p.N + (vert ? en.w : 0), cols = p.N + (vert ? 0 : en.w);
+                if (ly < rows && lx < cols) loc[u] = ly * ld + lx;
             }
         }
         float2 v[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-            v[u] = loc[u] >= 0 ? base[(size_t)sl[u] * p.pos_stride + loc[u]] : make_float2(0.f, 0.f);
+            v[u] = loc[u] >= 0 ? base[(size_t)sl[u] * pos_stride + loc[u]] : make_float2(0.f, 0.f);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) acc = cadd(acc, v[u]);
         if (want_w) {

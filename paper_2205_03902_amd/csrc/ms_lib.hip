@@ -88,6 +88,22 @@ struct HostPlan {
     std::vector<int> tile_off;                // nb x kChunks x (n_tiles + 1), absolute offsets
     std::vector<int4> tile_list;
     std::vector<int> class_off, class_list;   // nb x kChunks x (C + 1), absolute offsets
+    // Band sums of the line path's gradient patches (line_band_kernel).  Orientation o = 0: row
+    // launches (even slices), bands of one origin x ordered by origin y; o = 1: column launches (odd
+    // slices), bands of one origin y and one origin x modulo 16, ordered by origin x.  Per batch: the
+    // bands' members (batch-local positions, absolute offsets) with their offsets from the band's
+    // first origin, the workgroups (batch-local band, member range, first band line) and the
+    // scatter lists of the band images (entries (batch-local band, origin y, origin x, spread)),
+    // chunked like the patch lists with a count common to both orientations.
+    bool bands[2] = {false, false};                  // per orientation: whether its bands pay
+    int band_rows = 0, band_ld = 0;                  // row-launch band rows (pitch N); column-launch pitch
+    int64_t band_count = 0;                          // most bands of one batch and used orientation
+    std::vector<int> wg_first[2];                    // nb + 1: first workgroup of each batch
+    std::vector<int4> wg[2];
+    std::vector<int> bmem[2], bdelta[2];
+    std::vector<int> btile_off[2];                   // nb x kChunks x (n_tiles + 1), absolute offsets
+    std::vector<int4> btile_list[2];
+    std::vector<int> band_nch;                       // chunks per batch
 };
 
 // A batch of `count` positions is reduced in nch chunks of cs consecutive positions.
@@ -238,6 +254,207 @@ size_t tile_entries(const HostPlan &hp)
     return total;
 }
 
+// One band: its members in order (batch-local positions), their offsets from the first origin
+// along the cross axis, and the first member's origin.
+struct Band {
+    std::vector<int> mem, delta;
+    int oy = 0, ox = 0;
+};
+
+// Bands of positions [s0, s0 + count) in orientation o (see HostPlan).  A band ends where the next
+// origin lies more than N beyond the previous one (the windows would leave a gap) or more than
+// H - N (W - N) beyond the first (the band image would wrap onto itself).
+void make_bands(const HostPlan &hp, int64_t s0, int64_t count, int o, std::vector<Band> &out)
+{
+    out.clear();
+    std::vector<int> idx((size_t)count);
+    for (int64_t a = 0; a < count; ++a) idx[(size_t)a] = (int)a;
+    auto key = [&](int a) {
+        const int4 &q = hp.pos_info[s0 + a];
+        return o == 0 ? std::make_tuple(q.y, 0, q.x) : std::make_tuple(q.x, q.y & 15, q.y);
+    };
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+        const auto ka = key(a), kb = key(b);
+        return ka != kb ? ka < kb : a < b;
+    });
+    const int limit = o == 0 ? hp.H - hp.n : hp.W - hp.n;
+    for (size_t i = 0; i < idx.size();) {
+        Band bd;
+        const auto k0 = key(idx[i]);
+        const int first = std::get<2>(k0);
+        int prev = first;
+        size_t e = i;
+        while (e < idx.size()) {
+            const auto k = key(idx[e]);
+            if (std::get<0>(k) != std::get<0>(k0) || std::get<1>(k) != std::get<1>(k0)) break;
+            const int along = std::get<2>(k);
+            if (e > i && (along - prev > hp.n || along - first > limit)) break;
+            bd.mem.push_back(idx[e]);
+            bd.delta.push_back(along - first);
+            prev = along;
+            ++e;
+        }
+        const int4 &q = hp.pos_info[s0 + idx[i]];
+        bd.oy = q.x;
+        bd.ox = q.y;
+        out.push_back(std::move(bd));
+        i = e;
+    }
+}
+
+// Lines (rows or columns) of a band image: N plus the spread of its origins.
+int band_extent(const HostPlan &hp, const Band &bd) { return hp.n + bd.delta.back(); }
+
+// Tiles covered by an image of rows x cols at origin (oy, ox), wrapping.
+void image_tiles(const HostPlan &hp, int oy, int ox, int rows, int cols, std::vector<int> &out,
+                 std::vector<char> &mark_y, std::vector<char> &mark_x)
+{
+    std::vector<int> ty_list, tx_list;
+    std::fill(mark_y.begin(), mark_y.end(), 0);
+    std::fill(mark_x.begin(), mark_x.end(), 0);
+    for (int i = 0; i < rows; ++i) {
+        const int ty = ((oy + i) % hp.H) / kTileH;
+        if (!mark_y[ty]) { mark_y[ty] = 1; ty_list.push_back(ty); }
+    }
+    for (int i = 0; i < cols; ++i) {
+        const int tx = ((ox + i) % hp.W) / kTileW;
+        if (!mark_x[tx]) { mark_x[tx] = 1; tx_list.push_back(tx); }
+    }
+    out.clear();
+    for (int ty : ty_list)
+        for (int tx : tx_list) out.push_back(ty * hp.tiles_x + tx);
+}
+
+// Tiles of the band image of orientation o.
+void band_tiles(const HostPlan &hp, const Band &bd, int o, std::vector<int> &out, std::vector<char> &my,
+                std::vector<char> &mx)
+{
+    const int ext = band_extent(hp, bd);
+    image_tiles(hp, bd.oy, bd.ox, o == 0 ? ext : hp.n, o == 0 ? hp.n : ext, out, my, mx);
+}
+
+// Band sizes for batches of B.  Bands of an orientation pay when their images take at most three
+// quarters of the elements of the patches they replace; the image geometry covers the longest
+// band of each used orientation: rows (row launches, pitch N; a multiple of 16) and pitch (column
+// launches).
+struct BandStats {
+    bool on[2] = {false, false};
+    int rows = 0, ld = 0;
+    int64_t count_max = 0, count[2] = {0, 0}, entries[2] = {0, 0}, workgroups[2] = {0, 0};
+};
+
+BandStats band_stats(const HostPlan &hp, int64_t B)
+{
+    BandStats bs;
+    if (hp.n < 32) return bs;
+    const int64_t nb = (hp.S + B - 1) / B;
+    std::vector<Band> bands;
+    std::vector<int> tiles;
+    std::vector<char> my(hp.tiles_y), mx(hp.tiles_x);
+    int64_t maxc[2] = {0, 0};
+    int maxe[2] = {0, 0};
+    double elems[2] = {0.0, 0.0};
+    for (int o = 0; o < 2; ++o)
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t s0 = b * B, count = std::min(hp.S, s0 + B) - s0;
+            make_bands(hp, s0, count, o, bands);
+            bs.count[o] += (int64_t)bands.size();
+            maxc[o] = std::max(maxc[o], (int64_t)bands.size());
+            for (const Band &bd : bands) {
+                const int ext = band_extent(hp, bd);
+                maxe[o] = std::max(maxe[o], ext);
+                elems[o] += (double)ext * hp.n;
+                band_tiles(hp, bd, o, tiles, my, mx);
+                bs.entries[o] += (int64_t)tiles.size();
+                bs.workgroups[o] += (ext + 15) / 16;
+            }
+        }
+    const double patches = (double)hp.S * hp.n * hp.n;
+    for (int o = 0; o < 2; ++o) {
+        bs.on[o] = elems[o] <= 0.75 * patches;
+        if (bs.on[o]) bs.count_max = std::max(bs.count_max, maxc[o]);
+    }
+    bs.rows = bs.on[0] ? (maxe[0] + 15) / 16 * 16 : 0;
+    bs.ld = bs.on[1] ? maxe[1] : 0;
+    return bs;
+}
+
+// Elements of one band image (the stride between a slice's band images).
+size_t band_elems(const HostPlan &hp) { return (size_t)hp.n * std::max(hp.band_rows, hp.band_ld); }
+
+void build_band_lists(HostPlan &hp)
+{
+    const int64_t B = hp.B;
+    const size_t tstride = (size_t)hp.n_tiles + 1;
+    std::vector<int> tiles;
+    std::vector<char> my(hp.tiles_y), mx(hp.tiles_x);
+    std::vector<std::vector<Band>> per(2 * (size_t)hp.nb);
+    hp.band_nch.assign(hp.nb, 1);
+    for (int o = 0; o < 2; ++o)
+        for (int b = 0; b < hp.nb; ++b) {
+            const int64_t s0 = (int64_t)b * B, count = std::min(hp.S, s0 + B) - s0;
+            make_bands(hp, s0, count, o, per[(size_t)o * hp.nb + b]);
+        }
+    for (int b = 0; b < hp.nb; ++b)
+        for (int o = 0; o < 2; ++o)
+            if (hp.bands[o]) hp.band_nch[b] = std::max(hp.band_nch[b], chunking((int64_t)per[(size_t)o * hp.nb + b].size()).nch);
+    for (int o = 0; o < 2; ++o) {
+        hp.wg_first[o].assign(hp.nb + 1, 0);
+        if (!hp.bands[o]) continue;
+        hp.wg[o].clear(); hp.bmem[o].clear(); hp.bdelta[o].clear();
+        hp.btile_off[o].assign((size_t)hp.nb * kChunks * tstride, 0);
+        hp.btile_list[o].clear();
+        std::vector<int> cnt(hp.n_tiles);
+        int base = 0;
+        for (int b = 0; b < hp.nb; ++b) {
+            const std::vector<Band> &bands = per[(size_t)o * hp.nb + b];
+            // members and workgroups: each 16 band lines, the members whose window meets them;
+            // the longest first (ties in band and line order) so that the launch ends evenly
+            hp.wg_first[o][b] = (int)hp.wg[o].size();
+            std::vector<int4> wgs;
+            for (size_t g = 0; g < bands.size(); ++g) {
+                const Band &bd = bands[g];
+                const int m0 = (int)hp.bmem[o].size();
+                hp.bmem[o].insert(hp.bmem[o].end(), bd.mem.begin(), bd.mem.end());
+                hp.bdelta[o].insert(hp.bdelta[o].end(), bd.delta.begin(), bd.delta.end());
+                const int lines = (band_extent(hp, bd) + 15) / 16 * 16;
+                size_t lo = 0, hi = 0;
+                for (int u0 = 0; u0 < lines; u0 += 16) {
+                    while (lo < bd.delta.size() && bd.delta[lo] + hp.n <= u0) ++lo;
+                    while (hi < bd.delta.size() && bd.delta[hi] < u0 + 16) ++hi;
+                    if (hi > lo) wgs.push_back(make_int4((int)g, m0 + (int)lo, m0 + (int)hi, u0));
+                }
+            }
+            std::stable_sort(wgs.begin(), wgs.end(), [](const int4 &x, const int4 &y) { return x.z - x.y > y.z - y.y; });
+            hp.wg[o].insert(hp.wg[o].end(), wgs.begin(), wgs.end());
+            // scatter lists of the band images, chunks of consecutive bands
+            const int64_t ng = (int64_t)bands.size();
+            std::vector<std::vector<int>> cover((size_t)ng);
+            for (int64_t g = 0; g < ng; ++g) band_tiles(hp, bands[(size_t)g], o, cover[(size_t)g], my, mx);
+            const Chunking ch = chunking(ng);
+            for (int c = 0; c < kChunks; ++c) {
+                const int64_t a0 = std::min<int64_t>((int64_t)c * ch.cs, ng);
+                const int64_t a1 = std::min<int64_t>(a0 + ch.cs, ng);
+                std::fill(cnt.begin(), cnt.end(), 0);
+                for (int64_t g = a0; g < a1; ++g)
+                    for (int t : cover[(size_t)g]) cnt[t]++;
+                int *off = &hp.btile_off[o][((size_t)b * kChunks + c) * tstride];
+                off[0] = base;
+                for (int t = 0; t < hp.n_tiles; ++t) off[t + 1] = off[t] + cnt[t];
+                hp.btile_list[o].resize((size_t)off[hp.n_tiles]);
+                std::vector<int> cur(off, off + hp.n_tiles);
+                for (int64_t g = a0; g < a1; ++g) {
+                    const Band &bd = bands[(size_t)g];
+                    const int4 e = make_int4((int)g, bd.oy, bd.ox, bd.delta.back());
+                    for (int t : cover[(size_t)g]) hp.btile_list[o][(size_t)cur[t]++] = e;
+                }
+                base = off[hp.n_tiles];
+            }
+        }
+        hp.wg_first[o][hp.nb] = (int)hp.wg[o].size();
+    }
+}
+
 // Stored incident waves per position: all M with K = 1; otherwise the checkpoints psi_K,
 // psi_2K, ... (floor((M - 1) / K) of them) and one work slot, which holds the recomputed wave
 // of the slice being taken and then its gradient patch.
@@ -254,6 +471,7 @@ struct Layout {
     size_t tile_off, tile_list, class_off, class_list, sub_class_off, sub_class_list;
     size_t spart, wpart, cpart;
     size_t waves, probe_patch, overlap, loss_pos, half, replay, loss_part, energy;
+    size_t wg[2], bmem[2], bdelta[2], btile_off[2], btile_list[2], band;
     size_t total;
 };
 
@@ -319,6 +537,18 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     L.replay = take((lines_possible && hp.K > 1) ? (size_t)B * NN * 8 : 0);
     L.loss_part = take(lines_possible ? (size_t)B * (n / 16) * 8 : 0);
     L.energy = take((n / 16) * 8);
+    // band sums of the line path: workgroups, members, scatter lists and the band images of the
+    // slices one scatter takes
+    const BandStats bs = band_stats(hp, B);
+    for (int d = 0; d < 2; ++d) {
+        const bool on = bs.on[d];
+        L.wg[d] = take(on ? (size_t)bs.workgroups[d] * 16 : 0);
+        L.bmem[d] = take(on ? S * 4 : 0);
+        L.bdelta[d] = take(on ? S * 4 : 0);
+        L.btile_off[d] = take(on ? nb * kChunks * (hp.n_tiles + 1) * 4 : 0);
+        L.btile_list[d] = take(on ? (size_t)bs.entries[d] * 16 : 0);
+    }
+    L.band = take(scattered * (size_t)bs.count_max * n * std::max(bs.rows, bs.ld) * 8);
     L.total = o;
     return L;
 }
@@ -375,6 +605,9 @@ struct ms_plan {
     std::vector<hipEvent_t> ev_start, ev_stop;
     size_t ev_used = 0;
     bool lines = false;   // line kernels instead of the fused per-position kernel
+    // the line path sums gradient patches into band images when the plan has them: of row and
+    // column launches (MS_BANDS_ALL), row launches only, or none
+    int band_mode = MS_BANDS_ALL;
     // A second stream (default priority) for the probe-gradient reductions, which only read
     // what the per-position kernel wrote and so run beside the slice scatter; fork and join
     // through events on the caller's stream.
@@ -388,6 +621,12 @@ struct ms_plan {
     long long wave_stride() const { return (long long)wave_slots(hp.M, hp.K) * hp.n * hp.n; }
     long long ovl_stride() const { return (long long)overlap_slots(hp.M, hp.K) * hp.n * hp.n; }
     bool recompute() const { return hp.K > 1; }
+    bool bands_active(int o) const
+    {
+        return lines && hp.bands[o] && (band_mode == MS_BANDS_ALL || (band_mode == MS_BANDS_ROWS && o == 0));
+    }
+    long long band_stride() const { return (long long)band_elems(hp); }
+    long long band_slice_stride() const { return (long long)hp.band_count * band_stride(); }
 };
 
 namespace {
@@ -441,6 +680,38 @@ void launch_line_n(int n, bool row, const LineParams &lp, int stage, int count, 
     }
 }
 
+template <int N>
+void launch_band(bool row, const LineParams &lp, const BandParams &bp, int workgroups, hipStream_t st)
+{
+    const dim3 block(kLinesPerGroup * Win<N>::R);
+    if (row) line_band_kernel<N, true><<<workgroups, block, 0, st>>>(lp, bp);
+    else line_band_kernel<N, false><<<workgroups, block, 0, st>>>(lp, bp);
+}
+
+// Adjoint launch of slice lp.m for batch b with the gradient patches summed into the band images
+// at out (row launches for even slices).
+void launch_band_n(ms_plan *p, int b, const LineParams &lp, float2 *out, hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
+    const int o = lp.m & 1;
+    const int first = hp.wg_first[o][b], workgroups = hp.wg_first[o][b + 1] - first;
+    if (workgroups < 1) return;
+    BandParams bp{};
+    bp.wg = p->at<int4>(p->L.wg[o]) + first;
+    bp.mem = p->at<int>(p->L.bmem[o]);
+    bp.delta = p->at<int>(p->L.bdelta[o]);
+    bp.band = out;
+    bp.band_stride = p->band_stride();
+    bp.ld = o == 0 ? hp.n : hp.band_ld;
+    const bool row = o == 0;
+    switch (hp.n) {
+        case 32: launch_band<32>(row, lp, bp, workgroups, st); break;
+        case 64: launch_band<64>(row, lp, bp, workgroups, st); break;
+        case 128: launch_band<128>(row, lp, bp, workgroups, st); break;
+        default: launch_band<256>(row, lp, bp, workgroups, st); break;
+    }
+}
+
 // Line-kernel parameters shared by every launch of one batch (per-launch fields cleared).
 LineParams line_params(ms_plan *p, const FusedParams &fp, int mode)
 {
@@ -461,7 +732,8 @@ LineParams line_params(ms_plan *p, const FusedParams &fp, int mode)
 // Forward launches m = 0..M-1 (layout of slice m: rows for even m), the far-field launch
 // in the other layout, then (unless forward-only) the adjoint launches m = M-1 .. m_stop.
 // Every wave the mode needs is stored (K = 1 layout; the layer mode uses slot 0).
-void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream_t st)
+// Batch b >= 0 of a plain adjoint sums the gradient patches into bands when the plan has them.
+void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream_t st, int b)
 {
     const HostPlan &hp = p->hp;
     const int M = hp.M;
@@ -498,7 +770,10 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
         }
         lp.patch_stride = lp.psi_in_stride = fp.wave_stride;
         lp.go_on = (m > m_stop) || (mode != kLayer);
-        launch_line_n(hp.n, (m & 1) == 0, lp, kStageAdjoint, count, st);
+        if (mode == kAdjoint && !fp.full && b >= 0 && p->bands_active(m & 1))
+            launch_band_n(p, b, lp, p->at<float2>(p->L.band) + m * p->band_slice_stride(), st);
+        else
+            launch_line_n(hp.n, (m & 1) == 0, lp, kStageAdjoint, count, st);
     }
 }
 
@@ -518,15 +793,17 @@ struct TimedRegion {
 };
 
 // All per-position work of one batch, with optional timing.
-void launch_fused(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream_t st)
+void launch_fused(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream_t st, int b = -1)
 {
     TimedRegion t(p, st);
-    if (p->lines) run_lines(p, mode, fp, count, st);
+    if (p->lines) run_lines(p, mode, fp, count, st, b);
     else launch_fused_raw(p->hp.n, mode, fp, count, st);
 }
 
 void scatter(ms_plan *p, int b, int count, const float2 *patches, long long pos_stride, const float *wpatch,
              long long w_stride, int n_m, float2 *out, float *wout, int accumulate, hipStream_t st);
+void scatter_slices(ms_plan *p, int b, int count, const float2 *patches, long long pos_stride, int m0, int n_m,
+                    float2 *out, int accumulate, hipStream_t st);
 
 // Adjoint of one batch with recomputed incident waves (K > 1): the forward chain stores psi_K,
 // psi_2K, ... and the head slice M - 1; then, slice by slice from M - 1 down to 0, the wave of the
@@ -558,6 +835,7 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
     }
     LineParams lp = line_params(p, fp, kAdjoint);
     float2 *R = p->at<float2>(p->L.replay);
+
     {
         TimedRegion t(p, st);
         for (int m = 0; m < M; ++m) {
@@ -601,6 +879,11 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
         }
         lp.m = m;
         lp.psi_in = (m == 0) ? nullptr : (m % K == 0 ? ck_slot(m) : work);
+        if (!w && p->bands_active(m & 1)) {
+            launch_band_n(p, b, lp, p->at<float2>(p->L.band), st);
+            scatter_slices(p, b, count, work, fp.wave_stride, m, 1, g + m * hw, accumulate, st);
+            continue;
+        }
         launch_line_n(hp.n, (m & 1) == 0, lp, kStageAdjoint, count, st);
         scatter(p, b, count, work, fp.wave_stride, ovl, fp.ovl_stride, 1, g + m * hw, w ? w + m * hw : nullptr,
                 accumulate, st);
@@ -751,29 +1034,22 @@ int grid_for(long long count) { return (int)std::max<long long>(1, std::min<long
 // Gradient patches of batch b for n_m consecutive slices into out (n_m x H x W), and the
 // overlap patches into wout if given; accumulate adds to what out already holds.  patches:
 // slice i of position a at patches + a * pos_stride + i * N^2 (wpatch likewise with w_stride).
-void scatter(ms_plan *p, int b, int count, const float2 *patches, long long pos_stride, const float *wpatch,
-             long long w_stride, int n_m, float2 *out, float *wout, int accumulate, hipStream_t st)
+// Pass 1 over nch chunks of images and pass 2 (chunk partials in order) for n_m slices.
+void scatter_launch(ms_plan *p, ScatterParams &sp, int nch, int n_m, float2 *out, float *wout, int accumulate,
+                    hipStream_t st)
 {
     const HostPlan &hp = p->hp;
-    const Chunking ch = chunking(count);
-    ScatterParams sp{};
-    sp.patches = patches;
-    sp.wpatch = wpatch;
-    sp.pos_stride = pos_stride;
-    sp.tile_off = p->at<int>(p->L.tile_off) + (size_t)b * kChunks * (hp.n_tiles + 1);
-    sp.entries = p->at<int4>(p->L.tile_list);
     sp.partial = p->at<float2>(p->L.spart);
     sp.wpartial = wout ? p->at<float>(p->L.wpart) : nullptr;
-    sp.w_stride = w_stride;
     sp.H = hp.H; sp.W = hp.W; sp.N = hp.n; sp.tiles_x = hp.tiles_x; sp.n_tiles = hp.n_tiles;
-    // Consecutive chunks are summed in one block (in ascending position order, as one longer
-    // chunk) while the grid keeps about kScatterBlocks blocks: fewer partial planes to write
-    // and reduce when many slices are scattered at once.
+    // Consecutive chunks are summed in one block (in ascending order, as one longer chunk) while
+    // the grid keeps about kScatterBlocks blocks: fewer partial planes to write and reduce when
+    // many slices are scattered at once.
     const long long per_group = (long long)hp.n_tiles * n_m;
-    const int groups = (int)std::min<long long>(ch.nch, std::max<long long>(1, (kScatterBlocks + per_group - 1) / per_group));
-    sp.nch = ch.nch;
-    sp.cpb = (ch.nch + groups - 1) / groups;
-    const int ngrp = (ch.nch + sp.cpb - 1) / sp.cpb;
+    const int groups = (int)std::min<long long>(nch, std::max<long long>(1, (kScatterBlocks + per_group - 1) / per_group));
+    sp.nch = nch;
+    sp.cpb = (nch + groups - 1) / groups;
+    const int ngrp = (nch + sp.cpb - 1) / sp.cpb;
     scatter_partial_kernel<<<dim3(hp.n_tiles, ngrp, n_m), 256, 0, st>>>(sp);
     const long long plane = (long long)n_m * hp.H * hp.W;
     chunk_reduce_kernel<float2><<<grid_for(plane), 256, 0, st>>>(sp.partial, ngrp, plane, out, accumulate);
@@ -782,6 +1058,62 @@ void scatter(ms_plan *p, int b, int count, const float2 *patches, long long pos_
         chunk_reduce_kernel<float><<<grid_for(n_m * hw), 256, 0, st>>>(sp.wpartial, ngrp, n_m * hw, wout,
                                                                         accumulate);
     }
+}
+
+void scatter(ms_plan *p, int b, int count, const float2 *patches, long long pos_stride, const float *wpatch,
+             long long w_stride, int n_m, float2 *out, float *wout, int accumulate, hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
+    ScatterParams sp{};
+    sp.patches0 = sp.patches1 = patches;
+    sp.wpatch = wpatch;
+    sp.pos_stride0 = sp.pos_stride1 = pos_stride;
+    sp.slice_stride0 = sp.slice_stride1 = (long long)hp.n * hp.n;
+    sp.tile_off0 = sp.tile_off1 = p->at<int>(p->L.tile_off) + (size_t)b * kChunks * (hp.n_tiles + 1);
+    sp.entries0 = sp.entries1 = p->at<int4>(p->L.tile_list);
+    sp.ld0 = sp.ld1 = hp.n;
+    sp.w_stride = w_stride;
+    scatter_launch(p, sp, chunking(count).nch, n_m, out, wout, accumulate, st);
+}
+
+// Gradient images of batch b for slices m0 .. m0 + n_m - 1 into out (n_m x H x W): for each
+// parity the band images (slice i's at the band buffer + i * band slice stride) when its launches
+// sum bands, else the per-position patches (slice i of position a at patches + a * pos_stride +
+// i * N^2).
+void scatter_slices(ms_plan *p, int b, int count, const float2 *patches, long long pos_stride, int m0, int n_m,
+                    float2 *out, int accumulate, hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
+    ScatterParams sp{};
+    const size_t toff = (size_t)b * kChunks * (hp.n_tiles + 1);
+    int nch = chunking(count).nch;
+    for (int o = 0; o < 2; ++o) {
+        // list o serves the slices m0 + i of parity o
+        const float2 *img = patches;
+        long long ps = pos_stride, ss = (long long)hp.n * hp.n;
+        const int *off = p->at<int>(p->L.tile_off) + toff;
+        const int4 *ent = p->at<int4>(p->L.tile_list);
+        int ld = hp.n, vert = 0;
+        if (p->bands_active(o)) {
+            img = p->at<float2>(p->L.band);
+            ps = p->band_stride();
+            ss = p->band_slice_stride();
+            off = p->at<int>(p->L.btile_off[o]) + toff;
+            ent = p->at<int4>(p->L.btile_list[o]);
+            ld = o == 0 ? hp.n : hp.band_ld;   // row launches: N + spread rows of N; columns: N rows
+            vert = o == 0 ? 1 : 0;
+            nch = std::max(nch, hp.band_nch[b]);
+        }
+        if (o == 0) {
+            sp.patches0 = img; sp.pos_stride0 = ps; sp.slice_stride0 = ss;
+            sp.tile_off0 = off; sp.entries0 = ent; sp.ld0 = ld; sp.vert0 = vert;
+        } else {
+            sp.patches1 = img; sp.pos_stride1 = ps; sp.slice_stride1 = ss;
+            sp.tile_off1 = off; sp.entries1 = ent; sp.ld1 = ld; sp.vert1 = vert;
+        }
+    }
+    sp.m0 = m0;
+    scatter_launch(p, sp, nch, n_m, out, nullptr, accumulate, st);
 }
 
 // Probe patches of one batch summed per shift class into class_acc (accumulate adds).
@@ -896,6 +1228,15 @@ ms_status build_plan(ms_plan *p, const ms_problem *pb, char *ws, size_t ws_bytes
                                        std::to_string(make_layout(one, 1, ne).total) + ")");
     }
     build_lists(hp, B);
+    {
+        const BandStats bs = band_stats(hp, B);
+        hp.bands[0] = bs.on[0];
+        hp.bands[1] = bs.on[1];
+        hp.band_rows = bs.rows;
+        hp.band_ld = bs.ld;
+        hp.band_count = bs.count_max;
+        if (bs.on[0] || bs.on[1]) build_band_lists(hp);
+    }
     p->L = make_layout(hp, B, ne);
     if (p->L.total > ws_bytes) return fail(MS_ERR_BUDGET, std::string(ws_name) + " too small");
     p->ws = ws;
@@ -961,6 +1302,12 @@ ms_status build_plan(ms_plan *p, const ms_problem *pb, char *ws, size_t ws_bytes
               up(p->L.tile_list, hp.tile_list.data(), hp.tile_list.size() * 16) &&
               up(p->L.class_off, hp.class_off.data(), hp.class_off.size() * 4) &&
               up(p->L.class_list, hp.class_list.data(), hp.class_list.size() * 4);
+    for (int d = 0; ok && d < 2; ++d)
+        ok = !hp.bands[d] || (up(p->L.wg[d], hp.wg[d].data(), hp.wg[d].size() * 16) &&
+             up(p->L.bmem[d], hp.bmem[d].data(), hp.bmem[d].size() * 4) &&
+             up(p->L.bdelta[d], hp.bdelta[d].data(), hp.bdelta[d].size() * 4) &&
+             up(p->L.btile_off[d], hp.btile_off[d].data(), hp.btile_off[d].size() * 4) &&
+             up(p->L.btile_list[d], hp.btile_list[d].data(), hp.btile_list[d].size() * 16));
     if (!ok) {
         hipError_t e = hipGetLastError();
         return fail(MS_ERR_HIP, std::string("table upload failed: ") + hipGetErrorString(e));
@@ -968,6 +1315,13 @@ ms_status build_plan(ms_plan *p, const ms_problem *pb, char *ws, size_t ws_bytes
     // the per-position tile vectors are no longer needed on the host
     hp.tile_list.clear();
     hp.tile_list.shrink_to_fit();
+    for (int d = 0; d < 2; ++d) {
+        std::vector<int4>().swap(hp.wg[d]);
+        std::vector<int>().swap(hp.bmem[d]);
+        std::vector<int>().swap(hp.bdelta[d]);
+        std::vector<int>().swap(hp.btile_off[d]);
+        std::vector<int4>().swap(hp.btile_list[d]);
+    }
     return MS_OK;
 }
 
@@ -1100,6 +1454,18 @@ ms_status ms_plan_set_path(ms_plan *p, int32_t path)
     }
 }
 
+ms_status ms_plan_set_bands(ms_plan *p, int32_t mode)
+{
+    g_err.clear();
+    if (!p) return fail(MS_ERR_INVALID_ARG, "plan is NULL");
+    if (mode != MS_BANDS_NONE && mode != MS_BANDS_ROWS && mode != MS_BANDS_ALL)
+        return fail(MS_ERR_INVALID_ARG, "unknown band mode");
+    p->band_mode = mode;
+    return MS_OK;
+}
+
+int32_t ms_plan_has_bands(const ms_plan *p) { return p ? (p->hp.bands[0] ? 1 : 0) | (p->hp.bands[1] ? 2 : 0) : 0; }
+
 namespace {
 
 ms_status make_probe(ms_plan *p, hipStream_t st, double alpha, const Aberrations &ab, ms_c64 *probe_out)
@@ -1214,7 +1580,7 @@ ms_status adjoint_impl(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms
         if (p->recompute())
             adjoint_recompute(p, fp, b, count, st, reinterpret_cast<float2 *>(grad_slices), nullptr, b > 0);
         else
-            launch_fused(p, kAdjoint, fp, count, st);
+            launch_fused(p, kAdjoint, fp, count, st, b);
         // the loss and the probe-gradient reductions read only the per-position outputs: they
         // run on the side stream while the slice scatter runs here; the next batch (which
         // overwrites those outputs) and the return wait for them
@@ -1232,8 +1598,8 @@ ms_status adjoint_impl(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms
         }
         if (fork && hipEventRecord(p->ev_join, aux) != hipSuccess) return check_hip("ms_adjoint join");
         if (!p->recompute())
-            scatter(p, b, count, fp.waves, fp.wave_stride, nullptr, 0, hp.M, reinterpret_cast<float2 *>(grad_slices),
-                    nullptr, b > 0, st);
+            scatter_slices(p, b, count, fp.waves, fp.wave_stride, 0, hp.M, reinterpret_cast<float2 *>(grad_slices),
+                           b > 0, st);
         if (fork && hipStreamWaitEvent(st, p->ev_join, 0) != hipSuccess) return check_hip("ms_adjoint join");
     }
     return check_hip("ms_adjoint");
