@@ -133,20 +133,20 @@ ms_status ms_plan_set_path(ms_plan *plan, int32_t path);
 /* Band sums of the line path's gradient patches in ms_adjoint.  The gradient of a slice
  * (Sec. 3.2) is the sum over positions of the patches conj(psi_m) o g placed at their
  * windows.  Where the scan puts many windows on one origin x (a scan column), the
- * adjoint launches of even slices (row launches) let each workgroup take 16 object rows
- * for all windows of such a band and write one image of the band's summed patches; odd
- * slices (column launches) do the same for windows of one origin y whose origins x agree
- * modulo 16.  The scatter then reads band images instead of one patch per position.  The
- * plan decides at creation, for row and for column launches, whether bands pay (their
- * images take at most three quarters of the elements of the patches they replace) and
- * holds their tables and images in the workspace; launches without them write patches.
- * The sums take another order than the per-position scatter, so results agree to
- * rounding; each setting is reproducible bit for bit.  MS_BANDS_ALL (the default): both;
- * MS_BANDS_ROWS: row launches only; MS_BANDS_NONE: patches everywhere. */
+ * adjoint launches of even slices let each workgroup take 16 object rows for all windows
+ * of such a band and write one image of the band's summed patches; odd slices (whose
+ * launches work on columns) do the same for the windows of one origin y.  The scatter
+ * then reads band images instead of one patch per position.  The plan decides at
+ * creation, for even and for odd slices, whether bands pay (their images take at most
+ * three quarters of the elements of the patches they replace) and holds their tables and
+ * images in the workspace; launches without them write patches.  The sums take another
+ * order than the per-position scatter, so results agree to rounding; each setting is
+ * reproducible bit for bit.  MS_BANDS_ALL (the default): both; MS_BANDS_ROWS: even
+ * slices only; MS_BANDS_NONE: patches everywhere. */
 typedef enum { MS_BANDS_NONE = 0, MS_BANDS_ROWS = 1, MS_BANDS_ALL = 2 } ms_band_mode;
 ms_status ms_plan_set_bands(ms_plan *plan, int32_t mode);
-/* Which launches of the plan have band tables (bands pay for its scan): bit 0 row
- * launches, bit 1 column launches. */
+/* Which slices of the plan have band tables (bands pay for its scan): bit 0 even
+ * slices, bit 1 odd slices. */
 int32_t ms_plan_has_bands(const ms_plan *plan);
 
 /* The data term of every loss, gradient and step of the plan.

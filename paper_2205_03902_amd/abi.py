@@ -229,7 +229,7 @@ class Plan:
         self.batch = lib().ms_plan_batch(handle)
         self.shift_classes = lib().ms_plan_shift_classes(handle)
         self.checkpoint_every = lib().ms_plan_checkpoint_every(handle)
-        self.has_bands = int(lib().ms_plan_has_bands(handle))   # bit 0 row launches, bit 1 column launches
+        self.has_bands = int(lib().ms_plan_has_bands(handle))   # bit 0 even slices, bit 1 odd slices
         self.workspace_bytes = ws
         self.budget_bytes = int(budget_bytes)
         self._path, self._objective, self._bands = MS_PATH_AUTO, MS_OBJECTIVE_AMPLITUDE, MS_BANDS_ALL

@@ -1,16 +1,21 @@
 // Line-resident multislice kernels for windows too large for one workgroup
 // (N = 256: a 256 x 256 complex window is 512 KB, beyond the LDS and the
-// register file of a CU).  A workgroup owns 16 lines (rows or columns) of one
-// position; each line is held by R = N/16 lanes of one wavefront exactly as in
-// the fused kernel.  Between launches the half-propagated window lives in a
-// per-position buffer A in global memory (L2/MALL-resident for a batch).
+// register file of a CU).  A workgroup owns 16 lines of one position; each line
+// is held by R = N/16 lanes of one wavefront exactly as in the fused kernel.
 //
 // The Fresnel propagator factorises over the two axes, so a propagation is a
-// row pass and a column pass that commute.  Launch m works in layout L_m (rows
-// for even m, columns for odd m): it finishes the propagation of gap m-1 along
-// its own axis, which yields the incident wave psi_m, applies slice m, and
-// starts the propagation of gap m along the same axis.  The next launch, in the
-// other layout, finishes it.  One global round trip per slice.
+// row pass and a column pass that commute.  Launch m works in frame m: the
+// natural layout for even m (lines are rows), the transposed one for odd m
+// (lines are columns).  Every per-position buffer a launch reads is stored in
+// its own frame, so each line is one contiguous row of it: the half-propagated
+// window A (written by the previous launch), the incident wave psi_m (stored by
+// the forward launch of slice m for its adjoint), and for odd slices a
+// transposed copy of the slice.  Launch m finishes the propagation of gap m-1
+// along its lines, which yields psi_m, applies slice m, starts the propagation
+// of gap m along the same lines and stores the result in the other frame for the
+// next launch: one global round trip per slice, the store staged through LDS so
+// that 16 lines go out as 128-byte pieces.  A alternates between two buffers
+// (a launch reads one and writes every row of the other).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,6 +36,7 @@ enum LineStage : int {
 struct LineParams {
     const float2 *class_probe;   // [C][N][N]
     const float2 *slices;        // [M][H][W]
+    const float2 *slices_t;      // [M / 2][W][H]: odd slice 2 i + 1 transposed at i
     const int4 *pos_info;        // [S]
     const int *pos_list;         // [count]
     const float2 *tw;            // [R][17]
@@ -39,14 +45,15 @@ struct LineParams {
     const float *measured;       // [S][N][N]
     float *intensity;            // [S][N][N] (forward mode)
     float2 *exit_waves;          // [S][N][N] or null
-    float2 *A;                   // [count][N][N] half-propagated window, read and written in place
+    const float2 *A_in;          // [count][N][N] half-propagated window in this launch's frame
+    float2 *A_out;               // [count][N][N] the same for the next launch, in the other frame
     float2 *probe_patch;         // [count][N][N] or null
     double *loss_part;           // [count][N / 16]
     int H, W, M, m;
     int mode;                    // kForward: intensities in the far-field launch; otherwise the residual
     int objective;               // 0 amplitude, 1 Poisson deviance
-    // Per-launch destinations, each [count] x stride elements (null: not used by this launch).
-    // Forward launch of slice m:
+    // Per-launch destinations, each [count] x stride elements in the launch's frame (null: not
+    // used by this launch).  Forward launch of slice m:
     const float2 *restart;       //   psi_m read from here (m > 0) instead of finishing the propagation in A
     long long restart_stride;
     float2 *psi_out;             //   psi_m stored here
@@ -103,6 +110,16 @@ __device__ __forceinline__ void gstore(const float2 (&v)[16], float2 *dst, int l
 // synchronise the workgroup).
 __device__ __forceinline__ int tile_swz(int c) { return c & 15; }
 
+// Swizzled tile row of the k-th row a lane fills or drains (rows r0 + RP k, RP = R <= 16 rows
+// apart): as for tile_idx below, one of 16 / RP per-lane bases plus a multiple of 16 known at
+// compile time.
+template <int N>
+__device__ __forceinline__ int tile_row(int r0, int k, int sw)
+{
+    constexpr int RP = kLinesPerGroup * Win<N>::R / 16, G = 16 / RP;
+    return ((r0 + RP * (k % G)) ^ sw) + 16 * (k / G);
+}
+
 template <int N, class F>
 __device__ __forceinline__ void tile_fill(float2 *tile, F load)
 {
@@ -116,7 +133,7 @@ __device__ __forceinline__ void tile_fill(float2 *tile, F load)
 #pragma unroll
         for (int k = 0; k < G; ++k) buf[k] = load(r0 + (k0 + k) * RP, c);
 #pragma unroll
-        for (int k = 0; k < G; ++k) tile[c * Win<N>::LD + ((r0 + (k0 + k) * RP) ^ sw)] = buf[k];
+        for (int k = 0; k < G; ++k) tile[c * Win<N>::LD + tile_row<N>(r0, k0 + k, sw)] = buf[k];
     }
     __syncthreads();
 }
@@ -128,7 +145,7 @@ __device__ __forceinline__ void tile_drain(const float2 *tile, F store)
     const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4, sw = tile_swz(c);
     __syncthreads();
 #pragma unroll 4
-    for (int r = r0; r < N; r += RP) store(r, c, tile[c * Win<N>::LD + (r ^ sw)]);
+    for (int k = 0; k < N / RP; ++k) store(r0 + RP * k, c, tile[c * Win<N>::LD + tile_row<N>(r0, k, sw)]);
     __syncthreads();
 }
 
@@ -210,27 +227,6 @@ __device__ __forceinline__ void line_store_abs2(const float2 (&v)[16], float *ds
     }
 }
 
-// Transmission by the object patch (or its conjugate) with wrap-around.
-template <int N, bool ROW, bool CONJ>
-__device__ __forceinline__ void line_patch(float2 (&v)[16], const float2 *slice, int H, int W, int oy, int ox,
-                                           const LinePos &q, float2 *tile)
-{
-    if (ROW) {
-        apply_patch<N, true, CONJ>(v, slice, H, W, oy, ox, q.line, q.j);
-    } else {
-        tile_fill<N>(tile, [&](int r, int c) {
-            int yy = oy + r, xx = ox + q.c0 + c;
-            if (yy >= H) yy -= H;
-            if (xx >= W) xx -= W;
-            return slice[(unsigned)(yy * W + xx)];
-        });
-        float2 t[16];
-        tile_get<N, false>(t, tile, q.lloc, q.j);
-#pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = CONJ ? cconjmul(t[k], v[k]) : cmul(v[k], t[k]);
-    }
-}
-
 // Residual at spectral positions against measured intensities (as residual<>, with the
 // measured values already in registers); returns this lane's FP64 loss share.
 template <int N>
@@ -299,9 +295,26 @@ __device__ __forceinline__ double group_sum(double x, double *red)
     return t;
 }
 
-template <int N, bool ROW>
-// At least 4 waves a SIMD (128 VGPRs): four workgroups a CU, as the LDS allows.  The column
-// kernel gives up a few registers to spills for it, and for 8 tile loads in flight.
+// Transmission by slice m (or its conjugate) on this launch's lines, with wrap-around: rows of
+// the slice (even m) or of its transposed copy (odd m), whose rows are the slice's columns.
+template <int N, bool TR, bool CONJ>
+__device__ __forceinline__ void frame_patch(float2 (&v)[16], const LineParams &p, int oy, int ox, int line, int j)
+{
+    const size_t hw = (size_t)p.H * p.W;
+    if (TR) apply_patch<N, true, CONJ>(v, p.slices_t + (size_t)(p.m / 2) * hw, p.W, p.H, ox, oy, line, j);
+    else apply_patch<N, true, CONJ>(v, p.slices + (size_t)p.m * hw, p.H, p.W, oy, ox, line, j);
+}
+
+// A window in the natural layout from a launch of either frame (SPEC: at spectral positions).
+template <int N, bool TR, bool SPEC>
+__device__ __forceinline__ void natural_store(const float2 (&v)[16], float2 *dst, const LinePos &q, float2 *tile)
+{
+    if constexpr (TR) line_store<N, false, SPEC>(v, dst, q, tile);
+    else line_store<N, true, SPEC>(v, dst, q, tile);
+}
+
+template <int N, bool TR>
+// At least 4 waves a SIMD (128 VGPRs): four workgroups a CU, as the LDS allows.
 __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(LineParams p, int stage)
 {
     using Wn = Win<N>;
@@ -322,9 +335,10 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
     const int oy = info.x, ox = info.y, cls = info.z;
     const int M = p.M, m = p.m;
     float2 *xb = xbuf + lloc * Wn::LD;
-    float2 *A = p.A + (size_t)b * NN;
+    const float2 *A_in = p.A_in + (size_t)b * NN;
+    float2 *A_out = p.A_out + (size_t)b * NN;
     const float2 *probe = p.class_probe + (size_t)cls * NN;
-    const float2 *hown = ROW ? p.hx : p.hy;
+    const float2 *hown = TR ? p.hy : p.hx;
 
     // tables for this launch: twiddles, and the own-axis factor of the gap that is finished,
     // later replaced by that of the gap that is started (one table of N: with 4 workgroups of
@@ -357,126 +371,138 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
     const LinePos q{line, lloc, j, (int)blockIdx.x * kLinesPerGroup};
     float2 v[16];
     if (stage == kStageForward) {
-        // ---- psi_m: the probe, a stored wave, or the propagation of gap m-1 finished along this axis ----
+        // ---- psi_m: the probe (m = 0, natural frame), a stored wave, or the propagation of gap
+        // m-1 finished along this launch's lines ----
         if (m == 0) {
-            line_load<N, ROW, false>(v, probe, q, xbuf);
+            line_load<N, true, false>(v, probe, q, xbuf);
         } else if (restart) {
-            line_load<N, ROW, false>(v, p.restart + (size_t)b * p.restart_stride, q, xbuf);
+            line_load<N, true, false>(v, p.restart + (size_t)b * p.restart_stride, q, xbuf);
         } else {
-            line_load<N, ROW, false>(v, A, q, xbuf);
+            line_load<N, true, false>(v, A_in, q, xbuf);
             prop_axis<N, false>(v, s_tw, xb, s_h, j);
         }
-        if (p.psi_out) line_store<N, ROW, false>(v, p.psi_out + (size_t)b * p.psi_out_stride, q, xbuf);
-        if (p.ovl_out) line_store_abs2<N, ROW, false>(v, p.ovl_out + (size_t)b * p.ovl_stride, q, xbuf);
+        if (p.psi_out) line_store<N, true, false>(v, p.psi_out + (size_t)b * p.psi_out_stride, q, xbuf);
+        if (p.ovl_out) line_store_abs2<N, true, false>(v, p.ovl_out + (size_t)b * p.ovl_stride, q, xbuf);
         if (p.stop_after_psi) return;
-        line_patch<N, ROW, false>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, q, xbuf);
+        frame_patch<N, TR, false>(v, p, oy, ox, line, j);
         if (m + 1 < M) {
             next_h();
             prop_axis<N, false>(v, s_tw, xb, s_h, j);
-            line_store<N, ROW, false>(v, A, q, xbuf);
+            line_store<N, false, false>(v, A_out, q, xbuf);    // the next launch's frame
         } else {
             if (p.mode == kForward && p.exit_waves)
-                line_store<N, ROW, false>(v, p.exit_waves + (size_t)s * NN, q, xbuf);
+                natural_store<N, TR, false>(v, p.exit_waves + (size_t)s * NN, q, xbuf);
             line_fft_fwd<N>(v, s_tw, xb, j);
-            line_store<N, ROW, true>(v, A, q, xbuf);    // spectral along this axis, at natural frequency
+            line_store<N, false, true>(v, A_out, q, xbuf);     // spectral along these lines, at natural frequency
         }
         return;
     }
 
     if (stage == kStageFar) {
-        // line index = frequency along the first axis (natural); FFT along this axis
-        line_load<N, ROW, false>(v, A, q, xbuf);
+        // line index = frequency along the other axis (natural); FFT along these lines
+        line_load<N, true, false>(v, A_in, q, xbuf);
         line_fft_fwd<N>(v, s_tw, xb, j);
         if (p.mode == kForward) {
-            line_store_abs2<N, ROW, true>(v, p.intensity + (size_t)s * NN, q, xbuf);
+            float *I = p.intensity + (size_t)s * NN;
+            if constexpr (TR) line_store_abs2<N, false, true>(v, I, q, xbuf);
+            else line_store_abs2<N, true, true>(v, I, q, xbuf);
             return;
         }
-        double part = line_residual<N, ROW>(v, p.measured + (size_t)s * NN, q, xbuf, p.objective);
+        const double part = line_residual<N, !TR>(v, p.measured + (size_t)s * NN, q, xbuf, p.objective);
         double tot = group_sum<N>(part, red);
         if (tid == 0) p.loss_part[(size_t)b * gridDim.x + blockIdx.x] = tot;
         line_fft_inv<N>(v, s_tw, xb, j);
-        line_store<N, ROW, false>(v, A, q, xbuf);
+        line_store<N, false, false>(v, A_out, q, xbuf);
         return;
     }
 
     // ---- adjoint launch for slice m ----
     if (m + 1 == M) {
-        // finish F^H r along this axis: A holds it at natural frequency positions
-        line_load<N, ROW, true>(v, A, q, xbuf);
+        // finish F^H r along these lines: A holds it at natural frequency positions
+        line_load<N, true, true>(v, A_in, q, xbuf);
         line_fft_inv<N>(v, s_tw, xb, j);
     } else {
-        line_load<N, ROW, false>(v, A, q, xbuf);
+        line_load<N, true, false>(v, A_in, q, xbuf);
         prop_axis<N, true>(v, s_tw, xb, s_h, j);
     }
     if (p.patch_out) {
         const float2 *psi = p.psi_in ? p.psi_in + (size_t)b * p.psi_in_stride : probe;
         float2 *dst = p.patch_out + (size_t)b * p.patch_stride;
         float *ovl = p.ovl_out ? p.ovl_out + (size_t)b * p.ovl_stride : nullptr;
-        if (ROW) {
-            // reads before writes in two halves: vector memory operations retire in issue
-            // order, so interleaved loads would each wait for the stores before them
-            const int l2 = opaque(line), j2 = opaque(j);
+        // reads before writes in two halves: vector memory operations retire in issue order, so
+        // interleaved loads would each wait for the stores before them
+        const int l2 = opaque(line), j2 = opaque(j);
 #pragma unroll
-            for (int h = 0; h < 16; h += 8) {
-                float2 ps[8];
+        for (int h = 0; h < 16; h += 8) {
+            float2 ps[8];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) ps[k] = psi[l2 * N + Wn::nat(j2, h + k)];
+            for (int k = 0; k < 8; ++k) ps[k] = psi[l2 * N + Wn::nat(j2, h + k)];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int idx = l2 * N + Wn::nat(j2, h + k);
-                    if (ovl) ovl[idx] = cabs2(ps[k]);
-                    dst[idx] = cconjmul(ps[k], v[h + k]);
-                }
+            for (int k = 0; k < 8; ++k) {
+                const int idx = l2 * N + Wn::nat(j2, h + k);
+                if (ovl) ovl[idx] = cabs2(ps[k]);
+                dst[idx] = cconjmul(ps[k], v[h + k]);
             }
-        } else {
-            float2 g[16];
-            line_load<N, false, false>(g, psi, q, xbuf);
-            if (ovl) line_store_abs2<N, false, false>(g, ovl, q, xbuf);
-#pragma unroll
-            for (int k = 0; k < 16; ++k) g[k] = cconjmul(g[k], v[k]);
-            line_store<N, false, false>(g, dst, q, xbuf);
         }
     }
     if (!p.go_on) return;
-    line_patch<N, ROW, true>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, oy, ox, q, xbuf);
+    frame_patch<N, TR, true>(v, p, oy, ox, line, j);
     if (m > 0) {
         next_h();
         prop_axis<N, true>(v, s_tw, xb, s_h, j);
-        line_store<N, ROW, false>(v, A, q, xbuf);
+        line_store<N, false, false>(v, A_out, q, xbuf);
     } else if (p.probe_patch) {
-        line_store<N, ROW, false>(v, p.probe_patch + (size_t)b * NN, q, xbuf);
+        line_store<N, true, false>(v, p.probe_patch + (size_t)b * NN, q, xbuf);
+    }
+}
+
+// Odd slices transposed for the line path's odd launches: out[i][x][y] = slices[2 i + 1][y][x]
+// (32 x 32 tiles through LDS; grid (W / 32, H / 32, M / 2), 256 lanes).
+__global__ __launch_bounds__(256) void transpose_odd_kernel(const float2 *slices, float2 *out, int H, int W)
+{
+    __shared__ float2 tile[32][33];
+    const size_t hw = (size_t)H * W;
+    const float2 *src = slices + (size_t)(2 * blockIdx.z + 1) * hw;
+    float2 *dst = out + (size_t)blockIdx.z * hw;
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int y = y0 + r, x = x0 + tx;
+        if (y < H && x < W) tile[r][tx] = src[(size_t)y * W + x];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int x = x0 + r, y = y0 + tx;
+        if (x < W && y < H) dst[(size_t)x * H + y] = tile[tx][r];
     }
 }
 
 // ---- band sums of the adjoint's gradient patches ----
 //
 // The gradient of slice m (Sec. 3.2) sums, over positions, the patch conj(psi_m) o g placed at the
-// window's origin.  Windows of one scan column (one origin x) overlap row for row: a workgroup of a
-// row launch that takes 16 object rows, rather than 16 window rows, for every position of such a
-// band sums the band's patches on those rows in registers and writes one (N + spread) x N band
-// image instead of N x N values per position.  Column launches do the same with 16 object columns
-// for the positions of one scan row whose origins x agree modulo 16, so that the columns a
-// workgroup takes are an aligned group of 16 in every member's window (row launches need no such
-// alignment: a row is one contiguous piece whatever its index).  The scatter then reads bands.
+// window's origin.  Windows of one scan column (one origin x) overlap row for row: a workgroup of an
+// even slice's launch that takes 16 object rows, rather than 16 window rows, for every position of
+// such a band sums the band's patches on those rows in registers and writes one (N + spread) x N
+// band image instead of N x N values per position.  Odd slices do the same in their transposed
+// frame: 16 object columns for the windows of one scan row (one origin y).  The scatter then reads
+// bands.
 //
-// Workgroup w takes band rows (row launches) or band columns (column launches) u0 .. u0 + 15 of
-// band `band`, u counted from the band's first origin along the cross axis; member i (origin
-// delta_i further along) holds them as window lines u0 + l - delta_i.  For column launches every
-// member covers all 16 (u0 - delta_i is a multiple of 16 in [0, N)); for row launches lines outside
-// the window are computed on a clamped index and neither stored nor summed.
+// Workgroup w takes band lines u0 .. u0 + 15 of band `band`, u counted from the band's first
+// origin across the lines; member i (origin delta_i further on) holds them as window lines
+// u0 + l - delta_i.  Lines outside the window are computed on a clamped index and neither stored
+// nor summed.
 struct BandParams {
     const int4 *wg;              // per workgroup: (band, first member, end member, u0)
     const int *mem;              // batch-local position of each member
-    const int *delta;            // each member's origin minus the band's first, along the cross axis
-    float2 *band;                // [bands] x band_stride
+    const int *delta;            // each member's origin minus the band's first, across the lines
+    float2 *band;                // [bands] x band_stride, (N + spread) x N each, in the launch's frame
     long long band_stride;
-    int ld;                      // row pitch of a band image: N (row launches) or N + spread (column launches)
 };
 
 // Adjoint launch of slice m over band workgroups (1D grid); otherwise the adjoint stage of
 // line_kernel for each member in turn, with both propagation tables kept in LDS.
-template <int N, bool ROW>
-__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, ROW ? 3 : 2) void line_band_kernel(LineParams p, BandParams bp)
+template <int N, bool TR>
+__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 3) void line_band_kernel(LineParams p, BandParams bp)
 {
     using Wn = Win<N>;
     constexpr int R = Wn::R;
@@ -488,7 +514,7 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, ROW ? 3 : 2) void line_
 
     const int tid = threadIdx.x;
     const int M = p.M, m = p.m;
-    const float2 *hown = ROW ? p.hx : p.hy;
+    const float2 *hown = TR ? p.hy : p.hx;
     const int g_fin = (m + 1 < M) ? m : -1;
     const int g_start = (m > 0 && p.go_on) ? m - 1 : -1;
     for (int i = tid; i < Wn::TW_WORDS; i += NT) s_tw[i] = p.tw[i];
@@ -505,70 +531,51 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, ROW ? 3 : 2) void line_
     for (int i = w.y; i < w.z; ++i) {
         // the lane's line and place, hidden from the optimiser each member: the LDS and global
         // addresses derived from them are recomputed where used rather than hoisted out of the
-        // loop and kept live (which spilled most of them)
+        // loop and kept live
         const int lloc = opaque(tid / R), j = opaque(tid % R);
         float2 *xb = xbuf + lloc * Wn::LD;
         const int b = bp.mem[i];
         const int4 info = p.pos_info[p.pos_list[b]];
         const int l0 = w.w - bp.delta[i];            // window line of lloc = 0
         const int wl = l0 + lloc;
-        const bool valid = !ROW || (unsigned)wl < (unsigned)N;
+        const bool valid = (unsigned)wl < (unsigned)N;
         const LinePos q{valid ? wl : 0, lloc, j, l0};
-        float2 *A = p.A + (size_t)b * NN;
+        const float2 *A_in = p.A_in + (size_t)b * NN;
         float2 v[16];
         if (m + 1 == M) {
-            line_load<N, ROW, true>(v, A, q, xbuf);
+            line_load<N, true, true>(v, A_in, q, xbuf);
             line_fft_inv<N>(v, s_tw, xb, j);
         } else {
-            line_load<N, ROW, false>(v, A, q, xbuf);
+            line_load<N, true, false>(v, A_in, q, xbuf);
             prop_axis<N, true>(v, s_tw, xb, s_hf, j);
         }
-        {
-            // acc += conj(psi_m) o g, psi_m read element by element (through the LDS tile for columns)
+        if (valid) {
+            // acc += conj(psi_m) o g
             const float2 *psi = p.psi_in ? p.psi_in + (size_t)b * p.psi_in_stride
                                          : p.class_probe + (size_t)info.z * NN;
-            if (ROW) {
-                if (valid) {
-                    const int l2 = opaque(q.line), j2 = opaque(j);
+            const int l2 = opaque(q.line), j2 = opaque(j);
 #pragma unroll
-                    for (int k = 0; k < 16; ++k)
-                        acc[k] = cadd(acc[k], cconjmul(psi[l2 * N + Wn::nat(j2, k)], v[k]));
-                }
-            } else {
-                tile_fill<N>(xbuf, [&](int r, int c) { return psi[r * N + q.c0 + c]; });
-                const float2 *col = xbuf + lloc * Wn::LD;
-                const int sw = tile_swz(lloc);
-#pragma unroll
-                for (int k = 0; k < 16; ++k) acc[k] = cadd(acc[k], cconjmul(col[tile_idx<N, false>(j, k, sw)], v[k]));
-            }
+            for (int k = 0; k < 16; ++k) acc[k] = cadd(acc[k], cconjmul(psi[l2 * N + Wn::nat(j2, k)], v[k]));
         }
         if (!p.go_on) continue;
-        line_patch<N, ROW, true>(v, p.slices + (size_t)m * p.H * p.W, p.H, p.W, info.x, info.y, q, xbuf);
-        float2 *dst = nullptr;
+        frame_patch<N, TR, true>(v, p, info.x, info.y, q.line, j);
         if (m > 0) {
             prop_axis<N, true>(v, s_tw, xb, s_hs, j);
-            dst = A;
-        } else if (p.probe_patch) {
-            dst = p.probe_patch + (size_t)b * NN;
-        }
-        if (dst) {
-            if (ROW) {
-                if (valid) gstore<N, true, false>(v, dst, q.line, j);
-            } else {
-                line_store<N, false, false>(v, dst, q, xbuf);
-            }
+            // into the other frame: window line l0 + c of row r, lines outside the window skipped
+            float2 *A_out = p.A_out + (size_t)b * NN;
+            tile_put<N, false>(v, xbuf, lloc, j);
+            tile_drain<N>(xbuf, [&](int r, int c, float2 x) {
+                if ((unsigned)(l0 + c) < (unsigned)N) A_out[r * N + l0 + c] = x;
+            });
+        } else if (p.probe_patch && valid) {
+            gstore<N, true, false>(v, p.probe_patch + (size_t)b * NN, q.line, j);
         }
     }
     float2 *band = bp.band + (size_t)w.x * bp.band_stride;
     const int lloc = tid / R, j = tid % R;
-    if (ROW) {
-        const int row = w.w + lloc;
+    const int row = w.w + lloc;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) band[(size_t)row * bp.ld + Wn::nat(j, k)] = acc[k];
-    } else {
-        tile_put<N, false>(acc, xbuf, lloc, j);
-        tile_drain<N>(xbuf, [&](int r, int c, float2 x) { band[(size_t)r * bp.ld + w.w + c] = x; });
-    }
+    for (int k = 0; k < 16; ++k) band[(size_t)row * N + Wn::nat(j, k)] = acc[k];
 }
 
 }  // namespace imsp

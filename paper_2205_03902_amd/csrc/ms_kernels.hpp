@@ -516,16 +516,18 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
 // pixel and in ascending position order, the patches of the chunk's windows that touch
 // the tile; pass 2 adds the chunk partials in chunk order.  The order is fixed by the
 // plan, so results are reproducible bit for bit.
-constexpr int kTileW = 64;   // scatter tile: 64 x 4 pixels, one 256-lane block
-constexpr int kTileH = 4;
+// Scatter tile: 16 x 16 pixels, one 256-lane block.  Lanes run along x for images stored in the
+// natural layout and along y for transposed ones, so that either reads 128-byte pieces.
+constexpr int kTileW = 16;
+constexpr int kTileH = 16;
 constexpr int kChunks = 16;  // chunks per batch
 constexpr int kUnroll = 8;   // patch loads in flight per lane
 
 // The images scattered are per-position patches (N x N) or band images of several positions (see
 // line_band_kernel): an entry (image, origin y, origin x, extent) covers N rows and N + extent
 // columns of the object (N + extent rows and N columns for vertical bands), element (y, x) of the
-// image at y * ld + x.  Slices m0 + i of even and odd index (row and column launches) have images,
-// lists and geometry of their own (the same for patches).
+// image at y * ld + x, or at x * ld + y for images stored transposed (the line path's odd slices).
+// Slices m0 + i of even and odd index have images, lists and geometry of their own.
 struct ScatterParams {
     // image e of slice i of the launch: patches + e * pos_stride + i * slice_stride, per parity
     const float2 *patches0, *patches1;
@@ -533,7 +535,7 @@ struct ScatterParams {
     const float *wpatch;        // overlap patch of (position e, slice i): wpatch + e * w_stride + i * N * N
     const int *tile_off0, *tile_off1;    // this batch: [kChunks][n_tiles + 1]
     const int4 *entries0, *entries1;
-    int ld0, ld1, vert0, vert1;
+    int ld0, ld1, vert0, vert1, trans0, trans1;
     int m0;                     // slice index of i = 0
     float2 *partial;            // [groups][n_m][H][W]
     float *wpartial;            // [groups][n_m][H][W] or null (patches only)
@@ -545,11 +547,13 @@ struct ScatterParams {
 __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
 {
     const int t = blockIdx.x, grp = blockIdx.y, mi = blockIdx.z, n_m = gridDim.z;
-    const int y = (t / p.tiles_x) * kTileH + (int)(threadIdx.x / kTileW);
-    const int x = (t % p.tiles_x) * kTileW + (int)(threadIdx.x % kTileW);
-    if (y >= p.H || x >= p.W) return;
-    const size_t NN = (size_t)p.N * p.N;
     const bool odd = ((p.m0 + mi) & 1) != 0;
+    const bool trans = (odd ? p.trans1 : p.trans0) != 0;
+    const int ta = (int)(threadIdx.x / 16), tb = (int)(threadIdx.x % 16);
+    const int y = (t / p.tiles_x) * kTileH + (trans ? tb : ta);
+    const int x = (t % p.tiles_x) * kTileW + (trans ? ta : tb);
+    const bool inside = y < p.H && x < p.W;
+    const size_t NN = (size_t)p.N * p.N;
     const int *tile_off = odd ? p.tile_off1 : p.tile_off0;
     const int4 *entries = odd ? p.entries1 : p.entries0;
     const int ld = odd ? p.ld1 : p.ld0;
@@ -560,7 +564,7 @@ __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
     const float *wbase = want_w ? p.wpatch + (size_t)mi * NN : nullptr;
     float2 acc = make_float2(0.f, 0.f);
     float wacc = 0.f;
-    const int c_end = min(p.nch, (grp + 1) * p.cpb);
+    const int c_end = inside ? min(p.nch, (grp + 1) * p.cpb) : 0;
     for (int c = grp * p.cpb; c < c_end; ++c) {
     const int *off = tile_off + (size_t)c * (p.n_tiles + 1);
     const int e0 = off[t], e1 = off[t + 1];
@@ -578,7 +582,7 @@ __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
                 if (lx < 0) lx += p.W;
                 sl[u] = en.x;
                 const int rows = p.N + (vert ? en.w : 0), cols = p.N + (vert ? 0 : en.w);
-                if (ly < rows && lx < cols) loc[u] = ly * ld + lx;
+                if (ly < rows && lx < cols) loc[u] = trans ? lx * ld + ly : ly * ld + lx;
             }
         }
         float2 v[kUnroll];
@@ -596,7 +600,22 @@ __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
         }
     }
     }
-    const size_t HW = (size_t)p.H * p.W, pix = (size_t)y * p.W + x;
+    const size_t HW = (size_t)p.H * p.W;
+    int yo = y, xo = x;
+    if (trans) {
+        // back to lanes along x for the partial planes (natural layout)
+        __shared__ float2 sacc[kTileH][kTileW + 1];
+        __shared__ float swacc[kTileH][kTileW + 1];
+        sacc[tb][ta] = acc;
+        swacc[tb][ta] = wacc;
+        __syncthreads();
+        acc = sacc[ta][tb];
+        wacc = swacc[ta][tb];
+        yo = (t / p.tiles_x) * kTileH + ta;
+        xo = (t % p.tiles_x) * kTileW + tb;
+    }
+    if (yo >= p.H || xo >= p.W) return;
+    const size_t pix = (size_t)yo * p.W + xo;
     p.partial[((size_t)grp * n_m + mi) * HW + pix] = acc;
     if (want_w) p.wpartial[((size_t)grp * n_m + mi) * HW + pix] = wacc;
 }

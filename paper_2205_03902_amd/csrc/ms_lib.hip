@@ -34,6 +34,11 @@ constexpr long long kScatterBlocks = 32768;   // target grid of the scatter pass
 // Distinct sub-pixel probe shifts per plan.  A raster has a few; refined positions have one per
 // position.  The class tables and partial sums take about (kChunks + 5) C N^2 8 bytes.
 constexpr int kMaxClasses = 4096;
+// Band members share their origin modulo kBandAlign across the lines, so that each member's window
+// lines in a band workgroup start at a multiple of 16: its transposed store of 16 lines then
+// writes whole aligned 128-byte pieces (measured on the 16384-position workload: 124 ms of line
+// kernels a pass with 16, 132 with 8, 153 with 4, 161 with 1).
+constexpr int kBandAlign = 16;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -88,15 +93,15 @@ struct HostPlan {
     std::vector<int> tile_off;                // nb x kChunks x (n_tiles + 1), absolute offsets
     std::vector<int4> tile_list;
     std::vector<int> class_off, class_list;   // nb x kChunks x (C + 1), absolute offsets
-    // Band sums of the line path's gradient patches (line_band_kernel).  Orientation o = 0: row
-    // launches (even slices), bands of one origin x ordered by origin y; o = 1: column launches (odd
-    // slices), bands of one origin y and one origin x modulo 16, ordered by origin x.  Per batch: the
-    // bands' members (batch-local positions, absolute offsets) with their offsets from the band's
-    // first origin, the workgroups (batch-local band, member range, first band line) and the
-    // scatter lists of the band images (entries (batch-local band, origin y, origin x, spread)),
-    // chunked like the patch lists with a count common to both orientations.
+    // Band sums of the line path's gradient patches (line_band_kernel).  Orientation o = 0: even
+    // slices (natural frame), bands of one origin x ordered by origin y; o = 1: odd slices
+    // (transposed frame), bands of one origin y ordered by origin x.  Per batch: the bands' members
+    // (batch-local positions, absolute offsets) with their offsets from the band's first origin,
+    // the workgroups (batch-local band, member range, first band line) and the scatter lists of the
+    // band images (entries (batch-local band, origin y, origin x, spread)), chunked like the patch
+    // lists with a count common to both orientations.
     bool bands[2] = {false, false};                  // per orientation: whether its bands pay
-    int band_rows = 0, band_ld = 0;                  // row-launch band rows (pitch N); column-launch pitch
+    int band_rows = 0;                               // lines of a band image (of N), a multiple of 16
     int64_t band_count = 0;                          // most bands of one batch and used orientation
     std::vector<int> wg_first[2];                    // nb + 1: first workgroup of each batch
     std::vector<int4> wg[2];
@@ -271,7 +276,7 @@ void make_bands(const HostPlan &hp, int64_t s0, int64_t count, int o, std::vecto
     for (int64_t a = 0; a < count; ++a) idx[(size_t)a] = (int)a;
     auto key = [&](int a) {
         const int4 &q = hp.pos_info[s0 + a];
-        return o == 0 ? std::make_tuple(q.y, 0, q.x) : std::make_tuple(q.x, q.y & 15, q.y);
+        return o == 0 ? std::make_tuple(q.y, q.x % kBandAlign, q.x) : std::make_tuple(q.x, q.y % kBandAlign, q.y);
     };
     std::sort(idx.begin(), idx.end(), [&](int a, int b) {
         const auto ka = key(a), kb = key(b);
@@ -302,7 +307,8 @@ void make_bands(const HostPlan &hp, int64_t s0, int64_t count, int o, std::vecto
     }
 }
 
-// Lines (rows or columns) of a band image: N plus the spread of its origins.
+// Lines of a band image (rows of the object for o = 0, columns for o = 1): N plus the spread of
+// its origins.
 int band_extent(const HostPlan &hp, const Band &bd) { return hp.n + bd.delta.back(); }
 
 // Tiles covered by an image of rows x cols at origin (oy, ox), wrapping.
@@ -334,12 +340,11 @@ void band_tiles(const HostPlan &hp, const Band &bd, int o, std::vector<int> &out
 }
 
 // Band sizes for batches of B.  Bands of an orientation pay when their images take at most three
-// quarters of the elements of the patches they replace; the image geometry covers the longest
-// band of each used orientation: rows (row launches, pitch N; a multiple of 16) and pitch (column
-// launches).
+// quarters of the elements of the patches they replace; a band image holds the longest band of
+// the used orientations (lines of N, rounded up to 16 lines).
 struct BandStats {
     bool on[2] = {false, false};
-    int rows = 0, ld = 0;
+    int rows = 0;
     int64_t count_max = 0, count[2] = {0, 0}, entries[2] = {0, 0}, workgroups[2] = {0, 0};
 };
 
@@ -374,13 +379,13 @@ BandStats band_stats(const HostPlan &hp, int64_t B)
         bs.on[o] = elems[o] <= 0.75 * patches;
         if (bs.on[o]) bs.count_max = std::max(bs.count_max, maxc[o]);
     }
-    bs.rows = bs.on[0] ? (maxe[0] + 15) / 16 * 16 : 0;
-    bs.ld = bs.on[1] ? maxe[1] : 0;
+    const int longest = std::max(bs.on[0] ? maxe[0] : 0, bs.on[1] ? maxe[1] : 0);
+    bs.rows = (longest + 15) / 16 * 16;
     return bs;
 }
 
 // Elements of one band image (the stride between a slice's band images).
-size_t band_elems(const HostPlan &hp) { return (size_t)hp.n * std::max(hp.band_rows, hp.band_ld); }
+size_t band_elems(const HostPlan &hp) { return (size_t)hp.n * hp.band_rows; }
 
 void build_band_lists(HostPlan &hp)
 {
@@ -470,7 +475,7 @@ struct Layout {
     size_t full_g, full_w, maxw_all, mu_all;
     size_t tile_off, tile_list, class_off, class_list, sub_class_off, sub_class_list;
     size_t spart, wpart, cpart;
-    size_t waves, probe_patch, overlap, loss_pos, half, replay, loss_part, energy;
+    size_t waves, probe_patch, overlap, loss_pos, half, replay, slices_t, loss_part, energy;
     size_t wg[2], bmem[2], bdelta[2], btile_off[2], btile_list[2], band;
     size_t total;
 };
@@ -529,12 +534,13 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     L.probe_patch = take((size_t)B * NN * 8);
     L.overlap = take((size_t)B * overlap_slots(hp.M, hp.K) * NN * 4);
     L.loss_pos = take((size_t)B * 8);
-    // line kernels: the half-propagated window per position (and a second one for recomputed
-    // waves), per-line-group partials; recomputation on the fused kernel parks its adjoint
-    // state in the first
+    // line kernels: the two half-propagated windows per position that a chain of launches
+    // alternates between (two more for recomputed waves), the odd slices transposed, per-line-group
+    // partials; recomputation on the fused kernel parks its adjoint state in the first
     const bool lines_possible = hp.n >= 32;
-    L.half = take((lines_possible || hp.K > 1) ? (size_t)B * NN * 8 : 0);
-    L.replay = take((lines_possible && hp.K > 1) ? (size_t)B * NN * 8 : 0);
+    L.half = take(lines_possible ? 2 * (size_t)B * NN * 8 : (hp.K > 1 ? (size_t)B * NN * 8 : 0));
+    L.replay = take((lines_possible && hp.K > 1) ? 2 * (size_t)B * NN * 8 : 0);
+    L.slices_t = take(lines_possible ? (M / 2) * HW * 8 : 0);
     L.loss_part = take(lines_possible ? (size_t)B * (n / 16) * 8 : 0);
     L.energy = take((n / 16) * 8);
     // band sums of the line path: workgroups, members, scatter lists and the band images of the
@@ -548,7 +554,7 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
         L.btile_off[d] = take(on ? nb * kChunks * (hp.n_tiles + 1) * 4 : 0);
         L.btile_list[d] = take(on ? (size_t)bs.entries[d] * 16 : 0);
     }
-    L.band = take(scattered * (size_t)bs.count_max * n * std::max(bs.rows, bs.ld) * 8);
+    L.band = take(scattered * (size_t)bs.count_max * n * bs.rows * 8);
     L.total = o;
     return L;
 }
@@ -663,33 +669,57 @@ void launch_fused_raw(int n, int mode, const FusedParams &fp, int count, hipStre
 }
 
 template <int N>
-void launch_line(bool row, const LineParams &lp, int stage, int count, hipStream_t st)
+void launch_line(bool tr, const LineParams &lp, int stage, int count, hipStream_t st)
 {
     dim3 grid(N / kLinesPerGroup, count), block(kLinesPerGroup * Win<N>::R);
-    if (row) line_kernel<N, true><<<grid, block, 0, st>>>(lp, stage);
+    if (tr) line_kernel<N, true><<<grid, block, 0, st>>>(lp, stage);
     else line_kernel<N, false><<<grid, block, 0, st>>>(lp, stage);
 }
 
-void launch_line_n(int n, bool row, const LineParams &lp, int stage, int count, hipStream_t st)
+// A line launch in frame tr (the transposed frame of odd slices).
+void launch_line_n(int n, bool tr, const LineParams &lp, int stage, int count, hipStream_t st)
 {
     switch (n) {
-        case 32: launch_line<32>(row, lp, stage, count, st); break;
-        case 64: launch_line<64>(row, lp, stage, count, st); break;
-        case 128: launch_line<128>(row, lp, stage, count, st); break;
-        default: launch_line<256>(row, lp, stage, count, st); break;
+        case 32: launch_line<32>(tr, lp, stage, count, st); break;
+        case 64: launch_line<64>(tr, lp, stage, count, st); break;
+        case 128: launch_line<128>(tr, lp, stage, count, st); break;
+        default: launch_line<256>(tr, lp, stage, count, st); break;
     }
 }
 
 template <int N>
-void launch_band(bool row, const LineParams &lp, const BandParams &bp, int workgroups, hipStream_t st)
+void launch_band(bool tr, const LineParams &lp, const BandParams &bp, int workgroups, hipStream_t st)
 {
     const dim3 block(kLinesPerGroup * Win<N>::R);
-    if (row) line_band_kernel<N, true><<<workgroups, block, 0, st>>>(lp, bp);
+    if (tr) line_band_kernel<N, true><<<workgroups, block, 0, st>>>(lp, bp);
     else line_band_kernel<N, false><<<workgroups, block, 0, st>>>(lp, bp);
 }
 
+// The two half-propagation buffers of a chain of line launches: each launch reads the one the
+// previous launch wrote and writes the other.
+struct PingPong {
+    float2 *buf[2];
+    int cur = 0;
+    PingPong(float2 *base, long long elems) : buf{base, base + elems} {}
+    void next(LineParams &lp)
+    {
+        lp.A_in = buf[cur];
+        lp.A_out = buf[cur ^ 1];
+        cur ^= 1;
+    }
+};
+
+// The odd slices transposed (the rows of the line path's odd launches).
+void transpose_odd(ms_plan *p, const float2 *slices, hipStream_t st)
+{
+    const HostPlan &hp = p->hp;
+    if (hp.M < 2) return;
+    const dim3 grid((hp.W + 31) / 32, (hp.H + 31) / 32, hp.M / 2);
+    transpose_odd_kernel<<<grid, 256, 0, st>>>(slices, p->at<float2>(p->L.slices_t), hp.H, hp.W);
+}
+
 // Adjoint launch of slice lp.m for batch b with the gradient patches summed into the band images
-// at out (row launches for even slices).
+// at out (in the frame of slice m).
 void launch_band_n(ms_plan *p, int b, const LineParams &lp, float2 *out, hipStream_t st)
 {
     const HostPlan &hp = p->hp;
@@ -702,13 +732,12 @@ void launch_band_n(ms_plan *p, int b, const LineParams &lp, float2 *out, hipStre
     bp.delta = p->at<int>(p->L.bdelta[o]);
     bp.band = out;
     bp.band_stride = p->band_stride();
-    bp.ld = o == 0 ? hp.n : hp.band_ld;
-    const bool row = o == 0;
+    const bool tr = o == 1;
     switch (hp.n) {
-        case 32: launch_band<32>(row, lp, bp, workgroups, st); break;
-        case 64: launch_band<64>(row, lp, bp, workgroups, st); break;
-        case 128: launch_band<128>(row, lp, bp, workgroups, st); break;
-        default: launch_band<256>(row, lp, bp, workgroups, st); break;
+        case 32: launch_band<32>(tr, lp, bp, workgroups, st); break;
+        case 64: launch_band<64>(tr, lp, bp, workgroups, st); break;
+        case 128: launch_band<128>(tr, lp, bp, workgroups, st); break;
+        default: launch_band<256>(tr, lp, bp, workgroups, st); break;
     }
 }
 
@@ -718,9 +747,9 @@ LineParams line_params(ms_plan *p, const FusedParams &fp, int mode)
     const HostPlan &hp = p->hp;
     LineParams lp{};
     lp.class_probe = fp.class_probe; lp.slices = fp.slices; lp.pos_info = fp.pos_info; lp.pos_list = fp.pos_list;
+    lp.slices_t = p->at<float2>(p->L.slices_t);
     lp.tw = fp.tw; lp.hy = fp.hy; lp.hx = fp.hx; lp.gap_table = fp.gap_table;
     lp.measured = fp.measured; lp.intensity = fp.intensity; lp.exit_waves = fp.exit_waves;
-    lp.A = p->at<float2>(p->L.half);
     lp.probe_patch = fp.probe_patch;
     lp.loss_part = p->at<double>(p->L.loss_part);
     lp.H = hp.H; lp.W = hp.W; lp.M = hp.M;
@@ -740,6 +769,8 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
     const long long NN = (long long)hp.n * hp.n;
     float2 *waves = fp.waves;
     LineParams lp = line_params(p, fp, mode);
+    PingPong A(p->at<float2>(p->L.half), (long long)hp.B * NN);
+    transpose_odd(p, fp.slices, st);
     for (int m = 0; m < M; ++m) {
         lp.m = m;
         lp.psi_out = nullptr;
@@ -747,12 +778,14 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
         if (m > 0 && mode == kAdjoint) { lp.psi_out = waves + m * NN; lp.psi_out_stride = fp.wave_stride; }
         if (m > 0 && mode == kLayer && m == fp.layer) { lp.psi_out = waves; lp.psi_out_stride = fp.wave_stride; }
         if (mode == kLayer && m == fp.layer) { lp.ovl_out = fp.overlap_patch; lp.ovl_stride = fp.ovl_stride; }
-        launch_line_n(hp.n, (m & 1) == 0, lp, kStageForward, count, st);
+        A.next(lp);
+        launch_line_n(hp.n, (m & 1) != 0, lp, kStageForward, count, st);
     }
     lp.psi_out = nullptr;
     lp.ovl_out = nullptr;
     lp.m = M - 1;
-    launch_line_n(hp.n, ((M - 1) & 1) != 0, lp, kStageFar, count, st);
+    A.next(lp);
+    launch_line_n(hp.n, (M & 1) != 0, lp, kStageFar, count, st);
     if (mode == kForward) return;
     const int m_stop = (mode == kLayer) ? fp.layer : 0;
     for (int m = M - 1; m >= m_stop; --m) {
@@ -770,10 +803,11 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
         }
         lp.patch_stride = lp.psi_in_stride = fp.wave_stride;
         lp.go_on = (m > m_stop) || (mode != kLayer);
+        A.next(lp);
         if (mode == kAdjoint && !fp.full && b >= 0 && p->bands_active(m & 1))
             launch_band_n(p, b, lp, p->at<float2>(p->L.band) + m * p->band_slice_stride(), st);
         else
-            launch_line_n(hp.n, (m & 1) == 0, lp, kStageAdjoint, count, st);
+            launch_line_n(hp.n, (m & 1) != 0, lp, kStageAdjoint, count, st);
     }
 }
 
@@ -801,7 +835,7 @@ void launch_fused(ms_plan *p, int mode, const FusedParams &fp, int count, hipStr
 }
 
 void scatter(ms_plan *p, int b, int count, const float2 *patches, long long pos_stride, const float *wpatch,
-             long long w_stride, int n_m, float2 *out, float *wout, int accumulate, hipStream_t st);
+             long long w_stride, int m0, int n_m, float2 *out, float *wout, int accumulate, hipStream_t st);
 void scatter_slices(ms_plan *p, int b, int count, const float2 *patches, long long pos_stride, int m0, int n_m,
                     float2 *out, int accumulate, hipStream_t st);
 
@@ -828,14 +862,15 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
                 TimedRegion t(p, st);
                 launch_fused_raw(hp.n, kReplay, fp, count, st);
             }
-            scatter(p, b, count, work, fp.wave_stride, ovl, fp.ovl_stride, 1, g + seg * hw, w ? w + seg * hw : nullptr,
-                    accumulate, st);
+            scatter(p, b, count, work, fp.wave_stride, ovl, fp.ovl_stride, seg, 1, g + seg * hw,
+                    w ? w + seg * hw : nullptr, accumulate, st);
         }
         return;
     }
     LineParams lp = line_params(p, fp, kAdjoint);
-    float2 *R = p->at<float2>(p->L.replay);
-
+    const long long pair = (long long)hp.B * NN;
+    PingPong A(p->at<float2>(p->L.half), pair);
+    transpose_odd(p, fp.slices, st);
     {
         TimedRegion t(p, st);
         for (int m = 0; m < M; ++m) {
@@ -844,11 +879,13 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
             if (m > 0 && m % K == 0) lp.psi_out = ck_slot(m);
             else if (m == M - 1) lp.psi_out = work;
             lp.psi_out_stride = fp.wave_stride;
-            launch_line_n(hp.n, (m & 1) == 0, lp, kStageForward, count, st);
+            A.next(lp);
+            launch_line_n(hp.n, (m & 1) != 0, lp, kStageForward, count, st);
         }
         lp.psi_out = nullptr;
         lp.m = M - 1;
-        launch_line_n(hp.n, ((M - 1) & 1) != 0, lp, kStageFar, count, st);
+        A.next(lp);
+        launch_line_n(hp.n, (M & 1) != 0, lp, kStageFar, count, st);
     }
     lp.patch_out = work;
     lp.patch_stride = lp.psi_in_stride = fp.wave_stride;
@@ -858,10 +895,11 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
         TimedRegion t(p, st);
         if (m < M - 1 && m % K != 0) {
             // psi_m again: from the stored wave psi_c (or the probe), the forward launches c .. m
-            // in the second half-propagation buffer, the last one ending at psi_m in the work slot
+            // in the second pair of half-propagation buffers, the last one ending at psi_m in the
+            // work slot
             const int c = m - m % K;
             LineParams rp = lp;
-            rp.A = R;
+            PingPong Rb(p->at<float2>(p->L.replay), pair);
             rp.patch_out = nullptr;
             rp.psi_in = nullptr;
             rp.ovl_out = nullptr;
@@ -874,18 +912,20 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
                 rp.psi_out = (mm == m) ? work : nullptr;
                 rp.psi_out_stride = fp.wave_stride;
                 rp.stop_after_psi = (mm == m) ? 1 : 0;
-                launch_line_n(hp.n, (mm & 1) == 0, rp, kStageForward, count, st);
+                Rb.next(rp);
+                launch_line_n(hp.n, (mm & 1) != 0, rp, kStageForward, count, st);
             }
         }
         lp.m = m;
         lp.psi_in = (m == 0) ? nullptr : (m % K == 0 ? ck_slot(m) : work);
+        A.next(lp);
         if (!w && p->bands_active(m & 1)) {
             launch_band_n(p, b, lp, p->at<float2>(p->L.band), st);
             scatter_slices(p, b, count, work, fp.wave_stride, m, 1, g + m * hw, accumulate, st);
             continue;
         }
-        launch_line_n(hp.n, (m & 1) == 0, lp, kStageAdjoint, count, st);
-        scatter(p, b, count, work, fp.wave_stride, ovl, fp.ovl_stride, 1, g + m * hw, w ? w + m * hw : nullptr,
+        launch_line_n(hp.n, (m & 1) != 0, lp, kStageAdjoint, count, st);
+        scatter(p, b, count, work, fp.wave_stride, ovl, fp.ovl_stride, m, 1, g + m * hw, w ? w + m * hw : nullptr,
                 accumulate, st);
     }
 }
@@ -1031,9 +1071,6 @@ double step_norm(const ms_plan *p)
 
 int grid_for(long long count) { return (int)std::max<long long>(1, std::min<long long>(8192, (count + 255) / 256)); }
 
-// Gradient patches of batch b for n_m consecutive slices into out (n_m x H x W), and the
-// overlap patches into wout if given; accumulate adds to what out already holds.  patches:
-// slice i of position a at patches + a * pos_stride + i * N^2 (wpatch likewise with w_stride).
 // Pass 1 over nch chunks of images and pass 2 (chunk partials in order) for n_m slices.
 void scatter_launch(ms_plan *p, ScatterParams &sp, int nch, int n_m, float2 *out, float *wout, int accumulate,
                     hipStream_t st)
@@ -1060,11 +1097,16 @@ void scatter_launch(ms_plan *p, ScatterParams &sp, int nch, int n_m, float2 *out
     }
 }
 
+// Gradient patches of batch b for slices m0 .. m0 + n_m - 1 into out (n_m x H x W), and the
+// overlap patches into wout if given; accumulate adds to what out already holds.  patches:
+// slice i of position a at patches + a * pos_stride + i * N^2 (wpatch likewise with w_stride).
 void scatter(ms_plan *p, int b, int count, const float2 *patches, long long pos_stride, const float *wpatch,
-             long long w_stride, int n_m, float2 *out, float *wout, int accumulate, hipStream_t st)
+             long long w_stride, int m0, int n_m, float2 *out, float *wout, int accumulate, hipStream_t st)
 {
     const HostPlan &hp = p->hp;
     ScatterParams sp{};
+    sp.m0 = m0;
+    sp.trans1 = p->lines ? 1 : 0;    // the line path stores odd slices' patches transposed
     sp.patches0 = sp.patches1 = patches;
     sp.wpatch = wpatch;
     sp.pos_stride0 = sp.pos_stride1 = pos_stride;
@@ -1093,23 +1135,24 @@ void scatter_slices(ms_plan *p, int b, int count, const float2 *patches, long lo
         long long ps = pos_stride, ss = (long long)hp.n * hp.n;
         const int *off = p->at<int>(p->L.tile_off) + toff;
         const int4 *ent = p->at<int4>(p->L.tile_list);
-        int ld = hp.n, vert = 0;
+        // the line path stores odd slices' images transposed
+        const int trans = (p->lines && o == 1) ? 1 : 0;
+        int vert = 0;
         if (p->bands_active(o)) {
             img = p->at<float2>(p->L.band);
             ps = p->band_stride();
             ss = p->band_slice_stride();
             off = p->at<int>(p->L.btile_off[o]) + toff;
             ent = p->at<int4>(p->L.btile_list[o]);
-            ld = o == 0 ? hp.n : hp.band_ld;   // row launches: N + spread rows of N; columns: N rows
-            vert = o == 0 ? 1 : 0;
+            vert = o == 0 ? 1 : 0;    // the spread runs along y (even slices) or x (odd slices)
             nch = std::max(nch, hp.band_nch[b]);
         }
         if (o == 0) {
             sp.patches0 = img; sp.pos_stride0 = ps; sp.slice_stride0 = ss;
-            sp.tile_off0 = off; sp.entries0 = ent; sp.ld0 = ld; sp.vert0 = vert;
+            sp.tile_off0 = off; sp.entries0 = ent; sp.ld0 = hp.n; sp.vert0 = vert; sp.trans0 = trans;
         } else {
             sp.patches1 = img; sp.pos_stride1 = ps; sp.slice_stride1 = ss;
-            sp.tile_off1 = off; sp.entries1 = ent; sp.ld1 = ld; sp.vert1 = vert;
+            sp.tile_off1 = off; sp.entries1 = ent; sp.ld1 = hp.n; sp.vert1 = vert; sp.trans1 = trans;
         }
     }
     sp.m0 = m0;
@@ -1233,7 +1276,6 @@ ms_status build_plan(ms_plan *p, const ms_problem *pb, char *ws, size_t ws_bytes
         hp.bands[0] = bs.on[0];
         hp.bands[1] = bs.on[1];
         hp.band_rows = bs.rows;
-        hp.band_ld = bs.ld;
         hp.band_count = bs.count_max;
         if (bs.on[0] || bs.on[1]) build_band_lists(hp);
     }
@@ -1695,7 +1737,7 @@ ms_status ms_layer_step(ms_plan *p, hipStream_t st, int32_t layer, int32_t k_ste
             int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
             fp.pos_list = p->at<int>(p->L.pos_list) + s0;
             launch_fused(p, kLayer, fp, count, st);
-            scatter(p, b, count, fp.waves, fp.wave_stride, fp.overlap_patch, fp.ovl_stride, 1, g, w, b > 0, st);
+            scatter(p, b, count, fp.waves, fp.wave_stride, fp.overlap_patch, fp.ovl_stride, layer, 1, g, w, b > 0, st);
             {
                 int n_loss;
                 const double *lsrc = loss_entries(p, count, &n_loss);
@@ -1750,7 +1792,7 @@ ms_status ms_full_step(ms_plan *p, hipStream_t st, int32_t k_steps, double step_
                 adjoint_recompute(p, fp, b, count, st, g, w, b > 0);
             } else {
                 launch_fused(p, kAdjoint, fp, count, st);
-                scatter(p, b, count, fp.waves, fp.wave_stride, fp.overlap_patch, fp.ovl_stride, M, g, w, b > 0, st);
+                scatter(p, b, count, fp.waves, fp.wave_stride, fp.overlap_patch, fp.ovl_stride, 0, M, g, w, b > 0, st);
             }
             int n_loss;
             const double *lsrc = loss_entries(p, count, &n_loss);

@@ -1,6 +1,6 @@
-"""GPU parity of the band sums of the line path's adjoint: row launches take 16 object rows for
-the windows of one scan column, column launches 16 object columns for the windows of one scan row
-whose origins x agree modulo 16, and the scatter reads band images.  Checked against the FP64
+"""GPU parity of the band sums of the line path's adjoint: even slices' launches take 16 object rows
+for the windows of one scan column, odd slices' launches 16 object columns for the windows of one
+scan row, and the scatter reads band images.  Checked against the FP64
 oracle, against the per-position patches of the same plan, on a scan that wraps through the object
 edges (bands cut where their image would wrap onto itself), with recomputed waves, with batches,
 and at N = 256."""
@@ -27,11 +27,11 @@ def dev():
 
 
 def _geometry(name):
-    if name == "raster64":      # 8 x 8 raster, step 8: origins x in two classes modulo 16
+    if name == "raster64":      # 8 x 8 raster, step 8
         return configs.small(n=64, obj=128, n_slices=4, scan=(8, 8), step_px=8.0, seed=5, defocus=25.0)
     if name == "wrap64":        # 12 x 12 raster shifted so that windows wrap through both edges
         return configs.small(n=64, obj=128, n_slices=3, scan=(12, 12), step_px=8.0, seed=6, defocus=25.0)
-    if name == "raster256":     # N = 256, step 16: one class modulo 16
+    if name == "raster256":     # N = 256, step 16
         return configs.small(n=256, obj=384, n_slices=3, scan=(5, 5), step_px=16.0, seed=7, defocus=25.0)
     raise KeyError(name)
 
@@ -75,7 +75,7 @@ def test_bands_match_oracle_and_patches(dev, name):
     from paper_2205_03902_amd import abi
     c = case_for(name)
     plan = _plan(c, dev)
-    assert plan.has_bands == 3, f"{name}: bands expected on both launch kinds, got {plan.has_bands}"
+    assert plan.has_bands == 3, f"{name}: bands expected for even and odd slices, got {plan.has_bands}"
     l_all, g_all, p_all = _adjoint(plan, c, dev, abi.MS_BANDS_ALL)
     l_all2, g_all2, p_all2 = _adjoint(plan, c, dev, abi.MS_BANDS_ALL)
     l_row, g_row, p_row = _adjoint(plan, c, dev, abi.MS_BANDS_ROWS)
@@ -90,7 +90,7 @@ def test_bands_match_oracle_and_patches(dev, name):
     assert l_all == l_none == l_row and np.array_equal(p_all, p_none) and np.array_equal(p_row, p_none)
     assert e_none < TOL_REGROUP and e_row < TOL_REGROUP
     assert e_or < TOL_GRAD and rel(p_all, ref_gp) < TOL_GRAD and abs(l_all - ref_l) / ref_l < TOL_FWD
-    # slice by slice: both parities (row and column launches) agree with the patches
+    # slice by slice: both parities (natural and transposed frames) agree with the patches
     for m in range(c.geo.n_slices):
         assert rel(g_all[m], g_none[m]) < TOL_REGROUP, f"slice {m}"
 
