@@ -68,6 +68,8 @@ struct LineParams {
     float2 *patch_out;           //   dL/d conj(t_m) on the window, conj(psi_m) o g (may alias psi_in)
     long long patch_stride;
     int go_on;                   //   after the patch: conj(t_m), then G_{m-1}^H into A, or the probe patch
+    // Layout of A (see Apitch): with offsets, lines in groups aligned in object coordinates
+    int obj_in, obj_out;         //   A_in / A_out with the per-position offsets
 };
 
 // Global-memory window access for a line group in either layout: lane (line, j) owns
@@ -181,52 +183,6 @@ __device__ __forceinline__ void tile_put(const float2 (&v)[16], float2 *tile, in
     for (int i = 0; i < 16; ++i) col[tile_idx<N, SPEC>(j, i, sw)] = v[i];
 }
 
-// Where this lane's line is: (line) for row launches; for column launches also the
-// workgroup's first column c0 and the lane's column within the tile, lloc.
-struct LinePos {
-    int line, lloc, j, c0;
-};
-
-template <int N, bool ROW, bool SPEC>
-__device__ __forceinline__ void line_load(float2 (&v)[16], const float2 *src, const LinePos &q, float2 *tile)
-{
-    if (ROW) {
-        gload<N, true, SPEC>(v, src, q.line, q.j);
-    } else {
-        tile_fill<N>(tile, [&](int r, int c) { return src[r * N + q.c0 + c]; });
-        tile_get<N, SPEC>(v, tile, q.lloc, q.j);
-    }
-}
-
-template <int N, bool ROW, bool SPEC>
-__device__ __forceinline__ void line_store(const float2 (&v)[16], float2 *dst, const LinePos &q, float2 *tile)
-{
-    if (ROW) {
-        gstore<N, true, SPEC>(v, dst, q.line, q.j);
-    } else {
-        tile_put<N, SPEC>(v, tile, q.lloc, q.j);
-        tile_drain<N>(tile, [&](int r, int c, float2 x) { dst[r * N + q.c0 + c] = x; });
-    }
-}
-
-// |v|^2 into a float image (SPEC: at spectral positions).
-template <int N, bool ROW, bool SPEC>
-__device__ __forceinline__ void line_store_abs2(const float2 (&v)[16], float *dst, const LinePos &q, float2 *tile)
-{
-    using Wn = Win<N>;
-    if (ROW) {
-        const int l2 = opaque(q.line), j2 = opaque(q.j);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) dst[l2 * N + (SPEC ? Wn::spec(j2, i) : Wn::nat(j2, i))] = cabs2(v[i]);
-    } else {
-        float2 a[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) a[i] = make_float2(cabs2(v[i]), 0.0f);
-        tile_put<N, SPEC>(a, tile, q.lloc, q.j);
-        tile_drain<N>(tile, [&](int r, int c, float2 x) { dst[r * N + q.c0 + c] = x.x; });
-    }
-}
-
 // Residual at spectral positions against measured intensities (as residual<>, with the
 // measured values already in registers); returns this lane's FP64 loss share.
 template <int N>
@@ -250,20 +206,6 @@ __device__ __forceinline__ double residual_vals(float2 (&v)[16], const float (&m
         }
     }
     return acc;
-}
-
-template <int N, bool ROW>
-__device__ __forceinline__ double line_residual(float2 (&v)[16], const float *meas, const LinePos &q, float2 *tile,
-                                                int poisson)
-{
-    if (ROW) return residual<N, true>(v, meas, q.line, q.j, poisson);
-    tile_fill<N>(tile, [&](int r, int c) { return make_float2(meas[r * N + q.c0 + c], 0.0f); });
-    float2 t[16];
-    tile_get<N, true>(t, tile, q.lloc, q.j);
-    float mv[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) mv[i] = t[i].x;
-    return residual_vals<N>(v, mv, poisson);
 }
 
 // 1D propagation along the owned axis with the factor table h (LDS), or its adjoint.
@@ -305,12 +247,59 @@ __device__ __forceinline__ void frame_patch(float2 (&v)[16], const LineParams &p
     else apply_patch<N, true, CONJ>(v, p.slices + (size_t)p.m * hw, p.H, p.W, oy, ox, line, j);
 }
 
-// A window in the natural layout from a launch of either frame (SPEC: at spectral positions).
-template <int N, bool TR, bool SPEC>
-__device__ __forceinline__ void natural_store(const float2 (&v)[16], float2 *dst, const LinePos &q, float2 *tile)
+// ---- the half-propagated windows A ----
+//
+// A window written for a launch of frame F holds its line l (N lines) in a row of N + 16 elements,
+// element a at column a + s.  Two layouts: s = 0 with each launch's 16 lines a group aligned in
+// the window (the forward chain: every read and write aligned), or s = the position's origin
+// along F's elements (x for frame 0, y for frame 1) modulo 16 with each launch's 16 lines a group
+// aligned in object coordinates (its first line l0 has l0 + its line-axis origin = 0 modulo 16;
+// a window then takes N / 16 + 1 groups, the outer two partly outside it).  The second is what
+// band workgroups need (their members' lines are aligned in object coordinates, not in each
+// window), and its transposed stores still write whole aligned 128-byte pieces; its reads start
+// at s.  Launches always have N / 16 + 1 groups; with s = 0 the last one exits at once.
+template <int N>
+struct Apitch {
+    static constexpr int P = N + 16;
+};
+
+// Line `line` of A in this launch's frame, natural (SPEC: spectral) register order.
+template <int N, bool SPEC>
+__device__ __forceinline__ void aload(float2 (&v)[16], const float2 *src, int line, int j, int s)
 {
-    if constexpr (TR) line_store<N, false, SPEC>(v, dst, q, tile);
-    else line_store<N, true, SPEC>(v, dst, q, tile);
+    using Wn = Win<N>;
+    line = opaque(line);
+    j = opaque(j);
+    const float2 *row = src + line * Apitch<N>::P + s;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = row[SPEC ? Wn::spec(j, i) : Wn::nat(j, i)];
+}
+
+// The workgroup's lines l0 .. l0 + 15 into the other frame through the LDS tile: element a of line
+// l0 + c to dst[a * pitch + l0 + c + s]; lines outside the window skipped.  Collective.
+template <int N, bool SPEC>
+__device__ __forceinline__ void store_other(const float2 (&v)[16], float2 *dst, int pitch, int l0, int s, int lloc,
+                                            int j, float2 *tile)
+{
+    tile_put<N, SPEC>(v, tile, lloc, j);
+    tile_drain<N>(tile, [&](int r, int c, float2 x) {
+        if ((unsigned)(l0 + c) < (unsigned)N) dst[(size_t)r * pitch + l0 + c + s] = x;
+    });
+}
+
+// |v|^2 of the workgroup's lines into a natural-layout float image from a transposed launch
+// (SPEC: at spectral positions).  Collective.
+template <int N, bool SPEC>
+__device__ __forceinline__ void store_other_abs2(const float2 (&v)[16], float *dst, int l0, int lloc, int j,
+                                                 float2 *tile)
+{
+    float2 a[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = make_float2(cabs2(v[i]), 0.0f);
+    tile_put<N, SPEC>(a, tile, lloc, j);
+    tile_drain<N>(tile, [&](int r, int c, float2 x) {
+        if ((unsigned)(l0 + c) < (unsigned)N) dst[(size_t)r * N + l0 + c] = x.x;
+    });
 }
 
 template <int N, bool TR>
@@ -321,6 +310,7 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
     constexpr int R = Wn::R;
     constexpr int NT = kLinesPerGroup * R;
     constexpr size_t NN = (size_t)N * N;
+    constexpr size_t NA = (size_t)N * Apitch<N>::P;
     __shared__ float2 xbuf[kLinesPerGroup * Wn::LD];
     __shared__ float2 s_tw[Wn::TW_WORDS];
     __shared__ float2 s_h[N];
@@ -328,15 +318,26 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
 
     const int tid = threadIdx.x;
     const int lloc = tid / R, j = tid % R;
-    const int line = blockIdx.x * kLinesPerGroup + lloc;
     const int b = blockIdx.y;
     const int s = p.pos_list[b];
     const int4 info = p.pos_info[s];
     const int oy = info.x, ox = info.y, cls = info.z;
+    // offsets of A_in (the element-axis origin modulo 16) and A_out (the line-axis origin); this
+    // group's first line
+    const int s_line = p.obj_out ? (TR ? ox : oy) & 15 : 0, s_elem = p.obj_in ? (TR ? oy : ox) & 15 : 0;
+    const int l0 = (int)blockIdx.x * kLinesPerGroup - s_line;
+    if (l0 >= N) {                             // the extra group of an aligned window
+        if (stage == kStageFar && p.mode != kForward && tid == 0)
+            p.loss_part[(size_t)b * gridDim.x + blockIdx.x] = 0.0;
+        return;
+    }
+    const int line_raw = l0 + lloc;
+    const bool valid = (unsigned)line_raw < (unsigned)N;
+    const int line = valid ? line_raw : 0;
     const int M = p.M, m = p.m;
     float2 *xb = xbuf + lloc * Wn::LD;
-    const float2 *A_in = p.A_in + (size_t)b * NN;
-    float2 *A_out = p.A_out + (size_t)b * NN;
+    const float2 *A_in = p.A_in + (size_t)b * NA;
+    float2 *A_out = p.A_out + (size_t)b * NA;
     const float2 *probe = p.class_probe + (size_t)cls * NN;
     const float2 *hown = TR ? p.hy : p.hx;
 
@@ -368,64 +369,92 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
     else if (g_start >= 0) load_h(g_start);
     __syncthreads();
 
-    const LinePos q{line, lloc, j, (int)blockIdx.x * kLinesPerGroup};
     float2 v[16];
     if (stage == kStageForward) {
         // ---- psi_m: the probe (m = 0, natural frame), a stored wave, or the propagation of gap
         // m-1 finished along this launch's lines ----
         if (m == 0) {
-            line_load<N, true, false>(v, probe, q, xbuf);
+            gload<N, true, false>(v, probe, line, j);
         } else if (restart) {
-            line_load<N, true, false>(v, p.restart + (size_t)b * p.restart_stride, q, xbuf);
+            gload<N, true, false>(v, p.restart + (size_t)b * p.restart_stride, line, j);
         } else {
-            line_load<N, true, false>(v, A_in, q, xbuf);
+            aload<N, false>(v, A_in, line, j, s_elem);
             prop_axis<N, false>(v, s_tw, xb, s_h, j);
         }
-        if (p.psi_out) line_store<N, true, false>(v, p.psi_out + (size_t)b * p.psi_out_stride, q, xbuf);
-        if (p.ovl_out) line_store_abs2<N, true, false>(v, p.ovl_out + (size_t)b * p.ovl_stride, q, xbuf);
+        if (valid && p.psi_out) gstore<N, true, false>(v, p.psi_out + (size_t)b * p.psi_out_stride, line, j);
+        if (valid && p.ovl_out) {
+            float *o = p.ovl_out + (size_t)b * p.ovl_stride;
+            const int l2 = opaque(line), j2 = opaque(j);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) o[l2 * N + Wn::nat(j2, i)] = cabs2(v[i]);
+        }
         if (p.stop_after_psi) return;
         frame_patch<N, TR, false>(v, p, oy, ox, line, j);
         if (m + 1 < M) {
             next_h();
             prop_axis<N, false>(v, s_tw, xb, s_h, j);
-            line_store<N, false, false>(v, A_out, q, xbuf);    // the next launch's frame
+            store_other<N, false>(v, A_out, Apitch<N>::P, l0, s_line, lloc, j, xbuf);
         } else {
-            if (p.mode == kForward && p.exit_waves)
-                natural_store<N, TR, false>(v, p.exit_waves + (size_t)s * NN, q, xbuf);
+            if (p.mode == kForward && p.exit_waves) {
+                float2 *ew = p.exit_waves + (size_t)s * NN;
+                if constexpr (TR) store_other<N, false>(v, ew, N, l0, 0, lloc, j, xbuf);
+                else if (valid) gstore<N, true, false>(v, ew, line, j);
+            }
             line_fft_fwd<N>(v, s_tw, xb, j);
-            line_store<N, false, true>(v, A_out, q, xbuf);     // spectral along these lines, at natural frequency
+            store_other<N, true>(v, A_out, Apitch<N>::P, l0, s_line, lloc, j, xbuf);   // spectral, natural frequency
         }
         return;
     }
 
     if (stage == kStageFar) {
         // line index = frequency along the other axis (natural); FFT along these lines
-        line_load<N, true, false>(v, A_in, q, xbuf);
+        aload<N, false>(v, A_in, line, j, s_elem);
         line_fft_fwd<N>(v, s_tw, xb, j);
+        const float *meas = p.measured + (size_t)s * NN;
         if (p.mode == kForward) {
             float *I = p.intensity + (size_t)s * NN;
-            if constexpr (TR) line_store_abs2<N, false, true>(v, I, q, xbuf);
-            else line_store_abs2<N, true, true>(v, I, q, xbuf);
+            if constexpr (TR) {
+                store_other_abs2<N, true>(v, I, l0, lloc, j, xbuf);
+            } else if (valid) {
+                const int l2 = opaque(line), j2 = opaque(j);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) I[l2 * N + Wn::spec(j2, i)] = cabs2(v[i]);
+            }
             return;
         }
-        const double part = line_residual<N, !TR>(v, p.measured + (size_t)s * NN, q, xbuf, p.objective);
-        double tot = group_sum<N>(part, red);
+        double part;
+        if constexpr (TR) {
+            // the measured column of this line through the tile (lines outside read a clamped one)
+            tile_fill<N>(xbuf, [&](int r, int c) {
+                const int cc = min(max(l0 + c, 0), N - 1);
+                return make_float2(meas[r * N + cc], 0.0f);
+            });
+            float2 t[16];
+            tile_get<N, true>(t, xbuf, lloc, j);
+            float mv[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) mv[i] = t[i].x;
+            part = residual_vals<N>(v, mv, p.objective);
+        } else {
+            part = residual<N, true>(v, meas, line, j, p.objective);
+        }
+        double tot = group_sum<N>(valid ? part : 0.0, red);
         if (tid == 0) p.loss_part[(size_t)b * gridDim.x + blockIdx.x] = tot;
         line_fft_inv<N>(v, s_tw, xb, j);
-        line_store<N, false, false>(v, A_out, q, xbuf);
+        store_other<N, false>(v, A_out, Apitch<N>::P, l0, s_line, lloc, j, xbuf);
         return;
     }
 
     // ---- adjoint launch for slice m ----
     if (m + 1 == M) {
         // finish F^H r along these lines: A holds it at natural frequency positions
-        line_load<N, true, true>(v, A_in, q, xbuf);
+        aload<N, true>(v, A_in, line, j, s_elem);
         line_fft_inv<N>(v, s_tw, xb, j);
     } else {
-        line_load<N, true, false>(v, A_in, q, xbuf);
+        aload<N, false>(v, A_in, line, j, s_elem);
         prop_axis<N, true>(v, s_tw, xb, s_h, j);
     }
-    if (p.patch_out) {
+    if (p.patch_out && valid) {
         const float2 *psi = p.psi_in ? p.psi_in + (size_t)b * p.psi_in_stride : probe;
         float2 *dst = p.patch_out + (size_t)b * p.patch_stride;
         float *ovl = p.ovl_out ? p.ovl_out + (size_t)b * p.ovl_stride : nullptr;
@@ -450,9 +479,9 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
     if (m > 0) {
         next_h();
         prop_axis<N, true>(v, s_tw, xb, s_h, j);
-        line_store<N, false, false>(v, A_out, q, xbuf);
-    } else if (p.probe_patch) {
-        line_store<N, true, false>(v, p.probe_patch + (size_t)b * NN, q, xbuf);
+        store_other<N, false>(v, A_out, Apitch<N>::P, l0, s_line, lloc, j, xbuf);
+    } else if (p.probe_patch && valid) {
+        gstore<N, true, false>(v, p.probe_patch + (size_t)b * NN, line, j);
     }
 }
 
@@ -488,40 +517,51 @@ __global__ __launch_bounds__(256) void transpose_odd_kernel(const float2 *slices
 // bands.
 //
 // Workgroup w takes band lines u0 .. u0 + 15 of band `band`, u counted from the band's first
-// origin across the lines; member i (origin delta_i further on) holds them as window lines
-// u0 + l - delta_i.  Lines outside the window are computed on a clamped index and neither stored
-// nor summed.
+// origin across the lines and u0 + that origin = 0 modulo 16 (so u0 may be negative); member i
+// (origin delta_i further on) holds them as window lines u0 + l - delta_i, an aligned group as in
+// line_kernel.  Lines outside the window are computed on a clamped index and neither stored nor
+// summed.
 struct BandParams {
     const int4 *wg;              // per workgroup: (band, first member, end member, u0)
     const int *mem;              // batch-local position of each member
     const int *delta;            // each member's origin minus the band's first, across the lines
-    float2 *band;                // [bands] x band_stride, (N + spread) x N each, in the launch's frame
+    float2 *band;                // [bands] x band_stride: rows x N each, in the launch's frame
     long long band_stride;
+    int rows;                    // band image rows
 };
 
 // Adjoint launch of slice m over band workgroups (1D grid); otherwise the adjoint stage of
-// line_kernel for each member in turn, with both propagation tables kept in LDS.
+// line_kernel for each member in turn (both A layouts with offsets).  One propagation table in
+// LDS, reloaded between the two propagations of a member, so that a CU holds four workgroups.
 template <int N, bool TR>
-__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 3) void line_band_kernel(LineParams p, BandParams bp)
+__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_band_kernel(LineParams p, BandParams bp)
 {
     using Wn = Win<N>;
     constexpr int R = Wn::R;
     constexpr int NT = kLinesPerGroup * R;
     constexpr size_t NN = (size_t)N * N;
+    constexpr size_t NA = (size_t)N * Apitch<N>::P;
     __shared__ float2 xbuf[kLinesPerGroup * Wn::LD];
     __shared__ float2 s_tw[Wn::TW_WORDS];
-    __shared__ float2 s_hf[N], s_hs[N];
+    __shared__ float2 s_h[N];
 
     const int tid = threadIdx.x;
     const int M = p.M, m = p.m;
     const float2 *hown = TR ? p.hy : p.hx;
     const int g_fin = (m + 1 < M) ? m : -1;
     const int g_start = (m > 0 && p.go_on) ? m - 1 : -1;
+    // the table of gap g into LDS unless it is there, between barriers (every lane is done with
+    // the previous one); slices of one distance share a table
+    int loaded = -1;
+    auto load_h = [&](int g) {
+        const int u = p.gap_table[g];
+        if (u == loaded) return;
+        __syncthreads();
+        for (int i = tid; i < N; i += NT) s_h[i] = hown[u * N + i];
+        __syncthreads();
+        loaded = u;
+    };
     for (int i = tid; i < Wn::TW_WORDS; i += NT) s_tw[i] = p.tw[i];
-    if (g_fin >= 0)
-        for (int i = tid; i < N; i += NT) s_hf[i] = hown[p.gap_table[g_fin] * N + i];
-    if (g_start >= 0)
-        for (int i = tid; i < N; i += NT) s_hs[i] = hown[p.gap_table[g_start] * N + i];
     __syncthreads();
 
     const int4 w = bp.wg[blockIdx.x];
@@ -536,46 +576,46 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 3) void line_band_kerne
         float2 *xb = xbuf + lloc * Wn::LD;
         const int b = bp.mem[i];
         const int4 info = p.pos_info[p.pos_list[b]];
+        const int s_line = (TR ? info.y : info.x) & 15, s_elem = (TR ? info.x : info.y) & 15;
         const int l0 = w.w - bp.delta[i];            // window line of lloc = 0
         const int wl = l0 + lloc;
         const bool valid = (unsigned)wl < (unsigned)N;
-        const LinePos q{valid ? wl : 0, lloc, j, l0};
-        const float2 *A_in = p.A_in + (size_t)b * NN;
+        const int line = valid ? wl : 0;
+        const float2 *A_in = p.A_in + (size_t)b * NA;
         float2 v[16];
         if (m + 1 == M) {
-            line_load<N, true, true>(v, A_in, q, xbuf);
+            aload<N, true>(v, A_in, line, j, s_elem);
             line_fft_inv<N>(v, s_tw, xb, j);
         } else {
-            line_load<N, true, false>(v, A_in, q, xbuf);
-            prop_axis<N, true>(v, s_tw, xb, s_hf, j);
+            aload<N, false>(v, A_in, line, j, s_elem);
+            load_h(g_fin);
+            prop_axis<N, true>(v, s_tw, xb, s_h, j);
         }
         if (valid) {
             // acc += conj(psi_m) o g
             const float2 *psi = p.psi_in ? p.psi_in + (size_t)b * p.psi_in_stride
                                          : p.class_probe + (size_t)info.z * NN;
-            const int l2 = opaque(q.line), j2 = opaque(j);
+            const int l2 = opaque(line), j2 = opaque(j);
 #pragma unroll
             for (int k = 0; k < 16; ++k) acc[k] = cadd(acc[k], cconjmul(psi[l2 * N + Wn::nat(j2, k)], v[k]));
         }
         if (!p.go_on) continue;
-        frame_patch<N, TR, true>(v, p, info.x, info.y, q.line, j);
+        frame_patch<N, TR, true>(v, p, info.x, info.y, line, j);
         if (m > 0) {
-            prop_axis<N, true>(v, s_tw, xb, s_hs, j);
-            // into the other frame: window line l0 + c of row r, lines outside the window skipped
-            float2 *A_out = p.A_out + (size_t)b * NN;
-            tile_put<N, false>(v, xbuf, lloc, j);
-            tile_drain<N>(xbuf, [&](int r, int c, float2 x) {
-                if ((unsigned)(l0 + c) < (unsigned)N) A_out[r * N + l0 + c] = x;
-            });
+            load_h(g_start);
+            prop_axis<N, true>(v, s_tw, xb, s_h, j);
+            store_other<N, false>(v, p.A_out + (size_t)b * NA, Apitch<N>::P, l0, s_line, lloc, j, xbuf);
         } else if (p.probe_patch && valid) {
-            gstore<N, true, false>(v, p.probe_patch + (size_t)b * NN, q.line, j);
+            gstore<N, true, false>(v, p.probe_patch + (size_t)b * NN, line, j);
         }
     }
     float2 *band = bp.band + (size_t)w.x * bp.band_stride;
     const int lloc = tid / R, j = tid % R;
     const int row = w.w + lloc;
+    if ((unsigned)row < (unsigned)bp.rows) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) band[(size_t)row * N + Wn::nat(j, k)] = acc[k];
+        for (int k = 0; k < 16; ++k) band[(size_t)row * N + Wn::nat(j, k)] = acc[k];
+    }
 }
 
 }  // namespace imsp

@@ -34,14 +34,13 @@ constexpr long long kScatterBlocks = 32768;   // target grid of the scatter pass
 // Distinct sub-pixel probe shifts per plan.  A raster has a few; refined positions have one per
 // position.  The class tables and partial sums take about (kChunks + 5) C N^2 8 bytes.
 constexpr int kMaxClasses = 4096;
-// Band members share their origin modulo kBandAlign across the lines, so that each member's window
-// lines in a band workgroup start at a multiple of 16: its transposed store of 16 lines then
-// writes whole aligned 128-byte pieces (measured on the 16384-position workload: 124 ms of line
-// kernels a pass with 16, 132 with 8, 153 with 4, 161 with 1).
-constexpr int kBandAlign = 16;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Workgroups of a line launch per window: N / 16 groups of 16 lines aligned in object coordinates
+// take N / 16 + 1 (line_kernels.hpp).
+int line_groups(int n) { return n / 16 + 1; }
 
 bool supported_n(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
 
@@ -276,7 +275,7 @@ void make_bands(const HostPlan &hp, int64_t s0, int64_t count, int o, std::vecto
     for (int64_t a = 0; a < count; ++a) idx[(size_t)a] = (int)a;
     auto key = [&](int a) {
         const int4 &q = hp.pos_info[s0 + a];
-        return o == 0 ? std::make_tuple(q.y, q.x % kBandAlign, q.x) : std::make_tuple(q.x, q.y % kBandAlign, q.y);
+        return o == 0 ? std::make_tuple(q.y, q.x) : std::make_tuple(q.x, q.y);
     };
     std::sort(idx.begin(), idx.end(), [&](int a, int b) {
         const auto ka = key(a), kb = key(b);
@@ -286,13 +285,13 @@ void make_bands(const HostPlan &hp, int64_t s0, int64_t count, int o, std::vecto
     for (size_t i = 0; i < idx.size();) {
         Band bd;
         const auto k0 = key(idx[i]);
-        const int first = std::get<2>(k0);
+        const int first = std::get<1>(k0);
         int prev = first;
         size_t e = i;
         while (e < idx.size()) {
             const auto k = key(idx[e]);
-            if (std::get<0>(k) != std::get<0>(k0) || std::get<1>(k) != std::get<1>(k0)) break;
-            const int along = std::get<2>(k);
+            if (std::get<0>(k) != std::get<0>(k0)) break;
+            const int along = std::get<1>(k);
             if (e > i && (along - prev > hp.n || along - first > limit)) break;
             bd.mem.push_back(idx[e]);
             bd.delta.push_back(along - first);
@@ -310,6 +309,16 @@ void make_bands(const HostPlan &hp, int64_t s0, int64_t count, int o, std::vecto
 // Lines of a band image (rows of the object for o = 0, columns for o = 1): N plus the spread of
 // its origins.
 int band_extent(const HostPlan &hp, const Band &bd) { return hp.n + bd.delta.back(); }
+
+// First line of a band's first workgroup: groups of 16 lines aligned in object coordinates (the
+// band's first origin across the lines plus u0 is a multiple of 16).
+int band_u_start(const Band &bd, int o) { return -((o == 0 ? bd.oy : bd.ox) & 15); }
+
+// Workgroups of a band: its lines from band_u_start to the extent in groups of 16.
+int band_groups(const HostPlan &hp, const Band &bd, int o)
+{
+    return (band_extent(hp, bd) - band_u_start(bd, o) + 15) / 16;
+}
 
 // Tiles covered by an image of rows x cols at origin (oy, ox), wrapping.
 void image_tiles(const HostPlan &hp, int oy, int ox, int rows, int cols, std::vector<int> &out,
@@ -371,7 +380,7 @@ BandStats band_stats(const HostPlan &hp, int64_t B)
                 elems[o] += (double)ext * hp.n;
                 band_tiles(hp, bd, o, tiles, my, mx);
                 bs.entries[o] += (int64_t)tiles.size();
-                bs.workgroups[o] += (ext + 15) / 16;
+                bs.workgroups[o] += band_groups(hp, bd, o);
             }
         }
     const double patches = (double)hp.S * hp.n * hp.n;
@@ -422,9 +431,10 @@ void build_band_lists(HostPlan &hp)
                 const int m0 = (int)hp.bmem[o].size();
                 hp.bmem[o].insert(hp.bmem[o].end(), bd.mem.begin(), bd.mem.end());
                 hp.bdelta[o].insert(hp.bdelta[o].end(), bd.delta.begin(), bd.delta.end());
-                const int lines = (band_extent(hp, bd) + 15) / 16 * 16;
+                const int u_first = band_u_start(bd, o), groups = band_groups(hp, bd, o);
                 size_t lo = 0, hi = 0;
-                for (int u0 = 0; u0 < lines; u0 += 16) {
+                for (int k = 0; k < groups; ++k) {
+                    const int u0 = u_first + 16 * k;
                     while (lo < bd.delta.size() && bd.delta[lo] + hp.n <= u0) ++lo;
                     while (hi < bd.delta.size() && bd.delta[hi] < u0 + 16) ++hi;
                     if (hi > lo) wgs.push_back(make_int4((int)g, m0 + (int)lo, m0 + (int)hi, u0));
@@ -538,10 +548,11 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     // alternates between (two more for recomputed waves), the odd slices transposed, per-line-group
     // partials; recomputation on the fused kernel parks its adjoint state in the first
     const bool lines_possible = hp.n >= 32;
-    L.half = take(lines_possible ? 2 * (size_t)B * NN * 8 : (hp.K > 1 ? (size_t)B * NN * 8 : 0));
-    L.replay = take((lines_possible && hp.K > 1) ? 2 * (size_t)B * NN * 8 : 0);
+    const size_t NA = n * (n + 16);    // a line window: rows of N + 16 (line_kernels.hpp)
+    L.half = take(lines_possible ? 2 * (size_t)B * NA * 8 : (hp.K > 1 ? (size_t)B * NN * 8 : 0));
+    L.replay = take((lines_possible && hp.K > 1) ? 2 * (size_t)B * NA * 8 : 0);
     L.slices_t = take(lines_possible ? (M / 2) * HW * 8 : 0);
-    L.loss_part = take(lines_possible ? (size_t)B * (n / 16) * 8 : 0);
+    L.loss_part = take(lines_possible ? (size_t)B * line_groups(hp.n) * 8 : 0);
     L.energy = take((n / 16) * 8);
     // band sums of the line path: workgroups, members, scatter lists and the band images of the
     // slices one scatter takes
@@ -671,7 +682,7 @@ void launch_fused_raw(int n, int mode, const FusedParams &fp, int count, hipStre
 template <int N>
 void launch_line(bool tr, const LineParams &lp, int stage, int count, hipStream_t st)
 {
-    dim3 grid(N / kLinesPerGroup, count), block(kLinesPerGroup * Win<N>::R);
+    dim3 grid(line_groups(N), count), block(kLinesPerGroup * Win<N>::R);
     if (tr) line_kernel<N, true><<<grid, block, 0, st>>>(lp, stage);
     else line_kernel<N, false><<<grid, block, 0, st>>>(lp, stage);
 }
@@ -732,6 +743,7 @@ void launch_band_n(ms_plan *p, int b, const LineParams &lp, float2 *out, hipStre
     bp.delta = p->at<int>(p->L.bdelta[o]);
     bp.band = out;
     bp.band_stride = p->band_stride();
+    bp.rows = hp.band_rows;
     const bool tr = o == 1;
     switch (hp.n) {
         case 32: launch_band<32>(tr, lp, bp, workgroups, st); break;
@@ -769,7 +781,7 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
     const long long NN = (long long)hp.n * hp.n;
     float2 *waves = fp.waves;
     LineParams lp = line_params(p, fp, mode);
-    PingPong A(p->at<float2>(p->L.half), (long long)hp.B * NN);
+    PingPong A(p->at<float2>(p->L.half), (long long)hp.B * hp.n * (hp.n + 16));
     transpose_odd(p, fp.slices, st);
     for (int m = 0; m < M; ++m) {
         lp.m = m;
@@ -781,12 +793,16 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
         A.next(lp);
         launch_line_n(hp.n, (m & 1) != 0, lp, kStageForward, count, st);
     }
+    // the adjoint chain keeps A with per-position offsets when band workgroups take part in it
+    const bool obj = mode == kAdjoint && !fp.full && b >= 0 && (p->bands_active(0) || p->bands_active(1));
     lp.psi_out = nullptr;
     lp.ovl_out = nullptr;
     lp.m = M - 1;
+    lp.obj_out = obj ? 1 : 0;
     A.next(lp);
     launch_line_n(hp.n, (M & 1) != 0, lp, kStageFar, count, st);
     if (mode == kForward) return;
+    lp.obj_in = lp.obj_out;
     const int m_stop = (mode == kLayer) ? fp.layer : 0;
     for (int m = M - 1; m >= m_stop; --m) {
         lp.m = m;
@@ -868,9 +884,11 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
         return;
     }
     LineParams lp = line_params(p, fp, kAdjoint);
-    const long long pair = (long long)hp.B * NN;
+    const long long pair = (long long)hp.B * hp.n * (hp.n + 16);
     PingPong A(p->at<float2>(p->L.half), pair);
     transpose_odd(p, fp.slices, st);
+    // the adjoint chain keeps A with per-position offsets when band workgroups take part in it
+    const bool obj = !w && (p->bands_active(0) || p->bands_active(1));
     {
         TimedRegion t(p, st);
         for (int m = 0; m < M; ++m) {
@@ -884,9 +902,11 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
         }
         lp.psi_out = nullptr;
         lp.m = M - 1;
+        lp.obj_out = obj ? 1 : 0;
         A.next(lp);
         launch_line_n(hp.n, (M & 1) != 0, lp, kStageFar, count, st);
     }
+    lp.obj_in = lp.obj_out;
     lp.patch_out = work;
     lp.patch_stride = lp.psi_in_stride = fp.wave_stride;
     lp.go_on = 1;
@@ -900,6 +920,7 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
             const int c = m - m % K;
             LineParams rp = lp;
             PingPong Rb(p->at<float2>(p->L.replay), pair);
+            rp.obj_in = rp.obj_out = 0;
             rp.patch_out = nullptr;
             rp.psi_in = nullptr;
             rp.ovl_out = nullptr;
@@ -934,7 +955,7 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
 const double *loss_entries(ms_plan *p, int count, int *n_entries)
 {
     if (p->lines) {
-        *n_entries = count * (p->hp.n / kLinesPerGroup);
+        *n_entries = count * line_groups(p->hp.n);
         return p->at<double>(p->L.loss_part);
     }
     *n_entries = count;

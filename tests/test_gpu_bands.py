@@ -85,9 +85,11 @@ def test_bands_match_oracle_and_patches(dev, name):
     e_none, e_row = rel(g_all, g_none), rel(g_row, g_none)
     print(f"bands {name}: vs oracle grad {e_or:.2e} probe {rel(p_all, ref_gp):.2e} loss "
           f"{abs(l_all - ref_l) / ref_l:.2e}; vs patches {e_none:.2e} (rows only {e_row:.2e})")
-    # bit for bit repeatable; the loss and the probe gradient do not go through the bands
+    # bit for bit repeatable; the probe gradient does not go through the bands, and the FP64 loss
+    # only regroups its partial sums (the far-field launch's line groups follow the band layout)
     assert np.array_equal(g_all, g_all2) and np.array_equal(p_all, p_all2) and l_all == l_all2
-    assert l_all == l_none == l_row and np.array_equal(p_all, p_none) and np.array_equal(p_row, p_none)
+    assert abs(l_all - l_none) <= 1e-12 * l_none and abs(l_row - l_none) <= 1e-12 * l_none
+    assert np.array_equal(p_all, p_none) and np.array_equal(p_row, p_none)
     assert e_none < TOL_REGROUP and e_row < TOL_REGROUP
     assert e_or < TOL_GRAD and rel(p_all, ref_gp) < TOL_GRAD and abs(l_all - ref_l) / ref_l < TOL_FWD
     # slice by slice: both parities (natural and transposed frames) agree with the patches
