@@ -36,7 +36,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2205_03902_amd", "csrc")
 # the sources of each per-position kernel family (a traffic record is valid for these only)
 KERNEL_SOURCES = {"fused": ["ms_kernels.hpp", "fft_lines.hpp"],
-                  "lines": ["line_kernels.hpp", "ms_kernels.hpp", "fft_lines.hpp"]}
+                  "lines": ["line_kernels.hpp", "ms_kernels.hpp", "fft_lines.hpp", "ms_lib.hip"]}
 
 
 def log(*a):
@@ -363,8 +363,8 @@ def roofline(geo, family: str, kernel_ms: float):
     if family == "fused":
         roof["kernel"] = f"fused_kernel<{geo.n}, adjoint> (one launch per pass)"
     else:
-        roof["kernel"] = (f"line_kernel<{geo.n}, row|column> (the {2 * geo.n_slices + 1} launches of one pass, "
-                          f"timed together)")
+        roof["kernel"] = (f"line_kernel<{geo.n}, frame> (forward and far field) and line_band_kernel<{geo.n}, frame> "
+                          f"(adjoint): the {2 * geo.n_slices + 1} launches of one pass, timed together")
     roof["kernel_ms"] = kernel_ms
     roof["other"] = {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
     roof["algorithmic_bytes_per_launch"] = byt
