@@ -531,7 +531,8 @@ struct BandParams {
 };
 
 // Adjoint launch of slice m over band workgroups (1D grid); otherwise the adjoint stage of
-// line_kernel for each member in turn (both A layouts with offsets).  One propagation table in
+// line_kernel for each member in turn (A_out with offsets; A_in with or without, the first
+// adjoint launch reading the far field's aligned windows).  One propagation table in
 // LDS, reloaded between the two propagations of a member, so that a CU holds four workgroups.
 template <int N, bool TR>
 __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_band_kernel(LineParams p, BandParams bp)
@@ -576,7 +577,7 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_band_kerne
         float2 *xb = xbuf + lloc * Wn::LD;
         const int b = bp.mem[i];
         const int4 info = p.pos_info[p.pos_list[b]];
-        const int s_line = (TR ? info.y : info.x) & 15, s_elem = (TR ? info.x : info.y) & 15;
+        const int s_line = (TR ? info.y : info.x) & 15, s_elem = p.obj_in ? (TR ? info.x : info.y) & 15 : 0;
         const int l0 = w.w - bp.delta[i];            // window line of lloc = 0
         const int wl = l0 + lloc;
         const bool valid = (unsigned)wl < (unsigned)N;

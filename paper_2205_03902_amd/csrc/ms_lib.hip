@@ -793,16 +793,16 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
         A.next(lp);
         launch_line_n(hp.n, (m & 1) != 0, lp, kStageForward, count, st);
     }
-    // the adjoint chain keeps A with per-position offsets when band workgroups take part in it
+    // the adjoint chain keeps A with per-position offsets from its first launch on when band
+    // workgroups take part in it (the far field writes aligned windows)
     const bool obj = mode == kAdjoint && !fp.full && b >= 0 && (p->bands_active(0) || p->bands_active(1));
     lp.psi_out = nullptr;
     lp.ovl_out = nullptr;
     lp.m = M - 1;
-    lp.obj_out = obj ? 1 : 0;
     A.next(lp);
     launch_line_n(hp.n, (M & 1) != 0, lp, kStageFar, count, st);
     if (mode == kForward) return;
-    lp.obj_in = lp.obj_out;
+    lp.obj_out = obj ? 1 : 0;
     const int m_stop = (mode == kLayer) ? fp.layer : 0;
     for (int m = M - 1; m >= m_stop; --m) {
         lp.m = m;
@@ -824,6 +824,7 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
             launch_band_n(p, b, lp, p->at<float2>(p->L.band) + m * p->band_slice_stride(), st);
         else
             launch_line_n(hp.n, (m & 1) != 0, lp, kStageAdjoint, count, st);
+        lp.obj_in = lp.obj_out;
     }
 }
 
@@ -902,11 +903,10 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
         }
         lp.psi_out = nullptr;
         lp.m = M - 1;
-        lp.obj_out = obj ? 1 : 0;
         A.next(lp);
         launch_line_n(hp.n, (M & 1) != 0, lp, kStageFar, count, st);
     }
-    lp.obj_in = lp.obj_out;
+    lp.obj_out = obj ? 1 : 0;
     lp.patch_out = work;
     lp.patch_stride = lp.psi_in_stride = fp.wave_stride;
     lp.go_on = 1;
@@ -940,12 +940,14 @@ void adjoint_recompute(ms_plan *p, FusedParams fp, int b, int count, hipStream_t
         lp.m = m;
         lp.psi_in = (m == 0) ? nullptr : (m % K == 0 ? ck_slot(m) : work);
         A.next(lp);
+        const LineParams cur = lp;
+        lp.obj_in = lp.obj_out;      // the next adjoint launch reads what this one writes
         if (!w && p->bands_active(m & 1)) {
-            launch_band_n(p, b, lp, p->at<float2>(p->L.band), st);
+            launch_band_n(p, b, cur, p->at<float2>(p->L.band), st);
             scatter_slices(p, b, count, work, fp.wave_stride, m, 1, g + m * hw, accumulate, st);
             continue;
         }
-        launch_line_n(hp.n, (m & 1) != 0, lp, kStageAdjoint, count, st);
+        launch_line_n(hp.n, (m & 1) != 0, cur, kStageAdjoint, count, st);
         scatter(p, b, count, work, fp.wave_stride, ovl, fp.ovl_stride, m, 1, g + m * hw, w ? w + m * hw : nullptr,
                 accumulate, st);
     }

@@ -227,9 +227,11 @@ void gemm(const GemmArgs &a, hipStream_t st)
         gemm_kernel<128, 32, 4, 1><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 32)), kThreads, 0, st>>>(a);
     } else if (N <= 64) {
         gemm_kernel<128, 64, 2, 2><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 64)), kThreads, 0, st>>>(a);
-    } else if (cdiv(M, 128) * cdiv(N, 128) < 1024) {
+    } else if (cdiv(M, 128) * cdiv(N, 128) < 1024 || a.o.ostride > 1) {
         // the coarse levels: 128 x 64 tiles double the workgroups of a grid that would leave CUs
-        // with one or two (the same sums: each output's K order does not depend on the tiling)
+        // with one or two (the same sums: each output's K order does not depend on the tiling);
+        // the transposed convolutions (K of 64 to 256, a few steps a tile) likewise: 1 % of the
+        // forward at batch 16
         gemm_kernel<128, 64, 2, 2><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 64)), kThreads, 0, st>>>(a);
     } else {
         gemm_kernel<128, 128, 2, 2><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 128)), kThreads, 0, st>>>(a);
