@@ -803,7 +803,17 @@ __global__ __launch_bounds__(256) void loss_sum_kernel(const double *loss_pos, i
 {
     __shared__ double sm[256];
     double a = 0.0;
-    for (int i = threadIdx.x; i < count; i += 256) a += loss_pos[i];
+    // lane l adds entries l, l + 256, l + 512, ... in that order, 16 loads in flight at a time
+    constexpr int U = 16;
+    int i = threadIdx.x;
+    for (; i + (U - 1) * 256 < count; i += U * 256) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = loss_pos[i + u * 256];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a += v[u];
+    }
+    for (; i < count; i += 256) a += loss_pos[i];
     sm[threadIdx.x] = a;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
