@@ -2,8 +2,9 @@
 for the windows of one scan column, odd slices' launches 16 object columns for the windows of one
 scan row, and the scatter reads band images.  Checked against the FP64
 oracle, against the per-position patches of the same plan, on a scan that wraps through the object
-edges (bands cut where their image would wrap onto itself), with recomputed waves, with batches,
-and at N = 256."""
+edges (bands cut where their image would wrap onto itself), on fractional steps (shift classes) over
+an object whose side is not a multiple of 16, with recomputed waves, with batches, with the Poisson
+objective and tilted illumination, and at N = 256."""
 import numpy as np
 import pytest
 
@@ -33,6 +34,8 @@ def _geometry(name):
         return configs.small(n=64, obj=128, n_slices=3, scan=(12, 12), step_px=8.0, seed=6, defocus=25.0)
     if name == "raster256":     # N = 256, step 16
         return configs.small(n=256, obj=384, n_slices=3, scan=(5, 5), step_px=16.0, seed=7, defocus=25.0)
+    if name == "frac100":       # fractional step over a 100^2 object, shifted so that windows wrap
+        return configs.small(n=64, obj=100, n_slices=4, scan=(10, 10), step_px=8.5, seed=8, defocus=25.0)
     raise KeyError(name)
 
 
@@ -40,6 +43,8 @@ def _positions(name, geo):
     pos = geo.positions()
     if name == "wrap64":
         pos = np.mod(pos + 66.0, geo.obj_h)        # origins 70 + 8 i (mod 128): some windows wrap
+    if name == "frac100":
+        pos = np.mod(pos + 40.25, geo.obj_h)
     return pos
 
 
@@ -70,7 +75,7 @@ def _adjoint(plan, c, dev, mode):
     return loss.item(), gs.cpu().numpy(), gp.cpu().numpy()
 
 
-@pytest.mark.parametrize("name", ["raster64", "wrap64", "raster256"])
+@pytest.mark.parametrize("name", ["raster64", "wrap64", "frac100", "raster256"])
 def test_bands_match_oracle_and_patches(dev, name):
     from paper_2205_03902_amd import abi
     c = case_for(name)
@@ -125,3 +130,22 @@ def test_bands_across_batches(dev):
     print(f"bands batches: batch {small.batch} bands {small.has_bands}: grad {rel(g2, g1):.2e}")
     assert rel(g2, g1) < TOL_REGROUP and rel(p2, p1) < TOL_REGROUP
     assert abs(l1 - l2) <= 1e-12 * l1
+
+
+@pytest.mark.parametrize("variant", ["poisson", "tilt"])
+def test_bands_with_the_poisson_objective_and_tilt(dev, variant):
+    from paper_2205_03902_amd import abi
+    c = case_for("raster64")
+    g = c.geo
+    if variant == "tilt":
+        plan = abi.Plan(g.n, g.obj_h, g.obj_w, g.n_slices, c.model.positions, g.gaps(), g.pixel_size, g.wavelength,
+                        tilt_y=2e-3, tilt_x=-3e-3, device=dev, checkpoint_every=1)
+    else:
+        plan = _plan(c, dev)
+        plan.set_objective(abi.MS_OBJECTIVE_POISSON)
+    plan.set_path(abi.MS_PATH_LINES)
+    assert plan.has_bands == 3
+    l1, g1, p1 = _adjoint(plan, c, dev, abi.MS_BANDS_ALL)
+    l0, g0, p0 = _adjoint(plan, c, dev, abi.MS_BANDS_NONE)
+    print(f"bands {variant}: vs patches {rel(g1, g0):.2e}")
+    assert rel(g1, g0) < TOL_REGROUP and np.array_equal(p1, p0) and abs(l1 - l0) <= 1e-12 * abs(l0)
