@@ -149,6 +149,21 @@ ms_status ms_plan_set_bands(ms_plan *plan, int32_t mode);
  * slices, bit 1 odd slices. */
 int32_t ms_plan_has_bands(const ms_plan *plan);
 
+/* Kept windows in ms_adjoint on the line path.  Launch m of the forward chain (Sec. 2.1)
+ * reads the window that launch m - 1 left half-propagated and finishes the propagation
+ * along its own lines to obtain the incident wave psi_m.  When the adjoint's launches of
+ * both even and odd slices take bands, and every wave is stored (checkpoint interval 1),
+ * the forward chain can keep those windows, one per slice after the first, instead of
+ * storing psi_m; each adjoint launch then finishes psi_m again from the kept window along
+ * the same lines.  The windows take the place of the waves in the workspace (when
+ * (M - 1)(N + 16) <= M N), and the chain writes no wave, which saves one N x N complex
+ * store per position and slice.  psi_m is recomputed by the same steps, so results agree
+ * with the stored waves to rounding (bit for bit where the compiler emits the same
+ * instructions).  on = 1 (the default): keep windows where the conditions hold; 0: store
+ * waves.  ms_plan_kept_windows returns 1 when the plan's next ms_adjoint keeps windows. */
+ms_status ms_plan_set_kept_windows(ms_plan *plan, int32_t on);
+int32_t ms_plan_kept_windows(const ms_plan *plan);
+
 /* The data term of every loss, gradient and step of the plan.
  * MS_OBJECTIVE_AMPLITUDE (the default): L = sum (sqrt(I) - |Psi|)^2, the amplitude
  * flow of Sec. 3.2, residual Psi - sqrt(I) Psi / |Psi|.

@@ -25,6 +25,7 @@ MS_OBJECTIVE_AMPLITUDE, MS_OBJECTIVE_POISSON = 0, 1
 # every entry point declared in include/ms.h
 SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
            "ms_plan_checkpoint_every", "ms_plan_set_path", "ms_plan_set_bands", "ms_plan_has_bands",
+           "ms_plan_set_kept_windows", "ms_plan_kept_windows",
            "ms_plan_set_objective",
            "ms_make_probe", "ms_make_probe_aberrated", "ms_forward", "ms_adjoint", "ms_adjoint_scratch", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_position_grad", "ms_position_step", "ms_reconstruction_error",
            "ms_profile_begin",
@@ -74,6 +75,10 @@ def lib():
         L.ms_plan_set_bands.argtypes = [P, I32]
         L.ms_plan_has_bands.restype = I32
         L.ms_plan_has_bands.argtypes = [P]
+        L.ms_plan_set_kept_windows.restype = I32
+        L.ms_plan_set_kept_windows.argtypes = [P, I32]
+        L.ms_plan_kept_windows.restype = I32
+        L.ms_plan_kept_windows.argtypes = [P]
         L.ms_plan_set_objective.restype = I32
         L.ms_plan_set_objective.argtypes = [P, I32]
         L.ms_make_probe.restype = I32
@@ -233,6 +238,7 @@ class Plan:
         self.workspace_bytes = ws
         self.budget_bytes = int(budget_bytes)
         self._path, self._objective, self._bands = MS_PATH_AUTO, MS_OBJECTIVE_AMPLITUDE, MS_BANDS_ALL
+        self._kept_windows = 1
 
     def positions(self):
         """The scan positions (S, 2) this plan was built from (host float64 copy)."""
@@ -247,6 +253,7 @@ class Plan:
         plan.set_path(self._path)
         plan.set_objective(self._objective)
         plan.set_bands(self._bands)
+        plan.set_kept_windows(self._kept_windows)
         return plan
 
     @classmethod
@@ -296,6 +303,17 @@ class Plan:
         """MS_BANDS_ALL, MS_BANDS_ROWS or MS_BANDS_NONE (see include/ms.h)."""
         _check(lib().ms_plan_set_bands(self._h, int(mode)), "ms_plan_set_bands")
         self._bands = int(mode)
+
+    def set_kept_windows(self, on: int):
+        """1: the plain adjoint's forward chain keeps windows in place of waves where it can; 0:
+        stores waves (see include/ms.h)."""
+        _check(lib().ms_plan_set_kept_windows(self._h, int(on)), "ms_plan_set_kept_windows")
+        self._kept_windows = int(on)
+
+    @property
+    def kept_windows(self) -> bool:
+        """Whether the next adjoint keeps windows (line path, bands in both frames)."""
+        return bool(lib().ms_plan_kept_windows(self._h))
 
     def set_objective(self, objective: int):
         """MS_OBJECTIVE_AMPLITUDE or MS_OBJECTIVE_POISSON (see include/ms.h)."""

@@ -45,8 +45,8 @@ struct LineParams {
     const float *measured;       // [S][N][N]
     float *intensity;            // [S][N][N] (forward mode)
     float2 *exit_waves;          // [S][N][N] or null
-    const float2 *A_in;          // [count][N][N] half-propagated window in this launch's frame
-    float2 *A_out;               // [count][N][N] the same for the next launch, in the other frame
+    const float2 *A_in;          // [count][N][N + 16] half-propagated window in this launch's frame
+    float2 *A_out;               // [count][N][N + 16] the same for the next launch, in the other frame
     float2 *probe_patch;         // [count][N][N] or null
     double *loss_part;           // [count][N / 16]
     int H, W, M, m;
@@ -532,10 +532,20 @@ struct BandParams {
 
 // Adjoint launch of slice m over band workgroups (1D grid); otherwise the adjoint stage of
 // line_kernel for each member in turn (A_out with offsets; A_in with or without, the first
-// adjoint launch reading the far field's aligned windows).  One propagation table in
-// LDS, reloaded between the two propagations of a member, so that a CU holds four workgroups.
-template <int N, bool TR>
-__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_band_kernel(LineParams p, BandParams bp)
+// adjoint launch reading the far field's aligned windows).
+//
+// psi_m comes from psi_in as a stored wave, or (RECOMP, m > 0) as the window the forward launch
+// of slice m read: rows of N + 16 aligned, in this launch's frame, from which psi_m is the
+// propagation of gap m - 1 finished along the lines, as that launch did.  A forward chain that
+// keeps those windows then stores no waves: it writes each window once, where the ping-pong
+// would have overwritten it, and the adjoint reads it in place of the wave.
+//
+// Without RECOMP one propagation table in LDS, reloaded between the two propagations of a member,
+// so that a CU holds four workgroups; with it the recomputed wave is a third window line in
+// registers, three workgroups a CU fit, and both tables stay in LDS.
+template <int N, bool TR, bool RECOMP>
+__global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, RECOMP ? 3 : 4) void line_band_kernel(LineParams p,
+                                                                                              BandParams bp)
 {
     using Wn = Win<N>;
     constexpr int R = Wn::R;
@@ -544,17 +554,20 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_band_kerne
     constexpr size_t NA = (size_t)N * Apitch<N>::P;
     __shared__ float2 xbuf[kLinesPerGroup * Wn::LD];
     __shared__ float2 s_tw[Wn::TW_WORDS];
-    __shared__ float2 s_h[N];
+    __shared__ float2 s_h[RECOMP ? 2 * N : N];
 
     const int tid = threadIdx.x;
     const int M = p.M, m = p.m;
     const float2 *hown = TR ? p.hy : p.hx;
     const int g_fin = (m + 1 < M) ? m : -1;
-    const int g_start = (m > 0 && p.go_on) ? m - 1 : -1;
-    // the table of gap g into LDS unless it is there, between barriers (every lane is done with
-    // the previous one); slices of one distance share a table
+    const int g_start = (m > 0 && (p.go_on || RECOMP)) ? m - 1 : -1;
+    // the tables of gaps m (finished here) and m - 1 (started here; finished by the forward
+    // launch): one slot, filled on demand between barriers (every lane is done with the previous
+    // table; slices of one distance share a table), or with RECOMP a slot each, filled once
+    float2 *h_fin = s_h, *h_start = RECOMP ? s_h + N : s_h;
     int loaded = -1;
     auto load_h = [&](int g) {
+        if (RECOMP) return;
         const int u = p.gap_table[g];
         if (u == loaded) return;
         __syncthreads();
@@ -563,6 +576,12 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_band_kerne
         loaded = u;
     };
     for (int i = tid; i < Wn::TW_WORDS; i += NT) s_tw[i] = p.tw[i];
+    if (RECOMP) {
+        if (g_fin >= 0)
+            for (int i = tid; i < N; i += NT) h_fin[i] = hown[p.gap_table[g_fin] * N + i];
+        if (g_start >= 0)
+            for (int i = tid; i < N; i += NT) h_start[i] = hown[p.gap_table[g_start] * N + i];
+    }
     __syncthreads();
 
     const int4 w = bp.wg[blockIdx.x];
@@ -583,6 +602,12 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_band_kerne
         const bool valid = (unsigned)wl < (unsigned)N;
         const int line = valid ? wl : 0;
         const float2 *A_in = p.A_in + (size_t)b * NA;
+        float2 ps[16];
+        if (RECOMP && m > 0) {
+            // psi_m: the forward launch's window, the propagation of gap m - 1 finished
+            aload<N, false>(ps, p.psi_in + (size_t)b * p.psi_in_stride, line, j, 0);
+            prop_axis<N, false>(ps, s_tw, xb, h_start, j);
+        }
         float2 v[16];
         if (m + 1 == M) {
             aload<N, true>(v, A_in, line, j, s_elem);
@@ -590,21 +615,26 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_band_kerne
         } else {
             aload<N, false>(v, A_in, line, j, s_elem);
             load_h(g_fin);
-            prop_axis<N, true>(v, s_tw, xb, s_h, j);
+            prop_axis<N, true>(v, s_tw, xb, h_fin, j);
         }
         if (valid) {
             // acc += conj(psi_m) o g
-            const float2 *psi = p.psi_in ? p.psi_in + (size_t)b * p.psi_in_stride
-                                         : p.class_probe + (size_t)info.z * NN;
             const int l2 = opaque(line), j2 = opaque(j);
+            if (RECOMP && m > 0) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) acc[k] = cadd(acc[k], cconjmul(psi[l2 * N + Wn::nat(j2, k)], v[k]));
+                for (int k = 0; k < 16; ++k) acc[k] = cadd(acc[k], cconjmul(ps[k], v[k]));
+            } else {
+                const float2 *psi = p.psi_in && !RECOMP ? p.psi_in + (size_t)b * p.psi_in_stride
+                                                        : p.class_probe + (size_t)info.z * NN;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) acc[k] = cadd(acc[k], cconjmul(psi[l2 * N + Wn::nat(j2, k)], v[k]));
+            }
         }
         if (!p.go_on) continue;
         frame_patch<N, TR, true>(v, p, info.x, info.y, line, j);
         if (m > 0) {
             load_h(g_start);
-            prop_axis<N, true>(v, s_tw, xb, s_h, j);
+            prop_axis<N, true>(v, s_tw, xb, h_start, j);
             store_other<N, false>(v, p.A_out + (size_t)b * NA, Apitch<N>::P, l0, s_line, lloc, j, xbuf);
         } else if (p.probe_patch && valid) {
             gstore<N, true, false>(v, p.probe_patch + (size_t)b * NN, line, j);

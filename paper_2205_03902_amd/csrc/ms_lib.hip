@@ -625,6 +625,9 @@ struct ms_plan {
     // the line path sums gradient patches into band images when the plan has them: of row and
     // column launches (MS_BANDS_ALL), row launches only, or none
     int band_mode = MS_BANDS_ALL;
+    // with bands in both frames, the forward chain keeps each launch's window for the adjoint in
+    // place of the wave (ms_plan_set_kept_windows)
+    bool keep_windows = true;
     // A second stream (default priority) for the probe-gradient reductions, which only read
     // what the per-position kernel wrote and so run beside the slice scatter; fork and join
     // through events on the caller's stream.
@@ -641,6 +644,14 @@ struct ms_plan {
     bool bands_active(int o) const
     {
         return lines && hp.bands[o] && (band_mode == MS_BANDS_ALL || (band_mode == MS_BANDS_ROWS && o == 0));
+    }
+    // whether the plain adjoint's forward chain keeps windows: every wave stored (K = 1) and the
+    // M - 1 windows, rows of N + 16, fit where the M waves would be
+    bool kept_windows() const
+    {
+        const long long n = hp.n;
+        return lines && keep_windows && hp.K == 1 && hp.M > 1 && bands_active(0) && bands_active(1) &&
+               (hp.M - 1) * n * (n + 16) <= hp.M * n * n;
     }
     long long band_stride() const { return (long long)band_elems(hp); }
     long long band_slice_stride() const { return (long long)hp.band_count * band_stride(); }
@@ -699,11 +710,16 @@ void launch_line_n(int n, bool tr, const LineParams &lp, int stage, int count, h
 }
 
 template <int N>
-void launch_band(bool tr, const LineParams &lp, const BandParams &bp, int workgroups, hipStream_t st)
+void launch_band(bool tr, bool recomp, const LineParams &lp, const BandParams &bp, int workgroups, hipStream_t st)
 {
     const dim3 block(kLinesPerGroup * Win<N>::R);
-    if (tr) line_band_kernel<N, true><<<workgroups, block, 0, st>>>(lp, bp);
-    else line_band_kernel<N, false><<<workgroups, block, 0, st>>>(lp, bp);
+    if (recomp) {
+        if (tr) line_band_kernel<N, true, true><<<workgroups, block, 0, st>>>(lp, bp);
+        else line_band_kernel<N, false, true><<<workgroups, block, 0, st>>>(lp, bp);
+    } else {
+        if (tr) line_band_kernel<N, true, false><<<workgroups, block, 0, st>>>(lp, bp);
+        else line_band_kernel<N, false, false><<<workgroups, block, 0, st>>>(lp, bp);
+    }
 }
 
 // The two half-propagation buffers of a chain of line launches: each launch reads the one the
@@ -730,8 +746,9 @@ void transpose_odd(ms_plan *p, const float2 *slices, hipStream_t st)
 }
 
 // Adjoint launch of slice lp.m for batch b with the gradient patches summed into the band images
-// at out (in the frame of slice m).
-void launch_band_n(ms_plan *p, int b, const LineParams &lp, float2 *out, hipStream_t st)
+// at out (in the frame of slice m); recomp: lp.psi_in holds the forward launch's windows of slice m
+// rather than psi_m.
+void launch_band_n(ms_plan *p, int b, const LineParams &lp, float2 *out, hipStream_t st, bool recomp = false)
 {
     const HostPlan &hp = p->hp;
     const int o = lp.m & 1;
@@ -746,10 +763,10 @@ void launch_band_n(ms_plan *p, int b, const LineParams &lp, float2 *out, hipStre
     bp.rows = hp.band_rows;
     const bool tr = o == 1;
     switch (hp.n) {
-        case 32: launch_band<32>(tr, lp, bp, workgroups, st); break;
-        case 64: launch_band<64>(tr, lp, bp, workgroups, st); break;
-        case 128: launch_band<128>(tr, lp, bp, workgroups, st); break;
-        default: launch_band<256>(tr, lp, bp, workgroups, st); break;
+        case 32: launch_band<32>(tr, recomp, lp, bp, workgroups, st); break;
+        case 64: launch_band<64>(tr, recomp, lp, bp, workgroups, st); break;
+        case 128: launch_band<128>(tr, recomp, lp, bp, workgroups, st); break;
+        default: launch_band<256>(tr, recomp, lp, bp, workgroups, st); break;
     }
 }
 
@@ -773,33 +790,43 @@ LineParams line_params(ms_plan *p, const FusedParams &fp, int mode)
 // Forward launches m = 0..M-1 (layout of slice m: rows for even m), the far-field launch
 // in the other layout, then (unless forward-only) the adjoint launches m = M-1 .. m_stop.
 // Every wave the mode needs is stored (K = 1 layout; the layer mode uses slot 0).
-// Batch b >= 0 of a plain adjoint sums the gradient patches into bands when the plan has them.
+// Batch b >= 0 of a plain adjoint sums the gradient patches into bands when the plan has them;
+// when both frames do, the forward chain writes the window of each launch m = 1 .. M-1 into a
+// kept slot instead of a ping-pong buffer and stores no wave, and the band launches finish psi_m
+// from it (kept_windows).
 void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream_t st, int b)
 {
     const HostPlan &hp = p->hp;
     const int M = hp.M;
-    const long long NN = (long long)hp.n * hp.n;
+    const long long NN = (long long)hp.n * hp.n, NA = (long long)hp.n * (hp.n + 16);
     float2 *waves = fp.waves;
     LineParams lp = line_params(p, fp, mode);
-    PingPong A(p->at<float2>(p->L.half), (long long)hp.B * hp.n * (hp.n + 16));
+    PingPong A(p->at<float2>(p->L.half), (long long)hp.B * NA);
+    const bool bands = mode == kAdjoint && !fp.full && b >= 0;
+    const bool keep = bands && p->kept_windows();
+    auto kept = [&](int m) { return waves + (long long)(m - 1) * hp.B * NA; };
     transpose_odd(p, fp.slices, st);
     for (int m = 0; m < M; ++m) {
         lp.m = m;
         lp.psi_out = nullptr;
         lp.ovl_out = nullptr;
-        if (m > 0 && mode == kAdjoint) { lp.psi_out = waves + m * NN; lp.psi_out_stride = fp.wave_stride; }
+        if (m > 0 && mode == kAdjoint && !keep) { lp.psi_out = waves + m * NN; lp.psi_out_stride = fp.wave_stride; }
         if (m > 0 && mode == kLayer && m == fp.layer) { lp.psi_out = waves; lp.psi_out_stride = fp.wave_stride; }
         if (mode == kLayer && m == fp.layer) { lp.ovl_out = fp.overlap_patch; lp.ovl_stride = fp.ovl_stride; }
         A.next(lp);
+        if (keep) {
+            if (m > 0) lp.A_in = kept(m);
+            if (m + 1 < M) lp.A_out = kept(m + 1);
+        }
         launch_line_n(hp.n, (m & 1) != 0, lp, kStageForward, count, st);
     }
     // the adjoint chain keeps A with per-position offsets from its first launch on when band
     // workgroups take part in it (the far field writes aligned windows)
-    const bool obj = mode == kAdjoint && !fp.full && b >= 0 && (p->bands_active(0) || p->bands_active(1));
+    const bool obj = bands && (p->bands_active(0) || p->bands_active(1));
     lp.psi_out = nullptr;
     lp.ovl_out = nullptr;
     lp.m = M - 1;
-    A.next(lp);
+    A.next(lp);    // the buffer the last forward launch wrote, also when the others were kept
     launch_line_n(hp.n, (M & 1) != 0, lp, kStageFar, count, st);
     if (mode == kForward) return;
     lp.obj_out = obj ? 1 : 0;
@@ -818,10 +845,14 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
             lp.psi_in = m > 0 ? waves : nullptr;
         }
         lp.patch_stride = lp.psi_in_stride = fp.wave_stride;
+        if (keep) {
+            lp.psi_in = m > 0 ? kept(m) : nullptr;
+            lp.psi_in_stride = NA;
+        }
         lp.go_on = (m > m_stop) || (mode != kLayer);
         A.next(lp);
-        if (mode == kAdjoint && !fp.full && b >= 0 && p->bands_active(m & 1))
-            launch_band_n(p, b, lp, p->at<float2>(p->L.band) + m * p->band_slice_stride(), st);
+        if (bands && p->bands_active(m & 1))
+            launch_band_n(p, b, lp, p->at<float2>(p->L.band) + m * p->band_slice_stride(), st, keep);
         else
             launch_line_n(hp.n, (m & 1) != 0, lp, kStageAdjoint, count, st);
         lp.obj_in = lp.obj_out;
@@ -1530,6 +1561,16 @@ ms_status ms_plan_set_bands(ms_plan *p, int32_t mode)
 }
 
 int32_t ms_plan_has_bands(const ms_plan *p) { return p ? (p->hp.bands[0] ? 1 : 0) | (p->hp.bands[1] ? 2 : 0) : 0; }
+
+ms_status ms_plan_set_kept_windows(ms_plan *p, int32_t on)
+{
+    g_err.clear();
+    if (!p) return fail(MS_ERR_INVALID_ARG, "plan is NULL");
+    p->keep_windows = on != 0;
+    return MS_OK;
+}
+
+int32_t ms_plan_kept_windows(const ms_plan *p) { return p && p->kept_windows() ? 1 : 0; }
 
 namespace {
 

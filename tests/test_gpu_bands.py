@@ -149,3 +149,47 @@ def test_bands_with_the_poisson_objective_and_tilt(dev, variant):
     l0, g0, p0 = _adjoint(plan, c, dev, abi.MS_BANDS_NONE)
     print(f"bands {variant}: vs patches {rel(g1, g0):.2e}")
     assert rel(g1, g0) < TOL_REGROUP and np.array_equal(p1, p0) and abs(l1 - l0) <= 1e-12 * abs(l0)
+
+
+@pytest.mark.parametrize("name", ["raster64", "wrap64", "frac100", "raster256"])
+def test_kept_windows_match_stored_waves(dev, name):
+    """The forward chain keeps each launch's window and the band launches finish psi_m from it:
+    the same gradients as with stored waves (to rounding), and the oracle's."""
+    from paper_2205_03902_amd import abi
+    c = case_for(name)
+    plan = _plan(c, dev)
+    assert plan.kept_windows, f"{name}: kept windows expected (bands in both frames, every wave stored)"
+    l1, g1, p1 = _adjoint(plan, c, dev, abi.MS_BANDS_ALL)
+    l1b, g1b, p1b = _adjoint(plan, c, dev, abi.MS_BANDS_ALL)
+    plan.set_kept_windows(0)
+    assert not plan.kept_windows
+    l0, g0, p0 = _adjoint(plan, c, dev, abi.MS_BANDS_ALL)
+    plan.set_kept_windows(1)
+    ref_l, ref_gs, ref_gp, _ = c.model.loss_grad(c.probe, c.start, c.measured)
+    print(f"kept windows {name}: vs stored waves grad {rel(g1, g0):.2e}; vs oracle grad {rel(g1, ref_gs):.2e} "
+          f"probe {rel(p1, ref_gp):.2e}")
+    assert np.array_equal(g1, g1b) and np.array_equal(p1, p1b) and l1 == l1b
+    # the forward values and the adjoint chain g are the same computations; only psi_m is taken
+    # from another place
+    assert l1 == l0 and np.array_equal(p1, p0)
+    assert rel(g1, g0) < TOL_REGROUP
+    for m in range(c.geo.n_slices):
+        assert rel(g1[m], g0[m]) < TOL_REGROUP, f"slice {m}"
+    assert rel(g1, ref_gs) < TOL_GRAD and rel(p1, ref_gp) < TOL_GRAD and abs(l1 - ref_l) / ref_l < TOL_FWD
+
+
+def test_kept_windows_only_where_they_fit(dev):
+    """Kept windows need bands in both frames, every wave stored and room where the waves were."""
+    from paper_2205_03902_amd import abi
+    c = case_for("raster64")
+    plan = _plan(c, dev)
+    assert plan.kept_windows
+    plan.set_bands(abi.MS_BANDS_ROWS)
+    assert not plan.kept_windows
+    plan.set_bands(abi.MS_BANDS_ALL)
+    assert plan.kept_windows
+    assert not _plan(c, dev, checkpoint_every=2).kept_windows
+    g = c.geo
+    fused = abi.Plan.from_geometry(g, positions=c.model.positions, device=dev, checkpoint_every=1)
+    fused.set_path(abi.MS_PATH_FUSED)
+    assert not fused.kept_windows
