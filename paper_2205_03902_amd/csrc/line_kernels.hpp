@@ -26,6 +26,9 @@
 namespace imsp {
 
 constexpr int kLinesPerGroup = 16;
+// lines of a wavefront in a line workgroup of window side N (R = N / 16 lanes a line)
+template <int N>
+constexpr int lines_per_wave() { return (kLinesPerGroup * (N / 16) < 64 ? kLinesPerGroup * (N / 16) : 64) / (N / 16); }
 
 enum LineStage : int {
     kStageForward = 0,   // forward launch for slice m
@@ -601,40 +604,55 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, RECOMP ? 3 : 4) void li
         const int wl = l0 + lloc;
         const bool valid = (unsigned)wl < (unsigned)N;
         const int line = valid ? wl : 0;
+        // a wavefront whose lines all lie outside this member's window (in the first or last
+        // group of 16 object lines) skips the member's arithmetic; it still takes part in the
+        // table loads and the LDS transpose, which synchronise the workgroup, and the transpose
+        // stores none of its lines
+        constexpr int LW = lines_per_wave<N>();
+        const int lw = l0 + (tid / 64) * LW;
+        const bool live = lw + LW > 0 && lw < N;
         const float2 *A_in = p.A_in + (size_t)b * NA;
-        float2 ps[16];
-        if (RECOMP && m > 0) {
-            // psi_m: the forward launch's window, the propagation of gap m - 1 finished
-            aload<N, false>(ps, p.psi_in + (size_t)b * p.psi_in_stride, line, j, 0);
-            prop_axis<N, false>(ps, s_tw, xb, h_start, j);
-        }
         float2 v[16];
-        if (m + 1 == M) {
-            aload<N, true>(v, A_in, line, j, s_elem);
-            line_fft_inv<N>(v, s_tw, xb, j);
-        } else {
-            aload<N, false>(v, A_in, line, j, s_elem);
-            load_h(g_fin);
-            prop_axis<N, true>(v, s_tw, xb, h_fin, j);
-        }
-        if (valid) {
-            // acc += conj(psi_m) o g
-            const int l2 = opaque(line), j2 = opaque(j);
+        if (m + 1 < M) load_h(g_fin);
+        if (live) {
+            float2 ps[16];
             if (RECOMP && m > 0) {
-#pragma unroll
-                for (int k = 0; k < 16; ++k) acc[k] = cadd(acc[k], cconjmul(ps[k], v[k]));
-            } else {
-                const float2 *psi = p.psi_in && !RECOMP ? p.psi_in + (size_t)b * p.psi_in_stride
-                                                        : p.class_probe + (size_t)info.z * NN;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) acc[k] = cadd(acc[k], cconjmul(psi[l2 * N + Wn::nat(j2, k)], v[k]));
+                // psi_m: the forward launch's window, the propagation of gap m - 1 finished
+                aload<N, false>(ps, p.psi_in + (size_t)b * p.psi_in_stride, line, j, 0);
+                prop_axis<N, false>(ps, s_tw, xb, h_start, j);
             }
+            if (m + 1 == M) {
+                aload<N, true>(v, A_in, line, j, s_elem);
+                line_fft_inv<N>(v, s_tw, xb, j);
+            } else {
+                aload<N, false>(v, A_in, line, j, s_elem);
+                prop_axis<N, true>(v, s_tw, xb, h_fin, j);
+            }
+            if (valid) {
+                // acc += conj(psi_m) o g
+                const int l2 = opaque(line), j2 = opaque(j);
+                if (RECOMP && m > 0) {
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) acc[k] = cadd(acc[k], cconjmul(ps[k], v[k]));
+                } else {
+                    const float2 *psi = p.psi_in && !RECOMP ? p.psi_in + (size_t)b * p.psi_in_stride
+                                                            : p.class_probe + (size_t)info.z * NN;
+#pragma unroll
+                    for (int k = 0; k < 16; ++k)
+                        acc[k] = cadd(acc[k], cconjmul(psi[l2 * N + Wn::nat(j2, k)], v[k]));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = make_float2(0.f, 0.f);
         }
         if (!p.go_on) continue;
-        frame_patch<N, TR, true>(v, p, info.x, info.y, line, j);
+        if (m > 0) load_h(g_start);
+        if (live) {
+            frame_patch<N, TR, true>(v, p, info.x, info.y, line, j);
+            if (m > 0) prop_axis<N, true>(v, s_tw, xb, h_start, j);
+        }
         if (m > 0) {
-            load_h(g_start);
-            prop_axis<N, true>(v, s_tw, xb, h_start, j);
             store_other<N, false>(v, p.A_out + (size_t)b * NA, Apitch<N>::P, l0, s_line, lloc, j, xbuf);
         } else if (p.probe_patch && valid) {
             gstore<N, true, false>(v, p.probe_patch + (size_t)b * NN, line, j);
