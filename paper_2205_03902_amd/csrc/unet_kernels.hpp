@@ -94,10 +94,10 @@ __device__ __forceinline__ void kpos_init(KPos &s, int k, const Gather &g)
     s.v = s.tap - s.u * g.kw;
 }
 
-__device__ __forceinline__ void kpos_advance(KPos &s, const Gather &g)
+__device__ __forceinline__ void kpos_advance(KPos &s, const Gather &g, int step = kBK)
 {
     const int C = g.c0 + g.c1;
-    s.ch += kBK;
+    s.ch += step;
     while (s.ch >= C) {
         s.ch -= C;
         ++s.tap;
@@ -130,17 +130,18 @@ __device__ __forceinline__ long long dest_pixel(const OutMap &o, int b, int y, i
     return ((long long)((b << o.hd_log) + y * o.ostride + ty) << o.wd_log) + x * o.ostride + tx;
 }
 
-template <int FM, int FN>
+// One pipeline step of BK columns of K, in K order (16 at a time), from LDS rows of LDK bf16.
+template <int FM, int FN, int BK = kBK, int LDK = kLDK>
 __device__ __forceinline__ void mfma_step(f32x16 (&acc)[FM][FN], const uint16_t *sa, const uint16_t *sb, int lane)
 {
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
+    for (int kk = 0; kk < BK / 16; ++kk) {
         bf16x8 fa[FM], fb[FN];
-        const int off = (lane & 31) * kLDK + kk * 16 + (lane >> 5) * 8;
+        const int off = (lane & 31) * LDK + kk * 16 + (lane >> 5) * 8;
 #pragma unroll
-        for (int i = 0; i < FM; ++i) fa[i] = *reinterpret_cast<const bf16x8 *>(sa + i * 32 * kLDK + off);
+        for (int i = 0; i < FM; ++i) fa[i] = *reinterpret_cast<const bf16x8 *>(sa + i * 32 * LDK + off);
 #pragma unroll
-        for (int j = 0; j < FN; ++j) fb[j] = *reinterpret_cast<const bf16x8 *>(sb + j * 32 * kLDK + off);
+        for (int j = 0; j < FN; ++j) fb[j] = *reinterpret_cast<const bf16x8 *>(sb + j * 32 * LDK + off);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -151,28 +152,32 @@ __device__ __forceinline__ void mfma_step(f32x16 (&acc)[FM][FN], const uint16_t 
 
 // One BM x BN output tile per workgroup; WM x WN wavefronts, each a (BM/WM) x (BN/WN) sub-tile
 // of 32 x 32 matrix-core blocks.  Two LDS stages: the global loads of step s+1 are in flight
-// while step s runs on the matrix cores.
-template <int BM, int BN, int WM, int WN>
+// while step s runs on the matrix cores.  BK columns of K a step (kpad a multiple of BK): 64
+// gives each barrier twice the matrix-core work of 32, with the same products in the same order.
+template <int BM, int BN, int WM, int WN, int BK = kBK>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(const GemmArgs a)
 {
     constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
-    constexpr int CA = BM * 4 / kThreads;                 // A chunks (16 B) per thread
-    constexpr int NB = BN * 4;                            // B chunks per tile
+    constexpr int LDK = BK + 8;                           // LDS row stride (bf16): 16 B past a multiple of 64 B
+    constexpr int KC = BK / 8;                            // 16-byte chunks of a row per step
+    constexpr int RP = kThreads / KC;                     // rows the workgroup fills per pass
+    constexpr int CA = BM / RP;                           // A chunks per thread
+    constexpr int NB = BN * KC;                           // B chunks per tile
     constexpr int CB = (NB + kThreads - 1) / kThreads;
-    static_assert(WM * WN == 4 && TM % 32 == 0 && TN % 32 == 0 && CA >= 1, "tile shape");
-    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * kLDK];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * kLDK];
+    static_assert(WM * WN == 4 && TM % 32 == 0 && TN % 32 == 0 && CA >= 1 && BM % RP == 0, "tile shape");
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * LDK];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const int kc = tid & 3;
+    const int kc = tid % KC;
 
     int ab[CA], ay[CA], ax[CA];
     bool aok[CA];
 #pragma unroll
     for (int i = 0; i < CA; ++i) {
-        const int m = m0 + (tid >> 2) + 64 * i;
+        const int m = m0 + tid / KC + RP * i;
         int b, y, x;
         decode(m, a.r.ho_log, a.r.wo_log, b, y, x);
         aok[i] = m < a.r.m_total;
@@ -190,20 +195,20 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const GemmArgs a)
 #pragma unroll
         for (int i = 0; i < CB; ++i) {
             const int q = tid + kThreads * i;
-            const int n = n0 + (q >> 2);
+            const int n = n0 + q / KC;
             rb[i] = make_uint4(0u, 0u, 0u, 0u);
             if (q < NB && n < a.o.n_total)
-                rb[i] = *reinterpret_cast<const uint4 *>(a.w + (long long)n * a.kpad + step * kBK + (q & 3) * 8);
+                rb[i] = *reinterpret_cast<const uint4 *>(a.w + (long long)n * a.kpad + step * BK + (q % KC) * 8);
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < CA; ++i)
-            *reinterpret_cast<uint4 *>(&sA[buf][((tid >> 2) + 64 * i) * kLDK + kc * 8]) = ra[i];
+            *reinterpret_cast<uint4 *>(&sA[buf][(tid / KC + RP * i) * LDK + kc * 8]) = ra[i];
 #pragma unroll
         for (int i = 0; i < CB; ++i) {
             const int q = tid + kThreads * i;
-            if (q < NB) *reinterpret_cast<uint4 *>(&sB[buf][(q >> 2) * kLDK + (q & 3) * 8]) = rb[i];
+            if (q < NB) *reinterpret_cast<uint4 *>(&sB[buf][(q / KC) * LDK + (q % KC) * 8]) = rb[i];
         }
     };
 
@@ -215,17 +220,17 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const GemmArgs a)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
 
-    const int nsteps = a.kpad / kBK;
+    const int nsteps = a.kpad / BK;
     load(0);
     store(0);
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
         const int cur = s & 1;
         if (s + 1 < nsteps) {
-            kpos_advance(kp, a.g);
+            kpos_advance(kp, a.g, BK);
             load(s + 1);
         }
-        mfma_step<FM, FN>(acc, &sA[cur][wm * TM * kLDK], &sB[cur][wn * TN * kLDK], lane);
+        mfma_step<FM, FN, BK, LDK>(acc, &sA[cur][wm * TM * LDK], &sB[cur][wn * TN * LDK], lane);
         if (s + 1 < nsteps) store(cur ^ 1);
         __syncthreads();
     }

@@ -223,18 +223,29 @@ void gemm(const GemmArgs &a, hipStream_t st)
 {
     const long long M = a.r.m_total;
     const int N = a.o.n_total;
+    const long long g128 = cdiv(M, 128) * cdiv(N, 128), g64 = cdiv(M, 128) * cdiv(N, 64);
+    // K steps of 64 give each barrier twice the matrix-core work of 32 (the same products in the
+    // same order) but hold 55-74 KB of LDS, two workgroups a CU: they pay where the grid fits in
+    // one round of those (the 64^2 and 32^2 levels at batch 16: forward 0.855 -> 0.815 ms), not
+    // where it takes several (the 128^2 GEMM: 0.815 -> 0.828 ms)
+    const bool k64 = a.kpad % 64 == 0 && a.o.ostride == 1;
+    const dim3 grid64((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 64)), grid128((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 128));
     if (N <= 32) {
         gemm_kernel<128, 32, 4, 1><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 32)), kThreads, 0, st>>>(a);
     } else if (N <= 64) {
-        gemm_kernel<128, 64, 2, 2><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 64)), kThreads, 0, st>>>(a);
-    } else if (cdiv(M, 128) * cdiv(N, 128) < 1024 || a.o.ostride > 1) {
+        gemm_kernel<128, 64, 2, 2><<<grid64, kThreads, 0, st>>>(a);
+    } else if (k64 && g128 > 256 && g128 <= 512) {
+        gemm_kernel<128, 128, 2, 2, 64><<<grid128, kThreads, 0, st>>>(a);
+    } else if (k64 && g64 <= 512) {
+        gemm_kernel<128, 64, 2, 2, 64><<<grid64, kThreads, 0, st>>>(a);
+    } else if (g128 < 1024 || a.o.ostride > 1) {
         // the coarse levels: 128 x 64 tiles double the workgroups of a grid that would leave CUs
         // with one or two (the same sums: each output's K order does not depend on the tiling);
         // the transposed convolutions (K of 64 to 256, a few steps a tile) likewise: 1 % of the
         // forward at batch 16
-        gemm_kernel<128, 64, 2, 2><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 64)), kThreads, 0, st>>>(a);
+        gemm_kernel<128, 64, 2, 2><<<grid64, kThreads, 0, st>>>(a);
     } else {
-        gemm_kernel<128, 128, 2, 2><<<dim3((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 128)), kThreads, 0, st>>>(a);
+        gemm_kernel<128, 128, 2, 2><<<grid128, kThreads, 0, st>>>(a);
     }
 }
 
