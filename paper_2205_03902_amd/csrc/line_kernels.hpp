@@ -250,6 +250,15 @@ __device__ __forceinline__ void frame_patch(float2 (&v)[16], const LineParams &p
     else apply_patch<N, true, CONJ>(v, p.slices + (size_t)p.m * hw, p.H, p.W, oy, ox, line, j);
 }
 
+// The transmission values of frame_patch, loaded ahead of their use.
+template <int N, bool TR>
+__device__ __forceinline__ void frame_load(float2 (&t)[16], const LineParams &p, int oy, int ox, int line, int j)
+{
+    const size_t hw = (size_t)p.H * p.W;
+    if (TR) load_patch<N, true>(t, p.slices_t + (size_t)(p.m / 2) * hw, p.W, p.H, ox, oy, line, j);
+    else load_patch<N, true>(t, p.slices + (size_t)p.m * hw, p.H, p.W, oy, ox, line, j);
+}
+
 // ---- the half-propagated windows A ----
 //
 // A window written for a launch of frame F holds its line l (N lines) in a row of N + 16 elements,
@@ -374,6 +383,10 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
 
     float2 v[16];
     if (stage == kStageForward) {
+        // the transmission of slice m on these lines, loaded before the propagation that it
+        // follows so that the loads' latency passes during it
+        float2 tv[16];
+        if (!p.stop_after_psi) frame_load<N, TR>(tv, p, oy, ox, line, j);
         // ---- psi_m: the probe (m = 0, natural frame), a stored wave, or the propagation of gap
         // m-1 finished along this launch's lines ----
         if (m == 0) {
@@ -392,7 +405,7 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
             for (int i = 0; i < 16; ++i) o[l2 * N + Wn::nat(j2, i)] = cabs2(v[i]);
         }
         if (p.stop_after_psi) return;
-        frame_patch<N, TR, false>(v, p, oy, ox, line, j);
+        mul_patch<false>(v, tv);
         if (m + 1 < M) {
             next_h();
             prop_axis<N, false>(v, s_tw, xb, s_h, j);
@@ -410,10 +423,32 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
     }
 
     if (stage == kStageFar) {
-        // line index = frequency along the other axis (natural); FFT along these lines
+        // line index = frequency along the other axis (natural); FFT along these lines.  The
+        // measured values of the line are loaded first, so that their latency passes during the
+        // FFT (whose wavefront fences keep the compiler from moving loads across it).
         aload<N, false>(v, A_in, line, j, s_elem);
-        line_fft_fwd<N>(v, s_tw, xb, j);
         const float *meas = p.measured + (size_t)s * NN;
+        float mv[16];
+        if (p.mode != kForward) {
+            if constexpr (TR) {
+                // the measured column of this line through the tile (lines outside read a clamped
+                // one); each line's values come back from its own exchange slot, which its
+                // wavefront's FFT then reuses
+                tile_fill<N>(xbuf, [&](int r, int c) {
+                    const int cc = min(max(l0 + c, 0), N - 1);
+                    return make_float2(meas[r * N + cc], 0.0f);
+                });
+                float2 t[16];
+                tile_get<N, true>(t, xbuf, lloc, j);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) mv[i] = t[i].x;
+            } else {
+                const int l2 = opaque(line), j2 = opaque(j);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) mv[i] = meas[l2 * N + Wn::spec(j2, i)];
+            }
+        }
+        line_fft_fwd<N>(v, s_tw, xb, j);
         if (p.mode == kForward) {
             float *I = p.intensity + (size_t)s * NN;
             if constexpr (TR) {
@@ -425,22 +460,7 @@ __global__ __launch_bounds__(kLinesPerGroup * Win<N>::R, 4) void line_kernel(Lin
             }
             return;
         }
-        double part;
-        if constexpr (TR) {
-            // the measured column of this line through the tile (lines outside read a clamped one)
-            tile_fill<N>(xbuf, [&](int r, int c) {
-                const int cc = min(max(l0 + c, 0), N - 1);
-                return make_float2(meas[r * N + cc], 0.0f);
-            });
-            float2 t[16];
-            tile_get<N, true>(t, xbuf, lloc, j);
-            float mv[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) mv[i] = t[i].x;
-            part = residual_vals<N>(v, mv, p.objective);
-        } else {
-            part = residual<N, true>(v, meas, line, j, p.objective);
-        }
+        const double part = residual_vals<N>(v, mv, p.objective);
         double tot = group_sum<N>(valid ? part : 0.0, red);
         if (tid == 0) p.loss_part[(size_t)b * gridDim.x + blockIdx.x] = tot;
         line_fft_inv<N>(v, s_tw, xb, j);
