@@ -240,23 +240,26 @@ __device__ __forceinline__ double group_sum(double x, double *red)
     return t;
 }
 
-// Transmission by slice m (or its conjugate) on this launch's lines, with wrap-around: rows of
-// the slice (even m) or of its transposed copy (odd m), whose rows are the slice's columns.
-template <int N, bool TR, bool CONJ>
-__device__ __forceinline__ void frame_patch(float2 (&v)[16], const LineParams &p, int oy, int ox, int line, int j)
-{
-    const size_t hw = (size_t)p.H * p.W;
-    if (TR) apply_patch<N, true, CONJ>(v, p.slices_t + (size_t)(p.m / 2) * hw, p.W, p.H, ox, oy, line, j);
-    else apply_patch<N, true, CONJ>(v, p.slices + (size_t)p.m * hw, p.H, p.W, oy, ox, line, j);
-}
-
-// The transmission values of frame_patch, loaded ahead of their use.
+// Transmission of slice m on this launch's lines, with wrap-around: rows of the slice (even m) or
+// of its transposed copy (odd m), whose rows are the slice's columns.  A window inside the object
+// (no index wraps; the same for every lane of a position) takes the loads at a per-lane base plus
+// constant steps.
 template <int N, bool TR>
 __device__ __forceinline__ void frame_load(float2 (&t)[16], const LineParams &p, int oy, int ox, int line, int j)
 {
     const size_t hw = (size_t)p.H * p.W;
-    if (TR) load_patch<N, true>(t, p.slices_t + (size_t)(p.m / 2) * hw, p.W, p.H, ox, oy, line, j);
-    else load_patch<N, true>(t, p.slices + (size_t)p.m * hw, p.H, p.W, oy, ox, line, j);
+    const bool inside = oy + N <= p.H && ox + N <= p.W;
+    if (TR) load_patch<N, true>(t, p.slices_t + (size_t)(p.m / 2) * hw, p.W, p.H, ox, oy, line, j, inside);
+    else load_patch<N, true>(t, p.slices + (size_t)p.m * hw, p.H, p.W, oy, ox, line, j, inside);
+}
+
+// v *= the transmission (or its conjugate).
+template <int N, bool TR, bool CONJ>
+__device__ __forceinline__ void frame_patch(float2 (&v)[16], const LineParams &p, int oy, int ox, int line, int j)
+{
+    float2 t[16];
+    frame_load<N, TR>(t, p, oy, ox, line, j);
+    mul_patch<CONJ>(v, t);
 }
 
 // ---- the half-propagated windows A ----
