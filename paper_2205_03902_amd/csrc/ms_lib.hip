@@ -124,6 +124,11 @@ Chunking chunking(int64_t count)
     return c;
 }
 
+// Chunk partial planes a scatter of a batch of B positions may write per slice: the chunks of any
+// list of at most B entries (positions or bands).  chunking(B).nch can be fewer: 9 for B = 17,
+// whose 16 bands would take 16.
+int partial_chunks(int64_t B) { return (int)std::min<int64_t>(std::max<int64_t>(B, 1), kChunks); }
+
 void derive_positions(const ms_problem *pb, HostPlan &hp)
 {
     hp.n = pb->n; hp.H = pb->obj_h; hp.W = pb->obj_w; hp.M = pb->n_slices; hp.S = pb->n_pos;
@@ -535,8 +540,9 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     L.sub_class_off = take(nb * kChunks * (C + 1) * 4);
     L.sub_class_list = take(S * 4);
     // chunk partials of the slices one scatter takes: all M at once, or one at a time when the
-    // waves are recomputed slice by slice
-    const size_t nch = (size_t)chunking(B).nch, scattered = hp.K > 1 ? 1 : M;
+    // waves are recomputed slice by slice; a batch's band lists may have more chunks than its
+    // position lists (at most min(B, 16))
+    const size_t nch = (size_t)partial_chunks(B), scattered = hp.K > 1 ? 1 : M;
     L.spart = take(nch * scattered * HW * 8);
     L.wpart = take(nch * scattered * HW * 4);
     L.cpart = take(nch * C * NN * 8);
