@@ -82,8 +82,9 @@ def traffic_file(geo, family: str) -> str:
 
 
 def traffic_record(geo, family: str):
-    """HBM bytes per pass of the per-position kernels, measured with rocprofv3 counters on this
-    workload and on the current kernel sources; None for any other workload, path or source."""
+    """The counter record of the per-position kernels (HBM bytes per pass, and where measured the
+    VALU instructions per pass), taken with rocprofv3 on this workload and on the current kernel
+    sources; None for any other workload, path or source."""
     try:
         with open(traffic_file(geo, family)) as fh:
             rec = json.load(fh)
@@ -93,7 +94,7 @@ def traffic_record(geo, family: str):
         return None
     if rec.get("kernel_source_hash") != kernel_source_hash(family):
         return None
-    return rec.get("bytes_per_pass")
+    return rec
 
 
 def cpu_baseline(geo, n_sample: int, truth=None):
@@ -359,7 +360,15 @@ def roofline(geo, family: str, kernel_ms: float):
     alu["frac"] = alu["achieved"] / alu["peak"]
     roof = dict(alu if alu["frac"] >= hbm["frac"] else hbm)
     other = hbm if roof["bound"] == "alu" else alu
-    roof["traffic"] = traffic_record(geo, family)
+    rec = traffic_record(geo, family)
+    roof["traffic"] = rec.get("bytes_per_pass") if rec else None
+    if roof["traffic"]:
+        # the counted bytes over this run's kernel time: the achieved HBM rate
+        roof["traffic_GB_s"] = roof["traffic"] / k_s / 1e9
+    if rec and rec.get("valu_issue_ms_per_pass"):
+        # the share of the kernel time the counted VALU instructions alone take at one 4-cycle
+        # issue per wave64 instruction on 1024 SIMDs at 2.4 GHz (FP32 VALU utilisation)
+        roof["valu_issue_frac"] = rec["valu_issue_ms_per_pass"] / kernel_ms
     if family == "fused":
         roof["kernel"] = f"fused_kernel<{geo.n}, adjoint> (one launch per pass)"
     else:
