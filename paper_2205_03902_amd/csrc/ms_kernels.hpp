@@ -516,10 +516,15 @@ __global__ __launch_bounds__(Win<N>::NT) __attribute__((amdgpu_waves_per_eu(4)))
 // pixel and in ascending position order, the patches of the chunk's windows that touch
 // the tile; pass 2 adds the chunk partials in chunk order.  The order is fixed by the
 // plan, so results are reproducible bit for bit.
-// Scatter tile: 16 x 16 pixels, one 256-lane block.  Lanes run along x for images stored in the
-// natural layout and along y for transposed ones, so that either reads 128-byte pieces.
+// Scatter tiles, one 256-lane block each.  16 x 16 pixels where images may be stored transposed
+// (the line path): lanes run along x for images in the natural layout and along y for transposed
+// ones, so that either reads 128-byte pieces.  64 x 4 pixels where every image is in the natural
+// layout (the fused path): a lane row reads 512 contiguous bytes, so a window that starts off a
+// 128-byte boundary over-fetches a quarter of a row rather than a whole row.
 constexpr int kTileW = 16;
 constexpr int kTileH = 16;
+constexpr int kWideW = 64;
+constexpr int kWideH = 4;
 constexpr int kChunks = 16;  // chunks per batch
 constexpr int kUnroll = 8;   // patch loads in flight per lane
 
@@ -544,14 +549,17 @@ struct ScatterParams {
     int nch, cpb;               // chunks of the batch; consecutive chunks summed per block
 };
 
+template <int TW, int TH>
 __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
 {
+    static_assert(TW * TH == 256, "one lane a pixel");
     const int t = blockIdx.x, grp = blockIdx.y, mi = blockIdx.z, n_m = gridDim.z;
     const bool odd = ((p.m0 + mi) & 1) != 0;
-    const bool trans = (odd ? p.trans1 : p.trans0) != 0;
-    const int ta = (int)(threadIdx.x / 16), tb = (int)(threadIdx.x % 16);
-    const int y = (t / p.tiles_x) * kTileH + (trans ? tb : ta);
-    const int x = (t % p.tiles_x) * kTileW + (trans ? ta : tb);
+    // transposed images only with square tiles
+    const bool trans = TW == TH && (odd ? p.trans1 : p.trans0) != 0;
+    const int ta = (int)(threadIdx.x / TW), tb = (int)(threadIdx.x % TW);
+    const int y = (t / p.tiles_x) * TH + (trans ? tb : ta);
+    const int x = (t % p.tiles_x) * TW + (trans ? ta : tb);
     const bool inside = y < p.H && x < p.W;
     const size_t NN = (size_t)p.N * p.N;
     const int *tile_off = odd ? p.tile_off1 : p.tile_off0;
@@ -602,17 +610,19 @@ __global__ __launch_bounds__(256) void scatter_partial_kernel(ScatterParams p)
     }
     const size_t HW = (size_t)p.H * p.W;
     int yo = y, xo = x;
-    if (trans) {
-        // back to lanes along x for the partial planes (natural layout)
-        __shared__ float2 sacc[kTileH][kTileW + 1];
-        __shared__ float swacc[kTileH][kTileW + 1];
-        sacc[tb][ta] = acc;
-        swacc[tb][ta] = wacc;
-        __syncthreads();
-        acc = sacc[ta][tb];
-        wacc = swacc[ta][tb];
-        yo = (t / p.tiles_x) * kTileH + ta;
-        xo = (t % p.tiles_x) * kTileW + tb;
+    if constexpr (TW == TH) {
+        if (trans) {
+            // back to lanes along x for the partial planes (natural layout)
+            __shared__ float2 sacc[TH][TW + 1];
+            __shared__ float swacc[TH][TW + 1];
+            sacc[tb][ta] = acc;
+            swacc[tb][ta] = wacc;
+            __syncthreads();
+            acc = sacc[ta][tb];
+            wacc = swacc[ta][tb];
+            yo = (t / p.tiles_x) * TH + ta;
+            xo = (t % p.tiles_x) * TW + tb;
+        }
     }
     if (yo >= p.H || xo >= p.W) return;
     const size_t pix = (size_t)yo * p.W + xo;

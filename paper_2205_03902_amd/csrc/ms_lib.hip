@@ -82,15 +82,19 @@ struct HostPlan {
     int K = 1;                                // incident waves stored every K slices (1: all)
     int64_t S = 0, B = 0;
     int nb = 0, tiles_x = 0, tiles_y = 0, n_tiles = 0;
+    // 64 x 4 scatter tiles for the fused path's patches (natural layout), where that path exists
+    bool wide = false;
+    int wtiles_x = 0, wtiles_y = 0, n_wtiles = 0;
     std::vector<int4> pos_info;
     std::vector<double> cls_fy, cls_fx;
     std::vector<double> dz_unique;            // distinct slice distances
     std::vector<int> gap_table;               // M - 1 entries: index into dz_unique
     // Scatter lists.  Each batch is cut into at most kChunks chunks of consecutive
     // positions; per (batch, chunk, tile) the entries (batch-local s, origin y, origin x)
-    // of the windows that touch the tile, per (batch, chunk, class) its positions.
-    std::vector<int> tile_off;                // nb x kChunks x (n_tiles + 1), absolute offsets
-    std::vector<int4> tile_list;
+    // of the windows that touch the tile, per (batch, chunk, class) its positions.  The lists of
+    // 16 x 16 tiles, then (wide) those of 64 x 4 tiles, back to back.
+    std::vector<int> tile_off;                // nb x kChunks x (n_tiles + 1) [+ nb x kChunks x (n_wtiles + 1)]
+    std::vector<int4> tile_list;              // entries of both, the offsets absolute
     std::vector<int> class_off, class_list;   // nb x kChunks x (C + 1), absolute offsets
     // Band sums of the line path's gradient patches (line_band_kernel).  Orientation o = 0: even
     // slices (natural frame), bands of one origin x ordered by origin y; o = 1: odd slices
@@ -135,6 +139,10 @@ void derive_positions(const ms_problem *pb, HostPlan &hp)
     hp.tiles_y = (hp.H + kTileH - 1) / kTileH;
     hp.tiles_x = (hp.W + kTileW - 1) / kTileW;
     hp.n_tiles = hp.tiles_y * hp.tiles_x;
+    hp.wide = hp.n <= 128;
+    hp.wtiles_y = hp.wide ? (hp.H + kWideH - 1) / kWideH : 0;
+    hp.wtiles_x = hp.wide ? (hp.W + kWideW - 1) / kWideW : 0;
+    hp.n_wtiles = hp.wtiles_y * hp.wtiles_x;
     hp.pos_info.resize(hp.S);
     std::map<std::pair<double, double>, int> classes;
     for (int64_t s = 0; s < hp.S; ++s) {
@@ -184,43 +192,54 @@ int table_capacity(int n)
 
 bool too_many_classes(const HostPlan &hp) { return hp.C > kMaxClasses; }
 
+// A tiling of the object for the scatter: tiles of tw x th pixels, tiles_x a row.
+struct Tiling {
+    int tw, th, tiles_x, tiles_y, n_tiles;
+};
+Tiling square_tiles(const HostPlan &hp) { return {kTileW, kTileH, hp.tiles_x, hp.tiles_y, hp.n_tiles}; }
+Tiling wide_tiles(const HostPlan &hp) { return {kWideW, kWideH, hp.wtiles_x, hp.wtiles_y, hp.n_wtiles}; }
+
 // Tiles (row-major) covered by the window of one position.
-void window_tiles(const HostPlan &hp, const int4 &info, std::vector<int> &rows, std::vector<int> &cols,
-                  std::vector<char> &mark_y, std::vector<char> &mark_x)
+void window_tiles(const HostPlan &hp, const Tiling &tg, const int4 &info, std::vector<int> &rows,
+                  std::vector<int> &cols, std::vector<char> &mark_y, std::vector<char> &mark_x)
 {
     rows.clear(); cols.clear();
     std::fill(mark_y.begin(), mark_y.end(), 0);
     std::fill(mark_x.begin(), mark_x.end(), 0);
     for (int i = 0; i < hp.n; ++i) {
-        int ty = ((info.x + i) % hp.H) / kTileH;
+        int ty = ((info.x + i) % hp.H) / tg.th;
         if (!mark_y[ty]) { mark_y[ty] = 1; rows.push_back(ty); }
-        int tx = ((info.y + i) % hp.W) / kTileW;
+        int tx = ((info.y + i) % hp.W) / tg.tw;
         if (!mark_x[tx]) { mark_x[tx] = 1; cols.push_back(tx); }
     }
 }
 
-void build_lists(HostPlan &hp, int64_t B)
+// The position lists of tiling tg appended to hp.tile_off / hp.tile_list (offsets absolute), and
+// with classes also the class lists.
+void append_lists(HostPlan &hp, const Tiling &tg, bool classes)
 {
-    hp.B = B;
-    hp.nb = (int)((hp.S + B - 1) / B);
+    const int64_t B = hp.B;
     std::vector<int> rows, cols;
-    std::vector<char> my(hp.tiles_y), mx(hp.tiles_x);
+    std::vector<char> my(tg.tiles_y), mx(tg.tiles_x);
     std::vector<std::vector<int>> per_pos(hp.S);
     size_t total = 0;
     for (int64_t s = 0; s < hp.S; ++s) {
-        window_tiles(hp, hp.pos_info[s], rows, cols, my, mx);
+        window_tiles(hp, tg, hp.pos_info[s], rows, cols, my, mx);
         per_pos[s].reserve(rows.size() * cols.size());
         for (int ty : rows)
-            for (int tx : cols) per_pos[s].push_back(ty * hp.tiles_x + tx);
+            for (int tx : cols) per_pos[s].push_back(ty * tg.tiles_x + tx);
         total += per_pos[s].size();
     }
-    const size_t tstride = (size_t)hp.n_tiles + 1, cstride = (size_t)hp.C + 1;
-    hp.tile_off.assign((size_t)hp.nb * kChunks * tstride, 0);
-    hp.class_off.assign((size_t)hp.nb * kChunks * cstride, 0);
-    hp.tile_list.assign(total, make_int4(0, 0, 0, 0));
-    hp.class_list.assign(hp.S, 0);
-    int base = 0, cbase = 0;
-    std::vector<int> cnt(hp.n_tiles), ccnt(hp.C);
+    const size_t tstride = (size_t)tg.n_tiles + 1, cstride = (size_t)hp.C + 1;
+    const size_t off0 = hp.tile_off.size(), list0 = hp.tile_list.size();
+    hp.tile_off.resize(off0 + (size_t)hp.nb * kChunks * tstride, 0);
+    hp.tile_list.resize(list0 + total, make_int4(0, 0, 0, 0));
+    if (classes) {
+        hp.class_off.assign((size_t)hp.nb * kChunks * cstride, 0);
+        hp.class_list.assign(hp.S, 0);
+    }
+    int base = (int)list0, cbase = 0;
+    std::vector<int> cnt(tg.n_tiles), ccnt(hp.C);
     for (int b = 0; b < hp.nb; ++b) {
         const int64_t s0 = (int64_t)b * B, count = std::min(hp.S, s0 + B) - s0;
         const Chunking ch = chunking(count);
@@ -233,32 +252,48 @@ void build_lists(HostPlan &hp, int64_t B)
                 for (int t : per_pos[s0 + a]) cnt[t]++;
                 ccnt[hp.pos_info[s0 + a].z]++;
             }
-            int *off = &hp.tile_off[((size_t)b * kChunks + c) * tstride];
+            int *off = &hp.tile_off[off0 + ((size_t)b * kChunks + c) * tstride];
             off[0] = base;
-            for (int t = 0; t < hp.n_tiles; ++t) off[t + 1] = off[t] + cnt[t];
-            int *coff = &hp.class_off[((size_t)b * kChunks + c) * cstride];
-            coff[0] = cbase;
-            for (int k = 0; k < hp.C; ++k) coff[k + 1] = coff[k] + ccnt[k];
-            std::vector<int> cur(off, off + hp.n_tiles), ccur(coff, coff + hp.C);
+            for (int t = 0; t < tg.n_tiles; ++t) off[t + 1] = off[t] + cnt[t];
+            std::vector<int> cur(off, off + tg.n_tiles);
             for (int64_t a = a0; a < a1; ++a) {
                 const int4 info = hp.pos_info[s0 + a];
                 for (int t : per_pos[s0 + a]) hp.tile_list[cur[t]++] = make_int4((int)a, info.x, info.y, 0);
-                hp.class_list[ccur[info.z]++] = (int)a;
             }
-            base = off[hp.n_tiles];
+            base = off[tg.n_tiles];
+            if (!classes) continue;
+            int *coff = &hp.class_off[((size_t)b * kChunks + c) * cstride];
+            coff[0] = cbase;
+            for (int k = 0; k < hp.C; ++k) coff[k + 1] = coff[k] + ccnt[k];
+            std::vector<int> ccur(coff, coff + hp.C);
+            for (int64_t a = a0; a < a1; ++a) hp.class_list[ccur[hp.pos_info[s0 + a].z]++] = (int)a;
             cbase = coff[hp.C];
         }
     }
 }
 
+void build_lists(HostPlan &hp, int64_t B)
+{
+    hp.B = B;
+    hp.nb = (int)((hp.S + B - 1) / B);
+    hp.tile_off.clear();
+    hp.tile_list.clear();
+    append_lists(hp, square_tiles(hp), true);
+    if (hp.wide) append_lists(hp, wide_tiles(hp), false);
+}
+
+// Entries of the position lists of both tilings.
 size_t tile_entries(const HostPlan &hp)
 {
     std::vector<int> rows, cols;
-    std::vector<char> my(hp.tiles_y), mx(hp.tiles_x);
     size_t total = 0;
-    for (int64_t s = 0; s < hp.S; ++s) {
-        window_tiles(hp, hp.pos_info[s], rows, cols, my, mx);
-        total += rows.size() * cols.size();
+    for (int w = 0; w < (hp.wide ? 2 : 1); ++w) {
+        const Tiling tg = w ? wide_tiles(hp) : square_tiles(hp);
+        std::vector<char> my(tg.tiles_y), mx(tg.tiles_x);
+        for (int64_t s = 0; s < hp.S; ++s) {
+            window_tiles(hp, tg, hp.pos_info[s], rows, cols, my, mx);
+            total += rows.size() * cols.size();
+        }
     }
     return total;
 }
@@ -533,7 +568,7 @@ Layout make_layout(const HostPlan &hp, int64_t B, size_t n_entries)
     L.full_w = take(M * HW * 4);
     L.maxw_all = take(M * 4);
     L.mu_all = take(M * 8);
-    L.tile_off = take(nb * kChunks * (hp.n_tiles + 1) * 4);
+    L.tile_off = take(nb * kChunks * ((size_t)hp.n_tiles + 1 + (hp.wide ? (size_t)hp.n_wtiles + 1 : 0)) * 4);
     L.tile_list = take(n_entries * 16);
     L.class_off = take(nb * kChunks * (C + 1) * 4);
     L.class_list = take(S * 4);
@@ -658,6 +693,14 @@ struct ms_plan {
         const long long n = hp.n;
         return lines && keep_windows && hp.K == 1 && hp.M > 1 && bands_active(0) && bands_active(1) &&
                (hp.M - 1) * n * (n + 16) <= hp.M * n * n;
+    }
+    // the fused path scatters its patches (natural layout) over 64 x 4 tiles
+    bool wide_scatter() const { return !lines && hp.wide; }
+    // offset of batch b's position-list offsets of the square (or the wide) tiling
+    size_t tile_off_at(int b, bool wide) const
+    {
+        const size_t sq = (size_t)hp.nb * kChunks * (hp.n_tiles + 1);
+        return wide ? sq + (size_t)b * kChunks * (hp.n_wtiles + 1) : (size_t)b * kChunks * (hp.n_tiles + 1);
     }
     long long band_stride() const { return (long long)band_elems(hp); }
     long long band_slice_stride() const { return (long long)hp.band_count * band_stride(); }
@@ -1133,21 +1176,23 @@ int grid_for(long long count) { return (int)std::max<long long>(1, std::min<long
 
 // Pass 1 over nch chunks of images and pass 2 (chunk partials in order) for n_m slices.
 void scatter_launch(ms_plan *p, ScatterParams &sp, int nch, int n_m, float2 *out, float *wout, int accumulate,
-                    hipStream_t st)
+                    hipStream_t st, bool wide)
 {
     const HostPlan &hp = p->hp;
+    const Tiling tg = wide ? wide_tiles(hp) : square_tiles(hp);
     sp.partial = p->at<float2>(p->L.spart);
     sp.wpartial = wout ? p->at<float>(p->L.wpart) : nullptr;
-    sp.H = hp.H; sp.W = hp.W; sp.N = hp.n; sp.tiles_x = hp.tiles_x; sp.n_tiles = hp.n_tiles;
+    sp.H = hp.H; sp.W = hp.W; sp.N = hp.n; sp.tiles_x = tg.tiles_x; sp.n_tiles = tg.n_tiles;
     // Consecutive chunks are summed in one block (in ascending order, as one longer chunk) while
     // the grid keeps about kScatterBlocks blocks: fewer partial planes to write and reduce when
     // many slices are scattered at once.
-    const long long per_group = (long long)hp.n_tiles * n_m;
+    const long long per_group = (long long)tg.n_tiles * n_m;
     const int groups = (int)std::min<long long>(nch, std::max<long long>(1, (kScatterBlocks + per_group - 1) / per_group));
     sp.nch = nch;
     sp.cpb = (nch + groups - 1) / groups;
     const int ngrp = (nch + sp.cpb - 1) / sp.cpb;
-    scatter_partial_kernel<<<dim3(hp.n_tiles, ngrp, n_m), 256, 0, st>>>(sp);
+    if (wide) scatter_partial_kernel<kWideW, kWideH><<<dim3(tg.n_tiles, ngrp, n_m), 256, 0, st>>>(sp);
+    else scatter_partial_kernel<kTileW, kTileH><<<dim3(tg.n_tiles, ngrp, n_m), 256, 0, st>>>(sp);
     const long long plane = (long long)n_m * hp.H * hp.W;
     chunk_reduce_kernel<float2><<<grid_for(plane), 256, 0, st>>>(sp.partial, ngrp, plane, out, accumulate);
     if (wout) {
@@ -1171,11 +1216,12 @@ void scatter(ms_plan *p, int b, int count, const float2 *patches, long long pos_
     sp.wpatch = wpatch;
     sp.pos_stride0 = sp.pos_stride1 = pos_stride;
     sp.slice_stride0 = sp.slice_stride1 = (long long)hp.n * hp.n;
-    sp.tile_off0 = sp.tile_off1 = p->at<int>(p->L.tile_off) + (size_t)b * kChunks * (hp.n_tiles + 1);
+    const bool wide = p->wide_scatter();
+    sp.tile_off0 = sp.tile_off1 = p->at<int>(p->L.tile_off) + p->tile_off_at(b, wide);
     sp.entries0 = sp.entries1 = p->at<int4>(p->L.tile_list);
     sp.ld0 = sp.ld1 = hp.n;
     sp.w_stride = w_stride;
-    scatter_launch(p, sp, chunking(count).nch, n_m, out, wout, accumulate, st);
+    scatter_launch(p, sp, chunking(count).nch, n_m, out, wout, accumulate, st, wide);
 }
 
 // Gradient images of batch b for slices m0 .. m0 + n_m - 1 into out (n_m x H x W): for each
@@ -1188,12 +1234,13 @@ void scatter_slices(ms_plan *p, int b, int count, const float2 *patches, long lo
     const HostPlan &hp = p->hp;
     ScatterParams sp{};
     const size_t toff = (size_t)b * kChunks * (hp.n_tiles + 1);
+    const bool wide = p->wide_scatter();     // no bands then: patches in the natural layout
     int nch = chunking(count).nch;
     for (int o = 0; o < 2; ++o) {
         // list o serves the slices m0 + i of parity o
         const float2 *img = patches;
         long long ps = pos_stride, ss = (long long)hp.n * hp.n;
-        const int *off = p->at<int>(p->L.tile_off) + toff;
+        const int *off = p->at<int>(p->L.tile_off) + p->tile_off_at(b, wide);
         const int4 *ent = p->at<int4>(p->L.tile_list);
         // the line path stores odd slices' images transposed
         const int trans = (p->lines && o == 1) ? 1 : 0;
@@ -1216,7 +1263,7 @@ void scatter_slices(ms_plan *p, int b, int count, const float2 *patches, long lo
         }
     }
     sp.m0 = m0;
-    scatter_launch(p, sp, nch, n_m, out, nullptr, accumulate, st);
+    scatter_launch(p, sp, nch, n_m, out, nullptr, accumulate, st, wide);
 }
 
 // Probe patches of one batch summed per shift class into class_acc (accumulate adds).
