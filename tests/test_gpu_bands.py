@@ -4,7 +4,8 @@ scan row, and the scatter reads band images.  Checked against the FP64
 oracle, against the per-position patches of the same plan, on a scan that wraps through the object
 edges (bands cut where their image would wrap onto itself), on fractional steps (shift classes) over
 an object whose side is not a multiple of 16, with recomputed waves, with batches, with the Poisson
-objective and tilted illumination, and at N = 256."""
+objective and tilted illumination, and at N = 256; and the forward chain's kept windows (psi_m
+finished again in the band launches) against the same plans storing the waves, at N = 64, 128, 256."""
 import numpy as np
 import pytest
 
@@ -34,6 +35,8 @@ def _geometry(name):
         return configs.small(n=64, obj=128, n_slices=3, scan=(12, 12), step_px=8.0, seed=6, defocus=25.0)
     if name == "raster256":     # N = 256, step 16
         return configs.small(n=256, obj=384, n_slices=3, scan=(5, 5), step_px=16.0, seed=7, defocus=25.0)
+    if name == "raster128":     # N = 128 on the line path, 6 slices (the kept windows fit up to 9)
+        return configs.small(n=128, obj=256, n_slices=6, scan=(6, 6), step_px=12.0, seed=10, defocus=25.0)
     if name == "frac100":       # fractional step over a 100^2 object, shifted so that windows wrap
         return configs.small(n=64, obj=100, n_slices=4, scan=(10, 10), step_px=8.5, seed=8, defocus=25.0)
     raise KeyError(name)
@@ -151,7 +154,7 @@ def test_bands_with_the_poisson_objective_and_tilt(dev, variant):
     assert rel(g1, g0) < TOL_REGROUP and np.array_equal(p1, p0) and abs(l1 - l0) <= 1e-12 * abs(l0)
 
 
-@pytest.mark.parametrize("name", ["raster64", "wrap64", "frac100", "raster256"])
+@pytest.mark.parametrize("name", ["raster64", "wrap64", "frac100", "raster128", "raster256"])
 def test_kept_windows_match_stored_waves(dev, name):
     """The forward chain keeps each launch's window and the band launches finish psi_m from it:
     the same gradients as with stored waves (to rounding), and the oracle's."""
