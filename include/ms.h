@@ -164,6 +164,19 @@ int32_t ms_plan_has_bands(const ms_plan *plan);
 ms_status ms_plan_set_kept_windows(ms_plan *plan, int32_t on);
 int32_t ms_plan_kept_windows(const ms_plan *plan);
 
+/* Incident waves carried between the layer steps of Algorithm 1 (Sec. 3.3) on the line path.
+ * ms_layer_step for layer l runs the forward chain (Sec. 2.1) from the probe through every slice;
+ * its incident wave psi_l depends only on the slices before l, and the step then updates slice l.
+ * With the carry on, the plan keeps psi_l after each layer step, and a following ms_layer_step for
+ * layer l (again) or l + 1 with the same probe, slices and measured buffers starts its chain from
+ * that wave, at launch l or l - 1, instead of from the probe: a sweep over M layers skips about
+ * M (M - 3) / 2 of its launches, with results bit for bit those of the full chain.  This relies on
+ * the caller changing none of those buffers between the calls other than through ms_layer_step
+ * (every other entry point that computes on the plan, or sets it up, drops the carried wave).  It
+ * applies on the line path with all positions in one batch.  on = 1: carry; 0 (the default): every
+ * layer step runs the whole chain. */
+ms_status ms_plan_set_layer_carry(ms_plan *plan, int32_t on);
+
 /* The data term of every loss, gradient and step of the plan.
  * MS_OBJECTIVE_AMPLITUDE (the default): L = sum (sqrt(I) - |Psi|)^2, the amplitude
  * flow of Sec. 3.2, residual Psi - sqrt(I) Psi / |Psi|.

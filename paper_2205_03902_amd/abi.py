@@ -25,7 +25,7 @@ MS_OBJECTIVE_AMPLITUDE, MS_OBJECTIVE_POISSON = 0, 1
 # every entry point declared in include/ms.h
 SYMBOLS = ("ms_workspace_size", "ms_plan_create", "ms_plan_destroy", "ms_plan_batch", "ms_plan_shift_classes",
            "ms_plan_checkpoint_every", "ms_plan_set_path", "ms_plan_set_bands", "ms_plan_has_bands",
-           "ms_plan_set_kept_windows", "ms_plan_kept_windows",
+           "ms_plan_set_kept_windows", "ms_plan_kept_windows", "ms_plan_set_layer_carry",
            "ms_plan_set_objective",
            "ms_make_probe", "ms_make_probe_aberrated", "ms_forward", "ms_adjoint", "ms_adjoint_scratch", "ms_layer_step", "ms_full_step", "ms_probe_step", "ms_position_grad", "ms_position_step", "ms_reconstruction_error",
            "ms_profile_begin",
@@ -79,6 +79,8 @@ def lib():
         L.ms_plan_set_kept_windows.argtypes = [P, I32]
         L.ms_plan_kept_windows.restype = I32
         L.ms_plan_kept_windows.argtypes = [P]
+        L.ms_plan_set_layer_carry.restype = I32
+        L.ms_plan_set_layer_carry.argtypes = [P, I32]
         L.ms_plan_set_objective.restype = I32
         L.ms_plan_set_objective.argtypes = [P, I32]
         L.ms_make_probe.restype = I32
@@ -309,6 +311,12 @@ class Plan:
         stores waves (see include/ms.h)."""
         _check(lib().ms_plan_set_kept_windows(self._h, int(on)), "ms_plan_set_kept_windows")
         self._kept_windows = int(on)
+
+    def set_layer_carry(self, on: int):
+        """1: layer steps carry the incident wave of their layer to the next step (line path, one
+        batch; the caller changes the probe, slices and measured data only through layer steps
+        in between); 0: every layer step runs the whole chain (see include/ms.h)."""
+        _check(lib().ms_plan_set_layer_carry(self._h, int(on)), "ms_plan_set_layer_carry")
 
     @property
     def kept_windows(self) -> bool:

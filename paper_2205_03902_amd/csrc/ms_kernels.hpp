@@ -54,6 +54,12 @@ struct FusedParams {
     int ck;                      // replay: psi_m stored for m = ck, 2 ck, ... (ck >= 2)
     int seg;                     // replay: the slice whose patch this launch writes (M - 1 first)
     float2 *park;                // replay: [count][N][N] adjoint state between launches
+    // line path, layer mode: the forward chain starts at launch chain_from (> 0: from the stored
+    // wave chain_wave, psi of that slice, per position wave_stride apart); carry: psi_layer goes to
+    // slot 1 of the waves and the patch to slot 0, so that the wave outlives the step
+    int chain_from;
+    const float2 *chain_wave;
+    int carry;
 };
 
 // Incident-wave load/store in natural [y][x] order from either layout, with 32-bit element

@@ -669,6 +669,11 @@ struct ms_plan {
     // with bands in both frames, the forward chain keeps each launch's window for the adjoint in
     // place of the wave (ms_plan_set_kept_windows)
     bool keep_windows = true;
+    // Algorithm 1 on the line path (ms_plan_set_layer_carry): the layer whose incident wave slot 1
+    // of the waves holds from the last layer step (-1: none), and the buffers it came from
+    bool layer_carry = false;
+    int carry_layer = -1;
+    const void *carry_key[3] = {nullptr, nullptr, nullptr};
     // A second stream (default priority) for the probe-gradient reductions, which only read
     // what the per-position kernel wrote and so run beside the slice scatter; fork and join
     // through events on the caller's stream.
@@ -855,12 +860,21 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
     const bool keep = bands && p->kept_windows();
     auto kept = [&](int m) { return waves + (long long)(m - 1) * hp.B * NA; };
     transpose_odd(p, fp.slices, st);
-    for (int m = 0; m < M; ++m) {
+    // the layer mode's wave of its slice: slot 0, or slot 1 when it is carried to the next step
+    float2 *layer_wave = (mode == kLayer && fp.carry) ? waves + NN : waves;
+    const int m_first = (mode == kLayer) ? fp.chain_from : 0;
+    for (int m = m_first; m < M; ++m) {
         lp.m = m;
         lp.psi_out = nullptr;
         lp.ovl_out = nullptr;
+        lp.restart = (m == m_first && m > 0) ? fp.chain_wave : nullptr;
+        lp.restart_stride = fp.wave_stride;
         if (m > 0 && mode == kAdjoint && !keep) { lp.psi_out = waves + m * NN; lp.psi_out_stride = fp.wave_stride; }
-        if (m > 0 && mode == kLayer && m == fp.layer) { lp.psi_out = waves; lp.psi_out_stride = fp.wave_stride; }
+        // a restart at the layer's own slice reads the wave already there
+        if (m > 0 && mode == kLayer && m == fp.layer && !(lp.restart == layer_wave)) {
+            lp.psi_out = layer_wave;
+            lp.psi_out_stride = fp.wave_stride;
+        }
         if (mode == kLayer && m == fp.layer) { lp.ovl_out = fp.overlap_patch; lp.ovl_stride = fp.ovl_stride; }
         A.next(lp);
         if (keep) {
@@ -874,6 +888,7 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
     const bool obj = bands && (p->bands_active(0) || p->bands_active(1));
     lp.psi_out = nullptr;
     lp.ovl_out = nullptr;
+    lp.restart = nullptr;
     lp.m = M - 1;
     A.next(lp);    // the buffer the last forward launch wrote, also when the others were kept
     launch_line_n(hp.n, (M & 1) != 0, lp, kStageFar, count, st);
@@ -891,7 +906,7 @@ void run_lines(ms_plan *p, int mode, const FusedParams &fp, int count, hipStream
             if (fp.full) { lp.ovl_out = fp.overlap_patch + m * NN; lp.ovl_stride = fp.ovl_stride; }
         } else if (mode == kLayer && m == fp.layer) {
             lp.patch_out = waves;
-            lp.psi_in = m > 0 ? waves : nullptr;
+            lp.psi_in = m > 0 ? layer_wave : nullptr;
         }
         lp.patch_stride = lp.psi_in_stride = fp.wave_stride;
         if (keep) {
@@ -1575,6 +1590,7 @@ ms_status ms_plan_set_objective(ms_plan *p, int32_t objective)
 {
     g_err.clear();
     if (!p) return fail(MS_ERR_INVALID_ARG, "plan is NULL");
+    p->carry_layer = -1;    // the carried wave no longer holds
     if (objective != MS_OBJECTIVE_AMPLITUDE && objective != MS_OBJECTIVE_POISSON)
         return fail(MS_ERR_INVALID_ARG, "unknown objective");
     p->objective = objective;
@@ -1585,6 +1601,7 @@ ms_status ms_plan_set_path(ms_plan *p, int32_t path)
 {
     g_err.clear();
     if (!p) return fail(MS_ERR_INVALID_ARG, "plan is NULL");
+    p->carry_layer = -1;    // the carried wave no longer holds
     const int n = p->hp.n;
     switch (path) {
         case MS_PATH_AUTO:
@@ -1607,6 +1624,7 @@ ms_status ms_plan_set_bands(ms_plan *p, int32_t mode)
 {
     g_err.clear();
     if (!p) return fail(MS_ERR_INVALID_ARG, "plan is NULL");
+    p->carry_layer = -1;    // the carried wave no longer holds
     if (mode != MS_BANDS_NONE && mode != MS_BANDS_ROWS && mode != MS_BANDS_ALL)
         return fail(MS_ERR_INVALID_ARG, "unknown band mode");
     p->band_mode = mode;
@@ -1619,11 +1637,21 @@ ms_status ms_plan_set_kept_windows(ms_plan *p, int32_t on)
 {
     g_err.clear();
     if (!p) return fail(MS_ERR_INVALID_ARG, "plan is NULL");
+    p->carry_layer = -1;    // the carried wave no longer holds
     p->keep_windows = on != 0;
     return MS_OK;
 }
 
 int32_t ms_plan_kept_windows(const ms_plan *p) { return p && p->kept_windows() ? 1 : 0; }
+
+ms_status ms_plan_set_layer_carry(ms_plan *p, int32_t on)
+{
+    g_err.clear();
+    if (!p) return fail(MS_ERR_INVALID_ARG, "plan is NULL");
+    p->layer_carry = on != 0;
+    p->carry_layer = -1;
+    return MS_OK;
+}
 
 namespace {
 
@@ -1656,6 +1684,7 @@ ms_status ms_make_probe(ms_plan *p, hipStream_t st, double alpha, double defocus
 {
     g_err.clear();
     if (!p || !probe_out) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    p->carry_layer = -1;    // the carried wave no longer holds
     if (!aligned8(probe_out)) return fail(MS_ERR_INVALID_ARG, "probe_out must be 8-byte aligned");
     if (!(alpha > 0.0) || !std::isfinite(alpha) || !std::isfinite(defocus))
         return fail(MS_ERR_INVALID_ARG, "alpha must be positive, both finite");
@@ -1667,6 +1696,7 @@ ms_status ms_make_probe_aberrated(ms_plan *p, hipStream_t st, double alpha, cons
 {
     g_err.clear();
     if (!p || !probe_out || !aberrations) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    p->carry_layer = -1;    // the carried wave no longer holds
     if (!aligned8(probe_out)) return fail(MS_ERR_INVALID_ARG, "probe_out must be 8-byte aligned");
     for (int i = 0; i < 4; ++i)
         if (!std::isfinite(aberrations[i])) return fail(MS_ERR_INVALID_ARG, "aberrations must be finite");
@@ -1681,6 +1711,7 @@ ms_status ms_forward(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c
 {
     g_err.clear();
     if (!p || !probe || !slices || !intensity_out) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    p->carry_layer = -1;    // the carried wave no longer holds
     if (!aligned8(probe) || !aligned8(slices) || !aligned8(exit_out) || ((uintptr_t)intensity_out & 3))
         return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
     const HostPlan &hp = p->hp;
@@ -1796,6 +1827,7 @@ ms_status ms_adjoint(ms_plan *p, hipStream_t st, const ms_c64 *probe, const ms_c
 {
     g_err.clear();
     if (!p) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    p->carry_layer = -1;    // the carried wave no longer holds
     ms_status bad;
     if (!adjoint_args_ok(probe, slices, measured, grad_slices, grad_probe, loss_out, &bad)) return bad;
     return adjoint_impl(p, st, probe, slices, measured, grad_slices, grad_probe, loss_out);
@@ -1843,6 +1875,13 @@ ms_status ms_layer_step(ms_plan *p, hipStream_t st, int32_t layer, int32_t k_ste
     FusedParams fp = fused_params(p, slices, measured);
     fp.layer = layer;
     fp.probe_patch = nullptr;
+    // the incident wave carried from the previous layer step: kept in slot 1 (one batch, two slots)
+    // and usable when that step took this layer or the one before with the same buffers
+    const bool carry = p->layer_carry && p->lines && hp.nb == 1 && wave_slots(hp.M, hp.K) >= 2;
+    if (!carry || p->carry_key[0] != probe || p->carry_key[1] != slices || p->carry_key[2] != measured)
+        p->carry_layer = -1;
+    fp.carry = carry ? 1 : 0;
+    const float2 *carried = fp.waves + (long long)hp.n * hp.n;
     double *mu = p->at<double>(p->L.scal);
     double *total = mu + 1;
     float2 *g = p->at<float2>(p->L.layer_g);
@@ -1853,7 +1892,24 @@ ms_status ms_layer_step(ms_plan *p, hipStream_t st, int32_t layer, int32_t k_ste
             int64_t s0 = (int64_t)b * hp.B;
             int count = (int)std::min<int64_t>(hp.B, hp.S - s0);
             fp.pos_list = p->at<int>(p->L.pos_list) + s0;
+            // psi_layer unchanged since it was carried (the slices before this layer are), or
+            // psi_{layer-1}, whose slice the last step updated, continued from there
+            fp.chain_from = 0;
+            fp.chain_wave = nullptr;
+            if (carry && layer >= 1 && p->carry_layer == layer) {
+                fp.chain_from = layer;
+                fp.chain_wave = carried;
+            } else if (carry && layer >= 2 && p->carry_layer == layer - 1) {
+                fp.chain_from = layer - 1;
+                fp.chain_wave = carried;
+            }
             launch_fused(p, kLayer, fp, count, st);
+            if (carry) {
+                p->carry_layer = layer;
+                p->carry_key[0] = probe;
+                p->carry_key[1] = slices;
+                p->carry_key[2] = measured;
+            }
             scatter(p, b, count, fp.waves, fp.wave_stride, fp.overlap_patch, fp.ovl_stride, layer, 1, g, w, b > 0, st);
             {
                 int n_loss;
@@ -1879,6 +1935,7 @@ ms_status ms_full_step(ms_plan *p, hipStream_t st, int32_t k_steps, double step_
 {
     g_err.clear();
     if (!p || !probe || !slices || !measured) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    p->carry_layer = -1;    // the carried wave no longer holds
     const HostPlan &hp = p->hp;
     if (k_steps < 0) return fail(MS_ERR_INVALID_ARG, "k_steps must be >= 0");
     if (!(step_scale > 0.0) || !std::isfinite(step_scale)) return fail(MS_ERR_INVALID_ARG, "step_scale must be > 0");
@@ -1936,6 +1993,7 @@ ms_status ms_probe_step(ms_plan *p, hipStream_t st, int32_t k_steps, ms_c64 *pro
 {
     g_err.clear();
     if (!p || !probe || !slices || !measured) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    p->carry_layer = -1;    // the carried wave no longer holds
     const HostPlan &hp = p->hp;
     if (k_steps < 0) return fail(MS_ERR_INVALID_ARG, "k_steps must be >= 0");
     if (!aligned8(probe) || !aligned8(slices) || !aligned8(loss_out) || !aligned8(mu_out) || ((uintptr_t)measured & 3))
@@ -2057,6 +2115,7 @@ ms_status ms_position_grad(ms_plan *p, hipStream_t st, const ms_c64 *probe, cons
 {
     g_err.clear();
     if (!p || !probe || !slices || !measured || !grad_pos) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    p->carry_layer = -1;    // the carried wave no longer holds
     if (!aligned8(probe) || !aligned8(slices) || !aligned8(grad_pos) || !aligned8(curv_pos) || !aligned8(loss_out) ||
         ((uintptr_t)measured & 3))
         return fail(MS_ERR_INVALID_ARG, "misaligned buffer");
@@ -2069,6 +2128,7 @@ ms_status ms_position_step(ms_plan *p, hipStream_t st, double step_scale, const 
 {
     g_err.clear();
     if (!p || !probe || !slices || !measured || !positions) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+    p->carry_layer = -1;    // the carried wave no longer holds
     if (!(step_scale > 0.0) || !std::isfinite(step_scale)) return fail(MS_ERR_INVALID_ARG, "step_scale must be > 0");
     if (!aligned8(probe) || !aligned8(slices) || !aligned8(positions) || !aligned8(loss_out) ||
         ((uintptr_t)measured & 3))

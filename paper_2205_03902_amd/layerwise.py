@@ -26,9 +26,13 @@ class History:
 
 
 def reconstruct(plan: Plan, probe: torch.Tensor, slices: torch.Tensor, measured: torch.Tensor, sweeps: int,
-                k_steps: int = 1, probe_steps: int = 0, subset: Optional[list] = None) -> History:
-    """Runs `sweeps` sweeps in place on `slices` (and `probe` when probe_steps > 0)."""
+                k_steps: int = 1, probe_steps: int = 0, subset: Optional[list] = None,
+                carry: bool = True) -> History:
+    """Runs `sweeps` sweeps in place on `slices` (and `probe` when probe_steps > 0).  carry: each
+    layer step starts its forward chain from the incident wave the previous one left (the same
+    results; the buffers change only through these calls meanwhile)."""
     M = plan.n_slices
+    plan.set_layer_carry(1 if carry else 0)
     per_sweep = M + (1 if probe_steps > 0 else 0)
     buf = torch.zeros((max(sweeps * per_sweep, 1), 2), dtype=torch.float64, device=plan.device)
     kinds = []
@@ -46,6 +50,7 @@ def reconstruct(plan: Plan, probe: torch.Tensor, slices: torch.Tensor, measured:
             i += 1
     torch.cuda.synchronize(plan.device)
     secs = time.perf_counter() - t0
+    plan.set_layer_carry(0)
     h = buf[:i].cpu().numpy()
     check_finite(h[:, 0], "reconstruct")
     return History(loss=h[:, 0].tolist(), mu=h[:, 1].tolist(), kind=kinds, seconds=secs)
