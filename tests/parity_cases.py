@@ -51,3 +51,53 @@ def small_positions(geo: configs.Geometry) -> np.ndarray:
     pos[0] = (-3.5, -2.0)                          # wraps through the top-left corner
     pos[-1] = (geo.obj_h - 2.0, geo.obj_w - 5.25)  # wraps through the bottom-right corner
     return pos
+
+
+@dataclasses.dataclass
+class FullRun:
+    """An oracle reconstruction stored under tests/golden/ (see the script that writes it)."""
+    sweeps: int
+    defocus_factor: float
+    final_loss: float
+    slice_error_to_truth: float
+    probe_rel_error_to_truth: float
+    spread_probe_change: float   # the oracle's own spread: its run from the unrounded probe
+    spread_final_loss: float
+    spread_slice_error: float
+    spread_probe_error: float
+    losses: np.ndarray      # the loss before every step
+    rows: np.ndarray        # sampled object rows and columns
+    cols: np.ndarray
+    slices: np.ndarray      # complex128 (M, len(rows), len(cols)): the final slices there
+    probe_stride: int
+    probe: np.ndarray       # complex128 (N / stride, N / stride): the final probe, every stride-th pixel
+
+
+def read_full_run(path: str, n_slices: int) -> FullRun:
+    with open(path) as f:
+        lines = [ln for ln in f.read().splitlines() if ln and not ln.startswith("#")]
+    it = iter(lines)
+    vals = {}
+
+    def block(count):
+        return np.array([[float(t) for t in next(it).split()] for _ in range(count)])
+
+    for ln in it:
+        key, arg = ln.split()
+        if key == "losses":
+            vals[key] = block(int(arg))[:, 0]
+        elif key in ("slice_rows", "slice_cols"):
+            vals[key] = np.array([int(t) for t in next(it).split()])
+            assert len(vals[key]) == int(arg)
+        elif key in ("slices", "probe"):
+            b = block(int(arg))
+            vals[key] = b[:, 0] + 1j * b[:, 1]
+        else:
+            vals[key] = float(arg)
+    rows, cols = vals["slice_rows"], vals["slice_cols"]
+    stride = int(vals["probe_stride"])
+    side = int(round(np.sqrt(len(vals["probe"]))))
+    return FullRun(int(vals["sweeps"]), vals["defocus_factor"], vals["final_loss"], vals["slice_error_to_truth"],
+                   vals["probe_rel_error_to_truth"], vals["spread_probe_change"], vals["spread_final_loss"],
+                   vals["spread_slice_error"], vals["spread_probe_error"], vals["losses"], rows, cols,
+                   vals["slices"].reshape(n_slices, len(rows), len(cols)), stride, vals["probe"].reshape(side, side))
