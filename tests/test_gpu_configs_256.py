@@ -160,3 +160,48 @@ def test_config4_block_gradients_match_the_oracle(dev):
     print(f"config 4 block: loss {el:.2e} grad slices {egs:.2e} (worst slice {max(per_slice):.2e}) probe {egp:.2e}")
     assert el < 1e-5 and egs < 1e-4 and egp < 1e-4
     assert max(per_slice) < 1e-4
+
+
+def test_config4_thirty_sweeps_with_the_probe(dev):
+    """Config 4 as specified: 30 sweeps of Algorithm 1 (Sec. 3.3), each followed by a probe step
+    (Sec. 3.5) over all 16384 positions, from t = 1 and the probe of 1.1x the defocus, on Poisson
+    counts at 1e5 electrons a pattern.  The oracle takes minutes a pass at this size, so the run is
+    checked by what holds at any size: the majorised steps of Sec. 3.2 never raise the loss (390
+    steps); the first sweep with the incident waves carried between layer steps is the sweep
+    without them, bit for bit; and at the end the loss of sampled positions is the oracle's at the
+    final slices and probe."""
+    import oracle
+    from paper_2205_03902_amd import abi, configs, datagen, layerwise, synth
+    geo = configs.CFG4
+    print(f"[case] config 4, {geo.iterations} sweeps with probe steps from the 1.1x-defocus probe", flush=True)
+    plan = abi.Plan.from_geometry(geo, device=dev)
+    truth = _t(synth.transmissions(synth.specimen(geo)), dev)
+    inten = plan.forward(plan.make_probe(geo.alpha, geo.defocus), truth)
+    meas = datagen.poisson(inten, geo.dose, seed=geo.seed + 1, stream_id=0)
+    del inten, truth
+    p0 = plan.make_probe(geo.alpha, 1.1 * geo.defocus)
+    start = torch.ones((geo.n_slices, geo.obj_h, geo.obj_w), dtype=torch.complex64, device=dev)
+    s_ref, p_ref = start.clone(), p0.clone()
+    h_ref = layerwise.reconstruct(plan, p_ref, s_ref, meas, sweeps=1, probe_steps=1, carry=False)
+    s, p = start.clone(), p0.clone()
+    h = layerwise.reconstruct(plan, p, s, meas, sweeps=1, probe_steps=1)
+    same = (torch.equal(torch.view_as_real(s), torch.view_as_real(s_ref))
+            and torch.equal(torch.view_as_real(p), torch.view_as_real(p_ref)))
+    del s_ref, p_ref, start
+    h2 = layerwise.reconstruct(plan, p, s, meas, sweeps=geo.iterations - 1, probe_steps=1)
+    losses = np.array(h.loss + h2.loss)
+    l_end = plan.adjoint(p, s, meas)[0].item()
+    print(f"config 4, {geo.iterations} sweeps: loss {losses[0]:.4e} -> {l_end:.4e} in "
+          f"{h.seconds + h2.seconds:.1f} s; first sweep with and without the carry equal: {same}")
+    assert same and h.loss == h_ref.loss
+    assert len(losses) == geo.iterations * (geo.n_slices + 1)
+    assert (np.diff(losses) <= 1e-6 * losses[0]).all() and l_end <= losses[-1] * (1 + 1e-6)
+    assert l_end < 0.5 * losses[0]
+    pick = _sample(geo, 8)
+    sub = oracle.Model.from_geometry(geo, positions=geo.positions()[pick])
+    sub_plan = abi.Plan.from_geometry(geo, positions=geo.positions()[pick], device=dev)
+    ms = meas[torch.from_numpy(pick).to(dev)].contiguous()
+    ls, _, _ = sub_plan.adjoint(p, s, ms)
+    ref = sub.loss(p.cpu().numpy(), s.cpu().numpy(), ms.cpu().numpy())
+    print(f"sampled end-state loss: {ls.item():.6e} (oracle {ref:.6e})")
+    assert abs(ls.item() - ref) / ref < 1e-5
