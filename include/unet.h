@@ -57,7 +57,7 @@ typedef enum {
 typedef enum { UN_CONV3X3 = 0, UN_UPCONV2X2 = 1, UN_CONV1X1 = 2 } un_kind;
 
 typedef struct {
-    int32_t in_ch, out_ch;     /* 1..8 each                                                   */
+    int32_t in_ch, out_ch;     /* 1..16 each                                                  */
     int32_t base, levels;      /* widths base << l for l < levels; base a multiple of 8;
                                   levels in [1, 5]; base << (levels - 1) <= 256               */
     int32_t height, width;     /* powers of two, each divisible by 2^(levels - 1), >= 8      */

@@ -665,10 +665,11 @@ __global__ void mse_stats_kernel(const double *__restrict__ part, int groups, do
     stats[2 * g + 1] = s2;
 }
 
-// Second pass: d loss / d y = 2 (e - mean e) / count, written as bf16 with 8 channels
-// (channels >= oc are zero); the loss itself by one lane.
+// Second pass: d loss / d y = 2 (e - mean e) / count, written as bf16 with gc channels a pixel
+// (oc rounded up to a multiple of 8; channels >= oc are zero); the loss itself by one lane.
 __global__ void mse_grad_kernel(const float *__restrict__ y, const float *__restrict__ tg, const double *__restrict__ stats,
-                                int oc, long long hw, long long pixels, uint16_t *__restrict__ gy, double *loss_out)
+                                int oc, int gc, long long hw, long long pixels, uint16_t *__restrict__ gy,
+                                double *loss_out)
 {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const double count = (double)pixels * oc;
@@ -680,13 +681,15 @@ __global__ void mse_grad_kernel(const float *__restrict__ y, const float *__rest
     }
     if (p >= pixels) return;
     const long long b = p / hw;
-    uint32_t o[4] = {0u, 0u, 0u, 0u};
-    for (int c = 0; c < oc; ++c) {
-        const double mean = stats[(b * oc + c) * 2] / (double)hw;
-        const double e = (double)y[p * oc + c] - (double)tg[p * oc + c];
-        o[c >> 1] |= (uint32_t)f2bf((float)(2.0 * (e - mean) / count)) << (16 * (c & 1));
+    for (int c8 = 0; c8 < gc; c8 += 8) {
+        uint32_t o[4] = {0u, 0u, 0u, 0u};
+        for (int c = c8; c < min(oc, c8 + 8); ++c) {
+            const double mean = stats[(b * oc + c) * 2] / (double)hw;
+            const double e = (double)y[p * oc + c] - (double)tg[p * oc + c];
+            o[(c - c8) >> 1] |= (uint32_t)f2bf((float)(2.0 * (e - mean) / count)) << (16 * (c & 1));
+        }
+        *reinterpret_cast<uint4 *>(gy + p * gc + c8) = make_uint4(o[0], o[1], o[2], o[3]);
     }
-    *reinterpret_cast<uint4 *>(gy + p * 8) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // Direct 3x3 convolution (stride 1, zero padding 1) to 32 output channels, for the two finest

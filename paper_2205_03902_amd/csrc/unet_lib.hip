@@ -82,8 +82,8 @@ namespace {
 un_status check_config(const un_config *c)
 {
     if (!c) return ufail(UN_ERR_INVALID_ARG, "config is NULL");
-    if (c->in_ch < 1 || c->in_ch > 8 || c->out_ch < 1 || c->out_ch > 8)
-        return ufail(UN_ERR_INVALID_ARG, "in_ch and out_ch must be in [1, 8]");
+    if (c->in_ch < 1 || c->in_ch > 16 || c->out_ch < 1 || c->out_ch > 16)
+        return ufail(UN_ERR_INVALID_ARG, "in_ch and out_ch must be in [1, 16]");
     if (c->levels < 1 || c->levels > 5) return ufail(UN_ERR_INVALID_ARG, "levels must be in [1, 5]");
     if (c->base < 8 || c->base % 8 || (c->base << (c->levels - 1)) > 256)
         return ufail(UN_ERR_INVALID_ARG, "base must be a multiple of 8 with base << (levels - 1) <= 256");
@@ -201,7 +201,7 @@ void plan(un_net &n)
         }
     }
     const size_t gmax = (size_t)n.pixels(B, 0) * c.base * 2;
-    y.gout = take((size_t)n.pixels(B, 0) * 8 * 2);
+    y.gout = take((size_t)n.pixels(B, 0) * r8(c.out_ch) * 2);
     y.gx = take(gmax);
     y.gy = take(gmax);
     y.stats = take((size_t)B * c.out_ch * 2 * sizeof(double));
@@ -518,11 +518,12 @@ void run_backward(un_net &n, int batch, const uint16_t *x, const float *target, 
     double *mpart = n.at<double>(L.mse_part);
     mse_partial_kernel<<<dim3(kMseChunks, batch), kThreads, 0, st>>>(y, target, oc, hw, mpart);
     mse_stats_kernel<<<(unsigned)cdiv(batch * oc, 64), 64, 0, st>>>(mpart, batch * oc, stats);
-    mse_grad_kernel<<<(unsigned)cdiv(P, 256), 256, 0, st>>>(y, target, stats, oc, hw, P, gout, loss);
+    const int gc = n.layers[n.head()].G;    // the output gradient's channels: out_ch rounded up to 8
+    mse_grad_kernel<<<(unsigned)cdiv(P, 256), 256, 0, st>>>(y, target, stats, oc, gc, hw, P, gout, loss);
 
     uint16_t *X = n.at<uint16_t>(L.gx), *Y = n.at<uint16_t>(L.gy);
     const uint16_t *last = n.L > 1 ? n.at<uint16_t>(L.dec_a1[0]) : n.at<uint16_t>(L.enc_a1[0]);
-    layer_weight_grad(n, n.head(), batch, 0, last, n.cfg.base, nullptr, 0, gout, 8, st);
+    layer_weight_grad(n, n.head(), batch, 0, last, n.cfg.base, nullptr, 0, gout, gc, st);
     layer_data_grad(n, n.head(), batch, 0, gout, X, n.cfg.base, nullptr, 0, last, st);
 
     for (int l = 0; l <= n.L - 2; ++l) {

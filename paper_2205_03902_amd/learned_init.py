@@ -1,4 +1,5 @@
-"""Learned initialisation of the layer-wise reconstruction (the 'config 3' workload).
+"""Learned initialisation of the layer-wise reconstruction (the 'config 3' workload, and the
+same comparison on the 16384-position, 12-slice workload).
 
 The plain method starts Algorithm 1 (Sec. 3.3) from t = 1 and runs T sweeps.  The
 learned path runs 2 coarse sweeps from t = 1, feeds the phases of the coarse slices
@@ -9,6 +10,11 @@ L_plain on the same data; a prediction is accepted only if the refinement reache
 L_plain within T sweeps, otherwise the plain result stands and the learned attempt
 adds to its time.
 
+On the 1024^2, 12-slice workload the network has 12 channels, is trained on the 4 x 4 grid
+of 256^2 tiles of each training specimen (simulated at the workload's full geometry, so that
+the tiles see its scan overlap), and is applied to the whole object at once: the network is
+fully convolutional, so the trained weights serve a 1024^2 instance unchanged.
+
 Everything runs on the device: specimens, simulation and noise (datagen), the
 multislice steps (libimsp), the network and Adam (unet).  This module only sequences
 the calls and reads back the losses.
@@ -17,7 +23,7 @@ from __future__ import annotations
 
 import dataclasses
 import time
-from typing import Dict, List
+from typing import Dict, List, Tuple
 
 import numpy as np
 import torch
@@ -37,6 +43,9 @@ class Setup:
     train_first: int = 30000         # training specimens train_first .. train_first + n_train - 1
     test_first: int = 39000          # held-out specimens
     noise_seed: int = 31
+    grid: int = 1                    # training crops per specimen and axis: 1 = the centre crop,
+                                     # g = the g x g tiles of crop x crop that cover the object
+    whole: bool = False              # the network initialises the whole object, not the centre crop
 
     @property
     def family(self) -> datagen.SpecimenFamily:
@@ -46,6 +55,32 @@ class Setup:
     @property
     def offset(self) -> int:
         return (self.geo.obj_h - self.crop) // 2
+
+    def train_offsets(self) -> List[Tuple[int, int]]:
+        """Top-left corners of the training crops of one specimen."""
+        if self.grid == 1:
+            return [(self.offset, self.offset)]
+        if self.grid * self.crop != self.geo.obj_h or self.grid * self.crop != self.geo.obj_w:
+            raise ValueError("the tiles must cover the object exactly")
+        return [(i * self.crop, j * self.crop) for i in range(self.grid) for j in range(self.grid)]
+
+    @property
+    def window(self) -> Tuple[int, int, int, int]:
+        """(y0, x0, h, w): where the network's prediction initialises the slices."""
+        if self.whole:
+            return 0, 0, self.geo.obj_h, self.geo.obj_w
+        return self.offset, self.offset, self.crop, self.crop
+
+
+def setup_for(config: int, sweeps=None) -> Setup:
+    """The learned-initialisation workloads: 3 (config 1's geometry, 6 slices, centre crop, T = 20)
+    and 4 (the 1024^2, 12-slice, 16384-position geometry, whole object, T = 30)."""
+    if config == 3:
+        return Setup(sweeps=20 if sweeps is None else sweeps)
+    if config == 4:
+        return Setup(geo=configs.CFG4, grid=4, whole=True, sweeps=configs.CFG4.iterations if sweeps is None else sweeps,
+                     noise_seed=41)
+    raise ValueError("learned initialisation is defined for configs 3 and 4")
 
 
 class Simulator:
@@ -57,6 +92,10 @@ class Simulator:
         self.plan = abi.Plan.from_geometry(g, device=device)
         self.device = self.plan.device
         self.probe = self.plan.make_probe(g.alpha, g.defocus)
+        # each layer step continues from the incident wave the previous one left (the line path;
+        # the same results, fewer launches); start() and edited() drop it whenever the slices
+        # change other than by a layer step
+        self.plan.set_layer_carry(1)
         shape = (g.n_slices, g.obj_h, g.obj_w)
         self.pot = torch.empty(shape, dtype=torch.float32, device=self.device)
         self.truth = torch.empty(shape, dtype=torch.complex64, device=self.device)
@@ -72,7 +111,12 @@ class Simulator:
     def start(self):
         t = torch.empty_like(self.truth)
         t.fill_(1.0)
+        self.edited()
         return t
+
+    def edited(self):
+        """The slices were written other than by a layer step: drop the carried incident wave."""
+        self.plan.set_layer_carry(1)
 
     def sweep(self, slices, losses: torch.Tensor, row: int):
         """One Algorithm 1 sweep in place; losses[row, l] = loss before layer step l."""
@@ -84,28 +128,39 @@ class Simulator:
 
 
 def make_example(sim: Simulator, index: int, x_out, y_out):
-    """Network input (coarse phases, bf16 [crop][crop][8]) and target (potential, [crop][crop][M])."""
+    """Network inputs (coarse phases, bf16 [crop][crop][in_pad]) and targets (potential,
+    [crop][crop][M]) of one specimen: one crop, or with a leading axis one row per training crop."""
     s = sim.s
+    offsets = s.train_offsets()
+    if x_out.dim() == 3:
+        if len(offsets) != 1:
+            raise ValueError("this setup takes several crops a specimen: pass one row per crop")
+        x_out, y_out = x_out[None], y_out[None]
     sim.load(index)
     t = sim.start()
     scratch = torch.zeros((s.coarse_sweeps, sim.plan.n_slices), dtype=torch.float64, device=sim.device)
     for k in range(s.coarse_sweeps):
         sim.sweep(t, scratch, k)
-    datagen.crop_phase(t, s.offset, s.offset, s.crop, s.crop, x_out.shape[-1], out=x_out)
-    datagen.crop_potential(sim.pot, s.offset, s.offset, s.crop, s.crop, out=y_out)
+    for r, (y0, x0) in enumerate(offsets):
+        datagen.crop_phase(t, y0, x0, s.crop, s.crop, x_out.shape[-1], out=x_out[r])
+        datagen.crop_potential(sim.pot, y0, x0, s.crop, s.crop, out=y_out[r])
 
 
-def generate(sim: Simulator, first: int, count: int, in_pad: int = 8, log=None):
+def generate(sim: Simulator, first: int, count: int, in_pad: int = 0, log=None):
+    """Training examples of specimens first .. first + count - 1: len(train_offsets()) rows each."""
     s = sim.s
     M = s.geo.n_slices
-    X = torch.empty((count, s.crop, s.crop, in_pad), dtype=torch.bfloat16, device=sim.device)
-    Y = torch.empty((count, s.crop, s.crop, M), dtype=torch.float32, device=sim.device)
-    t0 = time.perf_counter()
+    in_pad = in_pad or (M + 7) // 8 * 8
+    tiles = len(s.train_offsets())
+    X = torch.empty((count * tiles, s.crop, s.crop, in_pad), dtype=torch.bfloat16, device=sim.device)
+    Y = torch.empty((count * tiles, s.crop, s.crop, M), dtype=torch.float32, device=sim.device)
+    t0 = last = time.perf_counter()
     for i in range(count):
-        make_example(sim, first + i, X[i], Y[i])
-        if log and (i + 1) % 250 == 0:
+        make_example(sim, first + i, X[i * tiles:(i + 1) * tiles], Y[i * tiles:(i + 1) * tiles])
+        if log and ((i + 1) % 250 == 0 or time.perf_counter() - last > 20.0):
             torch.cuda.synchronize(sim.device)
-            log(f"generated {i + 1}/{count} specimens in {time.perf_counter() - t0:.1f} s")
+            last = time.perf_counter()
+            log(f"generated {i + 1}/{count} specimens in {last - t0:.1f} s")
     torch.cuda.synchronize(sim.device)
     return X, Y, time.perf_counter() - t0
 
@@ -160,15 +215,17 @@ def _init_path(sim: Simulator, net, x, vhat, T: int):
     their end times in ms from the start, loss at the initialisation, initialisation time)."""
     s = sim.s
     M = sim.plan.n_slices
+    y0, x0, h, w = s.window
     ll = torch.zeros((s.coarse_sweeps + T + 1, M), dtype=torch.float64, device=sim.device)
     t = sim.start()
     start = torch.cuda.Event(enable_timing=True)
     start.record()
     _run_sweeps(sim, t, s.coarse_sweeps, ll, [])
     if net is not None:
-        datagen.crop_phase(t, s.offset, s.offset, s.crop, s.crop, net.in_pad, out=x[0])
+        datagen.crop_phase(t, y0, x0, h, w, net.in_pad, out=x[0])
         net.forward(x, out=vhat)
-    datagen.apply_init(vhat[0], t, s.offset, s.offset, s.kappa)
+    datagen.apply_init(vhat[0], t, y0, x0, s.kappa)
+    sim.edited()
     init_done = torch.cuda.Event(enable_timing=True)
     init_done.record()
     ends: List = []
@@ -188,7 +245,8 @@ def _reach(losses, ms, target, fallback_ms):
 
 
 def time_to_loss(sim: Simulator, net: UNet, index: int) -> Dict:
-    """Plain, learned and control runs on held-out specimen `index`; times from HIP events (ms)."""
+    """Plain, learned and control runs on held-out specimen `index`; times from HIP events (ms).
+    net: an instance of the size of the setup's window (batch 1)."""
     s = sim.s
     T, M = s.sweeps, sim.plan.n_slices
     sim.load(index)
@@ -208,8 +266,9 @@ def time_to_loss(sim: Simulator, net: UNet, index: int) -> Dict:
     k_plain = int(np.argmax(plain_loss <= L_plain))
     t_plain = float(plain_ms[k_plain])
 
-    x = torch.empty((1, s.crop, s.crop, net.in_pad), dtype=torch.bfloat16, device=sim.device)
-    vhat = torch.zeros((1, s.crop, s.crop, M), dtype=torch.float32, device=sim.device)
+    _, _, h, w = s.window
+    x = torch.empty((1, h, w, net.in_pad), dtype=torch.bfloat16, device=sim.device)
+    vhat = torch.zeros((1, h, w, M), dtype=torch.float32, device=sim.device)
     c_loss, c_ms, c_init, _ = _init_path(sim, None, x, vhat, T)
     l_loss, l_ms, l_init, init_ms = _init_path(sim, net, x, vhat, T)
     acc, t_learned, k_learned = _reach(l_loss, l_ms, L_plain, float(plain_ms[-1]))
@@ -270,24 +329,35 @@ def main(argv=None, log=None):
     import json
     import sys
     ap = argparse.ArgumentParser(description="learned initialisation: generate, train, time to loss")
-    ap.add_argument("--train", type=int, default=2000)
-    ap.add_argument("--test", type=int, default=100)
+    ap.add_argument("--config", type=int, default=3, choices=(3, 4),
+                    help="3: config 1's geometry, centre crop; 4: the 1024^2, 12-slice workload, whole object")
+    ap.add_argument("--train", type=int, default=None,
+                    help="training specimens (default 2000; 125 for config 4, whose specimens give 16 tiles each)")
+    ap.add_argument("--test", type=int, default=None, help="held-out specimens (default 100; 3 for config 4)")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--sweeps", type=int, default=20)
+    ap.add_argument("--sweeps", type=int, default=None, help="T (default 20; 30 for config 4)")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         raise SystemExit("a GPU is required")
     if log is None:
         log = lambda m: print(f"[learned-init] {m}", file=sys.stderr, flush=True)
-    setup = Setup(sweeps=args.sweeps)
+    setup = setup_for(args.config, args.sweeps)
+    n_train = args.train if args.train is not None else (2000 if args.config == 3 else 125)
+    n_test = args.test if args.test is not None else (100 if args.config == 3 else 3)
     sim = Simulator(setup, "cuda")
     M = setup.geo.n_slices
-    X, Y, t_gen = generate(sim, setup.train_first, args.train, log=log)
-    log(f"training set: {args.train} specimens in {t_gen:.1f} s ({1e3 * t_gen / args.train:.2f} ms each)")
-    n_val = max(args.batch, (min(args.test, 256) // args.batch) * args.batch)
+    tiles = len(setup.train_offsets())
+    X, Y, t_gen = generate(sim, setup.train_first, n_train, log=log)
+    log(f"training set: {n_train} specimens, {X.shape[0]} crops, in {t_gen:.1f} s "
+        f"({1e3 * t_gen / n_train:.2f} ms a specimen)")
+    # held-out loss while training: crops of the first held-out specimens, whole batches of them
+    if tiles == 1:
+        n_val = max(args.batch, (min(n_test, 256) // args.batch) * args.batch)
+    else:
+        n_val = -(-args.batch // tiles)
     Xv, Yv, _ = generate(sim, setup.test_first, n_val)
     net = UNet(M, M, base=32, levels=4, height=setup.crop, width=setup.crop, max_batch=args.batch, device="cuda")
     net.init_he(seed=setup.geo.seed)
@@ -296,20 +366,30 @@ def main(argv=None, log=None):
         f"(batch {args.batch})")
     net.init_he(seed=setup.geo.seed)
     tr, held, t_train = train(net, X, Y, args.epochs, args.batch, lr=args.lr, seed=1, Xv=Xv, Yv=Yv, log=log)
-    del X, Y
+    del X, Y, Xv, Yv
+    _, _, h, w = setup.window
+    if (h, w) != (setup.crop, setup.crop):
+        # the same weights in an instance of the window's size, batch 1 (the network is fully
+        # convolutional)
+        trained = net
+        net = UNet(M, M, base=32, levels=4, height=h, width=w, max_batch=1, device="cuda")
+        net.set_params(trained.get_params(trained.shapes()))
+        del trained
     rows = []
-    for i in range(args.test):
+    for i in range(n_test):
         rows.append(time_to_loss(sim, net, setup.test_first + i))
         r = rows[-1]
         log(f"held-out {r['index']}: plain {r['t_plain_ms']:.1f} ms ({r['sweeps_plain']} sweeps), "
             f"learned {r['t_learned_ms']:.1f} ms ({r['sweeps_learned']} sweeps), control {r['t_control_ms']:.1f} ms "
             f"({r['sweeps_control']} sweeps); final loss learned / control {r['learned_final'] / r['control_final']:.4f}")
     summ = summarize(rows)
+    where = (f"U-Net trained on the {setup.grid} x {setup.grid} tiles of {setup.crop}^2, applied to the whole "
+             f"{h} x {w} object" if setup.whole else f"U-Net on the {setup.crop}^2 centre crop")
     result = dict(workload=f"{setup.geo.name}: {M} slices, {setup.geo.obj_h}^2 object, {sim.plan.n_pos} positions, "
-                           f"U-Net on the {setup.crop}^2 centre crop",
-                  train=args.train, test=args.test, epochs=args.epochs, batch=args.batch, lr=args.lr,
-                  sweeps=args.sweeps, coarse_sweeps=setup.coarse_sweeps, generation_s=t_gen, training_s=t_train,
-                  train_loss=tr, heldout_loss=held, unet=thr, time_to_loss=summ, rows=rows)
+                           + where,
+                  train=n_train, train_crops=n_train * tiles, test=n_test, epochs=args.epochs, batch=args.batch,
+                  lr=args.lr, sweeps=setup.sweeps, coarse_sweeps=setup.coarse_sweeps, generation_s=t_gen,
+                  training_s=t_train, train_loss=tr, heldout_loss=held, unet=thr, time_to_loss=summ, rows=rows)
     log(json.dumps(summ))
     if args.out:
         with open(args.out, "w") as f:

@@ -131,7 +131,7 @@ def test_unet_header_declares_the_binding_and_the_library_exports_it():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("kw", [dict(in_ch=0), dict(out_ch=9), dict(levels=0), dict(levels=6), dict(base=12),
+@pytest.mark.parametrize("kw", [dict(in_ch=0), dict(out_ch=17), dict(in_ch=17), dict(levels=0), dict(levels=6), dict(base=12),
                                 dict(base=64, levels=4), dict(height=48), dict(width=4), dict(max_batch=0),
                                 dict(height=8, levels=5, base=8)])
 def test_unet_invalid_configs_are_rejected(kw):

@@ -109,3 +109,52 @@ def test_a_briefly_trained_network_beats_the_control(sim):
     assert tr[-1] < tr[0]
     assert all(r["loss_at_learned_init"] < r["loss_at_control_init"] for r in rows)
     assert np.median([r["t_learned_ms"] / r["t_control_ms"] for r in rows]) < 1.0
+
+
+@pytest.fixture(scope="module")
+def tiled():
+    """The 12-slice workload's arrangement on a small geometry: training on the 2 x 2 tiles of 64^2
+    that cover a 128^2 object, the network applied to the whole object."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_03902_amd import configs, learned_init
+    geo = configs.small(n=64, obj=128, n_slices=4, scan=(6, 6), step_px=12.0, seed=77, defocus=50.0)
+    print("[case] learned-init simulator, 2 x 2 tiles of 64^2, whole 128^2 object", flush=True)
+    return learned_init.Simulator(learned_init.Setup(geo=geo, crop=64, grid=2, whole=True, sweeps=4), "cuda")
+
+
+def test_tiles_cover_the_whole_objects_input_and_target(tiled):
+    from paper_2205_03902_amd import datagen, learned_init
+    s, M = tiled.s, tiled.plan.n_slices
+    offsets = s.train_offsets()
+    assert offsets == [(0, 0), (0, 64), (64, 0), (64, 64)] and s.window == (0, 0, 128, 128)
+    X, Y, _ = learned_init.generate(tiled, 500, 1)
+    assert X.shape == (4, 64, 64, 8) and Y.shape == (4, 64, 64, M)
+    # the same coarse reconstruction again, read over the whole object
+    tiled.load(500)
+    t = tiled.start()
+    scratch = torch.zeros((s.coarse_sweeps, M), dtype=torch.float64, device=tiled.device)
+    for k in range(s.coarse_sweeps):
+        tiled.sweep(t, scratch, k)
+    xw = datagen.crop_phase(t, 0, 0, 128, 128, 8).cpu()
+    pot = tiled.pot.cpu().numpy()
+    for r, (y0, x0) in enumerate(offsets):
+        assert torch.equal(X[r].cpu(), xw[y0:y0 + 64, x0:x0 + 64])
+        assert np.array_equal(Y[r].cpu().numpy(), pot[:, y0:y0 + 64, x0:x0 + 64].transpose(1, 2, 0))
+
+
+def test_whole_object_network_takes_the_trained_weights_and_reports(tiled):
+    from paper_2205_03902_amd import learned_init
+    from paper_2205_03902_amd.unet import UNet
+    s, M = tiled.s, tiled.plan.n_slices
+    net = UNet(M, M, base=8, levels=2, height=s.crop, width=s.crop, max_batch=4, device=tiled.device)
+    net.init_he(5)
+    whole = UNet(M, M, base=8, levels=2, height=128, width=128, max_batch=1, device=tiled.device)
+    whole.set_params(net.get_params(net.shapes()))
+    a, b = net.get_params(net.shapes()), whole.get_params(whole.shapes())
+    assert all(np.array_equal(a[k][j], b[k][j]) for k in a for j in range(2))
+    r = learned_init.time_to_loss(tiled, whole, 501)
+    assert r["sweeps_plain"] <= s.sweeps and r["t_plain_ms"] > 0
+    for curve in ("plain_curve", "learned_curve", "control_curve"):
+        assert np.all(np.diff(r[curve]) <= 1e-9 * r[curve][0]), curve
+    assert r["init_ms"] > 0 and np.isfinite(r["loss_at_learned_init"])

@@ -55,14 +55,17 @@ def _nchw(t):
     return t.permute(0, 3, 1, 2).double().cpu().numpy()
 
 
-# (in, out, base, levels, height, width, batch, seed). The last two reach the direct 3x3
-# convolution, which takes images of 64 rows and more: 32 channels at 128 x 64 (two row tiles,
-# the concatenation's 64 input channels, its gradient split 32 / 32 over the two sources) and
-# 64 channels at 128 x 128 (two 32-channel launches a layer, the gradient split 64 / 64).
+# (in, out, base, levels, height, width, batch, seed). The fourth and fifth cases reach the
+# direct 3x3 convolution, which takes images of 64 rows and more: 32 channels at 128 x 64 (two
+# row tiles, the concatenation's 64 input channels, its gradient split 32 / 32 over the two
+# sources) and 64 channels at 128 x 128 (two 32-channel launches a layer, the gradient split
+# 64 / 64).  The sixth has 12 input channels, padded to 16, as the network of the 12-slice
+# workload has (its input layer on the implicit GEMM), over 4 levels of a non-square image.
 # The last case is the deployed network (4 levels, 32 base channels, 256 x 256 crops of 6 slices,
 # the only shape with 256-channel layers), at batch 1.
 CASES = [(3, 2, 8, 3, 16, 32, 2, 1), (6, 6, 16, 4, 32, 32, 2, 2), (8, 1, 8, 1, 8, 16, 3, 3),
-         (6, 6, 32, 2, 128, 64, 2, 4), (4, 3, 64, 2, 128, 128, 1, 6), (6, 6, 32, 4, 256, 256, 1, 5)]
+         (6, 6, 32, 2, 128, 64, 2, 4), (4, 3, 64, 2, 128, 128, 1, 6), (12, 12, 16, 4, 64, 128, 2, 7),
+         (6, 6, 32, 4, 256, 256, 1, 5)]
 
 
 @pytest.mark.parametrize("case", CASES)
