@@ -403,6 +403,9 @@ def main():
     ap.add_argument("--ttl-train", type=int, default=2000, help="training specimens of the time-to-loss run")
     ap.add_argument("--ttl-test", type=int, default=100, help="held-out specimens of the time-to-loss run")
     ap.add_argument("--ttl-epochs", type=int, default=20, help="training epochs of the time-to-loss run")
+    ap.add_argument("--time-to-loss-config4", action="store_true",
+                    help="also run plain vs learned initialisation on the 1024^2, 12-slice workload (about 8 "
+                         "minutes: 125 training specimens, 3 held-out)")
     ap.add_argument("--unet-only", type=int, default=0, metavar="REPS",
                     help="time only the network's forward pass (256^2 crops of 6 slices, batch 16) REPS times "
                          "and print its JSON with the flops of every layer")
@@ -577,6 +580,15 @@ def main():
                                    test=args.ttl_test, epochs=res["epochs"], sweeps=res["sweeps"],
                                    generation_s=res["generation_s"], training_s=res["training_s"],
                                    heldout_loss=res["heldout_loss"][-1:], unet=res["unet"])
+    if args.time_to_loss_config4:
+        from paper_2205_03902_amd import learned_init
+        log("bench: learned initialisation on the 1024^2, 12-slice workload")
+        torch.cuda.empty_cache()
+        res = learned_init.main(["--config", "4"], log=log)
+        out["time_to_loss_cfg4"] = dict(res["time_to_loss"], workload=res["workload"], train=res["train"],
+                                        train_crops=res["train_crops"], test=res["test"], epochs=res["epochs"],
+                                        sweeps=res["sweeps"], generation_s=res["generation_s"],
+                                        training_s=res["training_s"], heldout_loss=res["heldout_loss"][-1:])
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(geo, min(args.cpu_sample, geo.n_pos), truth=truth_np)
