@@ -147,7 +147,8 @@ def make_example(sim: Simulator, index: int, x_out, y_out):
 
 
 def generate(sim: Simulator, first: int, count: int, in_pad: int = 0, log=None):
-    """Training examples of specimens first .. first + count - 1: len(train_offsets()) rows each."""
+    """Training examples of specimens first .. first + count - 1: len(train_offsets()) rows each.
+    in_pad: the network input's channels (0: the slice count rounded up to a multiple of 8)."""
     s = sim.s
     M = s.geo.n_slices
     in_pad = in_pad or (M + 7) // 8 * 8
