@@ -86,3 +86,25 @@ def test_the_fused_path_ignores_the_carry(dev):
     s1, p1, l1, _, _ = _sweeps(c, dev, True, lines=False)
     s0, p0, l0, _, _ = _sweeps(c, dev, False, lines=False)
     assert np.array_equal(s1, s0) and np.array_equal(p1, p0) and np.array_equal(l1, l0)
+
+
+def test_carried_wave_with_the_poisson_objective_and_tilted_illumination(dev):
+    """The carry changes only where a layer step's forward chain starts: with the Poisson deviance
+    (its own residual and step) and tilted illumination (the tilt terms of the propagator) the
+    sweeps are again bit for bit those of the whole chain."""
+    from paper_2205_03902_amd import abi, layerwise
+    c = case_for(64)
+    g = c.geo
+    print("[case] layer carry with the Poisson objective and a tilt, n=64", flush=True)
+    runs = []
+    for carry in (True, False):
+        plan = abi.Plan(g.n, g.obj_h, g.obj_w, g.n_slices, c.model.positions, g.gaps(), g.pixel_size, g.wavelength,
+                        tilt_y=0.012, tilt_x=-0.007, device=dev, checkpoint_every=1)
+        plan.set_path(abi.MS_PATH_LINES)
+        plan.set_objective(abi.MS_OBJECTIVE_POISSON)
+        probe, slices, meas = _t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev)
+        h = layerwise.reconstruct(plan, probe, slices, meas, sweeps=2, k_steps=2, probe_steps=1, carry=carry)
+        runs.append((slices.cpu().numpy(), probe.cpu().numpy(), np.array(h.loss), np.array(h.mu)))
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+    assert np.all(np.isfinite(runs[0][2]))
