@@ -399,13 +399,16 @@ def main():
                     help="about this many positions per batch (0 = all at once): sets the plan's workspace "
                          "budget; the log reports the batch the plan chose")
     ap.add_argument("--no-time-to-loss", action="store_true",
-                    help="skip the learned-initialisation run (generation, training, time to loss)")
+                    help="skip the learned-initialisation runs (generation, training, time to loss)")
     ap.add_argument("--ttl-train", type=int, default=2000, help="training specimens of the time-to-loss run")
     ap.add_argument("--ttl-test", type=int, default=100, help="held-out specimens of the time-to-loss run")
     ap.add_argument("--ttl-epochs", type=int, default=20, help="training epochs of the time-to-loss run")
+    ap.add_argument("--ttl4-train", type=int, default=32,
+                    help="training specimens (16 tiles each) of the 1024^2, 12-slice time-to-loss run")
+    ap.add_argument("--ttl4-test", type=int, default=2, help="held-out specimens of that run")
     ap.add_argument("--time-to-loss-config4", action="store_true",
-                    help="also run plain vs learned initialisation on the 1024^2, 12-slice workload (about 8 "
-                         "minutes: 125 training specimens, 3 held-out)")
+                    help="run that comparison with its full protocol: 125 training specimens (2000 tiles) and 8 "
+                         "held-out (about 14 minutes)")
     ap.add_argument("--unet-only", type=int, default=0, metavar="REPS",
                     help="time only the network's forward pass (256^2 crops of 6 slices, batch 16) REPS times "
                          "and print its JSON with the flops of every layer")
@@ -580,11 +583,16 @@ def main():
                                    test=args.ttl_test, epochs=res["epochs"], sweeps=res["sweeps"],
                                    generation_s=res["generation_s"], training_s=res["training_s"],
                                    heldout_loss=res["heldout_loss"][-1:], unet=res["unet"])
-    if args.time_to_loss_config4:
+        del res
+    if not args.no_time_to_loss or args.time_to_loss_config4:
+        # the same comparison on the headline workload: by default a reduced training set (32
+        # specimens, 512 tiles) and 2 held-out specimens; the full protocol with the flag
         from paper_2205_03902_amd import learned_init
-        log("bench: learned initialisation on the 1024^2, 12-slice workload")
+        train4, test4 = (125, 8) if args.time_to_loss_config4 else (args.ttl4_train, args.ttl4_test)
+        log(f"bench: learned initialisation on the 1024^2, 12-slice workload ({train4} training specimens, "
+            f"{test4} held-out)")
         torch.cuda.empty_cache()
-        res = learned_init.main(["--config", "4"], log=log)
+        res = learned_init.main(["--config", "4", "--train", str(train4), "--test", str(test4)], log=log)
         out["time_to_loss_cfg4"] = dict(res["time_to_loss"], workload=res["workload"], train=res["train"],
                                         train_crops=res["train_crops"], test=res["test"], epochs=res["epochs"],
                                         sweeps=res["sweeps"], generation_s=res["generation_s"],
