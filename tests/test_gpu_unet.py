@@ -192,3 +192,20 @@ def test_full_size_network_first_layers_and_finite_output(dev):
     assert _rel(a0, ref.relu(ref.conv2d(x[:1], w0, b0))) < 4e-3
     p = _nchw(net.activation(2)[:1])
     assert np.array_equal(p, ref.maxpool2(_nchw(net.activation(1)[:1])))
+
+
+def test_whole_object_network_of_the_12_slice_workload(dev):
+    """The instance that initialises the whole 1024^2 object of the 12-slice workload (12 channels,
+    padded to 16; the trained weights of the 256^2 network): its first layer on an interior patch
+    against the FP64 convolution, the first pooling exactly, and a finite output."""
+    net, params, x, target, xg, tg = _setup(dev, 12, 12, 32, 4, 1024, 1024, 1, 9)
+    y = net.forward(xg)
+    torch.cuda.synchronize()
+    assert torch.isfinite(y).all()
+    y0, x0 = 500, 300
+    a0 = _nchw(net.activation(0)[:, y0:y0 + 64, x0:x0 + 64].contiguous())
+    w0, b0 = params["enc0.conv0"]
+    ref0 = ref.relu(ref.conv2d(x[:, :, y0 - 1:y0 + 65, x0 - 1:x0 + 65], w0, b0))[:, :, 1:65, 1:65]
+    assert _rel(a0, ref0) < 4e-3
+    p = _nchw(net.activation(2)[:, 250:282, 150:182].contiguous())
+    assert np.array_equal(p, ref.maxpool2(_nchw(net.activation(1)[:, 500:564, 300:364].contiguous())))
