@@ -51,6 +51,16 @@ def kernel_source_hash(family: str) -> str:
     return h.hexdigest()[:16]
 
 
+def guarded(out: dict, key: str, leg):
+    """Runs a leg that follows the headline measurement; if it raises, the error is logged and
+    recorded under `key`, and the line with the headline is still printed."""
+    try:
+        out[key] = leg()
+    except Exception as e:  # noqa: BLE001 -- any failure of the leg, recorded in the line
+        log(f"bench: {key} failed: {e!r}")
+        out[key] = {"error": repr(e)}
+
+
 def model_per_launch(geo):
     """Algorithmic bytes and flops of the per-position kernels of one adjoint pass over all
     positions (one fused launch, or the 2M + 1 line launches).
@@ -576,27 +586,31 @@ def main():
     out.update(extras)
     if not args.no_time_to_loss:
         from paper_2205_03902_amd import learned_init
-        log("bench: learned initialisation (generate, train, time to loss)")
-        res = learned_init.main(["--train", str(args.ttl_train), "--test", str(args.ttl_test),
-                                 "--epochs", str(args.ttl_epochs)], log=log)
-        out["time_to_loss"] = dict(res["time_to_loss"], workload=res["workload"], train=res["train"],
-                                   test=args.ttl_test, epochs=res["epochs"], sweeps=res["sweeps"],
-                                   generation_s=res["generation_s"], training_s=res["training_s"],
-                                   heldout_loss=res["heldout_loss"][-1:], unet=res["unet"])
-        del res
+
+        def ttl3():
+            log("bench: learned initialisation (generate, train, time to loss)")
+            res = learned_init.main(["--train", str(args.ttl_train), "--test", str(args.ttl_test),
+                                     "--epochs", str(args.ttl_epochs)], log=log)
+            return dict(res["time_to_loss"], workload=res["workload"], train=res["train"], test=args.ttl_test,
+                        epochs=res["epochs"], sweeps=res["sweeps"], generation_s=res["generation_s"],
+                        training_s=res["training_s"], heldout_loss=res["heldout_loss"][-1:], unet=res["unet"])
+        guarded(out, "time_to_loss", ttl3)
     if not args.no_time_to_loss or args.time_to_loss_config4:
         # the same comparison on the headline workload: by default a reduced training set (32
         # specimens, 512 tiles) and 2 held-out specimens; the full protocol with the flag
         from paper_2205_03902_amd import learned_init
         train4, test4 = (125, 8) if args.time_to_loss_config4 else (args.ttl4_train, args.ttl4_test)
-        log(f"bench: learned initialisation on the 1024^2, 12-slice workload ({train4} training specimens, "
-            f"{test4} held-out)")
-        torch.cuda.empty_cache()
-        res = learned_init.main(["--config", "4", "--train", str(train4), "--test", str(test4)], log=log)
-        out["time_to_loss_cfg4"] = dict(res["time_to_loss"], workload=res["workload"], train=res["train"],
-                                        train_crops=res["train_crops"], test=res["test"], epochs=res["epochs"],
-                                        sweeps=res["sweeps"], generation_s=res["generation_s"],
-                                        training_s=res["training_s"], heldout_loss=res["heldout_loss"][-1:])
+
+        def ttl4():
+            log(f"bench: learned initialisation on the 1024^2, 12-slice workload ({train4} training specimens, "
+                f"{test4} held-out)")
+            torch.cuda.empty_cache()
+            res = learned_init.main(["--config", "4", "--train", str(train4), "--test", str(test4)], log=log)
+            return dict(res["time_to_loss"], workload=res["workload"], train=res["train"],
+                        train_crops=res["train_crops"], test=res["test"], epochs=res["epochs"], sweeps=res["sweeps"],
+                        generation_s=res["generation_s"], training_s=res["training_s"],
+                        heldout_loss=res["heldout_loss"][-1:])
+        guarded(out, "time_to_loss_cfg4", ttl4)
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(geo, min(args.cpu_sample, geo.n_pos), truth=truth_np)

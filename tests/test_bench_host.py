@@ -73,3 +73,14 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2 and "exactly one GPU" in r.stderr and r.stdout == ""
 
+
+
+def test_a_failing_leg_is_recorded_and_the_line_survives(bench):
+    out = {"value": 1.0}
+    bench.guarded(out, "ok", lambda: {"ratio_median": 0.2})
+
+    def fails():
+        raise RuntimeError("out of memory")
+    bench.guarded(out, "broken", fails)
+    assert out["ok"] == {"ratio_median": 0.2} and out["value"] == 1.0
+    assert "out of memory" in out["broken"]["error"]
