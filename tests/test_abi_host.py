@@ -115,6 +115,12 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.ms_adjoint(None, None, None, None, None, None, None, None) == abi.MS_ERR_INVALID_ARG
     assert lib.ms_layer_step(None, None, 0, 1, None, None, None, None, None) == abi.MS_ERR_INVALID_ARG
     assert lib.ms_probe_step(None, None, 1, None, None, None, None, 0, None, None) == abi.MS_ERR_INVALID_ARG
+    # the plan's switches reject a missing plan; its queries answer 0
+    for setter in (lib.ms_plan_set_path, lib.ms_plan_set_bands, lib.ms_plan_set_kept_windows,
+                   lib.ms_plan_set_layer_carry, lib.ms_plan_set_objective):
+        assert setter(None, 1) == abi.MS_ERR_INVALID_ARG
+        assert "NULL" in lib.ms_last_error().decode()
+    assert lib.ms_plan_kept_windows(None) == 0 and lib.ms_plan_has_bands(None) == 0
 
 
 def _unet_declared():
