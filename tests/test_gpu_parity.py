@@ -222,9 +222,11 @@ def test_zero_far_field_follows_the_zero_phase_rule(dev):
     assert abs(loss.item() - ref) <= 1e-12 * ref
 
 
+@pytest.mark.parametrize("lines", [False, True])
 @pytest.mark.parametrize("kind", ["single_slice", "one_position", "object_equals_window"])
-def test_edge_geometries(dev, kind):
-    from paper_2205_03902_amd import configs
+def test_edge_geometries(dev, kind, lines):
+    """On the default path (the fused kernel at these sizes) and forced onto the line kernels."""
+    from paper_2205_03902_amd import abi, configs
     if kind == "single_slice":
         g = configs.small(n=32, obj=40, n_slices=1, scan=(2, 2), step_px=5.5, seed=3)
         pos = None
@@ -237,6 +239,9 @@ def test_edge_geometries(dev, kind):
         pos = None
     c = make_case(g, positions=pos)
     plan = _plan(c, dev)
+    if lines:
+        plan.set_path(abi.MS_PATH_LINES)
+    print(f"[case] edge geometry {kind}, {'line' if lines else 'default'} path", flush=True)
     inten = plan.forward(_t(c.probe, dev), _t(c.start, dev))
     loss, gs, gp = plan.adjoint(_t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev))
     ref_i = c.model.forward(c.probe, c.start)
