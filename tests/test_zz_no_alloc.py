@@ -79,3 +79,24 @@ def test_scratch_adjoint_rejects_a_problem_beyond_the_scratch(dev):
         abi.adjoint_scratch(pb, probe, slices, meas)
     assert e.value.status == abi.MS_ERR_BUDGET
     assert "scratch" in str(e.value)
+
+
+def test_scratch_adjoint_on_the_line_kernels(dev):
+    """256^2 windows (the line kernels) with wrapping positions: the problem needs 133 MiB with every
+    wave stored, so inside the scratch the call recomputes waves and cuts batches; against the
+    planned adjoint and the oracle at the parity bars."""
+    from paper_2205_03902_amd import abi
+    g = small_geometry(256)
+    c = make_case(g, positions=small_positions(g))
+    print(f"[case] scratch on the line kernels: {g.name}, {len(c.model.positions)} positions", flush=True)
+    pb, keep = _problem(c)
+    assert abi.workspace_size(pb) > 64 << 20      # more than the scratch (MS_SCRATCH_BYTES, include/ms.h)
+    p, s, m = _t(c.probe, dev), _t(c.start, dev), _t(c.measured, dev)
+    ls, gs, gp = abi.adjoint_scratch(pb, p, s, m)
+    plan = abi.Plan.from_geometry(g, positions=c.model.positions, device=dev)
+    l1, g1, p1 = plan.adjoint(p, s, m)
+    assert abs(ls.item() - l1.item()) / l1.item() < 1e-5
+    assert rel(gs.cpu().numpy(), g1.cpu().numpy()) < 1e-4 and rel(gp.cpu().numpy(), p1.cpu().numpy()) < 1e-4
+    ref_l, ref_gs, ref_gp, _ = c.model.loss_grad(c.probe, c.start, c.measured)
+    assert abs(ls.item() - ref_l) / ref_l < 1e-5
+    assert rel(gs.cpu().numpy(), ref_gs) < 1e-4 and rel(gp.cpu().numpy(), ref_gp) < 1e-4
